@@ -1,0 +1,90 @@
+"""Refinement residual and finite-difference gradients -- oracle side, FP64.
+
+Residual of one pose (the dense stage compares a rendered package with the
+query, Sec. 3.4; the form used here is an L1 photometric term plus a feature
+cosine term):
+    L = 1/(H W) * sum_p [ sum_c |rgb_c - rgb*_c| + lam_f (1 - cos(F_p, F*_p)) ]
+    cos(a, b) = a.b / (|a| |b| + 1e-8),   d|x|/dx = sign(x), sign(0) = 0.
+For a batch of poses the residual is the sum of the per-pose residuals.
+
+Finite differences use the frozen-decision renderer of the oracle: the set
+and order of Gaussians blended at each pixel are taken from a render at the
+reference point and held fixed, which is the smooth piece of the renderer the
+analytic gradient differentiates.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import render, render_frozen
+from .se3 import left_perturb
+
+COS_EPS = 1e-8
+
+
+def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0) -> float:
+    H, W = rgb.shape[1:]
+    l1 = np.abs(rgb - rgb_t).sum()
+    if feat is None or lam_f == 0.0:
+        return float(l1 / (H * W))
+    dot = (feat * feat_t).sum(axis=0)
+    na = np.sqrt((feat * feat).sum(axis=0))
+    nb = np.sqrt((feat_t * feat_t).sum(axis=0))
+    cos = dot / (na * nb + COS_EPS)
+    return float((l1 + lam_f * (1.0 - cos).sum()) / (H * W))
+
+
+def residual_grad(rgb, feat, rgb_t, feat_t, lam_f=1.0):
+    """Closed-form dL/d rgb (3,H,W) and dL/d feat (D,H,W)."""
+    H, W = rgb.shape[1:]
+    s = 1.0 / (H * W)
+    g_rgb = np.sign(rgb - rgb_t) * s
+    if feat is None or lam_f == 0.0:
+        return g_rgb, None
+    dot = (feat * feat_t).sum(axis=0)
+    na = np.sqrt((feat * feat).sum(axis=0))
+    nb = np.sqrt((feat_t * feat_t).sum(axis=0))
+    n = na * nb + COS_EPS
+    unit = np.divide(feat, na, out=np.zeros_like(feat), where=na > 0)
+    dcos = feat_t / n - (dot * nb / (n * n)) * unit
+    return g_rgb, -lam_f * s * dcos
+
+
+def linear_functional(out, weights) -> float:
+    """L = sum over channels of <w_k, out_k> for any subset of outputs (used to
+    check the depth and alpha gradients, which the residual does not touch)."""
+    return float(sum((out[k] * w).sum() for k, w in weights.items()))
+
+
+def fd_gradients(scene, pose, cam, loss_fn, h=1e-4, gauss_ids=(), tile=16, list_cap=512):
+    """Central differences of loss_fn(frozen render) with respect to the 6
+    left-perturbation pose coordinates (rho, phi) and, for each id in
+    gauss_ids, the 3 mean coordinates and the opacity.  Returns (g_pose (6,),
+    g_means (k,3), g_opac (k,), reference render)."""
+    ref = render(scene, pose, cam, mode="tiled", tile=tile, want_lists=True, list_cap=list_cap)
+    lists, counts = ref["lists"], ref["nblend"]
+
+    def L(pose12, means64=None, opac64=None):
+        out = render_frozen(scene, pose12, cam, lists, counts, means64=means64, opac64=opac64)
+        return loss_fn(out)
+
+    g_pose = np.zeros(6)
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        g_pose[k] = (L(left_perturb(pose, e)) - L(left_perturb(pose, -e))) / (2 * h)
+    ids = list(gauss_ids)
+    g_means = np.zeros((len(ids), 3))
+    g_opac = np.zeros(len(ids))
+    if ids:
+        m0 = scene.means.astype(np.float64)
+        o0 = scene.opacities.astype(np.float64)
+        for j, i in enumerate(ids):
+            for a in range(3):
+                mp = m0.copy(); mp[i, a] += h
+                mm = m0.copy(); mm[i, a] -= h
+                g_means[j, a] = (L(pose, means64=mp, opac64=o0) - L(pose, means64=mm, opac64=o0)) / (2 * h)
+            op = o0.copy(); op[i] += h
+            om = o0.copy(); om[i] -= h
+            g_opac[j] = (L(pose, means64=m0, opac64=op) - L(pose, means64=m0, opac64=om)) / (2 * h)
+    return g_pose, g_means, g_opac, ref

@@ -1,0 +1,454 @@
+"""Pins of the FP64 oracle against closed forms, library routines, brute force
+and invariants -- chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import synth
+from synth import Camera, Scene
+
+Y00 = 1.0 / (2.0 * math.sqrt(math.pi))  # textbook real SH, l = 0
+
+
+def _one(means, log_scales, quats, opac, rgb, feat=None, sh_degree=0):
+    n = len(means)
+    K = (sh_degree + 1) ** 2
+    sh = np.zeros((n, K, 3), dtype=np.float32)
+    sh[:, 0, :] = (np.asarray(rgb, dtype=np.float64) - 0.5) / Y00
+    return Scene(np.asarray(means, np.float32).reshape(n, 3), np.asarray(log_scales, np.float32).reshape(n, 3),
+                 np.asarray(quats, np.float32).reshape(n, 4), np.asarray(opac, np.float32).reshape(n),
+                 sh, sh_degree, None if feat is None else synth.f32_to_bf16_bits(np.asarray(feat, np.float32)))
+
+
+IDENT = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], dtype=np.float32)
+
+
+def _closed_alpha(cam, o, s2, u=None, v=None):
+    u = cam.cx if u is None else u
+    v = cam.cy if v is None else v
+    jj, ii = np.mgrid[0:cam.height, 0:cam.width]
+    d2 = (ii + 0.5 - u) ** 2 + (jj + 0.5 - v) ** 2
+    a = np.minimum(0.99, o * np.exp(-d2 / (2 * s2)))
+    return np.where(a >= 1 / 255, a, 0.0)
+
+
+# ------------------------------------------------------------------ projection
+def test_isotropic_closed_form(oracle_lib):
+    """One camera-facing isotropic Gaussian on the optical axis:
+    s^2 = (f sigma / z)^2 + 0.3 and alpha = min(0.99, o exp(-d^2 / 2 s^2))."""
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    sigma, z, o = 0.5, 10.0, 0.8
+    c = np.array([0.2, 0.6, 0.9])
+    f = np.linspace(-1, 1, 8).astype(np.float32) / 2
+    q = Rotation.random(random_state=3).as_quat()  # any rotation of an isotropic Gaussian
+    sc = _one([[0, 0, z]], [[math.log(sigma)] * 3], [[q[3], q[0], q[1], q[2]]], [o], [c], feat=[f])
+    sigma, o = math.exp(float(sc.log_scales[0, 0])), float(sc.opacities[0])  # the stored float32 values
+    c = sc.sh[0, 0].astype(np.float64) * Y00 + 0.5
+    r = oracle_lib.render(sc, IDENT, cam)
+    s2 = (cam.fx * sigma / z) ** 2 + 0.3
+    a = _closed_alpha(cam, o, s2)
+    np.testing.assert_allclose(r["alpha"], a, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["rgb"], c[:, None, None] * a[None], atol=1e-12)
+    np.testing.assert_allclose(r["depth"], np.where(a > 0, z, 0.0), atol=1e-12)
+    fb = synth.bf16_bits_to_f32(synth.f32_to_bf16_bits(f)).astype(np.float64)
+    np.testing.assert_allclose(r["feat"], fb[:, None, None] * a[None], atol=1e-12)
+    p = oracle_lib.project(sc, IDENT, cam)
+    np.testing.assert_allclose([p["cov_xx"][0], p["cov_xy"][0], p["cov_yy"][0]], [s2, 0, s2], rtol=1e-12, atol=1e-12)
+
+
+def test_anisotropic_axis_and_quaternion_order(oracle_lib):
+    """A 90-degree turn about z swaps the x and y variances (w,x,y,z order);
+    the world covariance equals scipy's rotation of diag(s^2)."""
+    cam = Camera(100.0, 120.0, 32.0, 24.0, 64, 48)
+    s = np.array([0.3, 0.7, 1.1])
+    z = 10.0
+    h = math.sqrt(0.5)
+    sc = _one([[0, 0, z], [0, 0, z]], [np.log(s)] * 2, [[h, 0, 0, h], [h, h, 0, 0]], [0.5, 0.5], [[0.5] * 3] * 2)
+    p = oracle_lib.project(sc, IDENT, cam)
+    np.testing.assert_allclose([p["cov_xx"][0], p["cov_yy"][0], p["cov_xy"][0]],
+                               [(cam.fx / z) ** 2 * s[1] ** 2 + 0.3, (cam.fy / z) ** 2 * s[0] ** 2 + 0.3, 0.0],
+                               rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose([p["cov_xx"][1], p["cov_yy"][1]],
+                               [(cam.fx / z) ** 2 * s[0] ** 2 + 0.3, (cam.fy / z) ** 2 * s[2] ** 2 + 0.3], rtol=1e-6)
+    rng = np.random.default_rng(0)
+    n = 50
+    q = rng.standard_normal((n, 4))
+    ls = rng.normal(-0.5, 0.3, (n, 3))
+    sc = _one(rng.normal(0, 1, (n, 3)) + [0, 0, 10], ls, q, np.full(n, 0.5), np.full((n, 3), 0.5))
+    p = oracle_lib.project(sc, IDENT, cam)
+    qf = sc.quats.astype(np.float64)
+    Rm = Rotation.from_quat(np.concatenate([qf[:, 1:], qf[:, :1]], axis=1)).as_matrix()
+    S2 = np.exp(2 * sc.log_scales.astype(np.float64))
+    Sw = np.einsum("nij,nj,nkj->nik", Rm, S2, Rm)
+    got = np.stack([p["cov3_xx"], p["cov3_xy"], p["cov3_xz"], p["cov3_yy"], p["cov3_yz"], p["cov3_zz"]], 1)
+    want = np.stack([Sw[:, 0, 0], Sw[:, 0, 1], Sw[:, 0, 2], Sw[:, 1, 1], Sw[:, 1, 2], Sw[:, 2, 2]], 1)
+    np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-12)
+
+
+def _rand_pose(seed):
+    rng = np.random.default_rng(seed)
+    R = Rotation.random(random_state=seed).as_matrix()
+    C = rng.normal(0, 3, 3)
+    t = -R @ C
+    return np.concatenate([R, t[:, None]], 1).reshape(12)
+
+
+def test_projection_matches_pinhole_and_ewa_jacobian(oracle_lib):
+    """u, v = K (X/Z) (the pinhole map of Algorithm 1); Sigma' - 0.3 I equals
+    J Sigma_c J^T with J the numerical Jacobian of that map (unclamped case)."""
+    cam = Camera(150.0, 140.0, 40.0, 30.0, 80, 60)
+    rng = np.random.default_rng(1)
+    pose = _rand_pose(7)
+    R, t = pose.reshape(3, 4)[:, :3], pose.reshape(3, 4)[:, 3]
+    n = 40
+    # place Gaussians in front of the camera inside the view
+    dirs = np.stack([rng.uniform(-0.2, 0.2, n), rng.uniform(-0.15, 0.15, n), np.ones(n)], 1)
+    depth = rng.uniform(5, 20, n)
+    mc = dirs * depth[:, None]
+    mw = (mc - t) @ R  # R^T (mc - t)
+    sc = _one(mw, rng.normal(-1, 0.3, (n, 3)), rng.standard_normal((n, 4)), np.full(n, 0.7), np.full((n, 3), 0.5))
+    mw = sc.means.astype(np.float64)
+    p = oracle_lib.project(sc, pose, cam)
+    mc = mw @ R.T + t
+    K = np.array([[cam.fx, 0, cam.cx], [0, cam.fy, cam.cy], [0, 0, 1]])
+    uvw = (K @ (mc / mc[:, 2:3]).T).T
+    np.testing.assert_allclose(p["u"], uvw[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(p["v"], uvw[:, 1], rtol=1e-12)
+    np.testing.assert_allclose(p["z"], mc[:, 2], rtol=1e-12)
+
+    def pix(x):
+        return np.array([cam.fx * x[0] / x[2] + cam.cx, cam.fy * x[1] / x[2] + cam.cy])
+
+    for i in range(n):
+        Sw = np.array([[p["cov3_xx"][i], p["cov3_xy"][i], p["cov3_xz"][i]],
+                       [p["cov3_xy"][i], p["cov3_yy"][i], p["cov3_yz"][i]],
+                       [p["cov3_xz"][i], p["cov3_yz"][i], p["cov3_zz"][i]]])
+        Sc = R @ Sw @ R.T
+        h = 1e-5 * mc[i, 2]
+        J = np.stack([(pix(mc[i] + h * e) - pix(mc[i] - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        S2 = J @ Sc @ J.T
+        got = np.array([[p["cov_xx"][i] - 0.3, p["cov_xy"][i]], [p["cov_xy"][i], p["cov_yy"][i] - 0.3]])
+        np.testing.assert_allclose(got, S2, rtol=1e-6, atol=1e-9 * np.abs(S2).max())
+        conic = np.linalg.inv(S2 + 0.3 * np.eye(2))
+        np.testing.assert_allclose([p["conic_a"][i], p["conic_b"][i], p["conic_c"][i]],
+                                   [conic[0, 0], conic[0, 1], conic[1, 1]], rtol=1e-6,
+                                   atol=1e-8 * np.abs(conic).max())
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_guard_clamp_freezes_jacobian(oracle_lib, axis):
+    """Inside 1.3x the half field of view Sigma' is the EWA form with the
+    pinhole Jacobian; beyond it the Jacobian is evaluated at the clamp, so
+    moving the Gaussian further out leaves Sigma' unchanged while the projected
+    mean keeps moving."""
+    cam = Camera(100.0, 110.0, 32.0, 24.0, 64, 48)
+    z = 10.0
+    tan = 32 / 100.0 if axis == 0 else 24 / 110.0
+    ratios = [1.2, 1.3, 1.5, 3.0]
+    pos = [[r * tan * z, 0.5, z] if axis == 0 else [0.5, r * tan * z, z] for r in ratios]
+    sc = _one(pos, [[0.0, -0.5, 0.3]] * 4, [[0.9, 0.1, 0.3, 0.2]] * 4, [0.6] * 4, [[0.5] * 3] * 4)
+    p = oracle_lib.project(sc, IDENT, cam)
+    for k in ("cov_xx", "cov_xy", "cov_yy"):
+        np.testing.assert_allclose(p[k][1:], p[k][1], rtol=1e-6)
+    uv = p["u"] if axis == 0 else p["v"]
+    assert uv[1] < uv[2] < uv[3]
+
+    def pix(x):
+        return np.array([cam.fx * x[0] / x[2] + cam.cx, cam.fy * x[1] / x[2] + cam.cy])
+
+    for i in (0, 1):  # at and inside the guard band the Jacobian is the pinhole one
+        m = sc.means[i].astype(np.float64)
+        Sw = np.array([[p["cov3_xx"][i], p["cov3_xy"][i], p["cov3_xz"][i]],
+                       [p["cov3_xy"][i], p["cov3_yy"][i], p["cov3_yz"][i]],
+                       [p["cov3_xz"][i], p["cov3_yz"][i], p["cov3_zz"][i]]])
+        h = 1e-6 * z
+        J = np.stack([(pix(m + h * e) - pix(m - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        S2 = J @ Sw @ J.T
+        np.testing.assert_allclose([p["cov_xx"][i] - 0.3, p["cov_xy"][i], p["cov_yy"][i] - 0.3],
+                                   [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-5)
+
+
+def test_alpha_clamped_at_099(oracle_lib):
+    """alpha = min(0.99, o e^{-q/2}): an opaque Gaussian centred on a pixel
+    centre gives exactly 0.99 there."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    sc = _one([[0, 0, 10]], [[0.0] * 3], [[1, 0, 0, 0]], [1.0], [[1, 1, 1]])
+    r = oracle_lib.render(sc, IDENT, cam)
+    assert r["alpha"][24, 32] == 0.99
+    assert r["alpha"].max() == 0.99
+
+
+# ------------------------------------------------------------------ blending
+def test_over_operator_two_gaussians(oracle_lib):
+    """Two Gaussians on the axis: rgb = c1 a1 + c2 a2 (1 - a1), alpha =
+    1 - (1-a1)(1-a2), depth = weighted mean of z; input order irrelevant."""
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    z1, z2, s1, s2_, o1, o2 = 10.0, 14.0, 0.4, 0.9, 0.7, 0.6
+    c1, c2 = np.array([1.0, 0.2, 0.1]), np.array([0.1, 0.3, 0.9])
+    for order in ([0, 1], [1, 0]):
+        means = np.array([[0, 0, z1], [0, 0, z2]])[order]
+        sc = _one(means, np.log([[s1] * 3, [s2_] * 3])[order], [[1, 0, 0, 0]] * 2, np.array([o1, o2])[order],
+                  np.array([c1, c2])[order])
+        r = oracle_lib.render(sc, IDENT, cam)
+        i1, i2 = order.index(0), order.index(1)
+        f1, f2 = float(sc.opacities[i1]), float(sc.opacities[i2])
+        g1, g2 = math.exp(float(sc.log_scales[i1, 0])), math.exp(float(sc.log_scales[i2, 0]))
+        c1 = sc.sh[i1, 0].astype(np.float64) * Y00 + 0.5
+        c2 = sc.sh[i2, 0].astype(np.float64) * Y00 + 0.5
+        a1 = _closed_alpha(cam, f1, (cam.fx * g1 / z1) ** 2 + 0.3)
+        a2 = _closed_alpha(cam, f2, (cam.fx * g2 / z2) ** 2 + 0.3)
+        np.testing.assert_allclose(r["rgb"], c1[:, None, None] * a1 + c2[:, None, None] * a2 * (1 - a1), atol=1e-12)
+        A = 1 - (1 - a1) * (1 - a2)
+        np.testing.assert_allclose(r["alpha"], A, atol=1e-12)
+        dep = np.divide(a1 * z1 + a2 * (1 - a1) * z2, A, out=np.zeros_like(A), where=A > 0)
+        np.testing.assert_allclose(r["depth"], dep, rtol=1e-12, atol=1e-12)
+
+
+def test_termination_stack(oracle_lib):
+    """Five o=0.95 Gaussians centred on a pixel: T = 0.05, 0.0025, 1.25e-4,
+    then 6.25e-6 < 1e-4 so the 4th is not blended; alpha = 0.999875."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    cols = np.random.default_rng(2).uniform(0, 1, (5, 3))
+    sc = _one([[0, 0, 10 + k] for k in range(5)], [[0.0] * 3] * 5, [[1, 0, 0, 0]] * 5, [0.95] * 5, cols)
+    r = oracle_lib.render(sc, IDENT, cam)
+    o = float(np.float32(0.95))
+    assert abs(r["alpha"][24, 32] - (1 - (1 - o) ** 3)) < 1e-12 and abs(r["alpha"][24, 32] - 0.999875) < 1e-7
+    assert r["nblend"][24, 32] == 3
+    cols = sc.sh[:, 0, :].astype(np.float64) * Y00 + 0.5
+    want = sum(cols[k] * o * (1 - o) ** k for k in range(3))
+    np.testing.assert_allclose(r["rgb"][:, 24, 32], want, atol=1e-12)
+
+
+def test_associativity_front_back(oracle_lib):
+    """Compositing the front half and then the back half with 'over' equals
+    compositing the whole depth-sorted list (no termination: low opacity)."""
+    sc, P, cam = synth.tiny_scene(120, 11, feat_dim=8)
+    sc.opacities[:] = np.minimum(sc.opacities, 0.35)
+    p = oracle_lib.project(sc, P[0], cam)
+    zmed = np.median(p["z"])
+    front = np.nonzero(p["z"] < zmed)[0]
+    back = np.nonzero(p["z"] >= zmed)[0]
+    r = oracle_lib.render(sc, P[0], cam)
+    assert r["T"].min() > 1e-3
+    rf = oracle_lib.render(sc.subset(front), P[0], cam)
+    rb = oracle_lib.render(sc.subset(back), P[0], cam)
+    np.testing.assert_allclose(r["rgb"], rf["rgb"] + rf["T"] * rb["rgb"], atol=1e-12)
+    np.testing.assert_allclose(r["T"], rf["T"] * rb["T"], atol=1e-12)
+    np.testing.assert_allclose(r["feat"], rf["feat"] + rf["T"] * rb["feat"], atol=1e-12)
+    Z = r["depth"] * r["alpha"]
+    np.testing.assert_allclose(Z, rf["depth"] * rf["alpha"] + rf["T"] * rb["depth"] * rb["alpha"], atol=1e-9)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_brute_force_equals_tiled_bitwise(oracle_lib, tile):
+    """The tiled renderer reaches exactly the per-pixel global-sort definition
+    (seeds 0-99, N <= 200, 64x48)."""
+    for seed in range(100):
+        n = 20 + (seed * 37) % 181
+        sc, P, cam = synth.tiny_scene(n, seed, feat_dim=4 if seed % 3 == 0 else 0, sh_degree=seed % 4)
+        b = oracle_lib.render(sc, P[0], cam, mode="brute")
+        t = oracle_lib.render(sc, P[0], cam, mode="tiled", tile=tile, margin=seed % 2)
+        for k in ("rgb", "depth", "alpha", "T", "nblend"):
+            assert np.array_equal(b[k], t[k]), (seed, k)
+        if sc.feat is not None:
+            assert np.array_equal(b["feat"], t["feat"])
+
+
+def test_permutation_invariance(oracle_lib):
+    sc, P, cam = synth.tiny_scene(200, 5, feat_dim=4, sh_degree=2)
+    r = oracle_lib.render(sc, P[0], cam)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    r2 = oracle_lib.render(sc.subset(perm), P[0], cam)
+    for k in ("rgb", "depth", "alpha", "feat"):
+        np.testing.assert_allclose(r[k], r2[k], atol=1e-12)
+
+
+def test_support_rectangle_is_exact(oracle_lib):
+    """Every pixel with alpha >= 1/255 lies in the Gaussian's rectangle, and the
+    rectangle is the tightest one: a row and a column of every border hold a
+    pixel within the ellipse's bounding box."""
+    sc, P, cam = synth.tiny_scene(150, 9)
+    p = oracle_lib.project(sc, P[0], cam)
+    jj, ii = np.mgrid[0:cam.height, 0:cam.width]
+    for i in np.nonzero(p["visible"])[0]:
+        dx = ii + 0.5 - p["u"][i]
+        dy = jj + 0.5 - p["v"][i]
+        q = p["conic_a"][i] * dx * dx + 2 * p["conic_b"][i] * dx * dy + p["conic_c"][i] * dy * dy
+        ok = p["o"][i] * np.exp(-0.5 * q) >= 1 / 255
+        inside = (ii >= p["px0"][i]) & (ii <= p["px1"][i]) & (jj >= p["py0"][i]) & (jj <= p["py1"][i])
+        assert not np.any(ok & ~inside), i
+        assert abs(p["rx"][i] - math.sqrt(2 * math.log(255 * p["o"][i]) * p["cov_xx"][i])) < 1e-9
+
+
+def test_degenerate_cases(oracle_lib):
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    # empty scene -> background
+    empty = _one(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)), np.zeros(0), np.zeros((0, 3)))
+    r = oracle_lib.render(empty, IDENT, cam, bg=(0.1, 0.2, 0.3))
+    np.testing.assert_allclose(r["rgb"][:, 5, 5], [0.1, 0.2, 0.3])
+    assert r["alpha"].max() == 0 and r["depth"].max() == 0
+    # opacity below 1/255, behind the near plane, behind the camera -> invisible
+    sc = _one([[0, 0, 10], [0, 0, 0.1], [0, 0, -5]], [[0.0] * 3] * 3, [[1, 0, 0, 0]] * 3,
+              [1 / 255 * 0.99, 0.9, 0.9], [[1, 1, 1]] * 3)
+    p = oracle_lib.project(sc, IDENT, cam)
+    assert list(p["visible"]) == [0, 0, 0]
+    r = oracle_lib.render(sc, IDENT, cam, bg=(0.5, 0.5, 0.5))
+    assert r["alpha"].max() == 0
+    np.testing.assert_allclose(r["rgb"], 0.5)
+    # background is added with the remaining transmittance
+    sc = _one([[0, 0, 10]], [[0.0] * 3], [[1, 0, 0, 0]], [0.8], [[1.0, 0.0, 0.0]])
+    r0 = oracle_lib.render(sc, IDENT, cam)
+    r1 = oracle_lib.render(sc, IDENT, cam, bg=(0.0, 1.0, 0.0))
+    np.testing.assert_allclose(r1["rgb"][1], r0["T"], atol=1e-12)
+
+
+def test_depth_is_camera_z_under_pose(oracle_lib):
+    """Depth of a lone Gaussian is its camera-space z (Algorithm 1's depth),
+    through a general pose."""
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    pose = _rand_pose(3)
+    R, t = pose.reshape(3, 4)[:, :3], pose.reshape(3, 4)[:, 3]
+    mc = np.array([0.3, -0.2, 12.0])
+    sc = _one([(mc - t) @ R], [[0.0] * 3], [[1, 0, 0, 0]], [0.9], [[0.5] * 3])
+    r = oracle_lib.render(sc, pose, cam)
+    zc = (R @ sc.means[0].astype(np.float64) + t)[2]
+    d = r["depth"][r["alpha"] > 0]
+    np.testing.assert_allclose(d, zc, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ SH
+def test_sh_orthonormal_by_quadrature(oracle_lib):
+    n_t, n_p = 24, 48
+    x, w = np.polynomial.legendre.leggauss(n_t)
+    phi = (np.arange(n_p) + 0.5) * 2 * np.pi / n_p
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    wts = (w[:, None] * np.full(n_p, 2 * np.pi / n_p)[None]).reshape(-1)
+    Y = oracle_lib.sh_basis(3, dirs)
+    G = (Y * wts[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_convention_matches_scipy(oracle_lib):
+    """Real SH = sqrt(2) Re / Im of scipy's complex harmonics (Condon-Shortley
+    phase), ordered m = -l..l."""
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((64, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle_lib.sh_basis(3, d)
+    theta = np.arccos(d[:, 2])
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), theta, phi)
+            want = c.real if m == 0 else (np.sqrt(2) * (c.real if m > 0 else c.imag))
+            np.testing.assert_allclose(Y[:, l * l + l + m], want, atol=1e-12)
+    # first-order terms are -C y, C z, -C x
+    C1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(Y[:, 1:4], np.stack([-C1 * d[:, 1], C1 * d[:, 2], -C1 * d[:, 0]], 1), atol=1e-12)
+
+
+def test_sh_degree0_reproduces_colour(oracle_lib):
+    sc, P, cam = synth.tiny_scene(50, 2)
+    p = oracle_lib.project(sc, P[0], cam)
+    want = np.maximum(0, sc.sh[:, 0, :].astype(np.float64) * Y00 + 0.5)
+    np.testing.assert_allclose(np.stack([p["r"], p["g"], p["b"]], 1), want, atol=1e-12)
+    assert want.min() >= 0 and want.max() <= 1
+
+
+def test_view_dependent_colour_uses_camera_centre(oracle_lib):
+    """A degree-1 coefficient on Y_1,0 (= C1 * d_z) gives colour 0.5 + k C1 d_z
+    with d the unit vector from the camera centre to the mean."""
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    pose = _rand_pose(5)
+    R, t = pose.reshape(3, 4)[:, :3], pose.reshape(3, 4)[:, 3]
+    mw = (np.array([0.1, 0.2, 9.0]) - t) @ R
+    sc = _one([mw], [[0.0] * 3], [[1, 0, 0, 0]], [0.9], [[0.5] * 3], sh_degree=1)
+    sc.sh[0, 0, :] = 0.0
+    sc.sh[0, 2, :] = [1.0, -0.5, 0.25]
+    p = oracle_lib.project(sc, pose, cam)
+    C = -R.T @ t
+    d = sc.means[0].astype(np.float64) - C
+    d /= np.linalg.norm(d)
+    C1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose([p["r"][0], p["g"][0], p["b"][0]],
+                               np.maximum(0, 0.5 + np.array([1.0, -0.5, 0.25]) * C1 * d[2]), atol=1e-12)
+
+
+# ------------------------------------------------------------------ tile lists
+def test_tile_lists_match_rectangles(oracle_lib):
+    sc, P, cam = synth.tiny_scene(180, 13)
+    tile = 16
+    p = oracle_lib.project(sc, P[0], cam)
+    off, ids, edge = oracle_lib.tile_lists(sc, P[0], cam, tile)
+    ntx = (cam.width + tile - 1) // tile
+    nty = (cam.height + tile - 1) // tile
+    for ty in range(nty):
+        for tx in range(ntx):
+            b = ty * ntx + tx
+            got = ids[off[b]:off[b + 1]]
+            want = [i for i in range(sc.n) if p["visible"][i] and p["px0"][i] // tile <= tx <= p["px1"][i] // tile
+                    and p["py0"][i] // tile <= ty <= p["py1"][i] // tile]
+            want.sort(key=lambda i: (p["z"][i], i))
+            assert list(got) == want
+
+
+# ------------------------------------------------------------------ pose tangent and residual
+def test_se3_exp_matches_matrix_exponential():
+    from scipy.linalg import expm
+    from oracle.se3 import exp_se3, hat
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        xi = rng.normal(0, 0.7, 6)
+        X = np.zeros((4, 4))
+        X[:3, :3] = hat(xi[3:])
+        X[:3, 3] = xi[:3]
+        np.testing.assert_allclose(exp_se3(xi), expm(X), atol=1e-12)
+    np.testing.assert_allclose(exp_se3(np.zeros(6)), np.eye(4))
+
+
+def test_residual_gradient_closed_form():
+    from oracle.loss import residual, residual_grad
+    rng = np.random.default_rng(1)
+    rgb, rgbt = rng.uniform(0, 1, (3, 5, 4)), rng.uniform(0, 1, (3, 5, 4))
+    f, ft = rng.normal(0, 1, (6, 5, 4)), rng.normal(0, 1, (6, 5, 4))
+    gr, gf = residual_grad(rgb, f, rgbt, ft)
+    h = 1e-6
+    for idx in [(0, 1, 2), (2, 4, 3), (1, 0, 0)]:
+        a = rgb.copy(); a[idx] += h
+        b = rgb.copy(); b[idx] -= h
+        assert abs((residual(a, f, rgbt, ft) - residual(b, f, rgbt, ft)) / (2 * h) - gr[idx]) < 1e-7
+    for idx in [(0, 1, 2), (5, 4, 3), (3, 2, 1)]:
+        a = f.copy(); a[idx] += h
+        b = f.copy(); b[idx] -= h
+        assert abs((residual(rgb, a, rgbt, ft) - residual(rgb, b, rgbt, ft)) / (2 * h) - gf[idx]) < 1e-7
+    # identical features give zero feature residual
+    assert abs(residual(rgbt, ft, rgbt, ft)) < 1e-8
+
+
+def test_frozen_render_reproduces_reference(oracle_lib):
+    sc, P, cam = synth.tiny_scene(150, 21, feat_dim=4)
+    r = oracle_lib.render(sc, P[0], cam, want_lists=True)
+    fz = oracle_lib.render_frozen(sc, P[0], cam, r["lists"], r["nblend"])
+    for k in ("rgb", "depth", "alpha", "T", "feat"):
+        assert np.array_equal(r[k], fz[k]), k
+
+
+def test_translation_identity_of_finite_differences(oracle_lib):
+    """Moving every mean by delta equals moving the camera by -delta, so
+    dL/drho = R sum_i dL/dmu_i (any SH degree)."""
+    from oracle.loss import fd_gradients, residual
+    sc, P, cam = synth.tiny_scene(25, 31, feat_dim=4, sh_degree=2)
+    pose = P[0].astype(np.float64)
+    tgt = oracle_lib.render(sc, synth.perturb_poses(P[0], 1, 99, 0.5, 1.0)[0], cam)
+    loss = lambda o: residual(o["rgb"], o["feat"], tgt["rgb"], tgt["feat"])
+    g_pose, g_means, _, _ = fd_gradients(sc, pose, cam, loss, h=1e-5, gauss_ids=range(sc.n))
+    R = pose.reshape(3, 4)[:, :3]
+    want = R @ g_means.sum(0)
+    assert np.linalg.norm(want) > 1e-4
+    np.testing.assert_allclose(g_pose[:3], want, rtol=1e-5, atol=1e-9)
