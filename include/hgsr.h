@@ -1,0 +1,283 @@
+/*
+ * hgsr -- MI355X (gfx950) tile rasterizer of 3D Gaussian splats: RGB, depth,
+ * alpha and feature maps of a Gaussian scene at one or many camera poses, and
+ * the gradient of a loss on those maps with respect to the poses and the
+ * Gaussian parameters.
+ *
+ * What it computes (Hi^2-GSLoc, arXiv 2507.15683):
+ *   - the scene is a set of Gaussian primitives with centre, rotation, scale,
+ *     opacity, colour and feature vector (Sec. 3.1);
+ *   - colour and feature are alpha-blended front to back by the same tile
+ *     rasterization (Sec. 3.1, the joint radiance/feature field);
+ *   - the renderer is called as rasterization(means, opacity, q, c, s, K, T)
+ *     (Algorithm 1) and, in the dense stage, renders dense feature and depth
+ *     maps at a candidate pose (Sec. 3.4), repeated at every refinement step;
+ *   - its backward gives the per-Gaussian gradients whose non-zero pattern is
+ *     the render-visibility test of Algorithm 1.
+ * The paper takes the rasterizer from 3D Gaussian Splatting and does not
+ * restate it; this library fixes it as follows.  Per Gaussian: EWA
+ * projection Sigma' = J R Sigma R^T J^T + 0.3 I with the pinhole Jacobian J
+ * evaluated at x/z, y/z clamped to 1.3x the half field of view; colour =
+ * max(0, sum_lm k_lm Y_lm(d) + 0.5) with d the unit vector from the camera
+ * centre; culled when z <= near_z or opacity < 1/255; its pixel support is
+ * the bounding box of the ellipse where o exp(-q/2) >= 1/255.  Per pixel,
+ * Gaussians in ascending (camera z, index) order: alpha = min(0.99,
+ * o exp(-q/2)) with q the conic distance; skipped when alpha < 1/255; the
+ * walk stops (without blending) at the first Gaussian that would take the
+ * transmittance T below 1e-4; rgb = sum w c + T bg, alpha = 1 - T,
+ * depth = sum w z / (1 - T) (0 when nothing is blended), feat = sum w f,
+ * with w = alpha T.
+ *
+ * Conventions
+ *   - Every data pointer is a DEVICE pointer, owned by the caller, unless the
+ *     comment says "host".  The library never frees caller memory.
+ *   - Gaussians: structure of arrays, FP32, feature vectors as bfloat16 bits.
+ *   - Poses: P x 12 floats, row-major [R | t], world -> camera, x_c = R x_w + t;
+ *     camera axes x right, y down, z forward.  Pixel (i, j) has its centre
+ *     at (i + 0.5, j + 0.5).
+ *   - Images are planar per pose: rgb P x 3 x H x W, depth/alpha P x H x W,
+ *     feat P x D x H x W (the D x H' x W' feature map of Sec. 3.1).
+ *   - Pose gradients are in the left-perturbation tangent T <- Exp(xi) T,
+ *     xi = (rho, phi), translation first.
+ *   - Every call returns an hgsr_status and never throws; arguments are
+ *     validated on the host before anything is enqueued.  HIP failures return
+ *     HGSR_ERR_HIP; hgsr_last_error() gives a thread-local message.
+ *   - All calls except hgsr_check_overflow, hgsr_stats, hgsr_debug_* and
+ *     hgsr_autotune are asynchronous on the given stream and can be captured
+ *     into a HIP graph.
+ */
+#ifndef HGSR_H_
+#define HGSR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hgsr_stream;  /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  HGSR_OK = 0,
+  HGSR_ERR_INVALID_ARG = 1, /* bad sizes, null required pointer, NaN input (validate) */
+  HGSR_ERR_HIP = 2,         /* a HIP runtime call failed */
+  HGSR_ERR_CAPACITY = 3,    /* workspace too small: the overflow flag was raised */
+  HGSR_ERR_UNSUPPORTED = 4, /* a combination this build does not implement */
+  HGSR_ERR_STATE = 5        /* call out of order (backward without render, ...) */
+} hgsr_status;
+
+typedef struct hgsr_ctx hgsr_ctx;
+
+/* The Gaussian scene (Sec. 3.1: centre, rotation, scale, opacity, colour,
+ * feature).  means n x 3; log_scales n x 3 (log of per-axis std. dev.);
+ * quats n x 4 in (w, x, y, z) order, normalised by the renderer; opacities n,
+ * already in [0, 1]; sh n x (sh_degree+1)^2 x 3 real spherical-harmonic
+ * coefficients (degree 0..3), colour = max(0, SH + 0.5); feat n x feat_dim
+ * bfloat16 bit patterns, feat_dim in {0, 8, 16, 32, 64}.
+ * Optional spatial partitions (VastGaussian cells, Sec. 3.1): the Gaussians
+ * of partition k are the contiguous range [part_offsets[k], part_offsets[k+1])
+ * (device int64, n_parts + 1 entries) and part_bounds (device, n_parts x 6:
+ * min xyz, max xyz) bound every point of those Gaussians' support; fill it
+ * with hgsr_partition_bounds.  n_parts = 0: unpartitioned. */
+typedef struct {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  int32_t sh_degree;
+  int32_t feat_dim;
+  const uint16_t* feat;
+  int32_t n_parts;
+  const int64_t* part_offsets;
+  const float* part_bounds;
+} hgsr_gaussians;
+
+/* Pinhole intrinsics (the K of Algorithm 1), host struct. */
+typedef struct {
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} hgsr_intrinsics;
+
+enum { HGSR_SORT_BUCKET = 0, HGSR_SORT_LSD = 1 };
+enum { HGSR_SCHED_GRID = 0, HGSR_SCHED_POSE_MAJOR = 1, HGSR_SCHED_TILE_MAJOR = 2, HGSR_SCHED_AUTO = -1 };
+
+/* Render options (host struct).  tile: 8, 16 or 32 pixels, or 0 for the
+ * autotuned choice (16 when none).  sort_mode: HGSR_SORT_BUCKET (counting
+ * sort on the tile id, then a per-tile LDS sort on (depth, index)) or
+ * HGSR_SORT_LSD (device LSD radix sort of (tile, depth, index) keys); both
+ * give the same order.  schedule: blend launch shape (HGSR_SCHED_*).
+ * bg: background colour added with the final transmittance.  near_z: camera
+ * z below which a Gaussian is culled (0.2).  feat_out_bf16: write the feature
+ * image as bfloat16 (FP32 accumulation).  lds_sort_cap: largest per-tile list
+ * sorted in LDS (0 = default 4096; larger lists take a global-memory path). */
+typedef struct {
+  int32_t tile;
+  int32_t sort_mode;
+  int32_t schedule;
+  float bg[3];
+  float near_z;
+  int32_t feat_out_bf16;
+  int32_t lds_sort_cap;
+} hgsr_opts;
+
+/* Output images (device, caller-allocated).  rgb, depth and alpha are
+ * required; feat may be NULL (not written).  feat is float or bfloat16 bits
+ * per hgsr_opts.feat_out_bf16. */
+typedef struct {
+  float* rgb;
+  float* depth;
+  float* alpha;
+  void* feat;
+} hgsr_outputs;
+
+/* Loss gradients with respect to the outputs (device, FP32, same layouts);
+ * any may be NULL meaning zero. */
+typedef struct {
+  const float* rgb;
+  const float* depth;
+  const float* alpha;
+  const float* feat;
+} hgsr_grad_outputs;
+
+/* Gradients written by hgsr_render_backward (device, FP32, overwritten; NULL
+ * = not computed).  pose: P x 6 (rho, phi); means n x 3; opacities n;
+ * log_scales n x 3; quats n x 4 (with respect to the stored, unnormalised
+ * quaternion); sh n x K x 3; feat n x feat_dim.  Gaussian gradients are summed
+ * over poses. */
+typedef struct {
+  float* pose;
+  float* means;
+  float* opacities;
+  float* log_scales;
+  float* quats;
+  float* sh;
+  float* feat;
+} hgsr_grads;
+
+/* Per-render counters (host struct, from hgsr_stats). */
+typedef struct {
+  int64_t visible;       /* (pose, Gaussian) pairs with a non-empty support */
+  int64_t keys;          /* (pose, tile, Gaussian) entries */
+  int64_t max_tile_list; /* longest per-tile list */
+  int32_t overflow;      /* bit 0 records, bit 1 keys */
+  int32_t tile;          /* tile size used */
+} hgsr_render_stats;
+
+/* Result of hgsr_autotune (host struct). */
+typedef struct {
+  int32_t tile;
+  int32_t schedule;
+  float ms;              /* best time per render */
+} hgsr_tune_result;
+
+/* Create a context on the current HIP device.  The context owns the
+ * workspace (projected splats, keys, per-tile lists, the per-pixel final
+ * transmittance and list length saved for the backward).  Capacity hints may
+ * be 0. */
+hgsr_status hgsr_ctx_create(hgsr_ctx** ctx, int64_t record_hint, int64_t key_hint);
+hgsr_status hgsr_ctx_destroy(hgsr_ctx* ctx);
+
+/* Pre-size the workspace for P poses of W x H at tile size `tile` with
+ * room for `records_per_pose` visible Gaussians per pose and `keys` tile
+ * entries in total.  Required before graph capture (no allocation is
+ * allowed while capturing). */
+hgsr_status hgsr_reserve(hgsr_ctx* ctx, int32_t P, int32_t width, int32_t height, int32_t tile,
+                         int64_t records_per_pose, int64_t keys, int64_t n_gaussians);
+
+/* Render P poses (device pointer, P x 12) of the scene:
+ * out = {rgb, depth, alpha, feat} per pose.  Enqueues the projection, tile
+ * binning, sort and blend kernels on `stream`; no host synchronisation.  The
+ * context keeps what the backward needs until the next hgsr_render.  When
+ * the workspace is too small the overflow flag is raised on the device, the
+ * outputs are undefined, and hgsr_check_overflow reports it. */
+hgsr_status hgsr_render(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream);
+
+/* Backward of the last hgsr_render on this context: replays each pixel's
+ * blend in reverse from the saved final transmittance and writes the
+ * requested gradients.  The forward's inputs and its depth/alpha outputs
+ * must still hold the values of that render. */
+hgsr_status hgsr_render_backward(hgsr_ctx* ctx, const hgsr_grad_outputs* grad_out, const hgsr_grads* grads,
+                                 hgsr_stream stream);
+
+/* Refinement residual of P rendered poses against targets (Sec. 3.4 compares
+ * the rendered package with the query): per pose
+ *   L = 1/(H W) sum_p [ sum_c |rgb - rgb*| + lam_f (1 - cos(F, F*)) ],
+ * cos(a, b) = a.b / (|a| |b| + 1e-8).  Writes loss (P floats), dL/drgb
+ * (P x 3 x H x W) and, when D > 0, dL/dfeat (P x D x H x W).  feat is float
+ * or bfloat16 bits per feat_bf16; targets are float. */
+hgsr_status hgsr_residual(const float* rgb, const void* feat, int32_t feat_bf16, const float* rgb_target,
+                          const float* feat_target, int32_t P, int32_t H, int32_t W, int32_t D, float lam_f,
+                          float* loss, float* grad_rgb, float* grad_feat, hgsr_stream stream);
+
+/* One Adam step on the pose tangents and the left update T <- Exp(-step) T.
+ * poses P x 12 (updated in place), grad P x 6, m and v P x 6 (state),
+ * step_count: device int32 incremented by the call (so graph replays
+ * advance it); lr_rho in metres, lr_phi in radians. */
+hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step_count, int32_t P,
+                           float lr_rho, float lr_phi, float beta1, float beta2, float eps, hgsr_stream stream);
+
+/* Fill part_bounds (device, n_parts x 6) with a box containing, for every
+ * Gaussian of each partition, the ball of radius 3.33 x its largest scale
+ * around its mean (the 1/255 support of the most opaque Gaussian). */
+hgsr_status hgsr_partition_bounds(const hgsr_gaussians* g, float* part_bounds, hgsr_stream stream);
+
+/* Check the Gaussian arrays for NaN/Inf, opacities outside [0, 1] and zero
+ * quaternions.  Synchronises `stream`.  Returns HGSR_ERR_INVALID_ARG on the
+ * first problem found. */
+hgsr_status hgsr_validate(const hgsr_gaussians* g, hgsr_stream stream);
+
+/* Graph capture of everything enqueued on `stream` between begin and end;
+ * launch replays it `replays` times on `stream`. */
+hgsr_status hgsr_graph_begin(hgsr_ctx* ctx, hgsr_stream stream);
+hgsr_status hgsr_graph_end(hgsr_ctx* ctx);
+hgsr_status hgsr_graph_launch(hgsr_ctx* ctx, int32_t replays, hgsr_stream stream);
+
+/* Synchronise `stream` and report whether the last render overflowed its
+ * workspace (*overflowed = bit mask, 0 = fine).  When it did, the workspace
+ * is grown to the sizes the device measured so that a re-render fits. */
+hgsr_status hgsr_check_overflow(hgsr_ctx* ctx, int32_t* overflowed, hgsr_stream stream);
+
+/* Counters of the last render (synchronises `stream`). */
+hgsr_status hgsr_stats(hgsr_ctx* ctx, hgsr_render_stats* out, hgsr_stream stream);
+
+/* Copy pose `pose`'s per-tile lists of the last render to host memory:
+ * ranges (host, tiles x 2: begin, end offsets into gids) and gids (host,
+ * capacity cap) holding Gaussian indices in blend order.  *n receives the
+ * number of entries.  Synchronises `stream`. */
+hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges, uint32_t* gids, int64_t cap,
+                                  int64_t* n, hgsr_stream stream);
+
+/* Time the renderer on this input for tile sizes 8/16/32 and the blend
+ * schedules, keep the fastest as the context's default (opts->tile == 0,
+ * opts->schedule == HGSR_SCHED_AUTO), and append it to the JSON cache file
+ * `cache_path` (host string, may be NULL).  Synchronises `stream`. */
+hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
+                          const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream);
+
+/* Stage timing.  While enabled, hgsr_render records HIP events on its
+ * stream around its stages (0: projection, 1: tile binning and sort,
+ * 2: blend) and hgsr_render_backward around its stages (3: blend backward,
+ * 4: projection backward); nothing is recorded while a graph is captured.
+ * hgsr_profile_read synchronises, returns the milliseconds accumulated per
+ * stage (host array of 6 doubles) and the number of timed calls per stage
+ * (host array of 6 int64, may be NULL), and resets the accumulators. */
+hgsr_status hgsr_profile_enable(hgsr_ctx* ctx, int32_t enable);
+hgsr_status hgsr_profile_read(hgsr_ctx* ctx, double* ms, int64_t* calls);
+
+/* Thread-local description of the last error. */
+const char* hgsr_last_error(void);
+
+/* Library version string. */
+const char* hgsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGSR_H_ */

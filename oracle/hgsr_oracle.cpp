@@ -268,16 +268,19 @@ Proj project(const orc_scene& s, int64_t i, const Pose& P, const orc_camera& cam
     }
   }
   g.visible = (g.z > cam.near_z && g.o >= kAlphaMin && g.px0 <= g.px1 && g.py0 <= g.py1) ? 1 : 0;
-  // FP32 error-bound estimates (for fragile-pixel flags): each camera-space
-  // coordinate is a 4-term sum whose rounding error is a few units of its
-  // largest term; the projection adds a product, a quotient and a sum.
-  const double ex = 4 * kEps32 * mag[0], ey = 4 * kEps32 * mag[1], ez = 4 * kEps32 * mag[2];
+  // FP32 error bounds of the renderer's arithmetic (for fragile-pixel flags):
+  // each camera-space coordinate is a chain of three fused multiply-adds, so
+  // its rounding error is at most 1.5 units in the last place of the largest
+  // partial sum, bounded by the sum of the terms' magnitudes; the projection
+  // adds a quotient and a fused multiply-add.  The conic inherits the relative
+  // error of the covariance chain amplified by the conditioning of det.
+  const double ex = 1.5 * kEps32 * mag[0], ey = 1.5 * kEps32 * mag[1], ez = 1.5 * kEps32 * mag[2];
   g.err_z = ez;
-  g.err_u = 4.0 * (cam.fx * (ex / z + std::fabs(g.mc[0]) * ez / (z * z)) +
-                   2 * kEps32 * (std::fabs(g.u) + std::fabs(cam.cx)));
-  g.err_v = 4.0 * (cam.fy * (ey / z + std::fabs(g.mc[1]) * ez / (z * z)) +
-                   2 * kEps32 * (std::fabs(g.v) + std::fabs(cam.cy)));
-  g.err_conic = 16 * kEps32 * (1.0 + (g.cov2[0] * g.cov2[2] + g.cov2[1] * g.cov2[1]) / det);
+  g.err_u = cam.fx * (ex / z + std::fabs(g.mc[0]) * ez / (z * z)) +
+            kEps32 * (cam.fx * std::fabs(g.mc[0] / z) + std::fabs(g.u));
+  g.err_v = cam.fy * (ey / z + std::fabs(g.mc[1]) * ez / (z * z)) +
+            kEps32 * (cam.fy * std::fabs(g.mc[1] / z) + std::fabs(g.v));
+  g.err_conic = kEps32 * (12.0 + 2.0 * (g.cov2[0] * g.cov2[2] + g.cov2[1] * g.cov2[1]) / det);
   return g;
 }
 
@@ -312,10 +315,16 @@ int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<
     if (!stopped) ++tested;
     if (q < 0.0) continue;
     const double araw = g.o * std::exp(-0.5 * q);
-    // FP32 error bound of ln(alpha) at this pair
+    // FP32 error bound of ln(alpha) at this pair: position error through the
+    // gradient of q, conic error, the rounding of the quadratic form, the
+    // exponential (argument scaling and result) and the opacity product;
+    // times a safety factor of 2.
     const double dqdu = 2.0 * std::fabs(g.conic[0] * dx + g.conic[1] * dy);
     const double dqdv = 2.0 * std::fabs(g.conic[1] * dx + g.conic[2] * dy);
-    const double dln = 4.0 * (0.5 * (dqdu * g.err_u + dqdv * g.err_v) + 0.5 * q * g.err_conic + 4 * kEps32);
+    const double qabs = std::fabs(g.conic[0]) * dx * dx + 2.0 * std::fabs(g.conic[1] * dx * dy) +
+                        std::fabs(g.conic[2]) * dy * dy;
+    const double dln = 2.0 * (0.5 * (dqdu * g.err_u + dqdv * g.err_v) + 0.5 * q * g.err_conic +
+                              2.0 * kEps32 * qabs + 2.0 * kEps32 * (2.0 + 0.5 * q));
     const double alpha = std::min(kAlphaMax, araw);
     if (alpha < kAlphaMin) {
       if (!stopped && std::fabs(std::log(araw * 255.0)) <= dln) frag = true;
@@ -323,14 +332,14 @@ int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<
     }
     if (!stopped && std::fabs(std::log(araw * 255.0)) <= dln) frag = true;
     // depth-order near-ties among Gaussians that pass the gate
-    const double ez = 4.0 * g.err_z;
+    const double ez = 2.0 * g.err_z;
     if (prev_z >= 0.0 && std::fabs(g.z - prev_z) <= ez + prev_ez) frag = true;
     prev_z = g.z;
     prev_ez = ez;
     if (stopped) break;  // only the next gate-passing Gaussian matters after a stop
     const double Tn = T * (1.0 - alpha);
-    lnT_err += (alpha / (1.0 - alpha)) * dln + 2 * kEps32;
-    if (std::fabs(std::log(Tn / kTMin)) <= 4.0 * lnT_err) frag = true;
+    lnT_err += (alpha / (1.0 - alpha)) * dln + 4 * kEps32;
+    if (std::fabs(std::log(Tn / kTMin)) <= 2.0 * lnT_err) frag = true;
     if (Tn < kTMin) {
       stopped = true;
       continue;

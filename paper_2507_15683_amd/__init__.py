@@ -1,0 +1,334 @@
+"""MI355X tile rasterizer of 3D Gaussian splats (RGB, depth, alpha, feature
+maps) with its pose/parameter backward and batched multi-pose rendering.
+
+Thin Python binding over libhgsr.so (include/hgsr.h): PyTorch provides device
+memory and the stream; every step of the renderer runs in the library's HIP
+kernels.  Importing this module does not touch the GPU; the library is loaded
+on first use and its absence is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (SCHED_AUTO, SCHED_GRID, SCHED_POSE_MAJOR, SCHED_TILE_MAJOR, SORT_BUCKET, SORT_LSD,  # noqa: F401
+                   HgsrError, check)
+
+__all__ = ["GaussianScene", "Intrinsics", "Renderer", "render", "residual", "pose_adam", "HgsrError",
+           "SORT_BUCKET", "SORT_LSD", "SCHED_GRID", "SCHED_POSE_MAJOR", "SCHED_TILE_MAJOR", "SCHED_AUTO"]
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class Intrinsics:
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+
+    def c(self) -> _lib.Intrinsics:
+        return _lib.Intrinsics(self.fx, self.fy, self.cx, self.cy, self.width, self.height)
+
+    @staticmethod
+    def of(cam) -> "Intrinsics":
+        return Intrinsics(float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy), int(cam.width), int(cam.height))
+
+
+@dataclasses.dataclass
+class GaussianScene:
+    """Device-resident Gaussian scene (structure of arrays).  feat holds
+    bfloat16 values (the same bits as the generator's uint16 arrays)."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+    feat: Optional[torch.Tensor] = None
+    part_offsets: Optional[torch.Tensor] = None
+    part_bounds: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def feat_dim(self) -> int:
+        return 0 if self.feat is None else int(self.feat.shape[1])
+
+    @staticmethod
+    def from_numpy(s, device="cuda") -> "GaussianScene":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        feat = None
+        if s.feat is not None:
+            feat = torch.from_numpy(np.ascontiguousarray(s.feat).view(np.int16)).to(device).view(torch.bfloat16)
+        sc = GaussianScene(t(s.means), t(s.log_scales), t(s.quats), t(s.opacities), t(s.sh), int(s.sh_degree), feat)
+        if getattr(s, "part_offsets", None) is not None:
+            sc.part_offsets = t(s.part_offsets.astype(np.int64))
+            sc.part_bounds = torch.empty((len(s.part_offsets) - 1, 6), dtype=torch.float32, device=device)
+            g = sc.c()
+            check(_lib.load().hgsr_partition_bounds(ctypes.byref(g), _ptr(sc.part_bounds), _stream_ptr()),
+                  "hgsr_partition_bounds")
+        return sc
+
+    def c(self, partitions: bool = True) -> _lib.Gaussians:
+        for name in ("means", "log_scales", "quats", "opacities", "sh"):
+            x = getattr(self, name)
+            if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float32 device tensor")
+        use_parts = partitions and self.part_offsets is not None
+        return _lib.Gaussians(
+            self.n, self.means.data_ptr(), self.log_scales.data_ptr(), self.quats.data_ptr(),
+            self.opacities.data_ptr(), self.sh.data_ptr(), self.sh_degree, self.feat_dim,
+            None if self.feat is None else self.feat.data_ptr(),
+            (self.part_offsets.shape[0] - 1) if use_parts else 0,
+            self.part_offsets.data_ptr() if use_parts else None,
+            self.part_bounds.data_ptr() if use_parts else None)
+
+    def validate(self):
+        g = self.c()
+        check(_lib.load().hgsr_validate(ctypes.byref(g), _stream_ptr()), "hgsr_validate")
+
+
+_SORTS = {"bucket": SORT_BUCKET, "lsd": SORT_LSD}
+_SCHEDS = {"grid": SCHED_GRID, "pose": SCHED_POSE_MAJOR, "tile": SCHED_TILE_MAJOR, "auto": SCHED_AUTO}
+
+
+class Renderer:
+    """One library context: owns the renderer's workspace and the state the
+    backward needs.  Not thread safe; one per stream."""
+
+    def __init__(self, record_hint: int = 0, key_hint: int = 0):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(self.lib.hgsr_ctx_create(ctypes.byref(h), record_hint, key_hint), "hgsr_ctx_create")
+        self.ctx = h
+        self._keep = None
+
+    def close(self):
+        if self.ctx:
+            self.lib.hgsr_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def opts(self, tile=16, sort="bucket", schedule="grid", bg=(0.0, 0.0, 0.0), near=0.2, feat_bf16=False,
+             lds_sort_cap=0) -> _lib.Opts:
+        return _lib.Opts(tile, _SORTS[sort], _SCHEDS[schedule], (ctypes.c_float * 3)(*bg), near, int(feat_bf16),
+                         lds_sort_cap)
+
+    def reserve(self, P, width, height, tile, records_per_pose, keys, n_gaussians):
+        check(self.lib.hgsr_reserve(self.ctx, P, width, height, tile, records_per_pose, keys, n_gaussians),
+              "hgsr_reserve")
+
+    def alloc_outputs(self, scene: GaussianScene, P: int, K: Intrinsics, feat_bf16=False):
+        dev = scene.means.device
+        H, W = K.height, K.width
+        out = dict(rgb=torch.empty((P, 3, H, W), dtype=torch.float32, device=dev),
+                   depth=torch.empty((P, H, W), dtype=torch.float32, device=dev),
+                   alpha=torch.empty((P, H, W), dtype=torch.float32, device=dev), feat=None)
+        if scene.feat_dim:
+            out["feat"] = torch.empty((P, scene.feat_dim, H, W), dtype=torch.bfloat16 if feat_bf16 else torch.float32,
+                                      device=dev)
+        return out
+
+    def render_into(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, opts: _lib.Opts,
+                    stream=None):
+        """Enqueue one render (no synchronisation)."""
+        if poses.dtype != torch.float32 or not poses.is_contiguous() or poses.shape[-1] != 12:
+            raise ValueError("poses must be a contiguous float32 (P, 12) device tensor")
+        P = poses.shape[0]
+        g = scene.c()
+        o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["feat"]))
+        kc = K.c()
+        self._keep = (scene, poses, out)
+        check(self.lib.hgsr_render(self.ctx, ctypes.byref(g), _ptr(poses), P, ctypes.byref(kc), ctypes.byref(opts),
+                                   ctypes.byref(o), _stream_ptr(stream)), "hgsr_render")
+
+    def check_overflow(self, stream=None) -> int:
+        f = ctypes.c_int32(0)
+        check(self.lib.hgsr_check_overflow(self.ctx, ctypes.byref(f), _stream_ptr(stream)), "hgsr_check_overflow")
+        return int(f.value)
+
+    def render(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, tile=16, sort="bucket",
+               schedule="grid", bg=(0.0, 0.0, 0.0), near=0.2, feat_bf16=False, lds_sort_cap=0, out=None,
+               check_overflow=True, stream=None) -> dict:
+        """Render P poses; returns dict(rgb (P,3,H,W), depth (P,H,W), alpha
+        (P,H,W), feat (P,D,H,W) or None).  With check_overflow the call
+        synchronises, and re-renders after growing the workspace if needed."""
+        if poses.dim() == 1:
+            poses = poses[None]
+        P = poses.shape[0]
+        if out is None:
+            out = self.alloc_outputs(scene, P, K, feat_bf16)
+        opts = self.opts(tile, sort, schedule, bg, near, feat_bf16, lds_sort_cap)
+        for _ in range(6):
+            self.render_into(scene, poses, K, out, opts, stream)
+            if not check_overflow or self.check_overflow(stream) == 0:
+                return out
+        raise HgsrError(3, "render: workspace kept overflowing")
+
+    def stats(self, stream=None) -> dict:
+        s = _lib.RenderStats()
+        check(self.lib.hgsr_stats(self.ctx, ctypes.byref(s), _stream_ptr(stream)), "hgsr_stats")
+        return dict(visible=s.visible, keys=s.keys, max_tile_list=s.max_tile_list, overflow=s.overflow, tile=s.tile)
+
+    def tile_lists(self, pose: int, n_tiles: int, cap: int, stream=None):
+        """Per-tile Gaussian lists of the last render in blend order:
+        (ranges (n_tiles, 2), gids)."""
+        ranges = np.zeros((n_tiles, 2), dtype=np.uint32)
+        gids = np.zeros(max(cap, 1), dtype=np.uint32)
+        n = ctypes.c_int64(0)
+        check(self.lib.hgsr_debug_tile_lists(self.ctx, pose, ranges.ctypes.data_as(ctypes.c_void_p),
+                                             gids.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n),
+                                             _stream_ptr(stream)), "hgsr_debug_tile_lists")
+        return ranges, gids[: n.value]
+
+    def backward(self, grad_out: dict, want=("pose", "means", "opacities"), P: Optional[int] = None,
+                 scene: Optional[GaussianScene] = None, stream=None) -> dict:
+        """Gradients of the last render given dL/d{rgb, depth, alpha, feat}
+        (device FP32 tensors; missing keys mean zero).  `want` names the
+        gradients to compute among pose, means, opacities, log_scales, quats,
+        sh, feat.  Returns a dict of device tensors."""
+        scene = scene if scene is not None else self._keep[0]
+        P = P if P is not None else self._keep[1].shape[0]
+        dev = scene.means.device
+        n, D, K = scene.n, scene.feat_dim, (scene.sh_degree + 1) ** 2
+        shapes = dict(pose=(P, 6), means=(n, 3), opacities=(n,), log_scales=(n, 3), quats=(n, 4), sh=(n, K, 3),
+                      feat=(n, D))
+        grads = {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in want}
+        go = _lib.GradOutputs(*[_ptr(_f32(grad_out.get(k))) for k in ("rgb", "depth", "alpha", "feat")])
+        gr = _lib.Grads(*[_ptr(grads.get(k)) for k in ("pose", "means", "opacities", "log_scales", "quats", "sh",
+                                                      "feat")])
+        self._keep_grad = (grad_out, grads)
+        check(self.lib.hgsr_render_backward(self.ctx, ctypes.byref(go), ctypes.byref(gr), _stream_ptr(stream)),
+              "hgsr_render_backward")
+        return grads
+
+    def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
+                 feat_bf16=False, cache_path: Optional[str] = None, stream=None) -> dict:
+        """Time tile sizes 8/16/32 and the blend schedules on this input; the
+        winner becomes this renderer's default for tile=0 / schedule="auto"."""
+        g = scene.c()
+        kc = K.c()
+        opts = self.opts(16, sort, "grid", feat_bf16=feat_bf16)
+        o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["feat"]))
+        res = _lib.TuneResult()
+        check(self.lib.hgsr_autotune(self.ctx, ctypes.byref(g), _ptr(poses), poses.shape[0], ctypes.byref(kc),
+                                     ctypes.byref(opts), ctypes.byref(o),
+                                     None if cache_path is None else cache_path.encode(), ctypes.byref(res),
+                                     _stream_ptr(stream)), "hgsr_autotune")
+        return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule], ms=res.ms)
+
+    def profile(self, enable: bool):
+        check(self.lib.hgsr_profile_enable(self.ctx, int(enable)), "hgsr_profile_enable")
+
+    def profile_read(self) -> dict:
+        ms = (ctypes.c_double * 6)()
+        calls = (ctypes.c_int64 * 6)()
+        check(self.lib.hgsr_profile_read(self.ctx, ms, calls), "hgsr_profile_read")
+        names = ["project", "bin_sort", "blend", "blend_bwd", "project_bwd", "unused"]
+        return {names[k]: (ms[k], calls[k]) for k in range(5)}
+
+    # graph capture
+    def graph_begin(self, stream):
+        check(self.lib.hgsr_graph_begin(self.ctx, _stream_ptr(stream)), "hgsr_graph_begin")
+
+    def graph_end(self):
+        check(self.lib.hgsr_graph_end(self.ctx), "hgsr_graph_end")
+
+    def graph_launch(self, replays: int, stream=None):
+        check(self.lib.hgsr_graph_launch(self.ctx, replays, _stream_ptr(stream)), "hgsr_graph_launch")
+
+
+def _f32(t):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        t = t.float().contiguous()
+    return t
+
+
+def render(scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, renderer: Optional[Renderer] = None, **kw):
+    r = renderer if renderer is not None else Renderer()
+    return r.render(scene, poses, K, **kw)
+
+
+def render_grad(renderer: Renderer, scene: GaussianScene, poses: torch.Tensor, out: dict, grad_out: dict,
+                want=("pose", "means", "opacities")) -> dict:
+    """Backward of renderer's last render (which must be `out` of `poses`)."""
+    return renderer.backward(grad_out, want=want, P=poses.shape[0], scene=scene)
+
+
+class _RenderFn(torch.autograd.Function):
+    """Differentiable render: gradients flow to the pose tangent xi (left
+    perturbation at 0) and to the Gaussian means and opacities."""
+
+    @staticmethod
+    def forward(ctx, xi, means, opacities, renderer, scene, poses, K, kw):
+        out = renderer.render(scene, poses, K, **kw)
+        ctx.renderer = renderer
+        ctx.scene = scene
+        ctx.P = poses.shape[0]
+        ctx.has_feat = out["feat"] is not None
+        ctx.needs = (xi.requires_grad, means.requires_grad, opacities.requires_grad)
+        feat = out["feat"] if out["feat"] is not None else torch.empty(0, device=poses.device)
+        return out["rgb"], out["depth"], out["alpha"], feat
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha, g_feat):
+        want = [k for k, need in zip(("pose", "means", "opacities"), ctx.needs) if need]
+        go = dict(rgb=g_rgb, depth=g_depth, alpha=g_alpha, feat=g_feat if ctx.has_feat else None)
+        grads = ctx.renderer.backward(go, want=want or ("pose",), P=ctx.P, scene=ctx.scene)
+        return (grads.get("pose"), grads.get("means"), grads.get("opacities"), None, None, None, None, None)
+
+
+def render_differentiable(renderer: Renderer, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics,
+                          xi: Optional[torch.Tensor] = None, **kw):
+    """Autograd form: returns (rgb, depth, alpha, feat); d/d xi is the pose
+    gradient in the left-perturbation tangent (rho, phi)."""
+    P = poses.shape[0]
+    if xi is None:
+        xi = torch.zeros((P, 6), dtype=torch.float32, device=poses.device, requires_grad=True)
+    kw = dict(kw)
+    kw.setdefault("check_overflow", True)
+    return _RenderFn.apply(xi, scene.means, scene.opacities, renderer, scene, poses, K, kw)
+
+
+def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0, stream=None):
+    """Per-pose refinement residual and its gradients (HIP kernel)."""
+    lib = _lib.load()
+    P, _, H, W = rgb.shape
+    D = 0 if feat is None else feat.shape[1]
+    loss = torch.empty(P, dtype=torch.float32, device=rgb.device)
+    g_rgb = torch.empty_like(rgb)
+    g_feat = torch.empty((P, D, H, W), dtype=torch.float32, device=rgb.device) if D else None
+    check(lib.hgsr_residual(_ptr(rgb), _ptr(feat), int(feat is not None and feat.dtype == torch.bfloat16),
+                            _ptr(rgb_t), _ptr(feat_t), P, H, W, D, lam_f, _ptr(loss), _ptr(g_rgb), _ptr(g_feat),
+                            _stream_ptr(stream)), "hgsr_residual")
+    return loss, g_rgb, g_feat
+
+
+def pose_adam(poses, grad, m, v, step, lr_rho=1e-2, lr_phi=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    lib = _lib.load()
+    check(lib.hgsr_pose_adam(_ptr(poses), _ptr(grad), _ptr(m), _ptr(v), _ptr(step), poses.shape[0], lr_rho, lr_phi,
+                             b1, b2, eps, _stream_ptr(stream)), "hgsr_pose_adam")

@@ -1,0 +1,513 @@
+// Backward of the splat rasterizer.
+//
+// blend_bwd: one workgroup per (pose, tile).  Each pixel starts from its
+// saved final transmittance and list length and walks its tile list back to
+// front, recovering T_j = T_{j+1} / (1 - alpha_j) instead of storing
+// per-pixel lists.  With h_j = gC.c_j + gZ z_j + gF.f_j and the suffix sum
+// S_j = sum_{k>j} w_k h_k,
+//   dL/dalpha_j = T_j h_j - (S_j + gT T_final) / (1 - alpha_j),
+// where gT collects the outputs' direct dependence on T_final (background,
+// depth normalisation, alpha).  Per-splat gradients are summed across the
+// 64 lanes of a wave before one atomic per value.
+//
+// project_bwd: one thread per visible (pose, Gaussian): chains the splat
+// gradients through the conic inverse, the EWA covariance, the clamped
+// pinhole Jacobian, the camera transform and the SH view direction, into
+// dL/d(mean, opacity, scales, rotation, SH) and the pose's left-perturbation
+// tangent (rho, phi), block-reduced per pose.
+#include "hgsr_device.hpp"
+#include "launch.hpp"
+
+namespace hgsr {
+
+template <int TILE>
+struct BackShape {
+  static constexpr int kThreads = TILE == 8 ? 64 : 256;
+  static constexpr int kPPT = TILE * TILE / kThreads;
+};
+
+template <int TILE, int D, bool FEATGRAD>
+__global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
+  constexpr int NT = BackShape<TILE>::kThreads;
+  constexpr int PPT = BackShape<TILE>::kPPT;
+  constexpr int DV = D / 8;
+  constexpr int DD = D > 0 ? D : 1;
+  __shared__ float4 s_geo[NT];
+  __shared__ float4 s_opz[NT];
+  __shared__ float4 s_col[NT];
+  __shared__ uint32_t s_rec[NT];
+  __shared__ uint4 s_feat[DV > 0 ? NT * DV : 1];
+  __shared__ uint32_t s_max;
+  if (a.flags[0] & 3) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int W = a.c.W, H = a.c.H;
+  const int64_t HW = static_cast<int64_t>(W) * H;
+  const int item = blockIdx.x;
+  const int pose = item / a.c.tiles_per_pose;
+  const int tile = item - pose * a.c.tiles_per_pose;
+  const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;
+  const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
+
+  float pxf[PPT], pyf[PPT], T[PPT], Tf[PPT], S[PPT], gC[PPT][3], GZ[PPT], gT[PPT];
+  float gF[PPT][DD];
+  uint32_t last[PPT];
+  if (tid == 0) s_max = 0;
+  __syncthreads();
+  uint32_t my_max = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = tid + k * NT;
+    const int px = tx * TILE + (li % TILE), py = ty * TILE + (li / TILE);
+    const bool inside = px < W && py < H;
+    pxf[k] = static_cast<float>(px) + 0.5f;
+    pyf[k] = static_cast<float>(py) + 0.5f;
+    last[k] = 0;
+    T[k] = Tf[k] = 1.f;
+    S[k] = 0.f;
+    gC[k][0] = gC[k][1] = gC[k][2] = 0.f;
+    GZ[k] = gT[k] = 0.f;
+#pragma unroll
+    for (int d = 0; d < DD; ++d) gF[k][d] = 0.f;
+    if (!inside) continue;
+    const int64_t pix = static_cast<int64_t>(py) * W + px;
+    const int64_t o = static_cast<int64_t>(pose) * HW + pix;
+    last[k] = a.n_used[o];
+    Tf[k] = T[k] = a.final_T[o];
+    const float A = 1.f - Tf[k];
+    float gtv = 0.f;
+    if (a.g_rgb) {
+      const int64_t o3 = static_cast<int64_t>(pose) * 3 * HW + pix;
+      gC[k][0] = a.g_rgb[o3];
+      gC[k][1] = a.g_rgb[o3 + HW];
+      gC[k][2] = a.g_rgb[o3 + 2 * HW];
+      gtv = gC[k][0] * a.bg[0] + gC[k][1] * a.bg[1] + gC[k][2] * a.bg[2];
+    }
+    if (a.g_depth && A > 0.f) {
+      const float gd = a.g_depth[o];
+      GZ[k] = gd / A;
+      gtv += gd * a.fwd_depth[o] / A;
+    }
+    if (a.g_alpha) gtv -= a.g_alpha[o];
+    gT[k] = gtv;
+    if constexpr (D > 0) {
+      if (a.g_feat) {
+        const int64_t of = static_cast<int64_t>(pose) * D * HW + pix;
+#pragma unroll
+        for (int d = 0; d < D; ++d) gF[k][d] = a.g_feat[of + d * HW];
+      }
+    }
+    my_max = max(my_max, last[k]);
+  }
+  atomicMax(&s_max, my_max);
+  __syncthreads();
+  const uint32_t n_max = s_max;
+  if (n_max == 0) return;
+
+  // batches back to front; positions are relative to range.x
+  const int n_batches = static_cast<int>((n_max + NT - 1) / NT);
+  for (int bi = n_batches - 1; bi >= 0; --bi) {
+    const uint32_t b0 = static_cast<uint32_t>(bi) * NT;
+    __syncthreads();
+    {
+      const uint32_t pos = b0 + tid;
+      if (pos < n_max) {
+        const uint32_t r = a.list[range.x + pos];
+        const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
+        const float4 g1 = sp[1];
+        s_geo[tid] = sp[0];
+        s_opz[tid] = g1;
+        s_col[tid] = sp[2];
+        s_rec[tid] = r;
+        if constexpr (DV > 0) {
+          const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(__float_as_uint(g1.w)) * DV;
+#pragma unroll
+          for (int q = 0; q < DV; ++q) s_feat[tid * DV + q] = fv[q];
+        }
+      }
+    }
+    __syncthreads();
+    const int nb = static_cast<int>(min(static_cast<uint32_t>(NT), n_max - b0));
+    for (int jj = nb - 1; jj >= 0; --jj) {
+      const uint32_t pos = b0 + jj;
+      const float4 geo = s_geo[jj];
+      const float4 opz = s_opz[jj];
+      const float4 col = s_col[jj];
+      float fv[DD];
+      if constexpr (DV > 0) {
+#pragma unroll
+        for (int q = 0; q < DV; ++q) {
+          const uint4 fq = s_feat[jj * DV + q];
+          fv[8 * q + 0] = bf16_lo(fq.x); fv[8 * q + 1] = bf16_hi(fq.x);
+          fv[8 * q + 2] = bf16_lo(fq.y); fv[8 * q + 3] = bf16_hi(fq.y);
+          fv[8 * q + 4] = bf16_lo(fq.z); fv[8 * q + 5] = bf16_hi(fq.z);
+          fv[8 * q + 6] = bf16_lo(fq.w); fv[8 * q + 7] = bf16_hi(fq.w);
+        }
+      }
+      float g[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) g[q] = 0.f;
+      float gfe[FEATGRAD ? DD : 1];
+      if constexpr (FEATGRAD) {
+#pragma unroll
+        for (int d = 0; d < DD; ++d) gfe[d] = 0.f;
+      }
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        if (pos >= last[k]) continue;
+        const float dx = pxf[k] - geo.x, dy = pyf[k] - geo.y;
+        const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
+        if (power > 0.f) continue;
+        const float G = __expf(power);
+        const float alpha = fminf(kAlphaMax, opz.y * G);
+        if (alpha < kAlphaMin) continue;
+        any = true;
+        const float om = 1.f - alpha;
+        const float Tj = T[k] / om;
+        const float w = alpha * Tj;
+        float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
+        if constexpr (D > 0) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) h = fmaf(gF[k][d], fv[d], h);
+        }
+        const float dA = Tj * h - (S[k] + gT[k] * Tf[k]) / om;
+        S[k] = fmaf(w, h, S[k]);
+        T[k] = Tj;
+        g[7] += w * gC[k][0];
+        g[8] += w * gC[k][1];
+        g[9] += w * gC[k][2];
+        g[6] += w * GZ[k];
+        if (opz.y * G <= kAlphaMax) {
+          const float dpow = dA * alpha;
+          g[5] += dA * G;
+          g[0] += dpow * (geo.z * dx + geo.w * dy);
+          g[1] += dpow * (geo.w * dx + opz.x * dy);
+          g[2] += -0.5f * dpow * dx * dx;
+          g[3] += -dpow * dx * dy;
+          g[4] += -0.5f * dpow * dy * dy;
+        }
+        if constexpr (FEATGRAD) {
+#pragma unroll
+          for (int d = 0; d < DD; ++d) gfe[d] = fmaf(w, gF[k][d], gfe[d]);
+        }
+      }
+      if (!__any(any)) continue;
+#pragma unroll
+      for (int q = 0; q < 10; ++q) g[q] = wave_sum(g[q]);
+      if constexpr (FEATGRAD) {
+#pragma unroll
+        for (int d = 0; d < DD; ++d) gfe[d] = wave_sum(gfe[d]);
+      }
+      if (lane == 0) {
+        float* dst = a.g_rec + static_cast<int64_t>(s_rec[jj]) * kGradRecStride;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) atomicAdd(dst + q, g[q]);
+        if constexpr (FEATGRAD) {
+          float* fd = a.g_featvec + static_cast<int64_t>(__float_as_uint(opz.w)) * D;
+#pragma unroll
+          for (int d = 0; d < DD; ++d) atomicAdd(fd + d, gfe[d]);
+        }
+      }
+    }
+  }
+}
+
+template <int TILE, int D>
+static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
+  constexpr int NT = BackShape<TILE>::kThreads;
+  if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true>), dim3(items), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false>), dim3(items), dim3(NT), 0, s, a);
+}
+
+template <int TILE>
+static void launch_bwd_t(const BackArgs& a, int items, hipStream_t s) {
+  switch (a.D) {
+    case 0: hipLaunchKernelGGL((blend_bwd_kernel<TILE, 0, false>), dim3(items), dim3(BackShape<TILE>::kThreads), 0,
+                               s, a); break;
+    case 8: launch_bwd_td<TILE, 8>(a, items, s); break;
+    case 16: launch_bwd_td<TILE, 16>(a, items, s); break;
+    case 32: launch_bwd_td<TILE, 32>(a, items, s); break;
+    default: launch_bwd_td<TILE, 64>(a, items, s); break;
+  }
+}
+
+void launch_blend_bwd(const BackArgs& a, hipStream_t s) {
+  const int items = a.P * a.c.tiles_per_pose;
+  switch (a.c.tile) {
+    case 8: launch_bwd_t<8>(a, items, s); break;
+    case 32: launch_bwd_t<32>(a, items, s); break;
+    default: launch_bwd_t<16>(a, items, s); break;
+  }
+}
+
+// ------------------------------------------------------------ projection backward
+// Gradient of the real SH basis polynomials (as functions on R^3) contracted
+// with per-basis weights c[k] (one colour channel): returns sum_k c_k grad Y_k.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dir(const float* c, float x, float y, float z, float g[3]) {
+  g[0] = g[1] = g[2] = 0.f;
+  if constexpr (DEG >= 1) {
+    const float C1 = 0.48860251190291987f;
+    g[1] += -C1 * c[1];
+    g[2] += C1 * c[2];
+    g[0] += -C1 * c[3];
+  }
+  if constexpr (DEG >= 2) {
+    const float A = 1.0925484305920792f, B = 0.31539156525252005f, Cc = 0.5462742152960396f;
+    g[0] += c[4] * A * y;
+    g[1] += c[4] * A * x;
+    g[1] += -c[5] * A * z;
+    g[2] += -c[5] * A * y;
+    g[0] += -2.f * c[6] * B * x;
+    g[1] += -2.f * c[6] * B * y;
+    g[2] += 4.f * c[6] * B * z;
+    g[0] += -c[7] * A * z;
+    g[2] += -c[7] * A * x;
+    g[0] += 2.f * c[8] * Cc * x;
+    g[1] += -2.f * c[8] * Cc * y;
+  }
+  if constexpr (DEG >= 3) {
+    const float a3 = 0.5900435899266435f, b3 = 2.890611442640554f, c3 = 0.4570457994644658f,
+                d3 = 0.3731763325901154f, e3 = 1.445305721320277f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    g[0] += c[9] * (-6.f * a3 * x * y);
+    g[1] += c[9] * (-a3 * (3.f * xx - 3.f * yy));
+    g[0] += c[10] * b3 * y * z;
+    g[1] += c[10] * b3 * x * z;
+    g[2] += c[10] * b3 * x * y;
+    g[0] += c[11] * (2.f * c3 * x * y);
+    g[1] += c[11] * (-c3 * (4.f * zz - xx - 3.f * yy));
+    g[2] += c[11] * (-8.f * c3 * y * z);
+    g[0] += c[12] * (-6.f * d3 * x * z);
+    g[1] += c[12] * (-6.f * d3 * y * z);
+    g[2] += c[12] * (d3 * (6.f * zz - 3.f * xx - 3.f * yy));
+    g[0] += c[13] * (-c3 * (4.f * zz - 3.f * xx - yy));
+    g[1] += c[13] * (2.f * c3 * x * y);
+    g[2] += c[13] * (-8.f * c3 * x * z);
+    g[0] += c[14] * (2.f * e3 * x * z);
+    g[1] += c[14] * (-2.f * e3 * y * z);
+    g[2] += c[14] * (e3 * (xx - yy));
+    g[0] += c[15] * (-a3 * (3.f * xx - 3.f * yy));
+    g[1] += c[15] * (6.f * a3 * x * y);
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ float s_red[6][256];
+  const int pose = blockIdx.y;
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const bool ok = !(a.flags[0] & 3);
+  const uint32_t cnt = ok ? min(a.pose_count[pose], a.rec_cap) : 0u;
+  if (slot < cnt) {
+    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+    const float* gr = a.g_rec + idx * kGradRecStride;
+    const float g_u = gr[0], g_v = gr[1], g_ca = gr[2], g_cb = gr[3], g_cc = gr[4], g_o = gr[5], g_z = gr[6];
+    const float gcol[3] = {gr[7], gr[8], gr[9]};
+    const Splat sp = a.recs[idx];
+    const int64_t i = sp.gid;
+    const float* Pm = a.poses + 12 * pose;
+    const float mu[3] = {a.g.means[3 * i], a.g.means[3 * i + 1], a.g.means[3 * i + 2]};
+    const float4 q4 = reinterpret_cast<const float4*>(a.g.quats)[i];
+    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+    float Sw[6];
+    cov3_from(q4, ls, Sw);
+    float mc[3];
+    to_camera(Pm, mu, mc);
+    const float x = mc[0], y = mc[1], z = mc[2];
+    const float iz = 1.f / z;
+    const float xz = x / z, yz = y / z;
+    const bool clx = fabsf(xz) > a.c.limx, cly = fabsf(yz) > a.c.limy;
+    const float xh = fminf(fmaxf(xz, -a.c.limx), a.c.limx);
+    const float yh = fminf(fmaxf(yz, -a.c.limy), a.c.limy);
+    const float fx = a.c.fx, fy = a.c.fy;
+    const float J00 = fx * iz, J02 = -fx * xh * iz, J11 = fy * iz, J12 = -fy * yh * iz;
+    // M = J R (rows m0, m1)
+    const float m0[3] = {J00 * Pm[0] + J02 * Pm[8], J00 * Pm[1] + J02 * Pm[9], J00 * Pm[2] + J02 * Pm[10]};
+    const float m1[3] = {J11 * Pm[4] + J12 * Pm[8], J11 * Pm[5] + J12 * Pm[9], J11 * Pm[6] + J12 * Pm[10]};
+    // dL/dSigma' = -C G C with G = [[g_ca, g_cb/2], [g_cb/2, g_cc]]
+    const float ca = sp.ca, cb = sp.cb, cc = sp.cc;
+    const float h01 = 0.5f * g_cb;
+    // C G
+    const float t00 = ca * g_ca + cb * h01, t01 = ca * h01 + cb * g_cc;
+    const float t10 = cb * g_ca + cc * h01, t11 = cb * h01 + cc * g_cc;
+    const float Gs00 = -(t00 * ca + t01 * cb);
+    const float Gs01 = -(t00 * cb + t01 * cc);
+    const float Gs11 = -(t10 * cb + t11 * cc);
+    // dL/dM = 2 Gs M Sw (2x3)
+    float SM0[3], SM1[3];  // Sw m0, Sw m1
+    SM0[0] = Sw[0] * m0[0] + Sw[1] * m0[1] + Sw[2] * m0[2];
+    SM0[1] = Sw[1] * m0[0] + Sw[3] * m0[1] + Sw[4] * m0[2];
+    SM0[2] = Sw[2] * m0[0] + Sw[4] * m0[1] + Sw[5] * m0[2];
+    SM1[0] = Sw[0] * m1[0] + Sw[1] * m1[1] + Sw[2] * m1[2];
+    SM1[1] = Sw[1] * m1[0] + Sw[3] * m1[1] + Sw[4] * m1[2];
+    SM1[2] = Sw[2] * m1[0] + Sw[4] * m1[1] + Sw[5] * m1[2];
+    float gM0[3], gM1[3];
+    for (int k = 0; k < 3; ++k) {
+      gM0[k] = 2.f * (Gs00 * SM0[k] + Gs01 * SM1[k]);
+      gM1[k] = 2.f * (Gs01 * SM0[k] + Gs11 * SM1[k]);
+    }
+    // dL/dJ = dL/dM R^T (only the structurally non-zero entries)
+    const float gJ00 = gM0[0] * Pm[0] + gM0[1] * Pm[1] + gM0[2] * Pm[2];
+    const float gJ02 = gM0[0] * Pm[8] + gM0[1] * Pm[9] + gM0[2] * Pm[10];
+    const float gJ11 = gM1[0] * Pm[4] + gM1[1] * Pm[5] + gM1[2] * Pm[6];
+    const float gJ12 = gM1[0] * Pm[8] + gM1[1] * Pm[9] + gM1[2] * Pm[10];
+    // dL/dmc
+    const float iz2 = iz * iz;
+    float gmc[3];
+    gmc[0] = g_u * fx * iz;
+    gmc[1] = g_v * fy * iz;
+    gmc[2] = -g_u * fx * x * iz2 - g_v * fy * y * iz2 + g_z;
+    gmc[2] += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
+    if (!clx) {
+      gmc[0] += -gJ02 * fx * iz2;
+      gmc[2] += 2.f * gJ02 * fx * x * iz2 * iz;
+    } else {
+      gmc[2] += gJ02 * fx * xh * iz2;
+    }
+    if (!cly) {
+      gmc[1] += -gJ12 * fy * iz2;
+      gmc[2] += 2.f * gJ12 * fy * y * iz2 * iz;
+    } else {
+      gmc[2] += gJ12 * fy * yh * iz2;
+    }
+    // dL/dR through the covariance: Jcol^T dL/dM, i.e. GRc[r][c] = sum_a J[a][r] gM[a][c]
+    float GRc[3][3];
+    for (int c2 = 0; c2 < 3; ++c2) {
+      GRc[0][c2] = J00 * gM0[c2];
+      GRc[1][c2] = J11 * gM1[c2];
+      GRc[2][c2] = J02 * gM0[c2] + J12 * gM1[c2];
+    }
+    // B = R GRc^T ; dL/dphi (covariance part) = (B12 - B21, B20 - B02, B01 - B10)
+    float B[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c2 = 0; c2 < 3; ++c2)
+        B[r][c2] = Pm[4 * r + 0] * GRc[c2][0] + Pm[4 * r + 1] * GRc[c2][1] + Pm[4 * r + 2] * GRc[c2][2];
+    // SH view direction
+    const float Cx = -(Pm[0] * Pm[3] + Pm[4] * Pm[7] + Pm[8] * Pm[11]);
+    const float Cy = -(Pm[1] * Pm[3] + Pm[5] * Pm[7] + Pm[9] * Pm[11]);
+    const float Cz = -(Pm[2] * Pm[3] + Pm[6] * Pm[7] + Pm[10] * Pm[11]);
+    float dir[3] = {mu[0] - Cx, mu[1] - Cy, mu[2] - Cz};
+    const float inv = rsqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    const float n0 = dir[0] * inv, n1 = dir[1] * inv, n2 = dir[2] * inv;
+    float raw[3];
+    sh_colour_raw<DEG>(a.g.sh, i, n0, n1, n2, raw);
+    float graw[3];
+    for (int c2 = 0; c2 < 3; ++c2) graw[c2] = raw[c2] > 0.f ? gcol[c2] : 0.f;
+    float gdir[3] = {0.f, 0.f, 0.f};
+    if constexpr (DEG >= 1) {
+      const float* shc = a.g.sh + static_cast<int64_t>(K) * 3 * i;
+      for (int c2 = 0; c2 < 3; ++c2) {
+        if (graw[c2] == 0.f) continue;
+        float cch[K];
+        for (int k = 0; k < K; ++k) cch[k] = shc[3 * k + c2];
+        float gg[3];
+        sh_grad_dir<DEG>(cch, n0, n1, n2, gg);
+        const float nd = gg[0] * n0 + gg[1] * n1 + gg[2] * n2;
+        gdir[0] += graw[c2] * (gg[0] - n0 * nd) * inv;
+        gdir[1] += graw[c2] * (gg[1] - n1 * nd) * inv;
+        gdir[2] += graw[c2] * (gg[2] - n2 * nd) * inv;
+      }
+    }
+    if (a.g_sh) {
+      float Y[K];
+      sh_basis<DEG>(n0, n1, n2, Y);
+      float* gs = a.g_sh + static_cast<int64_t>(K) * 3 * i;
+      for (int k = 0; k < K; ++k)
+        for (int c2 = 0; c2 < 3; ++c2)
+          if (graw[c2] != 0.f) atomicAdd(gs + 3 * k + c2, graw[c2] * Y[k]);
+    }
+    // Gaussian gradients
+    if (a.g_means) {
+      for (int c2 = 0; c2 < 3; ++c2) {
+        const float gm = Pm[c2] * gmc[0] + Pm[4 + c2] * gmc[1] + Pm[8 + c2] * gmc[2] + gdir[c2];
+        atomicAdd(a.g_means + 3 * i + c2, gm);
+      }
+    }
+    if (a.g_opac) atomicAdd(a.g_opac + i, g_o);
+    if (a.g_log_scales || a.g_quats) {
+      // dL/dSigma_w = M^T Gs M
+      float Gw[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c2 = 0; c2 < 3; ++c2)
+          Gw[r][c2] = m0[r] * (Gs00 * m0[c2] + Gs01 * m1[c2]) + m1[r] * (Gs01 * m0[c2] + Gs11 * m1[c2]);
+      const float qn = rsqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+      const float w = q4.x * qn, qx = q4.y * qn, qy = q4.z * qn, qz = q4.w * qn;
+      const float Rq[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - w * qz), 2.f * (qx * qz + w * qy)},
+                              {2.f * (qx * qy + w * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - w * qx)},
+                              {2.f * (qx * qz - w * qy), 2.f * (qy * qz + w * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
+      const float s2[3] = {__expf(2.f * ls[0]), __expf(2.f * ls[1]), __expf(2.f * ls[2])};
+      if (a.g_log_scales) {
+        for (int k = 0; k < 3; ++k) {
+          float acc = 0.f;
+          for (int r = 0; r < 3; ++r)
+            for (int c2 = 0; c2 < 3; ++c2) acc += Rq[r][k] * Gw[r][c2] * Rq[c2][k];
+          atomicAdd(a.g_log_scales + 3 * i + k, 2.f * s2[k] * acc);
+        }
+      }
+      if (a.g_quats) {
+        // dL/dRq = 2 Gw Rq S^2
+        float G[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int c2 = 0; c2 < 3; ++c2)
+            G[r][c2] = 2.f * (Gw[r][0] * Rq[0][c2] + Gw[r][1] * Rq[1][c2] + Gw[r][2] * Rq[2][c2]) * s2[c2];
+        const float gw = 2.f * (-qz * G[0][1] + qy * G[0][2] + qz * G[1][0] - qx * G[1][2] - qy * G[2][0] + qx * G[2][1]);
+        const float gx = 2.f * (qy * G[0][1] + qz * G[0][2] + qy * G[1][0] - 2.f * qx * G[1][1] - w * G[1][2] +
+                                qz * G[2][0] + w * G[2][1] - 2.f * qx * G[2][2]);
+        const float gy = 2.f * (-2.f * qy * G[0][0] + qx * G[0][1] + w * G[0][2] + qx * G[1][0] + qz * G[1][2] -
+                                w * G[2][0] + qz * G[2][1] - 2.f * qy * G[2][2]);
+        const float gz = 2.f * (-2.f * qz * G[0][0] - w * G[0][1] + qx * G[0][2] + w * G[1][0] - 2.f * qz * G[1][1] +
+                                qy * G[1][2] + qx * G[2][0] + qy * G[2][1]);
+        const float dq = gw * w + gx * qx + gy * qy + gz * qz;
+        atomicAdd(a.g_quats + 4 * i + 0, (gw - w * dq) * qn);
+        atomicAdd(a.g_quats + 4 * i + 1, (gx - qx * dq) * qn);
+        atomicAdd(a.g_quats + 4 * i + 2, (gy - qy * dq) * qn);
+        atomicAdd(a.g_quats + 4 * i + 3, (gz - qz * dq) * qn);
+      }
+    }
+    // pose tangent (rho, phi)
+    gp[0] = gmc[0] + Pm[0] * gdir[0] + Pm[1] * gdir[1] + Pm[2] * gdir[2];
+    gp[1] = gmc[1] + Pm[4] * gdir[0] + Pm[5] * gdir[1] + Pm[6] * gdir[2];
+    gp[2] = gmc[2] + Pm[8] * gdir[0] + Pm[9] * gdir[1] + Pm[10] * gdir[2];
+    gp[3] = (y * gmc[2] - z * gmc[1]) + (B[1][2] - B[2][1]);
+    gp[4] = (z * gmc[0] - x * gmc[2]) + (B[2][0] - B[0][2]);
+    gp[5] = (x * gmc[1] - y * gmc[0]) + (B[0][1] - B[1][0]);
+  }
+  if (!a.g_pose) return;
+  for (int k = 0; k < 6; ++k) s_red[k][threadIdx.x] = gp[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int k = 0; k < 6; ++k) s_red[k][threadIdx.x] += s_red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6 && blockIdx.x * 256 < cnt) atomicAdd(a.g_pose + 6 * pose + threadIdx.x, s_red[threadIdx.x][0]);
+}
+
+__global__ __launch_bounds__(256) void zero_grad_rec_kernel(float* g, const uint32_t* pose_count, uint32_t rec_cap) {
+  const int pose = blockIdx.y;
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= min(pose_count[pose], rec_cap)) return;
+  float4* d = reinterpret_cast<float4*>(g + (static_cast<int64_t>(pose) * rec_cap + slot) * kGradRecStride);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  d[0] = z; d[1] = z; d[2] = z;
+}
+
+void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap, int P, hipStream_t s) {
+  hipLaunchKernelGGL(zero_grad_rec_kernel, dim3((rec_cap + 255) / 256, P), dim3(256), 0, s, g, pose_count, rec_cap);
+}
+
+void launch_project_bwd(const ProjBackArgs& a, hipStream_t s) {
+  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+  switch (a.g.sh_degree) {
+    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, dim3(256), 0, s, a); break;
+  }
+}
+
+}  // namespace hgsr

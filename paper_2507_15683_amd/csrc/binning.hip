@@ -1,0 +1,438 @@
+// Tile binning: exclusive scans, tile-entry emission, and the two sorts that
+// put every tile's entries in (camera depth, Gaussian index) order:
+//   bucket: the tile id is one radix digit resolved by a counting pass
+//           (per-tile counts -> scan -> atomic slots), then each tile's
+//           (depth bits << 32 | index) keys are sorted in LDS;
+//   lsd:    a device least-significant-digit radix sort of
+//           (tile, depth, index) keys, 8-bit digits, stable passes.
+#include "hgsr_device.hpp"
+#include "launch.hpp"
+
+namespace hgsr {
+
+// ------------------------------------------------------------ fills
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_f32_kernel(float* p, float v, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+static unsigned fill_grid(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  return static_cast<unsigned>(b < 1 ? 1 : b);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, value, n);
+}
+void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(fill_f32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, value, n);
+}
+
+// ------------------------------------------------------------ block scan
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block; returns the
+// exclusive prefix and writes the block total to *total_out (all threads).
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_w, uint32_t* total_out) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t x = s_w[k];
+    before += (k < w) ? x : 0u;
+    tot += x;
+  }
+  __syncthreads();
+  *total_out = tot;
+  return before + inc - v;
+}
+
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* in, int64_t n, uint32_t* block_sums) {
+  __shared__ uint32_t s_w[4];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  uint32_t sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
+    if (i < n) sum += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan256(sum, s_w, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the block sums in place; total and capacity
+// check.
+__global__ __launch_bounds__(256) void scan_top_kernel(uint32_t* sums, int64_t nb, uint32_t* total, uint64_t cap,
+                                                       int32_t* flags, int32_t flag_bit) {
+  __shared__ uint32_t s_w[4];
+  const int64_t per = (nb + 255) / 256;
+  const int64_t b0 = threadIdx.x * per;
+  uint32_t local = 0;
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) local += sums[b0 + k];
+  uint32_t tot;
+  uint32_t run = block_excl_scan256(local, s_w, &tot);
+  for (int64_t k = 0; k < per; ++k)
+    if (b0 + k < nb) {
+      const uint32_t x = sums[b0 + k];
+      sums[b0 + k] = run;
+      run += x;
+    }
+  if (threadIdx.x == 0) {
+    if (total) *total = tot;
+    if (flags && static_cast<uint64_t>(tot) > cap) atomicOr(flags, flag_bit);
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t* in, int64_t n, const uint32_t* offsets,
+                                                        uint32_t* out, uint2* ranges) {
+  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_v[kScanChunk];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  // coalesced load into LDS, then each thread scans 16 consecutive values
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
+    s_v[k * 256 + threadIdx.x] = i < n ? in[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t vals[kScanItems];
+  uint32_t sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    vals[k] = s_v[threadIdx.x * kScanItems + k];
+    sum += vals[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan256(sum, s_w, &tot) + offsets[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    s_v[threadIdx.x * kScanItems + k] = run;
+    run += vals[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
+    if (i < n) {
+      const uint32_t st = s_v[k * 256 + threadIdx.x];
+      if (ranges) ranges[i] = make_uint2(st, st + in[i]);
+      else out[i] = st;
+    }
+  }
+}
+
+int64_t scan_block_count(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+
+void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
+                 uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s) {
+  const int64_t nb = scan_block_count(n);
+  if (nb == 0) return;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(256), 0, s, block_sums, nb, total, cap, flags, flag_bit);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, block_sums, out,
+                     ranges);
+}
+
+// ------------------------------------------------------------ bucket path
+// One thread per record: claim a slot in each overlapped tile's bucket.
+__global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
+  if (a.flags[0] & 1) return;
+  const int pose = blockIdx.y;
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t cnt = min(a.pose_count[pose], a.rec_cap);
+  if (slot >= cnt) return;
+  const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+  const uint2 r = a.rects[idx];
+  const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];  // cc, o, z, gid
+  const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
+  const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+  const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int64_t tg = tbase + ty * a.c.ntx + tx;
+      const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
+      if (pos < a.key_cap) {
+        a.keys[pos] = key;
+        a.vals[pos] = static_cast<uint32_t>(idx);
+      }
+    }
+}
+
+void launch_emit_bucket(const BinArgs& a, hipStream_t s) {
+  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+  hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
+}
+
+// Per-tile sort in LDS: bitonic network on (depth bits, gid) keys.
+constexpr int kLdsSortCap = 4096;
+
+__global__ __launch_bounds__(256) void tile_sort_kernel(TileSortArgs a) {
+  __shared__ uint64_t s_key[kLdsSortCap];
+  __shared__ uint32_t s_val[kLdsSortCap];
+  if (a.flags[0] & 3) return;
+  const int tg = blockIdx.x;
+  const uint2 r = a.ranges[tg];
+  const uint32_t n = r.y - r.x;
+  if (n <= 1 || n > static_cast<uint32_t>(a.lds_cap)) {
+    if (n == 1 && threadIdx.x == 0) a.list[r.x] = a.vals[r.x];
+    return;
+  }
+  uint32_t m = 2;
+  while (m < n) m <<= 1;
+  for (uint32_t k = threadIdx.x; k < m; k += 256) {
+    if (k < n) {
+      s_key[k] = a.keys[r.x + k];
+      s_val[k] = a.vals[r.x + k];
+    } else {
+      s_key[k] = ~0ull;
+      s_val[k] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= m; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < m; i += 256) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t ki = s_key[i], kj = s_key[ixj];
+          const bool up = (i & k) == 0;
+          if ((ki > kj) == up) {
+            s_key[i] = kj;
+            s_key[ixj] = ki;
+            const uint32_t t = s_val[i];
+            s_val[i] = s_val[ixj];
+            s_val[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t k = threadIdx.x; k < n; k += 256) a.list[r.x + k] = s_val[k];
+}
+
+// Stable rank of one element per thread within a 256-element chunk, by 8-bit
+// digit.  s_wc: 4 x 256 per-wave digit counts (zeroed by the caller).
+// Returns the element's rank among equal digits in earlier waves and lanes.
+__device__ __forceinline__ uint32_t chunk_rank(uint32_t d, bool valid, uint32_t (*s_wc)[256]) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
+  if (valid && rank == 0) s_wc[w][d] = static_cast<uint32_t>(__popcll(peers));
+  __syncthreads();
+  uint32_t before = 0;
+  if (valid)
+    for (int k = 0; k < w; ++k) before += s_wc[k][d];
+  return before + rank;
+}
+
+// Lists longer than the LDS capacity: one block runs a stable LSD radix sort
+// of that tile's keys in global memory (ping-pong with the alternate buffers).
+__global__ __launch_bounds__(256) void tile_sort_big_kernel(TileSortArgs a) {
+  __shared__ uint32_t s_off[256];
+  __shared__ uint32_t s_wc[4][256];
+  __shared__ uint32_t s_w[4];
+  if (a.flags[0] & 3) return;
+  const int tg = blockIdx.x;
+  const uint2 r = a.ranges[tg];
+  const uint32_t n = r.y - r.x;
+  if (n <= static_cast<uint32_t>(a.lds_cap)) return;
+  uint64_t* sk = a.keys + r.x;
+  uint32_t* sv = a.vals + r.x;
+  uint64_t* dk = a.keys_alt + r.x;
+  uint32_t* dv = a.vals_alt + r.x;
+  const int gid_passes = (a.gid_bits + 7) / 8;
+  const int passes = gid_passes + 4;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p < gid_passes ? 8 * p : 32 + 8 * (p - gid_passes);
+    s_off[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n; e += 256) atomicAdd(&s_off[(sk[e] >> shift) & 0xff], 1u);
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(s_off[threadIdx.x], s_w, &tot);
+    __syncthreads();
+    s_off[threadIdx.x] = ex;
+    for (uint32_t base = 0; base < n; base += 256) {
+      for (int w = 0; w < 4; ++w) s_wc[w][threadIdx.x] = 0;
+      __syncthreads();
+      const uint32_t e = base + threadIdx.x;
+      const bool valid = e < n;
+      uint64_t key = 0;
+      uint32_t val = 0, d = 0;
+      if (valid) {
+        key = sk[e];
+        val = sv[e];
+        d = static_cast<uint32_t>((key >> shift) & 0xff);
+      }
+      const uint32_t rk = chunk_rank(d, valid, s_wc);
+      if (valid) {
+        const uint32_t pos = s_off[d] + rk;
+        dk[pos] = key;
+        dv[pos] = val;
+      }
+      __syncthreads();
+      s_off[threadIdx.x] += s_wc[0][threadIdx.x] + s_wc[1][threadIdx.x] + s_wc[2][threadIdx.x] + s_wc[3][threadIdx.x];
+      __syncthreads();
+    }
+    uint64_t* tk = sk; sk = dk; dk = tk;
+    uint32_t* tv = sv; sv = dv; dv = tv;
+    __syncthreads();
+  }
+  for (uint32_t k = threadIdx.x; k < n; k += 256) a.list[r.x + k] = sv[k];
+}
+
+void launch_tile_sort(const TileSortArgs& a, hipStream_t s) {
+  if (a.n_tiles <= 0) return;
+  hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(tile_sort_big_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
+}
+
+// ------------------------------------------------------------ LSD path
+__global__ __launch_bounds__(256) void emit_lsd_kernel(BinArgs a, const uint32_t* rec_offsets, uint64_t* keys,
+                                                       uint32_t* gids, uint32_t* vals) {
+  if (a.flags[0] & 3) return;
+  const int pose = blockIdx.y;
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t cnt = min(a.pose_count[pose], a.rec_cap);
+  if (slot >= cnt) return;
+  const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+  const uint2 r = a.rects[idx];
+  const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];
+  const uint32_t zb = zbits(hdr.z), gid = __float_as_uint(hdr.w);
+  const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+  uint64_t pos = rec_offsets[idx];
+  const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
+      if (pos >= a.key_cap) continue;
+      keys[pos] = (static_cast<uint64_t>(tbase + ty * a.c.ntx + tx) << 32) | zb;
+      gids[pos] = gid;
+      vals[pos] = static_cast<uint32_t>(idx);
+    }
+}
+
+void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,
+                     uint32_t* vals, hipStream_t s) {
+  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+  hipLaunchKernelGGL(emit_lsd_kernel, grid, dim3(256), 0, s, a, rec_offsets, keys, gids, vals);
+}
+
+constexpr int kLsdItems = 8;
+constexpr int kLsdChunk = 256 * kLsdItems;
+
+__device__ __forceinline__ uint32_t lsd_digit(uint64_t key, uint32_t gid, int shift) {
+  // shift < 0: gid digit at bit -shift-1 ... encoded as shift = -(8k + 1)
+  return shift >= 0 ? static_cast<uint32_t>((key >> shift) & 0xff) : ((gid >> (-shift - 1)) & 0xffu);
+}
+
+__global__ __launch_bounds__(256) void lsd_hist_kernel(LsdArgs a, int src, int shift) {
+  __shared__ uint32_t s_h[256];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t total = (a.flags[0] & 3) ? 0u : min(*a.total, static_cast<uint32_t>(a.key_cap));
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kLsdChunk;
+  for (int k = 0; k < kLsdItems; ++k) {
+    const uint64_t e = base + k * 256 + threadIdx.x;
+    if (e < total) atomicAdd(&s_h[lsd_digit(a.keys[src][e], a.gids[src][e], shift)], 1u);
+  }
+  __syncthreads();
+  a.hist[static_cast<int64_t>(threadIdx.x) * a.n_blocks + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void lsd_scatter_kernel(LsdArgs a, int src, int shift) {
+  __shared__ uint32_t s_off[256];
+  __shared__ uint32_t s_wc[4][256];
+  const uint32_t total = (a.flags[0] & 3) ? 0u : min(*a.total, static_cast<uint32_t>(a.key_cap));
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kLsdChunk;
+  if (base >= total) return;
+  s_off[threadIdx.x] = a.hist[static_cast<int64_t>(threadIdx.x) * a.n_blocks + blockIdx.x];
+  const int dst = src ^ 1;
+  for (int k = 0; k < kLsdItems; ++k) {
+    for (int w = 0; w < 4; ++w) s_wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t e = base + k * 256 + threadIdx.x;
+    const bool valid = e < total;
+    uint64_t key = 0;
+    uint32_t gid = 0, val = 0, d = 0;
+    if (valid) {
+      key = a.keys[src][e];
+      gid = a.gids[src][e];
+      val = a.vals[src][e];
+      d = lsd_digit(key, gid, shift);
+    }
+    const uint32_t rk = chunk_rank(d, valid, s_wc);
+    if (valid) {
+      const uint32_t pos = s_off[d] + rk;
+      a.keys[dst][pos] = key;
+      a.gids[dst][pos] = gid;
+      a.vals[dst][pos] = val;
+    }
+    __syncthreads();
+    s_off[threadIdx.x] += s_wc[0][threadIdx.x] + s_wc[1][threadIdx.x] + s_wc[2][threadIdx.x] + s_wc[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+void launch_lsd_sort(LsdArgs& a, int passes_gid, int passes_z, int passes_tile, int* out_buffer, hipStream_t s) {
+  int src = 0;
+  const int passes = passes_gid + passes_z + passes_tile;
+  const int64_t nh = static_cast<int64_t>(a.n_blocks) * 256;
+  for (int p = 0; p < passes; ++p) {
+    int shift;
+    if (p < passes_gid) shift = -(8 * p + 1);
+    else if (p < passes_gid + passes_z) shift = 8 * (p - passes_gid);
+    else shift = 32 + 8 * (p - passes_gid - passes_z);
+    hipLaunchKernelGGL(lsd_hist_kernel, dim3(a.n_blocks), dim3(256), 0, s, a, src, shift);
+    launch_scan(a.hist, nh, a.hist, nullptr, a.hist + nh, nullptr, ~0ull, nullptr, 0, s);
+    hipLaunchKernelGGL(lsd_scatter_kernel, dim3(a.n_blocks), dim3(256), 0, s, a, src, shift);
+    src ^= 1;
+  }
+  *out_buffer = src;
+}
+
+__global__ void ranges_from_sorted_kernel(const uint64_t* keys, const uint32_t* total_p, uint64_t key_cap,
+                                          uint2* ranges, const int32_t* flags) {
+  if (flags[0] & 3) return;
+  const uint32_t total = min(*total_p, static_cast<uint32_t>(key_cap));
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t t = static_cast<uint32_t>(keys[i] >> 32);
+    if (i == 0 || static_cast<uint32_t>(keys[i - 1] >> 32) != t) ranges[t].x = static_cast<uint32_t>(i);
+    if (i + 1 == total || static_cast<uint32_t>(keys[i + 1] >> 32) != t) ranges[t].y = static_cast<uint32_t>(i + 1);
+  }
+}
+
+void launch_ranges_from_sorted(const uint64_t* keys, const uint32_t* total, uint64_t key_cap, uint2* ranges,
+                               int32_t n_tiles, const int32_t* flags, hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * static_cast<int64_t>(n_tiles), s);
+  hipLaunchKernelGGL(ranges_from_sorted_kernel, dim3(fill_grid(static_cast<int64_t>(key_cap))), dim3(256), 0, s,
+                     keys, total, key_cap, ranges, flags);
+}
+
+}  // namespace hgsr

@@ -1,0 +1,212 @@
+// Device-side definitions shared by the HIP kernels of the splat rasterizer
+// (gfx950, wave64).  Everything here is FP32; the exact per-pair expressions
+// used by the forward blend and by its reverse replay live in one place so
+// that both take bit-identical decisions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hgsr {
+
+constexpr float kAlphaMin = 1.0f / 255.0f;  // blend gate
+constexpr float kAlphaMax = 0.99f;          // opacity clamp
+constexpr float kTMin = 1e-4f;              // transmittance stop
+constexpr float kDilation = 0.3f;           // screen-space low-pass, px^2
+constexpr float kGuard = 1.3f;              // Jacobian guard band, x field of view
+constexpr float kRectPad = 5e-4f;           // support rectangle padding, px
+constexpr int kMaxPoses = 64;               // poses per projection launch
+constexpr int kWave = 64;
+
+// blend launch shapes: one workgroup per (pose, tile), or a persistent grid
+// pulling (pose, tile) items pose-major or tile-major from a device counter
+enum { kSchedGrid = 0, kSchedPoseMajor = 1, kSchedTileMajor = 2 };
+
+// One visible (pose, Gaussian): what the blend reads per list entry.
+struct alignas(16) Splat {
+  float u, v, ca, cb;   // projected mean (px), conic a, b
+  float cc, o, z;       // conic c, opacity, camera z
+  uint32_t gid;         // Gaussian index
+  float r, g, b;        // colour
+  uint32_t pose;        // pose index
+};
+
+struct GaussArgs {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  const uint16_t* feat;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t feat_dim;
+  int32_t n_parts;
+  const int64_t* part_offsets;
+  const float* part_bounds;
+};
+
+struct CamArgs {
+  float fx, fy, cx, cy;
+  int32_t W, H;
+  float near_z;
+  float limx, limy;      // guard band on x/z and y/z
+  int32_t tile, tile_shift;
+  int32_t ntx, nty, tiles_per_pose;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((b >> 16) | 0x40);  // quiet NaN
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// World covariance Sigma_w = R_q diag(exp(2 ls)) R_q^T, (w,x,y,z) quaternion
+// normalised here.  Returns xx, xy, xz, yy, yz, zz.
+__device__ __forceinline__ void cov3_from(const float4 q4, const float ls[3], float S[6]) {
+  const float qn = rsqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+  const float w = q4.x * qn, x = q4.y * qn, y = q4.z * qn, z = q4.w * qn;
+  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+  const float s0 = __expf(2.f * ls[0]), s1 = __expf(2.f * ls[1]), s2 = __expf(2.f * ls[2]);
+  S[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+  S[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+  S[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+  S[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+  S[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+  S[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+}
+
+// Camera-space mean m_c = R mu + t.
+__device__ __forceinline__ void to_camera(const float* P, const float mu[3], float mc[3]) {
+  mc[0] = fmaf(P[0], mu[0], fmaf(P[1], mu[1], fmaf(P[2], mu[2], P[3])));
+  mc[1] = fmaf(P[4], mu[0], fmaf(P[5], mu[1], fmaf(P[6], mu[2], P[7])));
+  mc[2] = fmaf(P[8], mu[0], fmaf(P[9], mu[1], fmaf(P[10], mu[2], P[11])));
+}
+
+struct Footprint {
+  float u, v;           // projected mean
+  float sxx, sxy, syy;  // Sigma' with dilation
+  float ca, cb, cc;     // conic
+  int px0, px1, py0, py1;
+};
+
+// EWA footprint of a Gaussian with camera-space mean mc and world covariance
+// S (pose P = [R|t] row-major).  k2 = 2 ln(255 o).  Returns false when the
+// support rectangle misses the image (or the covariance degenerates).
+__device__ __forceinline__ bool footprint(const float* P, const float mc[3], const float S[6], float k2,
+                                          const CamArgs& c, Footprint& f) {
+  const float z = mc[2];
+  const float iz = 1.0f / z;
+  const float xz = mc[0] / z, yz = mc[1] / z;
+  const float xh = fminf(fmaxf(xz, -c.limx), c.limx);
+  const float yh = fminf(fmaxf(yz, -c.limy), c.limy);
+  const float j00 = c.fx * iz, j02 = -c.fx * xh * iz;
+  const float j11 = c.fy * iz, j12 = -c.fy * yh * iz;
+  // rows of M = J R
+  const float a0 = j00 * P[0] + j02 * P[8], a1 = j00 * P[1] + j02 * P[9], a2 = j00 * P[2] + j02 * P[10];
+  const float b0 = j11 * P[4] + j12 * P[8], b1 = j11 * P[5] + j12 * P[9], b2 = j11 * P[6] + j12 * P[10];
+  // S a, S b
+  const float sa0 = S[0] * a0 + S[1] * a1 + S[2] * a2;
+  const float sa1 = S[1] * a0 + S[3] * a1 + S[4] * a2;
+  const float sa2 = S[2] * a0 + S[4] * a1 + S[5] * a2;
+  const float sb0 = S[0] * b0 + S[1] * b1 + S[2] * b2;
+  const float sb1 = S[1] * b0 + S[3] * b1 + S[4] * b2;
+  const float sb2 = S[2] * b0 + S[4] * b1 + S[5] * b2;
+  f.sxx = a0 * sa0 + a1 * sa1 + a2 * sa2 + kDilation;
+  f.sxy = b0 * sa0 + b1 * sa1 + b2 * sa2;
+  f.syy = b0 * sb0 + b1 * sb1 + b2 * sb2 + kDilation;
+  const float det = f.sxx * f.syy - f.sxy * f.sxy;
+  if (!(det > 0.f)) return false;
+  const float idet = 1.0f / det;
+  f.ca = f.syy * idet;
+  f.cb = -f.sxy * idet;
+  f.cc = f.sxx * idet;
+  f.u = fmaf(c.fx, xz, c.cx);
+  f.v = fmaf(c.fy, yz, c.cy);
+  const float rx = sqrtf(k2 * f.sxx), ry = sqrtf(k2 * f.syy);
+  const float bx0 = f.u - rx - 0.5f - kRectPad, bx1 = f.u + rx - 0.5f + kRectPad;
+  const float by0 = f.v - ry - 0.5f - kRectPad, by1 = f.v + ry - 0.5f + kRectPad;
+  const float wm1 = static_cast<float>(c.W - 1), hm1 = static_cast<float>(c.H - 1);
+  if (!(bx1 >= 0.f && by1 >= 0.f && bx0 <= wm1 && by0 <= hm1)) return false;
+  const float x0 = ceilf(fmaxf(bx0, 0.f)), x1 = floorf(fminf(bx1, wm1));
+  const float y0 = ceilf(fmaxf(by0, 0.f)), y1 = floorf(fminf(by1, hm1));
+  if (!(x0 <= x1 && y0 <= y1)) return false;
+  f.px0 = static_cast<int>(x0); f.px1 = static_cast<int>(x1);
+  f.py0 = static_cast<int>(y0); f.py1 = static_cast<int>(y1);
+  return true;
+}
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase, index
+// l^2 + l + m) at unit direction (x, y, z), with the standard normalisation
+// sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (x sqrt 2 for m != 0).
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float Y[(DEG + 1) * (DEG + 1)]) {
+  Y[0] = 0.28209479177387814f;
+  if constexpr (DEG >= 1) {
+    Y[1] = -0.48860251190291987f * y;
+    Y[2] = 0.48860251190291987f * z;
+    Y[3] = -0.48860251190291987f * x;
+  }
+  if constexpr (DEG >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.5462742152960396f * (xx - yy);
+    if constexpr (DEG >= 3) {
+      Y[9] = -0.5900435899266435f * y * (3.f * xx - yy);
+      Y[10] = 2.890611442640554f * x * y * z;
+      Y[11] = -0.4570457994644658f * y * (4.f * zz - xx - yy);
+      Y[12] = 0.3731763325901154f * z * (2.f * zz - 3.f * xx - 3.f * yy);
+      Y[13] = -0.4570457994644658f * x * (4.f * zz - xx - yy);
+      Y[14] = 1.445305721320277f * z * (xx - yy);
+      Y[15] = -0.5900435899266435f * x * (xx - 3.f * yy);
+    }
+  }
+}
+
+// Unclamped SH colour (before max(0, .)) of Gaussian `i` seen along dir.
+template <int DEG>
+__device__ __forceinline__ void sh_colour_raw(const float* sh, int64_t i, float dx, float dy, float dz,
+                                              float rgb[3]) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float Y[K];
+  sh_basis<DEG>(dx, dy, dz, Y);
+  const float* c = sh + static_cast<int64_t>(K) * 3 * i;
+  float r = 0.5f, g = 0.5f, b = 0.5f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    r = fmaf(c[3 * k + 0], Y[k], r);
+    g = fmaf(c[3 * k + 1], Y[k], g);
+    b = fmaf(c[3 * k + 2], Y[k], b);
+  }
+  rgb[0] = r; rgb[1] = g; rgb[2] = b;
+}
+
+// The per-pair exponent -q/2 of the blend, shared bit for bit by the forward
+// and the reverse replay.
+__device__ __forceinline__ float pair_power(float dx, float dy, float ca, float cb, float cc) {
+  const float quad = fmaf(ca, dx * dx, cc * (dy * dy));
+  return fmaf(-0.5f, quad, -cb * (dx * dy));
+}
+
+__device__ __forceinline__ float pair_alpha(float o, float power) { return fminf(kAlphaMax, o * __expf(power)); }
+
+// Tile-id bits of a pose-major tile index (for key packing).
+__device__ __forceinline__ uint32_t zbits(float z) { return __float_as_uint(z); }
+
+}  // namespace hgsr

@@ -1,0 +1,835 @@
+// Host runtime behind include/hgsr.h: argument checks, the workspace arena,
+// the per-render kernel sequence, graph capture, overflow handling and the
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hgsr.h"
+#include "launch.hpp"
+
+using namespace hgsr;
+
+namespace {
+
+thread_local std::string g_err;
+
+hgsr_status fail(hgsr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(HGSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// A device allocation that only grows.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+int ilog2(int v) {
+  int s = 0;
+  while ((1 << s) < v) ++s;
+  return s;
+}
+
+int bits_for(uint64_t n) {
+  int b = 0;
+  while (b < 64 && (1ull << b) < n) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct hgsr_ctx {
+  int device = 0;
+  int n_cu = 256;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  // capacities
+  int64_t rec_hint = 0, key_hint = 0;
+  uint32_t rec_cap = 0;  // records per pose
+  uint64_t key_cap = 0;
+
+  // workspace
+  Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
+      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg;
+  int32_t* h_misc = nullptr;  // pinned mirror of the misc block
+
+  // the last render
+  bool have_render = false;
+  hgsr_gaussians g{};
+  const float* poses = nullptr;
+  int32_t P = 0;
+  hgsr_intrinsics K{};
+  hgsr_opts opts{};
+  hgsr_outputs out{};
+  CamArgs cam{};
+  const uint32_t* sorted = nullptr;
+
+  // autotuned defaults
+  int tuned_tile = 0;
+  int tuned_sched = -1;
+
+  // stage timing
+  bool profiling = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+// misc block layout (int32 words)
+constexpr int kFlags = 0;       // overflow bits
+constexpr int kTotalKeys = 1;   // keys emitted (u32)
+constexpr int kQueue = 2;       // persistent blend work counter
+constexpr int kBad = 3;         // validation result
+constexpr int kMiscWords = 64;
+
+hgsr_status ensure(hgsr_ctx* c, Buf& b, size_t bytes) {
+  if (bytes <= b.bytes) return HGSR_OK;
+  if (c->capturing) return fail(HGSR_ERR_CAPACITY, "workspace must grow while a graph is being captured; call hgsr_reserve first");
+  if (b.p) HIP_TRY(hipFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  const size_t want = std::max<size_t>(bytes, 256);
+  HIP_TRY(hipMalloc(&b.p, want));
+  b.bytes = want;
+  return HGSR_OK;
+}
+
+#define TRY(expr)                        \
+  do {                                   \
+    hgsr_status s_ = (expr);             \
+    if (s_ != HGSR_OK) return s_;        \
+  } while (0)
+
+hipEvent_t take_event(hgsr_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record an event on s when profiling (outside capture); returns it or null.
+hipEvent_t stamp(hgsr_ctx* c, hipStream_t s) {
+  if (!c->profiling || c->capturing) return nullptr;
+  hipEvent_t e = take_event(c);
+  if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
+  return e;
+}
+
+void mark(hgsr_ctx* c, int stage, hipEvent_t a, hipEvent_t b) {
+  if (a && b) c->marks.push_back({stage, a, b});
+}
+
+CamArgs make_cam(const hgsr_intrinsics& K, int tile, float near_z) {
+  CamArgs c;
+  c.fx = K.fx; c.fy = K.fy; c.cx = K.cx; c.cy = K.cy;
+  c.W = K.width; c.H = K.height;
+  c.near_z = near_z;
+  c.limx = kGuard * (0.5f * static_cast<float>(K.width)) / K.fx;
+  c.limy = kGuard * (0.5f * static_cast<float>(K.height)) / K.fy;
+  c.tile = tile;
+  c.tile_shift = ilog2(tile);
+  c.ntx = (K.width + tile - 1) / tile;
+  c.nty = (K.height + tile - 1) / tile;
+  c.tiles_per_pose = c.ntx * c.nty;
+  return c;
+}
+
+GaussArgs make_gauss(const hgsr_gaussians& g) {
+  GaussArgs a;
+  a.means = g.means; a.log_scales = g.log_scales; a.quats = g.quats; a.opac = g.opacities; a.sh = g.sh;
+  a.feat = g.feat; a.n = g.n; a.sh_degree = g.sh_degree; a.feat_dim = g.feat_dim;
+  a.n_parts = g.n_parts; a.part_offsets = g.part_offsets; a.part_bounds = g.part_bounds;
+  return a;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+hgsr_status check_gaussians(const hgsr_gaussians* g) {
+  if (!g) return fail(HGSR_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0 || g->n >= (1ll << 31)) return fail(HGSR_ERR_INVALID_ARG, "n = %lld out of range", (long long)g->n);
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacities || !g->sh))
+    return fail(HGSR_ERR_INVALID_ARG, "a required Gaussian array is NULL");
+  if (g->sh_degree < 0 || g->sh_degree > 3) return fail(HGSR_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  const int D = g->feat_dim;
+  if (!(D == 0 || D == 8 || D == 16 || D == 32 || D == 64))
+    return fail(HGSR_ERR_INVALID_ARG, "feat_dim must be 0, 8, 16, 32 or 64");
+  if (D > 0 && g->n > 0 && !g->feat) return fail(HGSR_ERR_INVALID_ARG, "feat is NULL with feat_dim > 0");
+  if (g->quats && !aligned16(g->quats)) return fail(HGSR_ERR_INVALID_ARG, "quats must be 16-byte aligned");
+  if (g->feat && !aligned16(g->feat)) return fail(HGSR_ERR_INVALID_ARG, "feat must be 16-byte aligned");
+  if (g->n_parts < 0 || g->n_parts > 64) return fail(HGSR_ERR_INVALID_ARG, "n_parts must be 0..64");
+  if (g->n_parts > 0 && (!g->part_offsets || !g->part_bounds))
+    return fail(HGSR_ERR_INVALID_ARG, "partitions need part_offsets and part_bounds");
+  return HGSR_OK;
+}
+
+hgsr_status check_intrinsics(const hgsr_intrinsics* K) {
+  if (!K) return fail(HGSR_ERR_INVALID_ARG, "intrinsics is NULL");
+  if (K->width <= 0 || K->height <= 0 || K->width > 16384 || K->height > 16384)
+    return fail(HGSR_ERR_INVALID_ARG, "image size %dx%d out of range", K->width, K->height);
+  if (!(K->fx > 0.f) || !(K->fy > 0.f) || !std::isfinite(K->cx) || !std::isfinite(K->cy))
+    return fail(HGSR_ERR_INVALID_ARG, "bad focal length or principal point");
+  return HGSR_OK;
+}
+
+// Size the workspace for P poses, given tile config, gaussians n.
+hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bool lsd) {
+  if (c->rec_cap == 0) {
+    int64_t r = c->rec_hint > 0 ? c->rec_hint : std::max<int64_t>(1 << 16, n / 4);
+    r = std::min<int64_t>(std::max<int64_t>(r, 1024), std::max<int64_t>(n, 1024));
+    c->rec_cap = static_cast<uint32_t>(r);
+  }
+  if (c->key_cap == 0) {
+    c->key_cap = c->key_hint > 0 ? static_cast<uint64_t>(c->key_hint)
+                                 : std::max<uint64_t>(1ull << 21, 8ull * c->rec_cap * static_cast<uint64_t>(P));
+  }
+  const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
+  const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
+  const int64_t npix = static_cast<int64_t>(P) * cam.W * cam.H;
+  TRY(ensure(c, c->recs, nrec * sizeof(Splat)));
+  TRY(ensure(c, c->rects, nrec * sizeof(uint2)));
+  TRY(ensure(c, c->pose_count, P * sizeof(uint32_t)));
+  TRY(ensure(c, c->tile_count, ntile * sizeof(uint32_t)));
+  TRY(ensure(c, c->tile_cursor, ntile * sizeof(uint32_t)));
+  TRY(ensure(c, c->ranges, ntile * sizeof(uint2)));
+  TRY(ensure(c, c->keys0, c->key_cap * sizeof(uint64_t)));
+  TRY(ensure(c, c->keys1, c->key_cap * sizeof(uint64_t)));
+  TRY(ensure(c, c->vals0, c->key_cap * sizeof(uint32_t)));
+  TRY(ensure(c, c->vals1, c->key_cap * sizeof(uint32_t)));
+  TRY(ensure(c, c->list, c->key_cap * sizeof(uint32_t)));
+  const int64_t scan_n = std::max<int64_t>(ntile, lsd ? nrec : 0);
+  TRY(ensure(c, c->scan_tmp, (scan_block_count(scan_n) + 16) * sizeof(uint32_t)));
+  TRY(ensure(c, c->finalT, npix * sizeof(float)));
+  TRY(ensure(c, c->nused, npix * sizeof(uint32_t)));
+  TRY(ensure(c, c->part_vis, std::max(P, 1) * sizeof(uint64_t)));
+  if (lsd) {
+    TRY(ensure(c, c->rec_keys, nrec * sizeof(uint32_t)));
+    TRY(ensure(c, c->rec_offsets, nrec * sizeof(uint32_t)));
+    TRY(ensure(c, c->gids0, c->key_cap * sizeof(uint32_t)));
+    TRY(ensure(c, c->gids1, c->key_cap * sizeof(uint32_t)));
+    const int64_t nb = static_cast<int64_t>((c->key_cap + 2047) / 2048);
+    TRY(ensure(c, c->hist, (256 * nb + scan_block_count(256 * nb) + 16) * sizeof(uint32_t)));
+  }
+  return HGSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hgsr_last_error(void) { return g_err.c_str(); }
+const char* hgsr_version(void) { return "hgsr 0.1 gfx950"; }
+
+hgsr_status hgsr_ctx_create(hgsr_ctx** out, int64_t record_hint, int64_t key_hint) {
+  if (!out) return fail(HGSR_ERR_INVALID_ARG, "ctx out-pointer is NULL");
+  hgsr_ctx* c = new hgsr_ctx();
+  HIP_TRY(hipGetDevice(&c->device));
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0) c->n_cu = cu;
+  c->rec_hint = record_hint;
+  c->key_hint = key_hint;
+  hgsr_status st = ensure(c, c->misc, kMiscWords * sizeof(int32_t));
+  if (st != HGSR_OK) {
+    delete c;
+    return st;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_misc), kMiscWords * sizeof(int32_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return fail(HGSR_ERR_HIP, "hipHostMalloc failed");
+  }
+  HIP_TRY(hipMemset(c->misc.p, 0, kMiscWords * sizeof(int32_t)));
+  *out = c;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
+  if (!c) return HGSR_OK;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
+                &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
+                &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
+                &c->part_vis, &c->grad_rec, &c->dbg};
+  for (Buf* b : all)
+    if (b->p) (void)hipFree(b->p);
+  if (c->h_misc) (void)hipHostFree(c->h_misc);
+  for (auto& m : c->marks) {
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  std::sort(c->pool.begin(), c->pool.end());
+  c->pool.erase(std::unique(c->pool.begin(), c->pool.end()), c->pool.end());
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, int32_t tile,
+                         int64_t records_per_pose, int64_t keys, int64_t n_gaussians) {
+  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
+  if (P <= 0 || width <= 0 || height <= 0 || !(tile == 8 || tile == 16 || tile == 32))
+    return fail(HGSR_ERR_INVALID_ARG, "bad reserve arguments");
+  if (records_per_pose > 0 && static_cast<uint64_t>(records_per_pose) > c->rec_cap)
+    c->rec_cap = static_cast<uint32_t>(std::min<int64_t>(records_per_pose, 0x7fffffff));
+  if (keys > 0 && static_cast<uint64_t>(keys) > c->key_cap) c->key_cap = static_cast<uint64_t>(keys);
+  hgsr_intrinsics K{1.f, 1.f, 0.f, 0.f, width, height};
+  const CamArgs cam = make_cam(K, tile, 0.2f);
+  // size every buffer either sort path may use
+  TRY(size_workspace(c, P, cam, n_gaussians, true));
+  TRY(ensure(c, c->grad_rec, static_cast<size_t>(P) * c->rec_cap * kGradRecStride * sizeof(float)));
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream) {
+  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
+  TRY(check_gaussians(g));
+  TRY(check_intrinsics(K));
+  if (!opts || !out) return fail(HGSR_ERR_INVALID_ARG, "opts/out is NULL");
+  if (P <= 0 || P > 4096 || !poses) return fail(HGSR_ERR_INVALID_ARG, "need 1..4096 poses and a pose pointer");
+  if (!out->rgb || !out->depth || !out->alpha) return fail(HGSR_ERR_INVALID_ARG, "rgb, depth and alpha are required");
+  int tile = opts->tile ? opts->tile : (c->tuned_tile ? c->tuned_tile : 16);
+  if (!(tile == 8 || tile == 16 || tile == 32)) return fail(HGSR_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
+  int sched = opts->schedule;
+  if (sched == HGSR_SCHED_AUTO) sched = c->tuned_sched >= 0 ? c->tuned_sched : HGSR_SCHED_GRID;
+  if (sched < 0 || sched > 2) return fail(HGSR_ERR_INVALID_ARG, "bad schedule");
+  if (!(opts->sort_mode == HGSR_SORT_BUCKET || opts->sort_mode == HGSR_SORT_LSD))
+    return fail(HGSR_ERR_INVALID_ARG, "bad sort_mode");
+  const bool lsd = opts->sort_mode == HGSR_SORT_LSD;
+  const float near_z = opts->near_z > 0.f ? opts->near_z : 0.2f;
+  const CamArgs cam = make_cam(*K, tile, near_z);
+  if (static_cast<int64_t>(P) * cam.tiles_per_pose >= (1ll << 31))
+    return fail(HGSR_ERR_INVALID_ARG, "too many (pose, tile) items");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  TRY(size_workspace(c, P, cam, g->n, lsd));
+  int32_t* misc = c->misc.as<int32_t>();
+  uint32_t* pose_count = c->pose_count.as<uint32_t>();
+  const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
+  const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
+
+  // clear flags and counters (fill kernels, so the sequence can be captured)
+  launch_fill_u32(reinterpret_cast<uint32_t*>(misc), 0u, 3, s);
+  launch_fill_u32(pose_count, 0u, P, s);
+  if (!lsd) {
+    launch_fill_u32(c->tile_count.as<uint32_t>(), 0u, ntile, s);
+    launch_fill_u32(c->tile_cursor.as<uint32_t>(), 0u, ntile, s);
+  } else {
+    launch_fill_u32(c->rec_keys.as<uint32_t>(), 0u, nrec, s);
+  }
+
+  hipEvent_t e0 = stamp(c, s);
+  const GaussArgs ga = make_gauss(*g);
+  if (g->n_parts > 0) launch_partition_cull(poses, P, g->part_bounds, g->n_parts, cam, c->part_vis.as<uint64_t>(), s);
+
+  if (g->n > 0) {
+    for (int p0 = 0; p0 < P; p0 += kMaxPoses) {
+      ProjectArgs pa;
+      pa.g = ga;
+      pa.c = cam;
+      pa.poses = poses;
+      pa.P = std::min(kMaxPoses, P - p0);
+      pa.pose_base = p0;
+      pa.recs = c->recs.as<Splat>();
+      pa.rects = c->rects.as<uint2>();
+      pa.rec_keys = lsd ? c->rec_keys.as<uint32_t>() : nullptr;
+      pa.pose_count = pose_count;
+      pa.rec_cap = c->rec_cap;
+      pa.tile_count = lsd ? nullptr : c->tile_count.as<uint32_t>();
+      pa.part_vis = g->n_parts > 0 ? c->part_vis.as<uint64_t>() : nullptr;
+      pa.flags = misc + kFlags;
+      launch_project(pa, s);
+    }
+  }
+
+  hipEvent_t e1 = stamp(c, s);
+  BinArgs ba;
+  ba.c = cam;
+  ba.P = P;
+  ba.recs = c->recs.as<Splat>();
+  ba.rects = c->rects.as<uint2>();
+  ba.pose_count = pose_count;
+  ba.rec_cap = c->rec_cap;
+  ba.tile_cursor = c->tile_cursor.as<uint32_t>();
+  ba.ranges = c->ranges.as<uint2>();
+  ba.key_cap = c->key_cap;
+  ba.flags = misc + kFlags;
+  uint32_t* total = reinterpret_cast<uint32_t*>(misc + kTotalKeys);
+  const uint32_t* sorted = nullptr;
+  if (!lsd) {
+    launch_scan(c->tile_count.as<uint32_t>(), ntile, nullptr, c->ranges.as<uint2>(), c->scan_tmp.as<uint32_t>(), total,
+                c->key_cap, misc + kFlags, 2, s);
+    ba.keys = c->keys0.as<uint64_t>();
+    ba.vals = c->vals0.as<uint32_t>();
+    launch_emit_bucket(ba, s);
+    TileSortArgs ta;
+    ta.n_tiles = static_cast<int32_t>(ntile);
+    ta.ranges = c->ranges.as<uint2>();
+    ta.keys = c->keys0.as<uint64_t>();
+    ta.vals = c->vals0.as<uint32_t>();
+    ta.keys_alt = c->keys1.as<uint64_t>();
+    ta.vals_alt = c->vals1.as<uint32_t>();
+    ta.list = c->list.as<uint32_t>();
+    ta.lds_cap = opts->lds_sort_cap > 0 ? std::min(opts->lds_sort_cap, 4096) : 4096;
+    ta.gid_bits = bits_for(static_cast<uint64_t>(std::max<int64_t>(g->n, 2)));
+    ta.flags = misc + kFlags;
+    launch_tile_sort(ta, s);
+    sorted = c->list.as<uint32_t>();
+  } else {
+    launch_scan(c->rec_keys.as<uint32_t>(), nrec, c->rec_offsets.as<uint32_t>(), nullptr, c->scan_tmp.as<uint32_t>(),
+                total, c->key_cap, misc + kFlags, 2, s);
+    launch_emit_lsd(ba, c->rec_offsets.as<uint32_t>(), c->keys0.as<uint64_t>(), c->gids0.as<uint32_t>(),
+                    c->vals0.as<uint32_t>(), s);
+    LsdArgs la;
+    la.total = total;
+    la.key_cap = c->key_cap;
+    la.n_blocks = static_cast<int32_t>((c->key_cap + 2047) / 2048);
+    la.keys[0] = c->keys0.as<uint64_t>(); la.keys[1] = c->keys1.as<uint64_t>();
+    la.gids[0] = c->gids0.as<uint32_t>(); la.gids[1] = c->gids1.as<uint32_t>();
+    la.vals[0] = c->vals0.as<uint32_t>(); la.vals[1] = c->vals1.as<uint32_t>();
+    la.hist = c->hist.as<uint32_t>();
+    la.flags = misc + kFlags;
+    const int gid_passes = (bits_for(static_cast<uint64_t>(std::max<int64_t>(g->n, 2))) + 7) / 8;
+    const int tile_passes = std::max(1, (bits_for(static_cast<uint64_t>(ntile)) + 7) / 8);
+    int outb = 0;
+    launch_lsd_sort(la, gid_passes, 4, tile_passes, &outb, s);
+    launch_ranges_from_sorted(la.keys[outb], total, c->key_cap, c->ranges.as<uint2>(), static_cast<int32_t>(ntile),
+                              misc + kFlags, s);
+    sorted = la.vals[outb];
+  }
+
+  hipEvent_t e2 = stamp(c, s);
+  BlendArgs bl;
+  bl.c = cam;
+  bl.P = P;
+  bl.ranges = c->ranges.as<uint2>();
+  bl.list = sorted;
+  bl.recs = c->recs.as<Splat>();
+  bl.feat = g->feat;
+  for (int k = 0; k < 3; ++k) bl.bg[k] = opts->bg[k];
+  bl.rgb = out->rgb;
+  bl.depth = out->depth;
+  bl.alpha = out->alpha;
+  bl.out_feat = g->feat_dim > 0 ? out->feat : nullptr;
+  bl.final_T = c->finalT.as<float>();
+  bl.n_used = c->nused.as<uint32_t>();
+  bl.schedule = sched;
+  bl.n_items = static_cast<int32_t>(ntile);
+  bl.queue = reinterpret_cast<uint32_t*>(misc + kQueue);
+  bl.flags = misc + kFlags;
+  int n_ctas = static_cast<int>(ntile);
+  if (sched != HGSR_SCHED_GRID) n_ctas = static_cast<int>(std::min<int64_t>(ntile, 8ll * c->n_cu));
+  launch_blend_fwd(bl, g->feat_dim, opts->feat_out_bf16 != 0, n_ctas, s);
+  HIP_TRY(hipGetLastError());
+  hipEvent_t e3 = stamp(c, s);
+  mark(c, 0, e0, e1);
+  mark(c, 1, e1, e2);
+  mark(c, 2, e2, e3);
+
+  c->have_render = true;
+  c->g = *g;
+  c->poses = poses;
+  c->P = P;
+  c->K = *K;
+  c->opts = *opts;
+  c->opts.tile = tile;
+  c->out = *out;
+  c->cam = cam;
+  c->sorted = sorted;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream stream) {
+  if (!c || !overflowed) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> counts(std::max(c->P, 1), 0);
+  if (c->have_render)
+    HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, c->P * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int32_t f = c->h_misc[kFlags];
+  *overflowed = f;
+  if (f) {
+    if (c->capturing) return fail(HGSR_ERR_STATE, "cannot regrow during capture");
+    const uint32_t mx = *std::max_element(counts.begin(), counts.end());
+    if (f & 1) {
+      c->rec_cap = static_cast<uint32_t>(std::min<uint64_t>(0x7fffffffull, mx + mx / 4 + 1024));
+      c->key_cap = std::max<uint64_t>(c->key_cap * 2, c->key_cap);
+    }
+    if (f & 2) {
+      const uint64_t need = static_cast<uint32_t>(c->h_misc[kTotalKeys]);
+      c->key_cap = std::max<uint64_t>(c->key_cap, need + need / 4 + 4096);
+    }
+  }
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_stats(hgsr_ctx* c, hgsr_render_stats* out, hgsr_stream stream) {
+  if (!c || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (!c->have_render) return fail(HGSR_ERR_STATE, "no render yet");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t ntile = static_cast<int64_t>(c->P) * c->cam.tiles_per_pose;
+  std::vector<uint32_t> counts(c->P);
+  std::vector<uint2> ranges(ntile);
+  HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, c->P * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ranges.data(), c->ranges.p, ntile * sizeof(uint2), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->visible = 0;
+  for (uint32_t v : counts) out->visible += v;
+  out->keys = static_cast<uint32_t>(c->h_misc[kTotalKeys]);
+  out->max_tile_list = 0;
+  for (const uint2& r : ranges) out->max_tile_list = std::max<int64_t>(out->max_tile_list, (int64_t)r.y - (int64_t)r.x);
+  out->overflow = c->h_misc[kFlags];
+  out->tile = c->cam.tile;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_debug_tile_lists(hgsr_ctx* c, int32_t pose, uint32_t* ranges, uint32_t* gids, int64_t cap,
+                                  int64_t* n, hgsr_stream stream) {
+  if (!c || !ranges || !n) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (!c->have_render) return fail(HGSR_ERR_STATE, "no render yet");
+  if (pose < 0 || pose >= c->P) return fail(HGSR_ERR_INVALID_ARG, "pose out of range");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int tiles = c->cam.tiles_per_pose;
+  std::vector<uint2> rg(tiles);
+  HIP_TRY(hipMemcpyAsync(rg.data(), c->ranges.as<uint2>() + static_cast<int64_t>(pose) * tiles, tiles * sizeof(uint2),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (tiles == 0) {
+    *n = 0;
+    return HGSR_OK;
+  }
+  uint32_t lo = rg[0].x, hi = rg[0].y;
+  for (const uint2& r : rg) {
+    lo = std::min(lo, r.x);
+    hi = std::max(hi, r.y);
+  }
+  const int64_t cnt = static_cast<int64_t>(hi) - lo;
+  std::vector<uint32_t> idx(std::max<int64_t>(cnt, 1));
+  uint32_t nrec = 0;
+  HIP_TRY(hipMemcpyAsync(&nrec, c->pose_count.as<uint32_t>() + pose, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  if (cnt > 0)
+    HIP_TRY(hipMemcpyAsync(idx.data(), c->sorted + lo, cnt * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  nrec = std::min(nrec, c->rec_cap);
+  std::vector<Splat> recs(std::max<uint32_t>(nrec, 1));
+  const int64_t base = static_cast<int64_t>(pose) * c->rec_cap;
+  if (nrec > 0)
+    HIP_TRY(hipMemcpy(recs.data(), c->recs.as<Splat>() + base, nrec * sizeof(Splat), hipMemcpyDeviceToHost));
+  int64_t k = 0;
+  for (int t = 0; t < tiles; ++t) {
+    ranges[2 * t] = static_cast<uint32_t>(k);
+    for (uint32_t e = rg[t].x; e < rg[t].y; ++e, ++k) {
+      if (gids && k < cap) {
+        const int64_t r = static_cast<int64_t>(idx[e - lo]) - base;
+        gids[k] = (r >= 0 && r < nrec) ? recs[r].gid : 0xffffffffu;
+      }
+    }
+    ranges[2 * t + 1] = static_cast<uint32_t>(k);
+  }
+  *n = k;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_partition_bounds(const hgsr_gaussians* g, float* part_bounds, hgsr_stream stream) {
+  if (!g || !part_bounds || g->n_parts <= 0 || !g->part_offsets)
+    return fail(HGSR_ERR_INVALID_ARG, "need partitions and an output array");
+  GaussArgs ga = make_gauss(*g);
+  launch_partition_bounds(ga, part_bounds, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_validate(const hgsr_gaussians* g, hgsr_stream stream) {
+  TRY(check_gaussians(g));
+  if (g->n == 0) return HGSR_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int32_t* bad = nullptr;
+  HIP_TRY(hipMalloc(&bad, sizeof(int32_t)));
+  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+  launch_validate(make_gauss(*g), bad, s);
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipFree(bad));
+  if (h) return fail(HGSR_ERR_INVALID_ARG, "Gaussian arrays hold NaN/Inf, an opacity outside [0,1] or a zero quaternion");
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_graph_begin(hgsr_ctx* c, hgsr_stream stream) {
+  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->capturing) return fail(HGSR_ERR_STATE, "already capturing");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!s) return fail(HGSR_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  c->capturing = true;
+  c->cap_stream = s;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_graph_end(hgsr_ctx* c) {
+  if (!c || !c->capturing) return fail(HGSR_ERR_STATE, "not capturing");
+  c->capturing = false;
+  if (c->exec) {
+    (void)hipGraphExecDestroy(c->exec);
+    c->exec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  HIP_TRY(hipStreamEndCapture(c->cap_stream, &c->graph));
+  HIP_TRY(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_graph_launch(hgsr_ctx* c, int32_t replays, hgsr_stream stream) {
+  if (!c || !c->exec) return fail(HGSR_ERR_STATE, "no captured graph");
+  if (replays < 0) return fail(HGSR_ERR_INVALID_ARG, "negative replay count");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(c->exec, s));
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_profile_enable(hgsr_ctx* c, int32_t enable) {
+  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
+  c->profiling = enable != 0;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_profile_read(hgsr_ctx* c, double* ms, int64_t* calls) {
+  if (!c || !ms) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 6; ++k) {
+    ms[k] = 0.0;
+    if (calls) calls[k] = 0;
+  }
+  for (auto& m : c->marks) {
+    HIP_TRY(hipEventSynchronize(m.b));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, m.a, m.b));
+    ms[m.stage] += t;
+    if (calls) calls[m.stage] += 1;
+  }
+  // events are shared between consecutive marks; return each once
+  std::vector<hipEvent_t> seen;
+  for (auto& m : c->marks) {
+    for (hipEvent_t e : {m.a, m.b})
+      if (std::find(seen.begin(), seen.end(), e) == seen.end()) seen.push_back(e);
+  }
+  for (hipEvent_t e : seen) c->pool.push_back(e);
+  c->marks.clear();
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_render_backward(hgsr_ctx* c, const hgsr_grad_outputs* go, const hgsr_grads* gr,
+                                 hgsr_stream stream) {
+  if (!c || !go || !gr) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (!c->have_render) return fail(HGSR_ERR_STATE, "backward before any render");
+  const int D = c->g.feat_dim;
+  if ((go->feat || gr->feat) && D == 0) return fail(HGSR_ERR_INVALID_ARG, "feature gradients need feat_dim > 0");
+  if (go->depth && !c->out.depth) return fail(HGSR_ERR_STATE, "depth gradient needs the forward depth");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int P = c->P;
+  const int64_t n = c->g.n;
+  const int K = (c->g.sh_degree + 1) * (c->g.sh_degree + 1);
+  TRY(ensure(c, c->grad_rec, static_cast<size_t>(P) * c->rec_cap * kGradRecStride * sizeof(float)));
+  int32_t* misc = c->misc.as<int32_t>();
+  if (gr->pose) launch_fill_f32(gr->pose, 0.f, 6ll * P, s);
+  if (gr->means) launch_fill_f32(gr->means, 0.f, 3 * n, s);
+  if (gr->opacities) launch_fill_f32(gr->opacities, 0.f, n, s);
+  if (gr->log_scales) launch_fill_f32(gr->log_scales, 0.f, 3 * n, s);
+  if (gr->quats) launch_fill_f32(gr->quats, 0.f, 4 * n, s);
+  if (gr->sh) launch_fill_f32(gr->sh, 0.f, 3ll * K * n, s);
+  if (gr->feat) launch_fill_f32(gr->feat, 0.f, static_cast<int64_t>(D) * n, s);
+  launch_zero_grad_rec(c->grad_rec.as<float>(), c->pose_count.as<uint32_t>(), c->rec_cap, P, s);
+  hipEvent_t e0 = stamp(c, s);
+  BackArgs b;
+  b.c = c->cam;
+  b.P = P;
+  b.ranges = c->ranges.as<uint2>();
+  b.list = c->sorted;
+  b.recs = c->recs.as<Splat>();
+  b.feat = c->g.feat;
+  b.D = D;
+  for (int k = 0; k < 3; ++k) b.bg[k] = c->opts.bg[k];
+  b.fwd_depth = c->out.depth;
+  b.final_T = c->finalT.as<float>();
+  b.n_used = c->nused.as<uint32_t>();
+  b.g_rgb = go->rgb;
+  b.g_depth = go->depth;
+  b.g_alpha = go->alpha;
+  b.g_feat = go->feat;
+  b.g_rec = c->grad_rec.as<float>();
+  b.g_featvec = gr->feat;
+  b.flags = misc + kFlags;
+  launch_blend_bwd(b, s);
+  hipEvent_t e1 = stamp(c, s);
+  ProjBackArgs pb;
+  pb.g = make_gauss(c->g);
+  pb.c = c->cam;
+  pb.poses = c->poses;
+  pb.P = P;
+  pb.recs = c->recs.as<Splat>();
+  pb.pose_count = c->pose_count.as<uint32_t>();
+  pb.rec_cap = c->rec_cap;
+  pb.g_rec = c->grad_rec.as<float>();
+  pb.g_pose = gr->pose;
+  pb.g_means = gr->means;
+  pb.g_opac = gr->opacities;
+  pb.g_log_scales = gr->log_scales;
+  pb.g_quats = gr->quats;
+  pb.g_sh = gr->sh;
+  pb.flags = misc + kFlags;
+  launch_project_bwd(pb, s);
+  HIP_TRY(hipGetLastError());
+  hipEvent_t e2 = stamp(c, s);
+  mark(c, 3, e0, e1);
+  mark(c, 4, e1, e2);
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_residual(const float* rgb, const void* feat, int32_t feat_bf16, const float* rgb_target,
+                          const float* feat_target, int32_t P, int32_t H, int32_t W, int32_t D, float lam_f,
+                          float* loss, float* grad_rgb, float* grad_feat, hgsr_stream stream) {
+  if (!rgb || !rgb_target || !loss || !grad_rgb) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (P <= 0 || H <= 0 || W <= 0) return fail(HGSR_ERR_INVALID_ARG, "bad sizes");
+  if (!(D == 0 || D == 8 || D == 16 || D == 32 || D == 64)) return fail(HGSR_ERR_INVALID_ARG, "bad feature width");
+  if (D > 0 && (!feat || !feat_target || !grad_feat)) return fail(HGSR_ERR_INVALID_ARG, "feature arrays missing");
+  launch_residual(rgb, feat, feat_bf16, rgb_target, feat_target, P, H, W, D, lam_f, loss, grad_rgb, grad_feat,
+                  reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step_count, int32_t P,
+                           float lr_rho, float lr_phi, float beta1, float beta2, float eps, hgsr_stream stream) {
+  if (!poses || !grad || !m || !v || !step_count) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (P <= 0) return fail(HGSR_ERR_INVALID_ARG, "bad pose count");
+  launch_pose_adam(poses, grad, m, v, step_count, P, lr_rho, lr_phi, beta1, beta2, eps,
+                   reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                          const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream) {
+  if (!c || !g || !K || !opts || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  if (c->capturing) return fail(HGSR_ERR_STATE, "cannot autotune while capturing");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char key[256];
+  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d\"", K->width, K->height, P,
+           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode);
+  // cached answer?
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      int t = 0, sc = -1;
+      float ms = 0.f;
+      while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, key)) continue;
+        const char* pt = strstr(line, "\"tile\": ");
+        const char* ps = strstr(line, "\"schedule\": ");
+        const char* pm = strstr(line, "\"ms\": ");
+        if (pt && ps && pm) {
+          t = atoi(pt + 8);
+          sc = atoi(ps + 12);
+          ms = static_cast<float>(atof(pm + 6));
+        }
+      }
+      fclose(f);
+      if ((t == 8 || t == 16 || t == 32) && sc >= 0 && sc <= 2) {
+        c->tuned_tile = t;
+        c->tuned_sched = sc;
+        if (result) *result = {t, sc, ms};
+        return HGSR_OK;
+      }
+    }
+  }
+  const int tiles[3] = {8, 16, 32};
+  const int scheds[3] = {HGSR_SCHED_GRID, HGSR_SCHED_POSE_MAJOR, HGSR_SCHED_TILE_MAJOR};
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  float best = 1e30f;
+  int bt = 16, bs = HGSR_SCHED_GRID;
+  for (int t : tiles)
+    for (int sc : scheds) {
+      if (sc != HGSR_SCHED_GRID && P == 1 && sc == HGSR_SCHED_TILE_MAJOR) continue;
+      hgsr_opts o = *opts;
+      o.tile = t;
+      o.schedule = sc;
+      for (int tries = 0; tries < 6; ++tries) {
+        TRY(hgsr_render(c, g, poses, P, K, &o, out, stream));
+        int32_t ovf = 0;
+        TRY(hgsr_check_overflow(c, &ovf, stream));
+        if (!ovf) break;
+      }
+      const int reps = 5;
+      HIP_TRY(hipEventRecord(a, s));
+      for (int r = 0; r < reps; ++r) TRY(hgsr_render(c, g, poses, P, K, &o, out, stream));
+      HIP_TRY(hipEventRecord(b, s));
+      HIP_TRY(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, a, b));
+      ms /= reps;
+      if (ms < best) {
+        best = ms;
+        bt = t;
+        bs = sc;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  c->tuned_tile = bt;
+  c->tuned_sched = bs;
+  if (result) *result = {bt, bs, best};
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "{%s, \"tile\": %d, \"schedule\": %d, \"ms\": %.5f}\n", key, bt, bs, best);
+      fclose(f);
+    }
+  }
+  return HGSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Kernel argument blocks and host-side launchers (one per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hgsr_device.hpp"
+
+namespace hgsr {
+
+struct ProjectArgs {
+  GaussArgs g;
+  CamArgs c;
+  const float* poses;        // P_total x 12
+  int32_t P;                 // poses in this launch (<= kMaxPoses)
+  int32_t pose_base;         // first pose of this launch
+  Splat* recs;               // P_total x rec_cap
+  uint2* rects;              // tile rectangle per record (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  uint32_t* rec_keys;        // entries per record (LSD path) or null
+  uint32_t* pose_count;      // visible count per pose (may exceed rec_cap)
+  uint32_t rec_cap;          // records per pose
+  uint32_t* tile_count;      // entries per (pose, tile) (bucket path) or null
+  const uint64_t* part_vis;  // per pose: partitions that may be visible, or null
+  int32_t* flags;            // [0]: overflow bits
+};
+
+struct BinArgs {
+  CamArgs c;
+  int32_t P;
+  const Splat* recs;
+  const uint2* rects;
+  const uint32_t* pose_count;
+  uint32_t rec_cap;
+  uint32_t* tile_cursor;     // per (pose, tile) running slot
+  const uint2* ranges;       // per (pose, tile) [begin, end)
+  uint64_t* keys;            // (depth bits << 32 | gid) per entry
+  uint32_t* vals;            // record index per entry
+  uint64_t key_cap;
+  int32_t* flags;
+};
+
+struct TileSortArgs {
+  int32_t n_tiles;           // P x tiles
+  const uint2* ranges;
+  uint64_t* keys;
+  uint32_t* vals;
+  uint64_t* keys_alt;
+  uint32_t* vals_alt;
+  uint32_t* list;            // sorted record indices
+  int32_t lds_cap;
+  int32_t gid_bits;
+  const int32_t* flags;
+};
+
+struct LsdArgs {
+  const uint32_t* total;     // number of keys (device)
+  uint64_t key_cap;
+  int32_t n_blocks;          // blocks per pass (static, from capacity)
+  uint64_t* keys[2];
+  uint32_t* gids[2];
+  uint32_t* vals[2];
+  uint32_t* hist;            // 256 x n_blocks
+  const int32_t* flags;
+};
+
+struct BlendArgs {
+  CamArgs c;
+  int32_t P;
+  const uint2* ranges;
+  const uint32_t* list;
+  const Splat* recs;
+  const uint16_t* feat;      // n x D bf16
+  float bg[3];
+  float* rgb;
+  float* depth;
+  float* alpha;
+  void* out_feat;
+  float* final_T;
+  uint32_t* n_used;
+  int32_t schedule;
+  int32_t n_items;
+  uint32_t* queue;
+  const int32_t* flags;
+};
+
+struct BackArgs {
+  CamArgs c;
+  int32_t P;
+  const uint2* ranges;
+  const uint32_t* list;
+  const Splat* recs;
+  const uint16_t* feat;
+  int32_t D;
+  float bg[3];
+  const float* fwd_depth;
+  const float* final_T;
+  const uint32_t* n_used;
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_alpha;
+  const float* g_feat;
+  float* g_rec;              // per record: du dv da db dc do dz dr dg db (+2 pad)
+  float* g_featvec;          // n x D or null
+  const int32_t* flags;
+};
+
+struct ProjBackArgs {
+  GaussArgs g;
+  CamArgs c;
+  const float* poses;
+  int32_t P;
+  const Splat* recs;
+  const uint32_t* pose_count;
+  uint32_t rec_cap;
+  const float* g_rec;
+  float* g_pose;
+  float* g_means;
+  float* g_opac;
+  float* g_log_scales;
+  float* g_quats;
+  float* g_sh;
+  const int32_t* flags;
+};
+
+constexpr int kGradRecStride = 12;
+
+// project.hip
+void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s);
+void launch_partition_cull(const float* poses, int P, const float* bounds, int n_parts, const CamArgs& c,
+                           uint64_t* vis, hipStream_t s);
+void launch_project(const ProjectArgs& a, hipStream_t s);
+void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s);
+
+// binning.hip
+void launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
+int64_t scan_block_count(int64_t n);
+void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
+                 uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s);
+void launch_emit_bucket(const BinArgs& a, hipStream_t s);
+void launch_tile_sort(const TileSortArgs& a, hipStream_t s);
+void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,
+                     uint32_t* vals, hipStream_t s);
+void launch_lsd_sort(LsdArgs& a, int passes_gid, int passes_z, int passes_tile, int* out_buffer, hipStream_t s);
+void launch_ranges_from_sorted(const uint64_t* keys, const uint32_t* total, uint64_t key_cap, uint2* ranges,
+                               int32_t n_tiles, const int32_t* flags, hipStream_t s);
+
+// blend.hip
+void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipStream_t s);
+
+// backward.hip
+void launch_blend_bwd(const BackArgs& a, hipStream_t s);
+void launch_project_bwd(const ProjBackArgs& a, hipStream_t s);
+void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap, int P, hipStream_t s);
+
+// refine.hip
+void launch_residual(const float* rgb, const void* feat, int feat_bf16, const float* rgb_t, const float* feat_t,
+                     int P, int H, int W, int D, float lam_f, float* loss, float* g_rgb, float* g_feat,
+                     hipStream_t s);
+void launch_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step, int P, float lr_rho,
+                      float lr_phi, float b1, float b2, float eps, hipStream_t s);
+
+}  // namespace hgsr

@@ -1,0 +1,225 @@
+// Per-Gaussian stage: partition frustum cull, EWA projection, SH colour,
+// support rectangle, per-pose compaction of visible splats and the per-tile
+// entry counts of the tile binning.
+#include "hgsr_device.hpp"
+#include "launch.hpp"
+
+namespace hgsr {
+
+// ------------------------------------------------------------ partitions
+// Box of partition k: every Gaussian's ball of radius 3.33 x its largest
+// scale (the 1/255 support of an opaque Gaussian along its longest axis).
+__global__ __launch_bounds__(256) void partition_bounds_kernel(GaussArgs g, float* bounds) {
+  const int k = blockIdx.x;
+  const int64_t b = g.part_offsets[k], e = g.part_offsets[k + 1];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const float s = __expf(fmaxf(g.log_scales[3 * i], fmaxf(g.log_scales[3 * i + 1], g.log_scales[3 * i + 2])));
+    const float r = 3.33f * s;
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], g.means[3 * i + a] - r);
+      hi[a] = fmaxf(hi[a], g.means[3 * i + a] + r);
+    }
+  }
+  __shared__ float red[6][256];
+  for (int a = 0; a < 3; ++a) {
+    red[a][threadIdx.x] = lo[a];
+    red[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) bounds[6 * k + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Per (pose, partition): 1 when the partition's box may reach the image.
+// The box is rejected only when all 8 corners lie behind the near plane or on
+// the outer side of one of the four image-side planes (through the camera
+// centre, pushed out by a margin of `margin` pixels).
+__global__ void partition_cull_kernel(const float* poses, int P, const float* bounds, int n_parts, CamArgs c,
+                                      float margin, uint64_t* vis) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float* T = poses + 12 * p;
+  const float l = (-margin - c.cx) / c.fx, r = (c.W + margin - c.cx) / c.fx;
+  const float t = (-margin - c.cy) / c.fy, b = (c.H + margin - c.cy) / c.fy;
+  uint64_t mask = 0;
+  for (int k = 0; k < n_parts; ++k) {
+    const float* B = bounds + 6 * k;
+    bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
+    for (int q = 0; q < 8; ++q) {
+      const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
+      float m[3];
+      to_camera(T, w, m);
+      all_near &= m[2] < c.near_z;
+      all_l &= m[0] < l * m[2];
+      all_r &= m[0] > r * m[2];
+      all_t &= m[1] < t * m[2];
+      all_b &= m[1] > b * m[2];
+    }
+    if (!(all_near || all_l || all_r || all_t || all_b)) mask |= (1ull << k);
+  }
+  vis[p] = mask;
+}
+
+// ------------------------------------------------------------ projection
+// One thread per Gaussian, looping over the launch's poses (the Gaussian's
+// parameters are read once for all poses).  Visible (pose, Gaussian) pairs
+// are compacted per pose: phase 1 counts them per block in LDS, one global
+// atomic per (block, pose) reserves a range of that pose's record segment,
+// phase 2 recomputes the footprint and writes the records.
+template <int DEG>
+__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+  __shared__ uint32_t s_cnt[kMaxPoses];
+  __shared__ uint32_t s_base[kMaxPoses];
+  const int tid = threadIdx.x;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
+
+  bool live = i < a.g.n;
+  float mu[3] = {0.f, 0.f, 0.f}, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o = 0.f, k2 = 0.f;
+  uint64_t pose_ok = ~0ull;
+  if (live) {
+    o = a.g.opac[i];
+    live = o >= kAlphaMin;  // also false for NaN
+    if (live && a.g.n_parts > 0) {
+      int part = 0;
+      while (part + 1 < a.g.n_parts && a.g.part_offsets[part + 1] <= i) ++part;
+      pose_ok = 0;
+      for (int p = 0; p < a.P; ++p)
+        if ((a.part_vis[a.pose_base + p] >> part) & 1ull) pose_ok |= (1ull << p);
+      live = pose_ok != 0;
+    }
+  }
+  if (live) {
+    mu[0] = a.g.means[3 * i];
+    mu[1] = a.g.means[3 * i + 1];
+    mu[2] = a.g.means[3 * i + 2];
+    const float4 q = reinterpret_cast<const float4*>(a.g.quats)[i];
+    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+    cov3_from(q, ls, S);
+    k2 = 2.f * __logf(255.f * o);
+  }
+  __syncthreads();
+
+  // phase 1: count visible poses per block
+  if (live) {
+    for (int p = 0; p < a.P; ++p) {
+      if (!((pose_ok >> p) & 1ull)) continue;
+      const float* T = a.poses + 12 * (a.pose_base + p);
+      float mc[3];
+      to_camera(T, mu, mc);
+      if (!(mc[2] > a.c.near_z)) continue;
+      Footprint f;
+      if (footprint(T, mc, S, k2, a.c, f)) atomicAdd(&s_cnt[p], 1u);
+    }
+  }
+  __syncthreads();
+  for (int p = tid; p < a.P; p += 256) {
+    const uint32_t cnt = s_cnt[p];
+    s_base[p] = cnt ? atomicAdd(&a.pose_count[a.pose_base + p], cnt) : 0u;
+    s_cnt[p] = 0;
+  }
+  __syncthreads();
+
+  // phase 2: write records
+  if (!live) return;
+  for (int p = 0; p < a.P; ++p) {
+    if (!((pose_ok >> p) & 1ull)) continue;
+    const int pg = a.pose_base + p;
+    const float* T = a.poses + 12 * pg;
+    float mc[3];
+    to_camera(T, mu, mc);
+    if (!(mc[2] > a.c.near_z)) continue;
+    Footprint f;
+    if (!footprint(T, mc, S, k2, a.c, f)) continue;
+    const uint32_t slot = s_base[p] + atomicAdd(&s_cnt[p], 1u);
+    if (slot >= a.rec_cap) {
+      atomicOr(a.flags, 1);
+      continue;
+    }
+    // view direction from the camera centre C = -R^T t
+    const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
+    const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
+    const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
+    float dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
+    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    float rgb[3];
+    sh_colour_raw<DEG>(a.g.sh, i, dx, dy, dz, rgb);
+    const int64_t idx = static_cast<int64_t>(pg) * a.rec_cap + slot;
+    Splat sp;
+    sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
+    sp.cc = f.cc; sp.o = o; sp.z = mc[2]; sp.gid = static_cast<uint32_t>(i);
+    sp.r = fmaxf(rgb[0], 0.f); sp.g = fmaxf(rgb[1], 0.f); sp.b = fmaxf(rgb[2], 0.f);
+    sp.pose = static_cast<uint32_t>(pg);
+    float4* dst = reinterpret_cast<float4*>(a.recs + idx);
+    const float4* src = reinterpret_cast<const float4*>(&sp);
+    dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
+    const int tx0 = f.px0 >> a.c.tile_shift, tx1 = f.px1 >> a.c.tile_shift;
+    const int ty0 = f.py0 >> a.c.tile_shift, ty1 = f.py1 >> a.c.tile_shift;
+    a.rects[idx] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
+                              static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
+    const uint32_t ntiles = static_cast<uint32_t>((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    if (a.rec_keys) a.rec_keys[idx] = ntiles;
+    if (a.tile_count) {
+      uint32_t* tc = a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+    }
+  }
+}
+
+// ------------------------------------------------------------ validation
+__global__ void validate_kernel(GaussArgs g, int32_t* bad) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) ok &= isfinite(g.means[3 * i + a]) && isfinite(g.log_scales[3 * i + a]);
+  float qq = 0.f;
+  for (int a = 0; a < 4; ++a) {
+    const float q = g.quats[4 * i + a];
+    ok &= isfinite(q);
+    qq += q * q;
+  }
+  ok &= qq > 0.f;
+  const float o = g.opac[i];
+  ok &= (o >= 0.f && o <= 1.f);
+  const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+  for (int k = 0; k < 3 * K; ++k) ok &= isfinite(g.sh[static_cast<int64_t>(3 * K) * i + k]);
+  if (!ok) atomicOr(bad, 1);
+}
+
+// ------------------------------------------------------------ launchers
+void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s) {
+  hipLaunchKernelGGL(partition_bounds_kernel, dim3(g.n_parts), dim3(256), 0, s, g, bounds);
+}
+
+void launch_partition_cull(const float* poses, int P, const float* bounds, int n_parts, const CamArgs& c,
+                           uint64_t* vis, hipStream_t s) {
+  const float margin = 8.f + 0.05f * static_cast<float>(c.W > c.H ? c.W : c.H);
+  hipLaunchKernelGGL(partition_cull_kernel, dim3((P + 63) / 64), dim3(64), 0, s, poses, P, bounds, n_parts, c,
+                     margin, vis);
+}
+
+void launch_project(const ProjectArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((a.g.n + 255) / 256));
+  switch (a.g.sh_degree) {
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, a); break;
+  }
+}
+
+void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(validate_kernel, dim3(static_cast<unsigned>((g.n + 255) / 256)), dim3(256), 0, s, g, bad);
+}
+
+}  // namespace hgsr

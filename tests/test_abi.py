@@ -1,0 +1,76 @@
+"""The C-ABI library loads and exports every entry point include/hgsr.h
+declares (no compute calls: CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgsr.h")
+LIB = os.path.join(ROOT, "paper_2507_15683_amd", "libhgsr.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hgsr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2507_15683_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15, syms
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2507_15683_amd import _lib
+    assert set(_lib.SIGNATURES) == set(declared_symbols())
+
+
+def test_version_and_error_strings(lib):
+    lib.hgsr_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.hgsr_version()
+    lib.hgsr_last_error.restype = ctypes.c_char_p
+    assert isinstance(lib.hgsr_last_error(), bytes)
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the header structs have the C sizes (64-bit ABI)."""
+    from paper_2507_15683_amd import _lib
+    assert ctypes.sizeof(_lib.Gaussians) == 8 + 5 * 8 + 4 + 4 + 8 + 8 + 8 + 8  # n, 5 ptrs, deg, D, feat, parts...
+    assert ctypes.sizeof(_lib.Intrinsics) == 24
+    assert ctypes.sizeof(_lib.Opts) == 4 * 3 + 12 + 4 + 4 + 4
+    assert ctypes.sizeof(_lib.Outputs) == 32
+    assert ctypes.sizeof(_lib.Grads) == 56
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    """Argument validation runs before anything touches a device."""
+    from paper_2507_15683_amd import _lib
+    L = _lib.load()
+    # NULL ctx
+    assert L.hgsr_render(None, None, None, 1, None, None, None, None) == 1
+    assert L.hgsr_check_overflow(None, None, None) == 1
+    assert L.hgsr_graph_launch(None, 1, None) == 5
+    g = _lib.Gaussians()
+    g.n = -1
+    assert L.hgsr_validate(ctypes.byref(g), None) == 1
+    g.n = 10
+    assert L.hgsr_validate(ctypes.byref(g), None) == 1  # NULL arrays
+    g2 = _lib.Gaussians()
+    g2.n = 0
+    g2.sh_degree = 4
+    assert L.hgsr_validate(ctypes.byref(g2), None) == 1
+    g2.sh_degree = 0
+    g2.feat_dim = 12
+    assert L.hgsr_validate(ctypes.byref(g2), None) == 1

@@ -1,0 +1,212 @@
+"""GPU forward parity: the HIP path (through the C ABI) against the FP64
+oracle, element by element, plus bitwise self-consistency of the HIP path
+across tile sizes, sort paths, launch schedules, batching and workspace
+regrowth."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import log, parity, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2507_15683_amd as hg
+    return hg
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _poses(P):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(P, dtype=np.float32).reshape(-1, 12)).cuda()
+
+
+def _render(hg, sc, P, cam, r=None, **kw):
+    r = r or hg.Renderer()
+    out = r.render(hg.GaussianScene.from_numpy(sc), _poses(P), hg.Intrinsics.of(cam), **kw)
+    return out, r
+
+
+def test_config1_parity(hg, oracle_mod):
+    log("case: config1 k=0 tile16 bucket")
+    sc, P, cam = synth.config1(0)
+    out, r = _render(hg, sc, P, cam, tile=16)
+    ref = oracle_mod.render(sc, P[0], cam, tile=16, margin=1)
+    s = parity(out, ref, label="config1")
+    st = r.stats()
+    log("stats", st, "oracle", ref["stats"])
+    assert st["visible"] >= ref["stats"]["visible"]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tiny_ragged_parity(hg, oracle_mod, seed):
+    """Ragged image sizes, every tile size, both sort paths, SH degrees 0-3,
+    feature widths 0/8/16/32/64."""
+    n = 60 + 37 * seed
+    D = [0, 8, 16, 32, 64, 32, 8, 16][seed]
+    sc, P, cam = synth.tiny_scene(n, 100 + seed, width=67 + 5 * seed, height=45 + 3 * seed, sh_degree=seed % 4,
+                                  feat_dim=D)
+    ref = oracle_mod.render(sc, P[0], cam, tile=16, margin=1)
+    for tile in (8, 16, 32):
+        for sort in ("bucket", "lsd"):
+            log(f"case: tiny seed={seed} n={n} D={D} tile={tile} sort={sort}")
+            out, _ = _render(hg, sc, P, cam, tile=tile, sort=sort)
+            parity(out, ref, label=f"tiny{seed}/t{tile}/{sort}", max_fragile_frac=0.05)
+
+
+def test_tile_lists_match_oracle(hg, oracle_mod):
+    log("case: config1 tile lists")
+    sc, P, cam = synth.config1(0)
+    tile = 16
+    out, r = _render(hg, sc, P, cam, tile=tile)
+    off, ids, edge = oracle_mod.tile_lists(sc, P[0], cam, tile=tile, edge_px=1e-3)
+    proj = oracle_mod.project(sc, P[0], cam)
+    ntiles = len(off) - 1
+    ranges, gids = r.tile_lists(0, ntiles, cap=int(off[-1]) * 2 + 1024)
+    exempt = 0
+    order_ties = 0
+    for t in range(ntiles):
+        a = [int(i) for i in ids[off[t]:off[t + 1]]]
+        b = [int(i) for i in gids[ranges[t, 0]:ranges[t, 1]]]
+        exempt += sum(edge[i] for i in set(a) ^ set(b))
+        a2 = [i for i in a if not edge[i]]
+        b2 = [i for i in b if not edge[i]]
+        assert set(a2) == set(b2), (t, sorted(set(a2) ^ set(b2)))
+        if a2 != b2:
+            z = proj["z"]
+            for x, y in zip(a2, b2):
+                if x != y:
+                    assert abs(z[x] - z[y]) < 1e-5 * abs(z[x]), (t, x, y)
+                    order_ties += 1
+    log(f"tile lists: {int(off[-1])} oracle entries, {int(ranges[-1, 1])} GPU entries, "
+        f"{exempt} edge-exempt differences, {order_ties} depth near-ties")
+
+
+def test_tile_size_invariance_bitwise(hg):
+    sc, P, cam = synth.config1(1)
+    outs = []
+    for tile in (8, 16, 32):
+        log(f"case: config1 k=1 tile={tile}")
+        o, _ = _render(hg, sc, P, cam, tile=tile)
+        outs.append(o)
+    for o in outs[1:]:
+        for k in ("rgb", "depth", "alpha"):
+            assert np.array_equal(to_np(outs[0][k]), to_np(o[k])), k
+
+
+def test_sort_paths_and_schedules_bitwise(hg):
+    sc, P, cam = synth.tiny_scene(300, 7, width=96, height=80, feat_dim=16, sh_degree=3)
+    Ps = synth.perturb_poses(P[0], 5, 3, 1.0, 2.0)
+    base, _ = _render(hg, sc, Ps, cam)
+    for sort in ("bucket", "lsd"):
+        for sched in ("grid", "pose", "tile"):
+            for tile in (8, 16, 32):
+                log(f"case: 5 poses sort={sort} sched={sched} tile={tile}")
+                o, _ = _render(hg, sc, Ps, cam, sort=sort, schedule=sched, tile=tile)
+                for k in ("rgb", "depth", "alpha", "feat"):
+                    assert np.array_equal(to_np(base[k]), to_np(o[k])), (sort, sched, tile, k)
+
+
+def test_batched_equals_single(hg):
+    sc, P, cam = synth.tiny_scene(400, 8, width=80, height=64, feat_dim=8, sh_degree=2)
+    Ps = synth.perturb_poses(P[0], 7, 4, 1.5, 3.0)
+    log("case: batched 7 poses vs single")
+    batch, _ = _render(hg, sc, Ps, cam, schedule="tile")
+    for p in range(len(Ps)):
+        one, _ = _render(hg, sc, Ps[p:p + 1], cam)
+        for k in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(to_np(batch[k][p]), to_np(one[k][0])), (p, k)
+
+
+def test_more_than_64_poses(hg, oracle_mod):
+    """Poses beyond one projection launch (64) go through further launches."""
+    sc, P, cam = synth.tiny_scene(150, 9, width=40, height=32)
+    Ps = synth.perturb_poses(P[0], 70, 5, 1.0, 2.0)
+    log("case: 70 poses")
+    out, _ = _render(hg, sc, Ps, cam, schedule="pose")
+    for p in (0, 63, 64, 69):
+        ref = oracle_mod.render(sc, Ps[p], cam)
+        parity(out, ref, p=p, label=f"70poses/{p}", max_fragile_frac=0.05)
+
+
+def test_empty_and_culled_scenes(hg):
+    import torch
+    sc, P, cam = synth.tiny_scene(50, 10)
+    empty = sc.subset(np.zeros(0, dtype=np.int64))
+    log("case: empty scene")
+    out, _ = _render(hg, empty, P, cam, bg=(0.25, 0.5, 0.75))
+    assert np.allclose(to_np(out["rgb"][0][1]), 0.5) and to_np(out["alpha"]).max() == 0
+    behind = sc.copy()
+    behind.means[:, 2] += 500.0  # everything above the camera: behind it
+    log("case: all behind camera")
+    out, _ = _render(hg, behind, P, cam)
+    assert to_np(out["alpha"]).max() == 0 and to_np(out["depth"]).max() == 0
+    faint = sc.copy()
+    faint.opacities[:] = 0.5 / 255
+    log("case: all below 1/255")
+    out, _ = _render(hg, faint, P, cam)
+    assert to_np(out["alpha"]).max() == 0
+
+
+def test_overflow_regrows_to_same_result(hg):
+    sc, P, cam = synth.config1(2)
+    log("case: default capacity")
+    ref, _ = _render(hg, sc, P, cam)
+    small = hg.Renderer(record_hint=1024, key_hint=2048)
+    log("case: undersized workspace -> overflow -> regrow")
+    opts = small.opts()
+    outs = small.alloc_outputs(hg.GaussianScene.from_numpy(sc), 1, hg.Intrinsics.of(cam))
+    small.render_into(hg.GaussianScene.from_numpy(sc), _poses(P), hg.Intrinsics.of(cam), outs, opts)
+    assert small.check_overflow() != 0
+    out, _ = _render(hg, sc, P, cam, r=small)
+    assert small.check_overflow() == 0
+    for k in ("rgb", "depth", "alpha"):
+        assert np.array_equal(to_np(ref[k]), to_np(out[k])), k
+
+
+def test_lds_sort_fallback_bitwise(hg):
+    sc, P, cam = synth.tiny_scene(300, 11, width=64, height=48, feat_dim=8)
+    log("case: LDS sort cap 4 (global-memory radix path)")
+    a, _ = _render(hg, sc, P, cam)
+    b, r = _render(hg, sc, P, cam, lds_sort_cap=4)
+    assert r.stats()["max_tile_list"] > 4
+    for k in ("rgb", "depth", "alpha", "feat"):
+        assert np.array_equal(to_np(a[k]), to_np(b[k])), k
+
+
+def test_repeat_renders_bitwise(hg):
+    sc, P, cam = synth.config1(3)
+    r = hg.Renderer()
+    log("case: determinism")
+    a, _ = _render(hg, sc, P, cam, r=r)
+    a = {k: (None if v is None else v.clone()) for k, v in a.items()}
+    b, _ = _render(hg, sc, P, cam, r=r)
+    for k in ("rgb", "depth", "alpha"):
+        assert np.array_equal(to_np(a[k]), to_np(b[k])), k
+
+
+def test_config2_full_parity(hg, oracle_mod):
+    """1M Gaussians (SH3, 32-d features), 1920x1080: every pixel against the
+    oracle; bf16 feature output within bf16 rounding of the FP32 one."""
+    sc, P, cam = synth.config2(0)
+    log("case: config2 1080p fp32 features")
+    out, r = _render(hg, sc, P, cam, tile=16)
+    log("stats", r.stats())
+    ref = oracle_mod.render(sc, P[0], cam, tile=16, margin=1)
+    log("oracle stats", ref["stats"])
+    parity(out, ref, label="config2")
+    log("case: config2 bf16 features")
+    ob, _ = _render(hg, sc, P, cam, tile=16, feat_bf16=True)
+    f32 = to_np(out["feat"][0])
+    fb = to_np(ob["feat"][0])
+    assert np.all(np.abs(fb - f32) <= np.abs(f32) * 2.0 ** -8 + 1e-30)
