@@ -38,7 +38,8 @@ class _Scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
                 ("quats", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p),
                 ("sh_degree", ctypes.c_int32), ("feat_dim", ctypes.c_int32), ("feat", ctypes.c_void_p),
-                ("means64", ctypes.c_void_p), ("opac64", ctypes.c_void_p)]
+                ("means64", ctypes.c_void_p), ("opac64", ctypes.c_void_p), ("log_scales64", ctypes.c_void_p),
+                ("quats64", ctypes.c_void_p), ("sh64", ctypes.c_void_p), ("feat64", ctypes.c_void_p)]
 
 
 class _Camera(ctypes.Structure):
@@ -74,10 +75,11 @@ def _ptr(a: Optional[np.ndarray]):
 class _Bound:
     """Keeps the numpy arrays referenced by a ctypes struct alive."""
 
-    def __init__(self, scene, cam, near=0.2, bg=(0.0, 0.0, 0.0), means64=None, opac64=None):
+    def __init__(self, scene, cam, near=0.2, bg=(0.0, 0.0, 0.0), overrides=None):
         c = lambda a, dt: np.ascontiguousarray(a, dtype=dt)
-        self.m64 = None if means64 is None else c(means64, np.float64)
-        self.o64 = None if opac64 is None else c(opac64, np.float64)
+        ov = overrides or {}
+        self.ov = {k: c(ov[k], np.float64) for k in ("means", "opacities", "log_scales", "quats", "sh", "feat")
+                   if ov.get(k) is not None}
         self.arrays = [c(scene.means, np.float32), c(scene.log_scales, np.float32), c(scene.quats, np.float32),
                        c(scene.opacities, np.float32), c(scene.sh, np.float32)]
         self.feat = None if scene.feat is None else c(scene.feat, np.uint16)
@@ -85,8 +87,8 @@ class _Bound:
         self.s = _Scene(scene.means.shape[0], m.ctypes.data, ls.ctypes.data, q.ctypes.data, o.ctypes.data,
                         sh.ctypes.data, scene.sh_degree, 0 if self.feat is None else self.feat.shape[1],
                         None if self.feat is None else self.feat.ctypes.data,
-                        None if self.m64 is None else self.m64.ctypes.data,
-                        None if self.o64 is None else self.o64.ctypes.data)
+                        *[self.ov[k].ctypes.data if k in self.ov else None
+                          for k in ("means", "opacities", "log_scales", "quats", "sh", "feat")])
         self.c = _Camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, near,
                          (ctypes.c_double * 3)(*bg))
 
@@ -138,13 +140,13 @@ def render(scene, pose, cam, mode: str = "tiled", tile: int = 16, margin: int = 
                 lists=lists)
 
 
-def render_frozen(scene, pose, cam, lists, counts, near=0.2, bg=(0.0, 0.0, 0.0), means64=None,
-                  opac64=None) -> dict:
+def render_frozen(scene, pose, cam, lists, counts, near=0.2, bg=(0.0, 0.0, 0.0), overrides=None) -> dict:
     """Re-render with the per-pixel blend lists of a reference render held
     fixed (no gate, no stop): the smooth branch used for finite differences.
-    means64/opac64 optionally replace the float32 means/opacities."""
+    overrides: optional dict of float64 arrays replacing the scene's means,
+    opacities, log_scales, quats, sh or feat (feat as values, not bf16 bits)."""
     lib = _load()
-    b = _Bound(scene, cam, near, bg, means64, opac64)
+    b = _Bound(scene, cam, near, bg, overrides)
     H, W, D = cam.height, cam.width, b.s.feat_dim
     lists = np.ascontiguousarray(lists, dtype=np.int32)
     counts = np.ascontiguousarray(counts, dtype=np.int32).reshape(-1)

@@ -62,8 +62,14 @@ typedef struct {
   int32_t sh_degree;
   int32_t feat_dim;
   const uint16_t* feat;     // n x feat_dim bf16 bits (may be null when feat_dim == 0)
-  const double* means64;    // optional double-precision means (finite differences)
-  const double* opac64;     // optional double-precision opacities (finite differences)
+  // optional double-precision replacements of the float32 arrays (finite
+  // differences); each may be null
+  const double* means64;
+  const double* opac64;
+  const double* log_scales64;
+  const double* quats64;
+  const double* sh64;
+  const double* feat64;
 } orc_scene;
 
 typedef struct {
@@ -175,15 +181,20 @@ Proj project(const orc_scene& s, int64_t i, const Pose& P, const orc_camera& cam
     for (int k = 0; k < 3; ++k) m[k] = s.means[3 * i + k];
   }
   // 1. covariance in the world frame
-  const float* qf = s.quats + 4 * i;
-  double qw = qf[0], qx = qf[1], qy = qf[2], qz = qf[3];
+  double qw, qx, qy, qz;
+  if (s.quats64) {
+    qw = s.quats64[4 * i]; qx = s.quats64[4 * i + 1]; qy = s.quats64[4 * i + 2]; qz = s.quats64[4 * i + 3];
+  } else {
+    qw = s.quats[4 * i]; qx = s.quats[4 * i + 1]; qy = s.quats[4 * i + 2]; qz = s.quats[4 * i + 3];
+  }
   const double qn = std::sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw /= qn; qx /= qn; qy /= qn; qz /= qn;
   const double Rq[3][3] = {
       {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
       {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
       {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  const float* ls = s.log_scales + 3 * i;
+  double ls[3];
+  for (int k = 0; k < 3; ++k) ls[k] = s.log_scales64 ? s.log_scales64[3 * i + k] : s.log_scales[3 * i + k];
   const double s2[3] = {std::exp(2.0 * ls[0]), std::exp(2.0 * ls[1]), std::exp(2.0 * ls[2])};
   double Sw[3][3];
   for (int a = 0; a < 3; ++a)
@@ -240,13 +251,14 @@ Proj project(const orc_scene& s, int64_t i, const Pose& P, const orc_camera& cam
   const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   d[0] /= dn; d[1] /= dn; d[2] /= dn;
   const int K = (s.sh_degree + 1) * (s.sh_degree + 1);
-  const float* sh = s.sh + static_cast<int64_t>(K) * 3 * i;
+  const int64_t shb = static_cast<int64_t>(K) * 3 * i;
   for (int c = 0; c < 3; ++c) g.rgb[c] = 0.5;
   for (int l = 0; l <= s.sh_degree; ++l)
     for (int mm = -l; mm <= l; ++mm) {
       const double y = real_sh(l, mm, d);
       const int k = l * l + l + mm;
-      for (int c = 0; c < 3; ++c) g.rgb[c] += sh[3 * k + c] * y;
+      for (int c = 0; c < 3; ++c)
+        g.rgb[c] += (s.sh64 ? s.sh64[shb + 3 * k + c] : static_cast<double>(s.sh[shb + 3 * k + c])) * y;
     }
   for (int c = 0; c < 3; ++c) g.rgb[c] = std::max(0.0, g.rgb[c]);
   // 7. support rectangle
@@ -348,8 +360,8 @@ int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<
     for (int c = 0; c < 3; ++c) C[c] += w * g.rgb[c];
     Z += w * g.z;
     if (D) {
-      const uint16_t* f = s.feat + static_cast<int64_t>(D) * gi;
-      for (int k = 0; k < D; ++k) feat_out[k] += w * bf16_to_double(f[k]);
+      const int64_t fb = static_cast<int64_t>(D) * gi;
+      for (int k = 0; k < D; ++k) feat_out[k] += w * (s.feat64 ? s.feat64[fb + k] : bf16_to_double(s.feat[fb + k]));
     }
     T = Tn;
     if (list_out) {
@@ -531,8 +543,8 @@ int orc_render_frozen(const orc_scene* s, const double* pose, const orc_camera* 
         for (int c = 0; c < 3; ++c) C[c] += w * g.rgb[c];
         Z += w * g.z;
         if (D) {
-          const uint16_t* f = s->feat + static_cast<int64_t>(D) * gi;
-          for (int j = 0; j < D; ++j) F[j] += w * bf16_to_double(f[j]);
+          const int64_t fb = static_cast<int64_t>(D) * gi;
+          for (int j = 0; j < D; ++j) F[j] += w * (s->feat64 ? s->feat64[fb + j] : bf16_to_double(s->feat[fb + j]));
         }
         T *= (1.0 - a);
       }

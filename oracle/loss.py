@@ -34,6 +34,27 @@ def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0) -> float:
     return float((l1 + lam_f * (1.0 - cos).sum()) / (H * W))
 
 
+def residual_frozen_signs(rgb_ref, rgb_t, feat_t, lam_f=1.0):
+    """The residual with the sign pattern of |rgb - rgb*| taken at a reference
+    render and held fixed: the smooth piece of the L1 term that contains the
+    reference point (what its gradient sign(rgb - rgb*) differentiates).
+    Returns loss_fn(out) for finite differences."""
+    sgn = np.sign(rgb_ref - rgb_t)
+
+    def loss(out):
+        H, W = out["rgb"].shape[1:]
+        l1 = (sgn * (out["rgb"] - rgb_t)).sum()
+        if out.get("feat") is None or lam_f == 0.0:
+            return float(l1 / (H * W))
+        f = out["feat"]
+        dot = (f * feat_t).sum(axis=0)
+        na = np.sqrt((f * f).sum(axis=0))
+        nb = np.sqrt((feat_t * feat_t).sum(axis=0))
+        return float((l1 + lam_f * (1.0 - dot / (na * nb + COS_EPS)).sum()) / (H * W))
+
+    return loss
+
+
 def residual_grad(rgb, feat, rgb_t, feat_t, lam_f=1.0):
     """Closed-form dL/d rgb (3,H,W) and dL/d feat (D,H,W)."""
     H, W = rgb.shape[1:]
@@ -56,16 +77,24 @@ def linear_functional(out, weights) -> float:
     return float(sum((out[k] * w).sum() for k, w in weights.items()))
 
 
-def fd_gradients(scene, pose, cam, loss_fn, h=1e-4, gauss_ids=(), tile=16, list_cap=512):
+def _param64(scene, name):
+    if name == "feat":
+        return (np.asarray(scene.feat, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+    return np.asarray(getattr(scene, name), dtype=np.float64)
+
+
+def fd_gradients(scene, pose, cam, loss_fn, h=1e-4, gauss_ids=(), params=("means", "opacities"), tile=16,
+                 list_cap=512, bg=(0.0, 0.0, 0.0)):
     """Central differences of loss_fn(frozen render) with respect to the 6
     left-perturbation pose coordinates (rho, phi) and, for each id in
-    gauss_ids, the 3 mean coordinates and the opacity.  Returns (g_pose (6,),
-    g_means (k,3), g_opac (k,), reference render)."""
-    ref = render(scene, pose, cam, mode="tiled", tile=tile, want_lists=True, list_cap=list_cap)
+    gauss_ids, every component of each named Gaussian parameter.  Returns
+    (g_pose (6,), {param: (k, ...) array}, reference render)."""
+    ref = render(scene, pose, cam, mode="tiled", tile=tile, bg=bg, want_lists=True, list_cap=list_cap)
     lists, counts = ref["lists"], ref["nblend"]
+    base = {p: _param64(scene, p) for p in params}
 
-    def L(pose12, means64=None, opac64=None):
-        out = render_frozen(scene, pose12, cam, lists, counts, means64=means64, opac64=opac64)
+    def L(pose12, overrides=None):
+        out = render_frozen(scene, pose12, cam, lists, counts, bg=bg, overrides=overrides)
         return loss_fn(out)
 
     g_pose = np.zeros(6)
@@ -74,17 +103,17 @@ def fd_gradients(scene, pose, cam, loss_fn, h=1e-4, gauss_ids=(), tile=16, list_
         e[k] = h
         g_pose[k] = (L(left_perturb(pose, e)) - L(left_perturb(pose, -e))) / (2 * h)
     ids = list(gauss_ids)
-    g_means = np.zeros((len(ids), 3))
-    g_opac = np.zeros(len(ids))
-    if ids:
-        m0 = scene.means.astype(np.float64)
-        o0 = scene.opacities.astype(np.float64)
+    out = {}
+    for p in params:
+        arr = base[p]
+        per = arr[0].shape if arr.ndim > 1 else ()
+        g = np.zeros((len(ids),) + per)
         for j, i in enumerate(ids):
-            for a in range(3):
-                mp = m0.copy(); mp[i, a] += h
-                mm = m0.copy(); mm[i, a] -= h
-                g_means[j, a] = (L(pose, means64=mp, opac64=o0) - L(pose, means64=mm, opac64=o0)) / (2 * h)
-            op = o0.copy(); op[i] += h
-            om = o0.copy(); om[i] -= h
-            g_opac[j] = (L(pose, means64=m0, opac64=op) - L(pose, means64=m0, opac64=om)) / (2 * h)
-    return g_pose, g_means, g_opac, ref
+            for comp in np.ndindex(*per) if per else [()]:
+                plus = arr.copy()
+                minus = arr.copy()
+                plus[(i,) + comp] += h
+                minus[(i,) + comp] -= h
+                g[(j,) + comp] = (L(pose, {p: plus}) - L(pose, {p: minus})) / (2 * h)
+        out[p] = g
+    return g_pose, out, ref

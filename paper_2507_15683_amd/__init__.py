@@ -203,19 +203,25 @@ class Renderer:
                                              _stream_ptr(stream)), "hgsr_debug_tile_lists")
         return ranges, gids[: n.value]
 
-    def backward(self, grad_out: dict, want=("pose", "means", "opacities"), P: Optional[int] = None,
-                 scene: Optional[GaussianScene] = None, stream=None) -> dict:
-        """Gradients of the last render given dL/d{rgb, depth, alpha, feat}
-        (device FP32 tensors; missing keys mean zero).  `want` names the
-        gradients to compute among pose, means, opacities, log_scales, quats,
-        sh, feat.  Returns a dict of device tensors."""
-        scene = scene if scene is not None else self._keep[0]
-        P = P if P is not None else self._keep[1].shape[0]
+    @staticmethod
+    def alloc_grads(scene: GaussianScene, P: int, want=("pose", "means", "opacities")) -> dict:
         dev = scene.means.device
         n, D, K = scene.n, scene.feat_dim, (scene.sh_degree + 1) ** 2
         shapes = dict(pose=(P, 6), means=(n, 3), opacities=(n,), log_scales=(n, 3), quats=(n, 4), sh=(n, K, 3),
                       feat=(n, D))
-        grads = {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in want}
+        return {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in want}
+
+    def backward(self, grad_out: dict, want=("pose", "means", "opacities"), P: Optional[int] = None,
+                 scene: Optional[GaussianScene] = None, grads: Optional[dict] = None, stream=None) -> dict:
+        """Gradients of the last render given dL/d{rgb, depth, alpha, feat}
+        (device FP32 tensors; missing keys mean zero).  `want` names the
+        gradients to compute among pose, means, opacities, log_scales, quats,
+        sh, feat; `grads` may supply preallocated outputs (required under
+        graph capture).  Returns the dict of device tensors."""
+        scene = scene if scene is not None else self._keep[0]
+        P = P if P is not None else self._keep[1].shape[0]
+        if grads is None:
+            grads = self.alloc_grads(scene, P, want)
         go = _lib.GradOutputs(*[_ptr(_f32(grad_out.get(k))) for k in ("rgb", "depth", "alpha", "feat")])
         gr = _lib.Grads(*[_ptr(grads.get(k)) for k in ("pose", "means", "opacities", "log_scales", "quats", "sh",
                                                       "feat")])
@@ -314,14 +320,18 @@ def render_differentiable(renderer: Renderer, scene: GaussianScene, poses: torch
     return _RenderFn.apply(xi, scene.means, scene.opacities, renderer, scene, poses, K, kw)
 
 
-def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0, stream=None):
-    """Per-pose refinement residual and its gradients (HIP kernel)."""
+def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0, out=None, stream=None):
+    """Per-pose refinement residual and its gradients (HIP kernel).  `out` may
+    supply preallocated (loss, g_rgb, g_feat) (required under graph capture)."""
     lib = _lib.load()
     P, _, H, W = rgb.shape
     D = 0 if feat is None else feat.shape[1]
-    loss = torch.empty(P, dtype=torch.float32, device=rgb.device)
-    g_rgb = torch.empty_like(rgb)
-    g_feat = torch.empty((P, D, H, W), dtype=torch.float32, device=rgb.device) if D else None
+    if out is None:
+        loss = torch.empty(P, dtype=torch.float32, device=rgb.device)
+        g_rgb = torch.empty_like(rgb)
+        g_feat = torch.empty((P, D, H, W), dtype=torch.float32, device=rgb.device) if D else None
+    else:
+        loss, g_rgb, g_feat = out
     check(lib.hgsr_residual(_ptr(rgb), _ptr(feat), int(feat is not None and feat.dtype == torch.bfloat16),
                             _ptr(rgb_t), _ptr(feat_t), P, H, W, D, lam_f, _ptr(loss), _ptr(g_rgb), _ptr(g_feat),
                             _stream_ptr(stream)), "hgsr_residual")

@@ -5,6 +5,8 @@
 //           (depth bits << 32 | index) keys are sorted in LDS;
 //   lsd:    a device least-significant-digit radix sort of
 //           (tile, depth, index) keys, 8-bit digits, stable passes.
+#include <algorithm>
+
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -22,6 +24,17 @@ __global__ void fill_f32_kernel(float* p, float v, int64_t n) {
     p[i] = v;
 }
 
+// Zero up to four u32 ranges in one launch.
+__global__ void clear4_kernel(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
+                              uint32_t* p3, int64_t n3) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = t; i < n0; i += stride) p0[i] = 0u;
+  for (int64_t i = t; i < n1; i += stride) p1[i] = 0u;
+  for (int64_t i = t; i < n2; i += stride) p2[i] = 0u;
+  for (int64_t i = t; i < n3; i += stride) p3[i] = 0u;
+}
+
 static unsigned fill_grid(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -31,6 +44,12 @@ static unsigned fill_grid(int64_t n) {
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, value, n);
 }
+void launch_clear4(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2, uint32_t* p3,
+                   int64_t n3, hipStream_t s) {
+  const int64_t mx = std::max(std::max(n0, n1), std::max(n2, n3));
+  hipLaunchKernelGGL(clear4_kernel, dim3(fill_grid(mx)), dim3(256), 0, s, p0, n0, p1, n1, p2, n2, p3, n3);
+}
+
 void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(fill_f32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, value, n);
 }
@@ -139,12 +158,59 @@ __global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t* in, int6
   }
 }
 
+// Whole scan in one block, chunk after chunk (small inputs).
+__global__ __launch_bounds__(256) void scan_single_kernel(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges,
+                                                          uint32_t* total, uint64_t cap, int32_t* flags,
+                                                          int32_t flag_bit) {
+  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_v[kScanChunk];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += kScanChunk) {
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
+      s_v[k * 256 + threadIdx.x] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t vals[kScanItems];
+    uint32_t sum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+      vals[k] = s_v[threadIdx.x * kScanItems + k];
+      sum += vals[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan256(sum, s_w, &tot) + carry;
+    for (int k = 0; k < kScanItems; ++k) {
+      s_v[threadIdx.x * kScanItems + k] = run;
+      run += vals[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
+      if (i < n) {
+        const uint32_t st = s_v[k * 256 + threadIdx.x];
+        if (ranges) ranges[i] = make_uint2(st, st + in[i]);
+        else out[i] = st;
+      }
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (total) *total = carry;
+    if (flags && static_cast<uint64_t>(carry) > cap) atomicOr(flags, flag_bit);
+  }
+}
+
 int64_t scan_block_count(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 
 void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s) {
   const int64_t nb = scan_block_count(n);
   if (nb == 0) return;
+  if (nb <= 16) {
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(256), 0, s, in, n, out, ranges, total, cap, flags, flag_bit);
+    return;
+  }
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, block_sums);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(256), 0, s, block_sums, nb, total, cap, flags, flag_bit);
   hipLaunchKernelGGL(scan_down_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, block_sums, out,
@@ -152,11 +218,15 @@ void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, ui
 }
 
 // ------------------------------------------------------------ bucket path
-// One thread per record: claim a slot in each overlapped tile's bucket.
+// Four threads per record, each claiming slots in every fourth overlapped
+// tile's bucket (enough waves in flight to hide the atomics' latency).
+constexpr int kEmitLanes = 4;
+
 __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   if (a.flags[0] & 1) return;
   const int pose = blockIdx.y;
-  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t slot = t / kEmitLanes, sub = t % kEmitLanes;
   const uint32_t cnt = min(a.pose_count[pose], a.rec_cap);
   if (slot >= cnt) return;
   const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
@@ -164,24 +234,103 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];  // cc, o, z, gid
   const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
   const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+  const int nx = tx1 - tx0 + 1, ntl = nx * (ty1 - ty0 + 1);
   const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const int64_t tg = tbase + ty * a.c.ntx + tx;
-      const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
-      if (pos < a.key_cap) {
-        a.keys[pos] = key;
-        a.vals[pos] = static_cast<uint32_t>(idx);
-      }
+  for (int q = static_cast<int>(sub); q < ntl; q += kEmitLanes) {
+    const int ty = ty0 + q / nx, tx = tx0 + q % nx;
+    const int64_t tg = tbase + ty * a.c.ntx + tx;
+    const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
+    if (pos < a.key_cap) {
+      a.keys[pos] = key;
+      a.vals[pos] = static_cast<uint32_t>(idx);
     }
+  }
 }
 
 void launch_emit_bucket(const BinArgs& a, hipStream_t s) {
-  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+  const dim3 grid((a.rec_cap * kEmitLanes + 255) / 256, a.P);
   hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
 }
 
-// Per-tile sort in LDS: bitonic network on (depth bits, gid) keys.
+// Short lists (<= 256 entries): one wave per tile, 4 keys per lane, a
+// bitonic network in registers (partners across lanes by shuffle, across the
+// lane's 4 registers by swap); no block barriers.  4 tiles per workgroup.
+constexpr int kWaveSortCap = 256;
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), m, kWave);
+  const uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), m, kWave);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
+  if (a.flags[0] & 3) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tg >= a.n_tiles) return;
+  const uint2 r = a.ranges[tg];
+  const uint32_t n = r.y - r.x;
+  if (n <= 1 || n > static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) {
+    if (n == 1 && lane == 0) a.list[r.x] = a.vals[r.x];
+    return;
+  }
+  int R = 1;
+  while (R * kWave < static_cast<int>(n)) R <<= 1;  // 1, 2 or 4 registers
+  const uint32_t m = static_cast<uint32_t>(R) * kWave;
+  uint64_t key[4];
+  uint32_t val[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t e = q * kWave + lane;
+    key[q] = ~0ull;
+    val[q] = 0;
+    if (q < R && e < n) {
+      key[q] = a.keys[r.x + e];
+      val[q] = a.vals[r.x + e];
+    }
+  }
+  for (uint32_t k = 2; k <= m; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= kWave) {
+        const int rj = static_cast<int>(j / kWave);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int q2 = q ^ rj;
+          if (q >= R || q2 <= q) continue;
+          const uint32_t e = q * kWave + lane;
+          const bool up = (e & k) == 0;
+          if ((key[q] > key[q2]) == up) {
+            const uint64_t tk = key[q]; key[q] = key[q2]; key[q2] = tk;
+            const uint32_t tv = val[q]; val[q] = val[q2]; val[q2] = tv;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q >= R) continue;
+          const uint64_t ok = shfl_xor_u64(key[q], static_cast<int>(j));
+          const uint32_t ov = __shfl_xor(val[q], static_cast<int>(j), kWave);
+          const uint32_t e = q * kWave + lane;
+          const bool up = (e & k) == 0;
+          const bool lower = (e & j) == 0;
+          const bool take = lower == up ? (ok < key[q]) : (ok > key[q]);
+          if (take) {
+            key[q] = ok;
+            val[q] = ov;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t e = q * kWave + lane;
+    if (q < R && e < n) a.list[r.x + e] = val[q];
+  }
+}
+
+// Medium lists (256 < n <= LDS capacity): the workgroup runs a bitonic
+// network on (depth bits, gid) keys in LDS.
 constexpr int kLdsSortCap = 4096;
 
 __global__ __launch_bounds__(256) void tile_sort_kernel(TileSortArgs a) {
@@ -191,10 +340,7 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(TileSortArgs a) {
   const int tg = blockIdx.x;
   const uint2 r = a.ranges[tg];
   const uint32_t n = r.y - r.x;
-  if (n <= 1 || n > static_cast<uint32_t>(a.lds_cap)) {
-    if (n == 1 && threadIdx.x == 0) a.list[r.x] = a.vals[r.x];
-    return;
-  }
+  if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap)) || n > static_cast<uint32_t>(a.lds_cap)) return;
   uint32_t m = 2;
   while (m < n) m <<= 1;
   for (uint32_t k = threadIdx.x; k < m; k += 256) {
@@ -309,6 +455,7 @@ __global__ __launch_bounds__(256) void tile_sort_big_kernel(TileSortArgs a) {
 
 void launch_tile_sort(const TileSortArgs& a, hipStream_t s) {
   if (a.n_tiles <= 0) return;
+  hipLaunchKernelGGL(tile_sort_wave_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a);
   hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
   hipLaunchKernelGGL(tile_sort_big_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
 }

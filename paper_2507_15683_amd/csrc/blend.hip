@@ -1,13 +1,16 @@
 // Front-to-back alpha blend, one workgroup per (pose, tile).
 //
-// Each workgroup walks its tile's depth-ordered list in batches: every thread
-// stages one splat (geometry, colour and bf16 feature vector) into LDS, then
-// every thread runs its pixel(s) through the whole batch, reading each splat
-// as an LDS broadcast.  A pixel stops at the first splat that would take its
-// transmittance below 1e-4; the batch loop ends as soon as every pixel of the
-// tile has stopped (__syncthreads_and).  Colour, depth and the D feature
-// channels accumulate in FP32 registers.  Outputs are planar per pose, so a
-// wave's stores of one channel are contiguous row segments.
+// Each wave owns a square block of the tile (8x8 pixels at tile 8 and 16,
+// 16x16 at tile 32 with 4 pixels per lane).  The workgroup walks the tile's
+// depth-ordered list in batches: every thread stages one splat (geometry,
+// colour, FP32 feature vector) into LDS and marks which waves' blocks its
+// support rectangle touches; each wave then compacts the batch to the entries
+// that touch its block and runs its pixels through them, reading each splat
+// as an LDS broadcast.  Pairs whose exponent is clearly below the 1/255 gate
+// are rejected before the exponential; the exact gate, clamp and stop tests
+// follow.  A pixel stops at the first splat that would take its transmittance
+// below 1e-4; the batch loop ends when every pixel of the tile has stopped.
+// Outputs are planar per pose.
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -16,21 +19,42 @@ namespace hgsr {
 template <int TILE>
 struct BlendShape {
   static constexpr int kThreads = TILE == 8 ? 64 : 256;
-  static constexpr int kPPT = TILE * TILE / kThreads;  // pixels per thread
+  static constexpr int kWaves = kThreads / kWave;
+  static constexpr int kBlock = TILE == 32 ? 16 : 8;       // side of a wave's pixel block
+  static constexpr int kPPT = kBlock * kBlock / kWave;     // pixels per lane
+  static constexpr int kBlocksX = TILE / kBlock;
 };
+
+// Pixel-centre rectangle of a splat's support, padded; shared by the wave
+// culling of the forward and backward blends.
+__device__ __forceinline__ void splat_rect(const float4 geo, const float4 opz, float pmin, float& x0, float& x1,
+                                           float& y0, float& y1) {
+  const float det = geo.z * opz.x - geo.w * geo.w;
+  const float k2 = -2.f * pmin;
+  const float rx = 1.001f * sqrtf(fmaxf(k2 * opz.x / det, 0.f)) + 0.05f;
+  const float ry = 1.001f * sqrtf(fmaxf(k2 * geo.z / det, 0.f)) + 0.05f;
+  x0 = geo.x - rx - 0.5f;
+  x1 = geo.x + rx - 0.5f;
+  y0 = geo.y - ry - 0.5f;
+  y1 = geo.y + ry - 0.5f;
+}
 
 template <int TILE, int D, bool BF16>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
-  constexpr int NT = BlendShape<TILE>::kThreads;
-  constexpr int PPT = BlendShape<TILE>::kPPT;
-  constexpr int DV = D / 8;  // 16-byte vectors per feature
+  using S = BlendShape<TILE>;
+  constexpr int NT = S::kThreads, NW = S::kWaves, B = S::kBlock, PPT = S::kPPT;
+  constexpr bool LDS_F32 = D > 0 && D <= 32;            // features as FP32 in LDS
+  constexpr int FW = D == 0 ? 1 : (LDS_F32 ? D : D / 2);  // 32-bit words per feature vector
   __shared__ float4 s_geo[NT];
   __shared__ float4 s_opz[NT];
   __shared__ float4 s_col[NT];
-  __shared__ uint4 s_feat[DV > 0 ? NT * DV : 1];
+  __shared__ uint32_t s_fw[NT * FW];
+  __shared__ uint8_t s_mask[NT];
+  __shared__ uint16_t s_list[NW][NT];
   __shared__ int s_item;
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int W = a.c.W, H = a.c.H;
   const int64_t HW = static_cast<int64_t>(W) * H;
   const bool persistent = a.schedule != kSchedGrid;
@@ -57,6 +81,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     }
     const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;
     const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
+    // this wave's pixel block
+    const int bx0 = tx * TILE + (wave % S::kBlocksX) * B, by0 = ty * TILE + (wave / S::kBlocksX) * B;
 
     float pxf[PPT], pyf[PPT], T[PPT], C[PPT][3], Z[PPT];
     float F[PPT][D > 0 ? D : 1];
@@ -65,8 +91,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     int pix[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      const int li = tid + k * NT;
-      const int px = tx * TILE + (li % TILE), py = ty * TILE + (li / TILE);
+      const int li = lane + k * kWave;
+      const int px = bx0 + (li % B), py = by0 + (li / B);
       inside[k] = px < W && py < H;
       pix[k] = py * W + px;
       pxf[k] = static_cast<float>(px) + 0.5f;
@@ -93,27 +119,61 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
         s_geo[tid] = g0;
         s_opz[tid] = g1;
         s_col[tid] = g2;
-        if constexpr (DV > 0) {
-          const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(__float_as_uint(g1.w)) * DV;
+        float x0, x1, y0, y1;
+        splat_rect(g0, g1, g2.w, x0, x1, y0, y1);
+        uint8_t m = 0;
 #pragma unroll
-          for (int q = 0; q < DV; ++q) s_feat[tid * DV + q] = fv[q];
+        for (int w = 0; w < NW; ++w) {
+          const float wx0 = static_cast<float>(tx * TILE + (w % S::kBlocksX) * B);
+          const float wy0 = static_cast<float>(ty * TILE + (w / S::kBlocksX) * B);
+          if (x1 >= wx0 && x0 <= wx0 + (B - 1) && y1 >= wy0 && y0 <= wy0 + (B - 1)) m |= 1u << w;
         }
+        s_mask[tid] = m;
+        if constexpr (D > 0) {
+          const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(__float_as_uint(g1.w)) * (D / 8);
+          if constexpr (LDS_F32) {
+#pragma unroll
+            for (int q = 0; q < D / 8; ++q) {
+              const uint4 f = fv[q];
+              uint4* dst = reinterpret_cast<uint4*>(&s_fw[tid * FW + 8 * q]);
+              dst[0] = make_uint4(f.x << 16, f.x & 0xffff0000u, f.y << 16, f.y & 0xffff0000u);
+              dst[1] = make_uint4(f.z << 16, f.z & 0xffff0000u, f.w << 16, f.w & 0xffff0000u);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < D / 8; ++q) reinterpret_cast<uint4*>(&s_fw[tid * FW])[q] = fv[q];
+          }
+        }
+      } else {
+        s_mask[tid] = 0;
       }
       __syncthreads();
       const int nb = static_cast<int>(min(static_cast<uint32_t>(NT), range.y - b0));
-      for (int jj = 0; jj < nb; ++jj) {
+      // compact the batch to the entries touching this wave's block (in order)
+      int n_mine = 0;
+      for (int c0 = 0; c0 < nb; c0 += kWave) {
+        const int e = c0 + lane;
+        const bool hit = e < nb && ((s_mask[e] >> wave) & 1u);
+        const uint64_t bal = __ballot(hit);
+        if (hit) s_list[wave][n_mine + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(e);
+        n_mine += __popcll(bal);
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int ii = 0; ii < n_mine; ++ii) {
         bool mine = true;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) mine &= done[k];
         if (mine) break;
+        const int jj = s_list[wave][ii];
         const float4 geo = s_geo[jj];
         const float4 opz = s_opz[jj];
+        const float pmin = s_col[jj].w;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           if (done[k]) continue;
           const float dx = pxf[k] - geo.x, dy = pyf[k] - geo.y;
           const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
-          if (power > 0.f) continue;
+          if (power > 0.f || power < pmin - kPreReject) continue;
           const float alpha = pair_alpha(opz.y, power);
           if (alpha < kAlphaMin) continue;
           const float Tn = T[k] * (1.f - alpha);
@@ -127,18 +187,31 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
           C[k][1] = fmaf(w, col.y, C[k][1]);
           C[k][2] = fmaf(w, col.z, C[k][2]);
           Z[k] = fmaf(w, opz.z, Z[k]);
-          if constexpr (DV > 0) {
+          if constexpr (D > 0) {
+            if constexpr (LDS_F32) {
+              const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FW]);
 #pragma unroll
-            for (int q = 0; q < DV; ++q) {
-              const uint4 fq = s_feat[jj * DV + q];
-              F[k][8 * q + 0] = fmaf(w, bf16_lo(fq.x), F[k][8 * q + 0]);
-              F[k][8 * q + 1] = fmaf(w, bf16_hi(fq.x), F[k][8 * q + 1]);
-              F[k][8 * q + 2] = fmaf(w, bf16_lo(fq.y), F[k][8 * q + 2]);
-              F[k][8 * q + 3] = fmaf(w, bf16_hi(fq.y), F[k][8 * q + 3]);
-              F[k][8 * q + 4] = fmaf(w, bf16_lo(fq.z), F[k][8 * q + 4]);
-              F[k][8 * q + 5] = fmaf(w, bf16_hi(fq.z), F[k][8 * q + 5]);
-              F[k][8 * q + 6] = fmaf(w, bf16_lo(fq.w), F[k][8 * q + 6]);
-              F[k][8 * q + 7] = fmaf(w, bf16_hi(fq.w), F[k][8 * q + 7]);
+              for (int q = 0; q < D / 4; ++q) {
+                const float4 f = fq[q];
+                F[k][4 * q + 0] = fmaf(w, f.x, F[k][4 * q + 0]);
+                F[k][4 * q + 1] = fmaf(w, f.y, F[k][4 * q + 1]);
+                F[k][4 * q + 2] = fmaf(w, f.z, F[k][4 * q + 2]);
+                F[k][4 * q + 3] = fmaf(w, f.w, F[k][4 * q + 3]);
+              }
+            } else {
+              const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FW]);
+#pragma unroll
+              for (int q = 0; q < D / 8; ++q) {
+                const uint4 f = fq[q];
+                F[k][8 * q + 0] = fmaf(w, bf16_lo(f.x), F[k][8 * q + 0]);
+                F[k][8 * q + 1] = fmaf(w, bf16_hi(f.x), F[k][8 * q + 1]);
+                F[k][8 * q + 2] = fmaf(w, bf16_lo(f.y), F[k][8 * q + 2]);
+                F[k][8 * q + 3] = fmaf(w, bf16_hi(f.y), F[k][8 * q + 3]);
+                F[k][8 * q + 4] = fmaf(w, bf16_lo(f.z), F[k][8 * q + 4]);
+                F[k][8 * q + 5] = fmaf(w, bf16_hi(f.z), F[k][8 * q + 5]);
+                F[k][8 * q + 6] = fmaf(w, bf16_lo(f.w), F[k][8 * q + 6]);
+                F[k][8 * q + 7] = fmaf(w, bf16_hi(f.w), F[k][8 * q + 7]);
+              }
             }
           }
           T[k] = Tn;

@@ -15,6 +15,7 @@ constexpr float kTMin = 1e-4f;              // transmittance stop
 constexpr float kDilation = 0.3f;           // screen-space low-pass, px^2
 constexpr float kGuard = 1.3f;              // Jacobian guard band, x field of view
 constexpr float kRectPad = 5e-4f;           // support rectangle padding, px
+constexpr float kPreReject = 1e-3f;         // exponent margin below the gate for the early reject
 constexpr int kMaxPoses = 64;               // poses per projection launch
 constexpr int kWave = 64;
 
@@ -28,7 +29,7 @@ struct alignas(16) Splat {
   float cc, o, z;       // conic c, opacity, camera z
   uint32_t gid;         // Gaussian index
   float r, g, b;        // colour
-  uint32_t pose;        // pose index
+  float pmin;           // -ln(255 o): exponent at which o e^power = 1/255
 };
 
 struct GaussArgs {

@@ -344,15 +344,14 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
   const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
 
-  // clear flags and counters (fill kernels, so the sequence can be captured)
-  launch_fill_u32(reinterpret_cast<uint32_t*>(misc), 0u, 3, s);
-  launch_fill_u32(pose_count, 0u, P, s);
-  if (!lsd) {
-    launch_fill_u32(c->tile_count.as<uint32_t>(), 0u, ntile, s);
-    launch_fill_u32(c->tile_cursor.as<uint32_t>(), 0u, ntile, s);
-  } else {
-    launch_fill_u32(c->rec_keys.as<uint32_t>(), 0u, nrec, s);
-  }
+  // clear flags and counters (a kernel, not a memset, so the sequence can be
+  // captured and replayed)
+  if (!lsd)
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, P, c->tile_count.as<uint32_t>(), ntile,
+                  c->tile_cursor.as<uint32_t>(), ntile, s);
+  else
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, P, c->rec_keys.as<uint32_t>(), nrec, nullptr, 0,
+                  s);
 
   hipEvent_t e0 = stamp(c, s);
   const GaussArgs ga = make_gauss(*g);

@@ -134,6 +134,8 @@ void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s);
 // binning.hip
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
+void launch_clear4(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2, uint32_t* p3,
+                   int64_t n3, hipStream_t s);
 int64_t scan_block_count(int64_t n);
 void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s);

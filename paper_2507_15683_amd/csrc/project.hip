@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
     sp.cc = f.cc; sp.o = o; sp.z = mc[2]; sp.gid = static_cast<uint32_t>(i);
     sp.r = fmaxf(rgb[0], 0.f); sp.g = fmaxf(rgb[1], 0.f); sp.b = fmaxf(rgb[2], 0.f);
-    sp.pose = static_cast<uint32_t>(pg);
+    sp.pmin = -0.5f * k2;
     float4* dst = reinterpret_cast<float4*>(a.recs + idx);
     const float4* src = reinterpret_cast<const float4*>(&sp);
     dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];

@@ -447,7 +447,8 @@ def test_translation_identity_of_finite_differences(oracle_lib):
     pose = P[0].astype(np.float64)
     tgt = oracle_lib.render(sc, synth.perturb_poses(P[0], 1, 99, 0.5, 1.0)[0], cam)
     loss = lambda o: residual(o["rgb"], o["feat"], tgt["rgb"], tgt["feat"])
-    g_pose, g_means, _, _ = fd_gradients(sc, pose, cam, loss, h=1e-5, gauss_ids=range(sc.n))
+    g_pose, gp, _ = fd_gradients(sc, pose, cam, loss, h=1e-5, gauss_ids=range(sc.n), params=("means",))
+    g_means = gp["means"]
     R = pose.reshape(3, 4)[:, :3]
     want = R @ g_means.sum(0)
     assert np.linalg.norm(want) > 1e-4
