@@ -112,7 +112,14 @@ enum { HGSR_SCHED_GRID = 0, HGSR_SCHED_POSE_MAJOR = 1, HGSR_SCHED_TILE_MAJOR = 2
  * bg: background colour added with the final transmittance.  near_z: camera
  * z below which a Gaussian is culled (0.2).  feat_out_bf16: write the feature
  * image as bfloat16 (FP32 accumulation).  lds_sort_cap: largest per-tile list
- * sorted in LDS (0 = default 4096; larger lists take a global-memory path). */
+ * sorted in LDS (0 = default 4096; larger lists take a global-memory path).
+ * feat_accum: how 32-channel features are summed at tile 8 and 16 --
+ * HGSR_FEAT_AUTO (the autotuned choice, else the VALU), HGSR_FEAT_VALU
+ * (per-pixel FMAs in blend order) or HGSR_FEAT_MFMA (per batch, a 32x2 by
+ * 2x64 FP32 matrix-core product of features and per-pixel weights; the same
+ * sum in another association order). */
+enum { HGSR_FEAT_AUTO = 0, HGSR_FEAT_VALU = 1, HGSR_FEAT_MFMA = 2 };
+
 typedef struct {
   int32_t tile;
   int32_t sort_mode;
@@ -121,6 +128,7 @@ typedef struct {
   float near_z;
   int32_t feat_out_bf16;
   int32_t lds_sort_cap;
+  int32_t feat_accum;
 } hgsr_opts;
 
 /* Output images (device, caller-allocated).  rgb, depth and alpha are
@@ -170,6 +178,7 @@ typedef struct {
 typedef struct {
   int32_t tile;
   int32_t schedule;
+  int32_t feat_accum;
   float ms;              /* best time per render */
 } hgsr_tune_result;
 
@@ -252,10 +261,12 @@ hgsr_status hgsr_stats(hgsr_ctx* ctx, hgsr_render_stats* out, hgsr_stream stream
 hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges, uint32_t* gids, int64_t cap,
                                   int64_t* n, hgsr_stream stream);
 
-/* Time the renderer on this input for tile sizes 8/16/32 and the blend
- * schedules, keep the fastest as the context's default (opts->tile == 0,
- * opts->schedule == HGSR_SCHED_AUTO), and append it to the JSON cache file
- * `cache_path` (host string, may be NULL).  Synchronises `stream`. */
+/* Time the renderer on this input for tile sizes 8/16/32, the blend
+ * schedules and (32 channels) both feature accumulations; keep the fastest as
+ * the context's default (opts->tile == 0, opts->schedule == HGSR_SCHED_AUTO,
+ * opts->feat_accum == HGSR_FEAT_AUTO) and append it to the JSON-lines cache
+ * file `cache_path` (host string, may be NULL), which later calls on the same
+ * shape read instead of timing.  Synchronises `stream`. */
 hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
                           const char* cache_path, hgsr_tune_result* result, hgsr_stream stream);

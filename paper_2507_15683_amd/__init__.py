@@ -107,6 +107,7 @@ class GaussianScene:
 
 _SORTS = {"bucket": SORT_BUCKET, "lsd": SORT_LSD}
 _SCHEDS = {"grid": SCHED_GRID, "pose": SCHED_POSE_MAJOR, "tile": SCHED_TILE_MAJOR, "auto": SCHED_AUTO}
+_FEATS = {"auto": _lib.FEAT_AUTO, "valu": _lib.FEAT_VALU, "mfma": _lib.FEAT_MFMA}
 
 
 class Renderer:
@@ -132,9 +133,9 @@ class Renderer:
             pass
 
     def opts(self, tile=16, sort="bucket", schedule="grid", bg=(0.0, 0.0, 0.0), near=0.2, feat_bf16=False,
-             lds_sort_cap=0) -> _lib.Opts:
+             lds_sort_cap=0, feat_accum="auto") -> _lib.Opts:
         return _lib.Opts(tile, _SORTS[sort], _SCHEDS[schedule], (ctypes.c_float * 3)(*bg), near, int(feat_bf16),
-                         lds_sort_cap)
+                         lds_sort_cap, _FEATS[feat_accum])
 
     def reserve(self, P, width, height, tile, records_per_pose, keys, n_gaussians):
         check(self.lib.hgsr_reserve(self.ctx, P, width, height, tile, records_per_pose, keys, n_gaussians),
@@ -170,8 +171,8 @@ class Renderer:
         return int(f.value)
 
     def render(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, tile=16, sort="bucket",
-               schedule="grid", bg=(0.0, 0.0, 0.0), near=0.2, feat_bf16=False, lds_sort_cap=0, out=None,
-               check_overflow=True, stream=None) -> dict:
+               schedule="grid", bg=(0.0, 0.0, 0.0), near=0.2, feat_bf16=False, lds_sort_cap=0, feat_accum="auto",
+               out=None, check_overflow=True, stream=None) -> dict:
         """Render P poses; returns dict(rgb (P,3,H,W), depth (P,H,W), alpha
         (P,H,W), feat (P,D,H,W) or None).  With check_overflow the call
         synchronises, and re-renders after growing the workspace if needed."""
@@ -180,7 +181,7 @@ class Renderer:
         P = poses.shape[0]
         if out is None:
             out = self.alloc_outputs(scene, P, K, feat_bf16)
-        opts = self.opts(tile, sort, schedule, bg, near, feat_bf16, lds_sort_cap)
+        opts = self.opts(tile, sort, schedule, bg, near, feat_bf16, lds_sort_cap, feat_accum)
         for _ in range(6):
             self.render_into(scene, poses, K, out, opts, stream)
             if not check_overflow or self.check_overflow(stream) == 0:
@@ -243,7 +244,8 @@ class Renderer:
                                      ctypes.byref(opts), ctypes.byref(o),
                                      None if cache_path is None else cache_path.encode(), ctypes.byref(res),
                                      _stream_ptr(stream)), "hgsr_autotune")
-        return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule], ms=res.ms)
+        return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule],
+                    feat_accum={1: "valu", 2: "mfma"}.get(res.feat_accum, "valu"), ms=res.ms)
 
     def profile(self, enable: bool):
         check(self.lib.hgsr_profile_enable(self.ctx, int(enable)), "hgsr_profile_enable")

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP", 3: "CAPACITY", 4: "UNSUPPOR
 
 SORT_BUCKET, SORT_LSD = 0, 1
 SCHED_GRID, SCHED_POSE_MAJOR, SCHED_TILE_MAJOR, SCHED_AUTO = 0, 1, 2, -1
+FEAT_AUTO, FEAT_VALU, FEAT_MFMA = 0, 1, 2
 
 P_ = ctypes.c_void_p
 I32 = ctypes.c_int32
@@ -32,7 +33,7 @@ class Intrinsics(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tile", I32), ("sort_mode", I32), ("schedule", I32), ("bg", F32 * 3), ("near_z", F32),
-                ("feat_out_bf16", I32), ("lds_sort_cap", I32)]
+                ("feat_out_bf16", I32), ("lds_sort_cap", I32), ("feat_accum", I32)]
 
 
 class Outputs(ctypes.Structure):
@@ -53,7 +54,7 @@ class RenderStats(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("tile", I32), ("schedule", I32), ("ms", F32)]
+    _fields_ = [("tile", I32), ("schedule", I32), ("feat_accum", I32), ("ms", F32)]
 
 
 # (name, argtypes) for every entry point declared in include/hgsr.h

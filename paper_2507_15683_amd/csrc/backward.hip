@@ -301,8 +301,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
   const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
   float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const bool ok = !(a.flags[0] & 3);
-  const uint32_t cnt = ok ? min(a.pose_count[pose], a.rec_cap) : 0u;
-  if (slot < cnt) {
+  const bool use = ok && slot < a.rec_cap && rec_in_use(a.pose_count, a.rec_cap, pose, slot);
+  if (use) {
     const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
     const float* gr = a.g_rec + idx * kGradRecStride;
     const float g_u = gr[0], g_v = gr[1], g_ca = gr[2], g_cb = gr[3], g_cc = gr[4], g_o = gr[5], g_z = gr[6];
@@ -484,13 +484,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
       for (int k = 0; k < 6; ++k) s_red[k][threadIdx.x] += s_red[k][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 6 && blockIdx.x * 256 < cnt) atomicAdd(a.g_pose + 6 * pose + threadIdx.x, s_red[threadIdx.x][0]);
+  if (threadIdx.x < 6 && s_red[threadIdx.x][0] != 0.f) atomicAdd(a.g_pose + 6 * pose + threadIdx.x, s_red[threadIdx.x][0]);
 }
 
 __global__ __launch_bounds__(256) void zero_grad_rec_kernel(float* g, const uint32_t* pose_count, uint32_t rec_cap) {
   const int pose = blockIdx.y;
   const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-  if (slot >= min(pose_count[pose], rec_cap)) return;
+  if (slot >= rec_cap || !rec_in_use(pose_count, rec_cap, pose, slot)) return;
   float4* d = reinterpret_cast<float4*>(g + (static_cast<int64_t>(pose) * rec_cap + slot) * kGradRecStride);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   d[0] = z; d[1] = z; d[2] = z;

@@ -227,8 +227,7 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   const int pose = blockIdx.y;
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   const uint32_t slot = t / kEmitLanes, sub = t % kEmitLanes;
-  const uint32_t cnt = min(a.pose_count[pose], a.rec_cap);
-  if (slot >= cnt) return;
+  if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
   const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
   const uint2 r = a.rects[idx];
   const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];  // cc, o, z, gid
@@ -252,17 +251,9 @@ void launch_emit_bucket(const BinArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
 }
 
-// Short lists (<= 256 entries): one wave per tile, 4 keys per lane, a
-// bitonic network in registers (partners across lanes by shuffle, across the
-// lane's 4 registers by swap); no block barriers.  4 tiles per workgroup.
-constexpr int kWaveSortCap = 256;
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), m, kWave);
-  const uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), m, kWave);
-  return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
+// Short lists (<= 256 entries): one wave per tile (4 tiles per workgroup)
+// runs the register bitonic sort; used when the blend does not sort them
+// itself.
 __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
   if (a.flags[0] & 3) return;
   const int lane = threadIdx.x & (kWave - 1);
@@ -274,54 +265,9 @@ __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
     if (n == 1 && lane == 0) a.list[r.x] = a.vals[r.x];
     return;
   }
-  int R = 1;
-  while (R * kWave < static_cast<int>(n)) R <<= 1;  // 1, 2 or 4 registers
-  const uint32_t m = static_cast<uint32_t>(R) * kWave;
   uint64_t key[4];
   uint32_t val[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t e = q * kWave + lane;
-    key[q] = ~0ull;
-    val[q] = 0;
-    if (q < R && e < n) {
-      key[q] = a.keys[r.x + e];
-      val[q] = a.vals[r.x + e];
-    }
-  }
-  for (uint32_t k = 2; k <= m; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      if (j >= kWave) {
-        const int rj = static_cast<int>(j / kWave);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int q2 = q ^ rj;
-          if (q >= R || q2 <= q) continue;
-          const uint32_t e = q * kWave + lane;
-          const bool up = (e & k) == 0;
-          if ((key[q] > key[q2]) == up) {
-            const uint64_t tk = key[q]; key[q] = key[q2]; key[q2] = tk;
-            const uint32_t tv = val[q]; val[q] = val[q2]; val[q2] = tv;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q >= R) continue;
-          const uint64_t ok = shfl_xor_u64(key[q], static_cast<int>(j));
-          const uint32_t ov = __shfl_xor(val[q], static_cast<int>(j), kWave);
-          const uint32_t e = q * kWave + lane;
-          const bool up = (e & k) == 0;
-          const bool lower = (e & j) == 0;
-          const bool take = lower == up ? (ok < key[q]) : (ok > key[q]);
-          if (take) {
-            key[q] = ok;
-            val[q] = ov;
-          }
-        }
-      }
-    }
-  }
+  const int R = wave_sort256(a.keys + r.x, a.vals + r.x, n, key, val);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t e = q * kWave + lane;
@@ -333,14 +279,7 @@ __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
 // network on (depth bits, gid) keys in LDS.
 constexpr int kLdsSortCap = 4096;
 
-__global__ __launch_bounds__(256) void tile_sort_kernel(TileSortArgs a) {
-  __shared__ uint64_t s_key[kLdsSortCap];
-  __shared__ uint32_t s_val[kLdsSortCap];
-  if (a.flags[0] & 3) return;
-  const int tg = blockIdx.x;
-  const uint2 r = a.ranges[tg];
-  const uint32_t n = r.y - r.x;
-  if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap)) || n > static_cast<uint32_t>(a.lds_cap)) return;
+__device__ void tile_sort_lds(const TileSortArgs& a, uint2 r, uint32_t n, uint64_t* s_key, uint32_t* s_val) {
   uint32_t m = 2;
   while (m < n) m <<= 1;
   for (uint32_t k = threadIdx.x; k < m; k += 256) {
@@ -399,15 +338,8 @@ __device__ __forceinline__ uint32_t chunk_rank(uint32_t d, bool valid, uint32_t 
 
 // Lists longer than the LDS capacity: one block runs a stable LSD radix sort
 // of that tile's keys in global memory (ping-pong with the alternate buffers).
-__global__ __launch_bounds__(256) void tile_sort_big_kernel(TileSortArgs a) {
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_wc[4][256];
-  __shared__ uint32_t s_w[4];
-  if (a.flags[0] & 3) return;
-  const int tg = blockIdx.x;
-  const uint2 r = a.ranges[tg];
-  const uint32_t n = r.y - r.x;
-  if (n <= static_cast<uint32_t>(a.lds_cap)) return;
+__device__ void tile_sort_global(const TileSortArgs& a, uint2 r, uint32_t n, uint32_t* s_off, uint32_t (*s_wc)[256],
+                                 uint32_t* s_w) {
   uint64_t* sk = a.keys + r.x;
   uint32_t* sv = a.vals + r.x;
   uint64_t* dk = a.keys_alt + r.x;
@@ -453,11 +385,28 @@ __global__ __launch_bounds__(256) void tile_sort_big_kernel(TileSortArgs a) {
   for (uint32_t k = threadIdx.x; k < n; k += 256) a.list[r.x + k] = sv[k];
 }
 
-void launch_tile_sort(const TileSortArgs& a, hipStream_t s) {
+// Lists longer than one wave sorts: the workgroup sorts them in LDS up to the
+// LDS capacity, or with a stable LSD radix sort in global memory beyond it.
+__global__ __launch_bounds__(256) void tile_sort_long_kernel(TileSortArgs a) {
+  __shared__ uint64_t s_key[kLdsSortCap];
+  __shared__ uint32_t s_val[kLdsSortCap];
+  if (a.flags[0] & 3) return;
+  const uint2 r = a.ranges[blockIdx.x];
+  const uint32_t n = r.y - r.x;
+  if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) return;
+  if (n <= static_cast<uint32_t>(a.lds_cap)) {
+    tile_sort_lds(a, r, n, s_key, s_val);
+  } else {
+    // reuse the key array's LDS for the radix pass state
+    uint32_t* base = reinterpret_cast<uint32_t*>(s_key);
+    tile_sort_global(a, r, n, base, reinterpret_cast<uint32_t(*)[256]>(base + 256), base + 256 + 4 * 256);
+  }
+}
+
+void launch_tile_sort(const TileSortArgs& a, bool short_lists, hipStream_t s) {
   if (a.n_tiles <= 0) return;
-  hipLaunchKernelGGL(tile_sort_wave_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(tile_sort_big_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
+  if (short_lists) hipLaunchKernelGGL(tile_sort_wave_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(tile_sort_long_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------------ LSD path
@@ -466,8 +415,7 @@ __global__ __launch_bounds__(256) void emit_lsd_kernel(BinArgs a, const uint32_t
   if (a.flags[0] & 3) return;
   const int pose = blockIdx.y;
   const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t cnt = min(a.pose_count[pose], a.rec_cap);
-  if (slot >= cnt) return;
+  if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
   const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
   const uint2 r = a.rects[idx];
   const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];

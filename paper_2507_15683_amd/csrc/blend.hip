@@ -1,7 +1,10 @@
 // Front-to-back alpha blend, one workgroup per (pose, tile).
 //
 // Each wave owns a square block of the tile (8x8 pixels at tile 8 and 16,
-// 16x16 at tile 32 with 4 pixels per lane).  The workgroup walks the tile's
+// 16x16 with 4 pixels per lane at tile 32); compact blocks keep the lanes'
+// blend decisions coherent.  Tile lists up to `sort_cap` entries may arrive
+// unsorted and are then put in (depth, index) order by the workgroup's first
+// wave (a register bitonic sort).  The workgroup walks the tile's
 // depth-ordered list in batches: every thread stages one splat (geometry,
 // colour, FP32 feature vector) into LDS and marks which waves' blocks its
 // support rectangle touches; each wave then compacts the batch to the entries
@@ -16,13 +19,18 @@
 
 namespace hgsr {
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
 template <int TILE>
 struct BlendShape {
   static constexpr int kThreads = TILE == 8 ? 64 : 256;
+  static constexpr int kBatch = kThreads < 128 ? kThreads : 128;  // splats staged per round
   static constexpr int kWaves = kThreads / kWave;
-  static constexpr int kBlock = TILE == 32 ? 16 : 8;       // side of a wave's pixel block
-  static constexpr int kPPT = kBlock * kBlock / kWave;     // pixels per lane
-  static constexpr int kBlocksX = TILE / kBlock;
+  // a wave's pixel block: 8x8 (16x16 with 4 pixels per lane at tile 32)
+  static constexpr int kBlockW = TILE == 32 ? 16 : 8;
+  static constexpr int kBlockH = TILE * TILE / kWaves / kBlockW;
+  static constexpr int kPPT = kBlockW * kBlockH / kWave;  // pixels per lane
+  static constexpr int kBlocksX = TILE / kBlockW;
 };
 
 // Pixel-centre rectangle of a splat's support, padded; shared by the wave
@@ -39,18 +47,24 @@ __device__ __forceinline__ void splat_rect(const float4 geo, const float4 opz, f
   y1 = geo.y + ry - 0.5f;
 }
 
-template <int TILE, int D, bool BF16>
+template <int TILE, int D, bool BF16, bool MFK>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
   using S = BlendShape<TILE>;
-  constexpr int NT = S::kThreads, NW = S::kWaves, B = S::kBlock, PPT = S::kPPT;
+  constexpr int NT = S::kThreads, NB = S::kBatch, NW = S::kWaves, BW = S::kBlockW, BH = S::kBlockH, PPT = S::kPPT;
   constexpr bool LDS_F32 = D > 0 && D <= 32;            // features as FP32 in LDS
   constexpr int FW = D == 0 ? 1 : (LDS_F32 ? D : D / 2);  // 32-bit words per feature vector
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_opz[NT];
-  __shared__ float4 s_col[NT];
-  __shared__ uint32_t s_fw[NT * FW];
-  __shared__ uint8_t s_mask[NT];
-  __shared__ uint16_t s_list[NW][NT];
+  constexpr int DV = D / 8;                              // 16-byte bf16 vectors per feature
+  constexpr int PARTS = (DV >= NT / NB) ? NT / NB : 1;   // threads sharing one splat's feature load
+  // 32 feature channels, one pixel per lane: the feature sum runs on the
+  // matrix cores (F^T[32 ch x 64 px] += Feat^T[32 x 2 splats] W[2 x 64 px])
+  constexpr bool MF = MFK && D == 32 && PPT == 1;
+  __shared__ float4 s_geo[NB];
+  __shared__ float4 s_opz[NB];
+  __shared__ float4 s_col[NB];
+  __shared__ uint32_t s_fw[NB * FW];
+  __shared__ uint8_t s_mask[NB];
+  __shared__ uint16_t s_list[NW][NB];
+  __shared__ uint32_t s_order[kWaveSortCap];
   __shared__ int s_item;
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
@@ -82,17 +96,37 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;
     const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
     // this wave's pixel block
-    const int bx0 = tx * TILE + (wave % S::kBlocksX) * B, by0 = ty * TILE + (wave / S::kBlocksX) * B;
+    const int bx0 = tx * TILE + (wave % S::kBlocksX) * BW, by0 = ty * TILE + (wave / S::kBlocksX) * BH;
+    // short unsorted lists are put in (depth, index) order here by wave 0
+    const uint32_t n_list = range.y - range.x;
+    const bool fused = n_list <= static_cast<uint32_t>(a.sort_cap);
+    if (fused && n_list > 0) {
+      if (wave == 0) {
+        uint64_t key[4];
+        uint32_t val[4];
+        const int R = wave_sort256(a.keys + range.x, a.vals + range.x, n_list, key, val);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t e = q * kWave + lane;
+          if (q < R && e < n_list) {
+            s_order[e] = val[q];
+            a.list_out[range.x + e] = val[q];
+          }
+        }
+      }
+      __syncthreads();
+    }
 
     float pxf[PPT], pyf[PPT], T[PPT], C[PPT][3], Z[PPT];
-    float F[PPT][D > 0 ? D : 1];
+    float F[PPT][(D > 0 && !MF) ? D : 1];
+    floatx16 acc0 = {}, acc1 = {};
     uint32_t used[PPT];
     bool done[PPT], inside[PPT];
     int pix[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int li = lane + k * kWave;
-      const int px = bx0 + (li % B), py = by0 + (li / B);
+      const int px = bx0 + (li % BW), py = by0 + (li / BW);
       inside[k] = px < W && py < H;
       pix[k] = py * W + px;
       pxf[k] = static_cast<float>(px) + 0.5f;
@@ -101,121 +135,175 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       C[k][0] = C[k][1] = C[k][2] = 0.f;
       Z[k] = 0.f;
 #pragma unroll
-      for (int d = 0; d < (D > 0 ? D : 1); ++d) F[k][d] = 0.f;
+      for (int d = 0; d < ((D > 0 && !MF) ? D : 1); ++d) F[k][d] = 0.f;
       used[k] = 0;
       done[k] = !inside[k];
     }
 
-    for (uint32_t b0 = range.x; b0 < range.y; b0 += NT) {
+    for (uint32_t b0 = range.x; b0 < range.y; b0 += NB) {
       bool all_mine = true;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) all_mine &= done[k];
       if (__syncthreads_and(all_mine)) break;
-      const uint32_t j = b0 + tid;
+      const int e = tid % NB, part = tid / NB;
+      const uint32_t j = b0 + e;
       if (j < range.y) {
-        const uint32_t r = a.list[j];
+        const uint32_t r = fused ? s_order[j - range.x] : a.list[j];
         const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
-        const float4 g0 = sp[0], g1 = sp[1], g2 = sp[2];
-        s_geo[tid] = g0;
-        s_opz[tid] = g1;
-        s_col[tid] = g2;
-        float x0, x1, y0, y1;
-        splat_rect(g0, g1, g2.w, x0, x1, y0, y1);
-        uint8_t m = 0;
+        const float4 g1 = sp[1];
+        if (part == 0) {
+          const float4 g0 = sp[0], g2 = sp[2];
+          s_geo[e] = g0;
+          s_opz[e] = g1;
+          s_col[e] = g2;
+          float x0, x1, y0, y1;
+          splat_rect(g0, g1, g2.w, x0, x1, y0, y1);
+          uint8_t m = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const float wx0 = static_cast<float>(tx * TILE + (w % S::kBlocksX) * B);
-          const float wy0 = static_cast<float>(ty * TILE + (w / S::kBlocksX) * B);
-          if (x1 >= wx0 && x0 <= wx0 + (B - 1) && y1 >= wy0 && y0 <= wy0 + (B - 1)) m |= 1u << w;
+          for (int w = 0; w < NW; ++w) {
+            const float wx0 = static_cast<float>(tx * TILE + (w % S::kBlocksX) * BW);
+            const float wy0 = static_cast<float>(ty * TILE + (w / S::kBlocksX) * BH);
+            if (x1 >= wx0 && x0 <= wx0 + (BW - 1) && y1 >= wy0 && y0 <= wy0 + (BH - 1)) m |= 1u << w;
+          }
+          s_mask[e] = m;
         }
-        s_mask[tid] = m;
         if constexpr (D > 0) {
-          const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(__float_as_uint(g1.w)) * (D / 8);
-          if constexpr (LDS_F32) {
+          if (part < PARTS) {
+            constexpr int QV = DV / PARTS;
+            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) +
+                              static_cast<int64_t>(__float_as_uint(g1.w)) * DV + part * QV;
+            if constexpr (LDS_F32) {
 #pragma unroll
-            for (int q = 0; q < D / 8; ++q) {
-              const uint4 f = fv[q];
-              uint4* dst = reinterpret_cast<uint4*>(&s_fw[tid * FW + 8 * q]);
-              dst[0] = make_uint4(f.x << 16, f.x & 0xffff0000u, f.y << 16, f.y & 0xffff0000u);
-              dst[1] = make_uint4(f.z << 16, f.z & 0xffff0000u, f.w << 16, f.w & 0xffff0000u);
+              for (int q = 0; q < QV; ++q) {
+                const uint4 f = fv[q];
+                uint4* dst = reinterpret_cast<uint4*>(&s_fw[e * FW + 8 * (part * QV + q)]);
+                dst[0] = make_uint4(f.x << 16, f.x & 0xffff0000u, f.y << 16, f.y & 0xffff0000u);
+                dst[1] = make_uint4(f.z << 16, f.z & 0xffff0000u, f.w << 16, f.w & 0xffff0000u);
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < QV; ++q) reinterpret_cast<uint4*>(&s_fw[e * FW])[part * QV + q] = fv[q];
             }
-          } else {
-#pragma unroll
-            for (int q = 0; q < D / 8; ++q) reinterpret_cast<uint4*>(&s_fw[tid * FW])[q] = fv[q];
           }
         }
-      } else {
-        s_mask[tid] = 0;
+      } else if (part == 0) {
+        s_mask[e] = 0;
       }
       __syncthreads();
-      const int nb = static_cast<int>(min(static_cast<uint32_t>(NT), range.y - b0));
+      const int nb = static_cast<int>(min(static_cast<uint32_t>(NB), range.y - b0));
       // compact the batch to the entries touching this wave's block (in order)
       int n_mine = 0;
       for (int c0 = 0; c0 < nb; c0 += kWave) {
-        const int e = c0 + lane;
-        const bool hit = e < nb && ((s_mask[e] >> wave) & 1u);
+        const int ce = c0 + lane;
+        const bool hit = ce < nb && ((s_mask[ce] >> wave) & 1u);
         const uint64_t bal = __ballot(hit);
-        if (hit) s_list[wave][n_mine + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(e);
+        if (hit) s_list[wave][n_mine + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(ce);
         n_mine += __popcll(bal);
       }
       __builtin_amdgcn_wave_barrier();
-      for (int ii = 0; ii < n_mine; ++ii) {
-        bool mine = true;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) mine &= done[k];
-        if (mine) break;
-        const int jj = s_list[wave][ii];
-        const float4 geo = s_geo[jj];
-        const float4 opz = s_opz[jj];
-        const float pmin = s_col[jj].w;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          if (done[k]) continue;
-          const float dx = pxf[k] - geo.x, dy = pyf[k] - geo.y;
+      if constexpr (MF) {
+        // one splat for this wave's pixels: colour, depth and transmittance
+        // on the VALU; returns the pixel's blend weight (0 when not blended)
+        auto walk = [&](int jj) -> float {
+          if (done[0]) return 0.f;
+          const float4 geo = s_geo[jj];
+          const float4 opz = s_opz[jj];
+          const float dx = pxf[0] - geo.x, dy = pyf[0] - geo.y;
           const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
-          if (power > 0.f || power < pmin - kPreReject) continue;
+          if (power > 0.f || power < s_col[jj].w - kPreReject) return 0.f;
           const float alpha = pair_alpha(opz.y, power);
-          if (alpha < kAlphaMin) continue;
-          const float Tn = T[k] * (1.f - alpha);
+          if (alpha < kAlphaMin) return 0.f;
+          const float Tn = T[0] * (1.f - alpha);
           if (Tn < kTMin) {
-            done[k] = true;
-            continue;
+            done[0] = true;
+            return 0.f;
           }
-          const float w = alpha * T[k];
+          const float w = alpha * T[0];
           const float4 col = s_col[jj];
-          C[k][0] = fmaf(w, col.x, C[k][0]);
-          C[k][1] = fmaf(w, col.y, C[k][1]);
-          C[k][2] = fmaf(w, col.z, C[k][2]);
-          Z[k] = fmaf(w, opz.z, Z[k]);
-          if constexpr (D > 0) {
-            if constexpr (LDS_F32) {
-              const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FW]);
+          C[0][0] = fmaf(w, col.x, C[0][0]);
+          C[0][1] = fmaf(w, col.y, C[0][1]);
+          C[0][2] = fmaf(w, col.z, C[0][2]);
+          Z[0] = fmaf(w, opz.z, Z[0]);
+          T[0] = Tn;
+          used[0] = b0 + jj - range.x + 1;
+          return w;
+        };
+        for (int ii = 0; ii < n_mine; ii += 2) {
+          if (__all(done[0] ? 1 : 0)) break;  // every lane of the wave has stopped (uniform)
+          const int jj0 = s_list[wave][ii];
+          const int jj1 = ii + 1 < n_mine ? static_cast<int>(s_list[wave][ii + 1]) : -1;
+          const float w0 = walk(jj0);
+          const float w1 = jj1 >= 0 ? walk(jj1) : 0.f;
+          if (__any(w0 != 0.f || w1 != 0.f)) {
+            // B operands: lanes 0-31 carry splat jj0's weights, lanes 32-63
+            // splat jj1's, for pixels 0-31 (bw0) and 32-63 (bw1)
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(w0), __float_as_uint(w1), false, false);
+            const float bw0 = __uint_as_float(sw[0]), bw1 = __uint_as_float(sw[1]);
+            const int jsel = lane < 32 ? jj0 : jj1;
+            const float av = jsel >= 0 ? __uint_as_float(s_fw[jsel * FW + (lane & 31)]) : 0.f;
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bw0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bw1, acc1, 0, 0, 0);
+          }
+        }
+      } else {
+        for (int ii = 0; ii < n_mine; ++ii) {
+          bool mine = true;
 #pragma unroll
-              for (int q = 0; q < D / 4; ++q) {
-                const float4 f = fq[q];
-                F[k][4 * q + 0] = fmaf(w, f.x, F[k][4 * q + 0]);
-                F[k][4 * q + 1] = fmaf(w, f.y, F[k][4 * q + 1]);
-                F[k][4 * q + 2] = fmaf(w, f.z, F[k][4 * q + 2]);
-                F[k][4 * q + 3] = fmaf(w, f.w, F[k][4 * q + 3]);
-              }
-            } else {
-              const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FW]);
+          for (int k = 0; k < PPT; ++k) mine &= done[k];
+          if (mine) break;
+          const int jj = s_list[wave][ii];
+          const float4 geo = s_geo[jj];
+          const float4 opz = s_opz[jj];
+          const float pmin = s_col[jj].w;
 #pragma unroll
-              for (int q = 0; q < D / 8; ++q) {
-                const uint4 f = fq[q];
-                F[k][8 * q + 0] = fmaf(w, bf16_lo(f.x), F[k][8 * q + 0]);
-                F[k][8 * q + 1] = fmaf(w, bf16_hi(f.x), F[k][8 * q + 1]);
-                F[k][8 * q + 2] = fmaf(w, bf16_lo(f.y), F[k][8 * q + 2]);
-                F[k][8 * q + 3] = fmaf(w, bf16_hi(f.y), F[k][8 * q + 3]);
-                F[k][8 * q + 4] = fmaf(w, bf16_lo(f.z), F[k][8 * q + 4]);
-                F[k][8 * q + 5] = fmaf(w, bf16_hi(f.z), F[k][8 * q + 5]);
-                F[k][8 * q + 6] = fmaf(w, bf16_lo(f.w), F[k][8 * q + 6]);
-                F[k][8 * q + 7] = fmaf(w, bf16_hi(f.w), F[k][8 * q + 7]);
+          for (int k = 0; k < PPT; ++k) {
+            if (done[k]) continue;
+            const float dx = pxf[k] - geo.x, dy = pyf[k] - geo.y;
+            const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
+            if (power > 0.f || power < pmin - kPreReject) continue;
+            const float alpha = pair_alpha(opz.y, power);
+            if (alpha < kAlphaMin) continue;
+            const float Tn = T[k] * (1.f - alpha);
+            if (Tn < kTMin) {
+              done[k] = true;
+              continue;
+            }
+            const float w = alpha * T[k];
+            const float4 col = s_col[jj];
+            C[k][0] = fmaf(w, col.x, C[k][0]);
+            C[k][1] = fmaf(w, col.y, C[k][1]);
+            C[k][2] = fmaf(w, col.z, C[k][2]);
+            Z[k] = fmaf(w, opz.z, Z[k]);
+            if constexpr (D > 0) {
+              if constexpr (LDS_F32) {
+                const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FW]);
+#pragma unroll
+                for (int q = 0; q < D / 4; ++q) {
+                  const float4 f = fq[q];
+                  F[k][4 * q + 0] = fmaf(w, f.x, F[k][4 * q + 0]);
+                  F[k][4 * q + 1] = fmaf(w, f.y, F[k][4 * q + 1]);
+                  F[k][4 * q + 2] = fmaf(w, f.z, F[k][4 * q + 2]);
+                  F[k][4 * q + 3] = fmaf(w, f.w, F[k][4 * q + 3]);
+                }
+              } else {
+                const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FW]);
+#pragma unroll
+                for (int q = 0; q < D / 8; ++q) {
+                  const uint4 f = fq[q];
+                  F[k][8 * q + 0] = fmaf(w, bf16_lo(f.x), F[k][8 * q + 0]);
+                  F[k][8 * q + 1] = fmaf(w, bf16_hi(f.x), F[k][8 * q + 1]);
+                  F[k][8 * q + 2] = fmaf(w, bf16_lo(f.y), F[k][8 * q + 2]);
+                  F[k][8 * q + 3] = fmaf(w, bf16_hi(f.y), F[k][8 * q + 3]);
+                  F[k][8 * q + 4] = fmaf(w, bf16_lo(f.z), F[k][8 * q + 4]);
+                  F[k][8 * q + 5] = fmaf(w, bf16_hi(f.z), F[k][8 * q + 5]);
+                  F[k][8 * q + 6] = fmaf(w, bf16_lo(f.w), F[k][8 * q + 6]);
+                  F[k][8 * q + 7] = fmaf(w, bf16_hi(f.w), F[k][8 * q + 7]);
+                }
               }
             }
+            T[k] = Tn;
+            used[k] = b0 + jj - range.x + 1;
           }
-          T[k] = Tn;
-          used[k] = b0 + jj - range.x + 1;
         }
       }
     }
@@ -234,7 +322,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       a.depth[o] = A > 0.f ? Z[k] / A : 0.f;
       a.final_T[o] = T[k];
       a.n_used[o] = used[k];
-      if constexpr (D > 0) {
+      if constexpr (D > 0 && !MF) {
         if (a.out_feat) {
           const int64_t of = static_cast<int64_t>(pose) * D * HW + pix[k];
           if constexpr (BF16) {
@@ -249,6 +337,30 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
         }
       }
     }
+    if constexpr (MF) {
+      // accumulator layout (32x32 MFMA): lane l, register r holds channel
+      // 8 (r/4) + 4 (l/32) + r%4 of pixel l%32 (acc0) or 32 + l%32 (acc1)
+      if (a.out_feat) {
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int li = (lane & 31) + 32 * nb;
+          const int px = bx0 + (li % BW), py = by0 + (li / BW);
+          if (px < W && py < H) {
+            // 32-bit offsets within this pose's feature planes
+            const uint32_t pofs = static_cast<uint32_t>(py * W + px) +
+                                  static_cast<uint32_t>(4 * (lane >> 5)) * static_cast<uint32_t>(HW);
+            const int64_t pbase_f = static_cast<int64_t>(pose) * D * HW;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const uint32_t o = pofs + static_cast<uint32_t>(8 * (r / 4) + (r % 4)) * static_cast<uint32_t>(HW);
+              const float v = nb == 0 ? acc0[r] : acc1[r];
+              if constexpr (BF16) (static_cast<uint16_t*>(a.out_feat) + pbase_f)[o] = f32_to_bf16_rne(v);
+              else (static_cast<float*>(a.out_feat) + pbase_f)[o] = v;
+            }
+          }
+        }
+      }
+    }
     if (persistent) __syncthreads();
   }
 }
@@ -256,7 +368,10 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
 template <int TILE, int D, bool BF16>
 static void launch_t(const BlendArgs& a, int n_ctas, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
-  hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16>), dim3(n_ctas), dim3(NT), 0, s, a);
+  if (D == 32 && TILE != 32 && a.feat_mfma)
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, true>), dim3(n_ctas), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false>), dim3(n_ctas), dim3(NT), 0, s, a);
 }
 
 template <int TILE, int D>

@@ -17,6 +17,7 @@ constexpr float kGuard = 1.3f;              // Jacobian guard band, x field of v
 constexpr float kRectPad = 5e-4f;           // support rectangle padding, px
 constexpr float kPreReject = 1e-3f;         // exponent margin below the gate for the early reject
 constexpr int kMaxPoses = 64;               // poses per projection launch
+constexpr int kSub = 32;                    // record sub-segments (and counters) per pose
 constexpr int kWave = 64;
 
 // blend launch shapes: one workgroup per (pose, tile), or a persistent grid
@@ -206,6 +207,79 @@ __device__ __forceinline__ float pair_power(float dx, float dy, float ca, float 
 }
 
 __device__ __forceinline__ float pair_alpha(float o, float power) { return fminf(kAlphaMax, o * __expf(power)); }
+
+// Records of pose p live in kSub sub-segments of rec_cap / kSub slots; slot
+// `slot` is in use when its offset within its sub-segment is below that
+// sub-segment's counter.
+__device__ __forceinline__ bool rec_in_use(const uint32_t* sub_count, uint32_t rec_cap, int pose, uint32_t slot) {
+  const uint32_t sub_cap = rec_cap / kSub;
+  const uint32_t s = slot / sub_cap;
+  return slot - s * sub_cap < min(sub_count[pose * kSub + s], sub_cap);
+}
+
+// Bitonic sort of n <= 256 (key, value) pairs by one wave, 4 per lane in
+// registers: partners across lanes by shuffle, across a lane's registers by
+// swap.  Keys are unique except the ~0 padding.  Every lane of the wave must
+// call it; on return lane l holds sorted elements q*64 + l in key[q], val[q].
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), m, kWave);
+  const uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), m, kWave);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ int wave_sort256(const uint64_t* keys, const uint32_t* vals, uint32_t n, uint64_t key[4],
+                                            uint32_t val[4]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int R = 1;
+  while (R * kWave < static_cast<int>(n)) R <<= 1;  // 1, 2 or 4 registers
+  const uint32_t m = static_cast<uint32_t>(R) * kWave;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t e = q * kWave + lane;
+    key[q] = ~0ull;
+    val[q] = 0;
+    if (q < R && e < n) {
+      key[q] = keys[e];
+      val[q] = vals[e];
+    }
+  }
+  for (uint32_t k = 2; k <= m; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= kWave) {
+        const int rj = static_cast<int>(j / kWave);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int q2 = q ^ rj;
+          if (q >= R || q2 <= q) continue;
+          const uint32_t e = q * kWave + lane;
+          const bool up = (e & k) == 0;
+          if ((key[q] > key[q2]) == up) {
+            const uint64_t tk = key[q]; key[q] = key[q2]; key[q2] = tk;
+            const uint32_t tv = val[q]; val[q] = val[q2]; val[q2] = tv;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q >= R) continue;
+          const uint64_t ok = shfl_xor_u64(key[q], static_cast<int>(j));
+          const uint32_t ov = __shfl_xor(val[q], static_cast<int>(j), kWave);
+          const uint32_t e = q * kWave + lane;
+          const bool up = (e & k) == 0;
+          const bool lower = (e & j) == 0;
+          const bool take = lower == up ? (ok < key[q]) : (ok > key[q]);
+          if (take) {
+            key[q] = ok;
+            val[q] = ov;
+          }
+        }
+      }
+    }
+  }
+  return R;
+}
+
+constexpr int kWaveSortCap = 256;   // lists this short are sorted by one wave
 
 // Tile-id bits of a pose-major tile index (for key packing).
 __device__ __forceinline__ uint32_t zbits(float z) { return __float_as_uint(z); }

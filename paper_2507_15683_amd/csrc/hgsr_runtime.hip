@@ -93,6 +93,7 @@ struct hgsr_ctx {
   // autotuned defaults
   int tuned_tile = 0;
   int tuned_sched = -1;
+  int tuned_feat = 0;
 
   // stage timing
   bool profiling = false;
@@ -206,12 +207,20 @@ hgsr_status check_intrinsics(const hgsr_intrinsics* K) {
   return HGSR_OK;
 }
 
+// Records per pose: a multiple of the sub-segment count, with sub-segments
+// half again as large as an even split (block-to-counter imbalance).
+uint32_t round_rec_cap(int64_t r) {
+  int64_t sub = (r + kSub - 1) / kSub;
+  sub += sub / 2 + 64;
+  return static_cast<uint32_t>(std::min<int64_t>(sub * kSub, 0x7fffffffll / kSub * kSub));
+}
+
 // Size the workspace for P poses, given tile config, gaussians n.
 hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bool lsd) {
   if (c->rec_cap == 0) {
     int64_t r = c->rec_hint > 0 ? c->rec_hint : std::max<int64_t>(1 << 16, n / 4);
     r = std::min<int64_t>(std::max<int64_t>(r, 1024), std::max<int64_t>(n, 1024));
-    c->rec_cap = static_cast<uint32_t>(r);
+    c->rec_cap = round_rec_cap(r);
   }
   if (c->key_cap == 0) {
     c->key_cap = c->key_hint > 0 ? static_cast<uint64_t>(c->key_hint)
@@ -222,7 +231,7 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
   const int64_t npix = static_cast<int64_t>(P) * cam.W * cam.H;
   TRY(ensure(c, c->recs, nrec * sizeof(Splat)));
   TRY(ensure(c, c->rects, nrec * sizeof(uint2)));
-  TRY(ensure(c, c->pose_count, P * sizeof(uint32_t)));
+  TRY(ensure(c, c->pose_count, static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
   TRY(ensure(c, c->tile_count, ntile * sizeof(uint32_t)));
   TRY(ensure(c, c->tile_cursor, ntile * sizeof(uint32_t)));
   TRY(ensure(c, c->ranges, ntile * sizeof(uint2)));
@@ -304,8 +313,7 @@ hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, 
   if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
   if (P <= 0 || width <= 0 || height <= 0 || !(tile == 8 || tile == 16 || tile == 32))
     return fail(HGSR_ERR_INVALID_ARG, "bad reserve arguments");
-  if (records_per_pose > 0 && static_cast<uint64_t>(records_per_pose) > c->rec_cap)
-    c->rec_cap = static_cast<uint32_t>(std::min<int64_t>(records_per_pose, 0x7fffffff));
+  if (records_per_pose > 0 && round_rec_cap(records_per_pose) > c->rec_cap) c->rec_cap = round_rec_cap(records_per_pose);
   if (keys > 0 && static_cast<uint64_t>(keys) > c->key_cap) c->key_cap = static_cast<uint64_t>(keys);
   hgsr_intrinsics K{1.f, 1.f, 0.f, 0.f, width, height};
   const CamArgs cam = make_cam(K, tile, 0.2f);
@@ -331,6 +339,8 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   if (sched < 0 || sched > 2) return fail(HGSR_ERR_INVALID_ARG, "bad schedule");
   if (!(opts->sort_mode == HGSR_SORT_BUCKET || opts->sort_mode == HGSR_SORT_LSD))
     return fail(HGSR_ERR_INVALID_ARG, "bad sort_mode");
+  if (opts->feat_accum < HGSR_FEAT_AUTO || opts->feat_accum > HGSR_FEAT_MFMA)
+    return fail(HGSR_ERR_INVALID_ARG, "bad feat_accum");
   const bool lsd = opts->sort_mode == HGSR_SORT_LSD;
   const float near_z = opts->near_z > 0.f ? opts->near_z : 0.2f;
   const CamArgs cam = make_cam(*K, tile, near_z);
@@ -347,11 +357,11 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   // clear flags and counters (a kernel, not a memset, so the sequence can be
   // captured and replayed)
   if (!lsd)
-    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, P, c->tile_count.as<uint32_t>(), ntile,
-                  c->tile_cursor.as<uint32_t>(), ntile, s);
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, static_cast<int64_t>(P) * kSub,
+                  c->tile_count.as<uint32_t>(), ntile, c->tile_cursor.as<uint32_t>(), ntile, s);
   else
-    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, P, c->rec_keys.as<uint32_t>(), nrec, nullptr, 0,
-                  s);
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, static_cast<int64_t>(P) * kSub,
+                  c->rec_keys.as<uint32_t>(), nrec, nullptr, 0, s);
 
   hipEvent_t e0 = stamp(c, s);
   const GaussArgs ga = make_gauss(*g);
@@ -391,6 +401,7 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   ba.flags = misc + kFlags;
   uint32_t* total = reinterpret_cast<uint32_t*>(misc + kTotalKeys);
   const uint32_t* sorted = nullptr;
+  int blend_sort_cap = 0;
   if (!lsd) {
     launch_scan(c->tile_count.as<uint32_t>(), ntile, nullptr, c->ranges.as<uint2>(), c->scan_tmp.as<uint32_t>(), total,
                 c->key_cap, misc + kFlags, 2, s);
@@ -408,7 +419,7 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     ta.lds_cap = opts->lds_sort_cap > 0 ? std::min(opts->lds_sort_cap, 4096) : 4096;
     ta.gid_bits = bits_for(static_cast<uint64_t>(std::max<int64_t>(g->n, 2)));
     ta.flags = misc + kFlags;
-    launch_tile_sort(ta, s);
+    launch_tile_sort(ta, true, s);
     sorted = c->list.as<uint32_t>();
   } else {
     launch_scan(c->rec_keys.as<uint32_t>(), nrec, c->rec_offsets.as<uint32_t>(), nullptr, c->scan_tmp.as<uint32_t>(),
@@ -439,6 +450,15 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   bl.P = P;
   bl.ranges = c->ranges.as<uint2>();
   bl.list = sorted;
+  bl.keys = c->keys0.as<uint64_t>();
+  bl.vals = c->vals0.as<uint32_t>();
+  bl.list_out = c->list.as<uint32_t>();
+  bl.sort_cap = blend_sort_cap;
+  {
+    int fa = opts->feat_accum;
+    if (fa == HGSR_FEAT_AUTO) fa = c->tuned_feat ? c->tuned_feat : HGSR_FEAT_VALU;
+    bl.feat_mfma = fa == HGSR_FEAT_MFMA ? 1 : 0;
+  }
   bl.recs = c->recs.as<Splat>();
   bl.feat = g->feat;
   for (int k = 0; k < 3; ++k) bl.bg[k] = opts->bg[k];
@@ -478,17 +498,18 @@ hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream st
   if (!c || !overflowed) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  std::vector<uint32_t> counts(std::max(c->P, 1), 0);
+  std::vector<uint32_t> counts(std::max(c->P, 1) * kSub, 0);
   if (c->have_render)
-    HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, c->P * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, static_cast<size_t>(c->P) * kSub * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int32_t f = c->h_misc[kFlags];
   *overflowed = f;
   if (f) {
     if (c->capturing) return fail(HGSR_ERR_STATE, "cannot regrow during capture");
-    const uint32_t mx = *std::max_element(counts.begin(), counts.end());
+    const uint32_t mx = *std::max_element(counts.begin(), counts.end());  // largest sub-segment
     if (f & 1) {
-      c->rec_cap = static_cast<uint32_t>(std::min<uint64_t>(0x7fffffffull, mx + mx / 4 + 1024));
+      c->rec_cap = round_rec_cap(static_cast<int64_t>(mx) * kSub);
       c->key_cap = std::max<uint64_t>(c->key_cap * 2, c->key_cap);
     }
     if (f & 2) {
@@ -504,10 +525,10 @@ hgsr_status hgsr_stats(hgsr_ctx* c, hgsr_render_stats* out, hgsr_stream stream) 
   if (!c->have_render) return fail(HGSR_ERR_STATE, "no render yet");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t ntile = static_cast<int64_t>(c->P) * c->cam.tiles_per_pose;
-  std::vector<uint32_t> counts(c->P);
+  std::vector<uint32_t> counts(static_cast<size_t>(c->P) * kSub);
   std::vector<uint2> ranges(ntile);
   HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, c->P * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, counts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(ranges.data(), c->ranges.p, ntile * sizeof(uint2), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   out->visible = 0;
@@ -542,12 +563,10 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* c, int32_t pose, uint32_t* ranges, u
   }
   const int64_t cnt = static_cast<int64_t>(hi) - lo;
   std::vector<uint32_t> idx(std::max<int64_t>(cnt, 1));
-  uint32_t nrec = 0;
-  HIP_TRY(hipMemcpyAsync(&nrec, c->pose_count.as<uint32_t>() + pose, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  const uint32_t nrec = c->rec_cap;
   if (cnt > 0)
     HIP_TRY(hipMemcpyAsync(idx.data(), c->sorted + lo, cnt * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  nrec = std::min(nrec, c->rec_cap);
   std::vector<Splat> recs(std::max<uint32_t>(nrec, 1));
   const int64_t base = static_cast<int64_t>(pose) * c->rec_cap;
   if (nrec > 0)
@@ -761,41 +780,48 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     FILE* f = fopen(cache_path, "r");
     if (f) {
       char line[1024];
-      int t = 0, sc = -1;
+      int t = 0, sc = -1, fa = HGSR_FEAT_VALU;
       float ms = 0.f;
       while (fgets(line, sizeof(line), f)) {
         if (!strstr(line, key)) continue;
         const char* pt = strstr(line, "\"tile\": ");
         const char* ps = strstr(line, "\"schedule\": ");
+        const char* pf = strstr(line, "\"feat_accum\": ");
         const char* pm = strstr(line, "\"ms\": ");
         if (pt && ps && pm) {
           t = atoi(pt + 8);
           sc = atoi(ps + 12);
+          fa = pf ? atoi(pf + 14) : HGSR_FEAT_VALU;
           ms = static_cast<float>(atof(pm + 6));
         }
       }
       fclose(f);
-      if ((t == 8 || t == 16 || t == 32) && sc >= 0 && sc <= 2) {
+      if ((t == 8 || t == 16 || t == 32) && sc >= 0 && sc <= 2 && (fa == HGSR_FEAT_VALU || fa == HGSR_FEAT_MFMA)) {
         c->tuned_tile = t;
         c->tuned_sched = sc;
-        if (result) *result = {t, sc, ms};
+        c->tuned_feat = fa;
+        if (result) *result = {t, sc, fa, ms};
         return HGSR_OK;
       }
     }
   }
   const int tiles[3] = {8, 16, 32};
   const int scheds[3] = {HGSR_SCHED_GRID, HGSR_SCHED_POSE_MAJOR, HGSR_SCHED_TILE_MAJOR};
+  const int feats[2] = {HGSR_FEAT_VALU, HGSR_FEAT_MFMA};
   hipEvent_t a = nullptr, b = nullptr;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
   float best = 1e30f;
-  int bt = 16, bs = HGSR_SCHED_GRID;
+  int bt = 16, bs = HGSR_SCHED_GRID, bf = HGSR_FEAT_VALU;
   for (int t : tiles)
-    for (int sc : scheds) {
-      if (sc != HGSR_SCHED_GRID && P == 1 && sc == HGSR_SCHED_TILE_MAJOR) continue;
+    for (int sc : scheds)
+      for (int fa : feats) {
+      if (P == 1 && sc == HGSR_SCHED_TILE_MAJOR) continue;
+      if (fa == HGSR_FEAT_MFMA && (g->feat_dim != 32 || t == 32)) continue;
       hgsr_opts o = *opts;
       o.tile = t;
       o.schedule = sc;
+      o.feat_accum = fa;
       for (int tries = 0; tries < 6; ++tries) {
         TRY(hgsr_render(c, g, poses, P, K, &o, out, stream));
         int32_t ovf = 0;
@@ -814,17 +840,20 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
         best = ms;
         bt = t;
         bs = sc;
+        bf = fa;
       }
     }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   c->tuned_tile = bt;
   c->tuned_sched = bs;
-  if (result) *result = {bt, bs, best};
+  c->tuned_feat = bf;
+  if (result) *result = {bt, bs, bf, best};
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "{%s, \"tile\": %d, \"schedule\": %d, \"ms\": %.5f}\n", key, bt, bs, best);
+      fprintf(f, "{%s, \"tile\": %d, \"schedule\": %d, \"feat_accum\": %d, \"ms\": %.5f}\n", key, bt, bs, bf,
+              best);
       fclose(f);
     }
   }

@@ -17,8 +17,8 @@ struct ProjectArgs {
   Splat* recs;               // P_total x rec_cap
   uint2* rects;              // tile rectangle per record (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t* rec_keys;        // entries per record (LSD path) or null
-  uint32_t* pose_count;      // visible count per pose (may exceed rec_cap)
-  uint32_t rec_cap;          // records per pose
+  uint32_t* pose_count;      // P x kSub sub-segment counters (may exceed rec_cap / kSub)
+  uint32_t rec_cap;          // records per pose (a multiple of kSub)
   uint32_t* tile_count;      // entries per (pose, tile) (bucket path) or null
   const uint64_t* part_vis;  // per pose: partitions that may be visible, or null
   int32_t* flags;            // [0]: overflow bits
@@ -67,7 +67,12 @@ struct BlendArgs {
   CamArgs c;
   int32_t P;
   const uint2* ranges;
-  const uint32_t* list;
+  const uint32_t* list;      // sorted record indices (lists the blend does not sort itself)
+  const uint64_t* keys;      // unsorted (depth bits << 32 | gid) keys, when the blend sorts
+  const uint32_t* vals;      // their record indices
+  uint32_t* list_out;        // where the blend stores the lists it sorted (for the backward)
+  int32_t sort_cap;          // lists up to this length are sorted by the blend; 0 = none
+  int32_t feat_mfma;         // accumulate 32 feature channels on the matrix cores
   const Splat* recs;
   const uint16_t* feat;      // n x D bf16
   float bg[3];
@@ -140,7 +145,7 @@ int64_t scan_block_count(int64_t n);
 void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s);
 void launch_emit_bucket(const BinArgs& a, hipStream_t s);
-void launch_tile_sort(const TileSortArgs& a, hipStream_t s);
+void launch_tile_sort(const TileSortArgs& a, bool short_lists, hipStream_t s);
 void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,
                      uint32_t* vals, hipStream_t s);
 void launch_lsd_sort(LsdArgs& a, int passes_gid, int passes_z, int passes_tile, int* out_buffer, hipStream_t s);

@@ -121,9 +121,13 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     }
   }
   __syncthreads();
+  // each block reserves its slots from one of kSub counters per pose, so the
+  // blocks' atomics spread over kSub addresses instead of one
+  const int sub = static_cast<int>(blockIdx.x % kSub);
+  const uint32_t sub_cap = a.rec_cap / kSub;
   for (int p = tid; p < a.P; p += 256) {
     const uint32_t cnt = s_cnt[p];
-    s_base[p] = cnt ? atomicAdd(&a.pose_count[a.pose_base + p], cnt) : 0u;
+    s_base[p] = cnt ? atomicAdd(&a.pose_count[(a.pose_base + p) * kSub + sub], cnt) : 0u;
     s_cnt[p] = 0;
   }
   __syncthreads();
@@ -139,11 +143,12 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     if (!(mc[2] > a.c.near_z)) continue;
     Footprint f;
     if (!footprint(T, mc, S, k2, a.c, f)) continue;
-    const uint32_t slot = s_base[p] + atomicAdd(&s_cnt[p], 1u);
-    if (slot >= a.rec_cap) {
+    const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
+    if (local >= sub_cap) {
       atomicOr(a.flags, 1);
       continue;
     }
+    const uint32_t slot = sub * sub_cap + local;
     // view direction from the camera centre C = -R^T t
     const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
     const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);

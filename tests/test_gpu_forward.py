@@ -117,6 +117,27 @@ def test_sort_paths_and_schedules_bitwise(hg):
                     assert np.array_equal(to_np(base[k]), to_np(o[k])), (sort, sched, tile, k)
 
 
+@pytest.mark.parametrize("tile", [8, 16])
+def test_mfma_feature_accumulation(hg, oracle_mod, tile):
+    """The matrix-core feature sum (32 channels) matches the oracle to the same
+    bar, leaves colour/depth/alpha bitwise unchanged, and differs from the VALU
+    sum only by association order."""
+    sc, P, cam = synth.tiny_scene(500, 21, width=99, height=70, feat_dim=32, sh_degree=3)
+    Ps = synth.perturb_poses(P[0], 3, 22, 1.0, 2.0)
+    log(f"case: mfma features tile={tile}")
+    mf, _ = _render(hg, sc, Ps, cam, tile=tile, feat_accum="mfma")
+    va, _ = _render(hg, sc, Ps, cam, tile=tile, feat_accum="valu")
+    for k in ("rgb", "depth", "alpha", "final_T"):
+        if k in mf:
+            assert np.array_equal(to_np(mf[k]), to_np(va[k])), k
+    d = np.abs(to_np(mf["feat"]) - to_np(va["feat"])).max()
+    log(f"mfma vs valu feature max abs diff {d:.3g}")
+    assert d < 1e-5
+    for p in range(len(Ps)):
+        ref = oracle_mod.render(sc, Ps[p], cam, tile=16, margin=1)
+        parity(mf, ref, p=p, label=f"mfma/t{tile}/{p}", max_fragile_frac=0.05)
+
+
 def test_batched_equals_single(hg):
     sc, P, cam = synth.tiny_scene(400, 8, width=80, height=64, feat_dim=8, sh_degree=2)
     Ps = synth.perturb_poses(P[0], 7, 4, 1.5, 3.0)
