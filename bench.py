@@ -1,16 +1,33 @@
 """Benchmark of the splat rasterizer on one MI355X.
 
-Workload (default): 1,000,000 Gaussians (900k on a 1x1 km heightfield plus
-2,000 box buildings, SH degree 3, 32-d bf16 features), one 1920x1080 view,
-fx = 1500, 100-300 m altitude, tilt <= 30 deg.  A step renders that view
-(projection, tile binning, sort, blend: RGB + depth + alpha + 32-channel FP32
-feature map).  Prints one JSON line.
+Headline (the JSON line's `value`): forward rendering throughput on
+1,000,000 Gaussians (900k on a 1x1 km heightfield plus 2,000 box buildings,
+SH degree 3, 32-d bf16 features), one 1920x1080 view, fx = 1500, 100-300 m
+altitude, tilt <= 30 deg.  A step renders that view (projection, tile
+binning, sort, blend: RGB + depth + alpha + 32-channel FP32 feature map).
+
+Beside it, in the same line:
+  fwd_bwd     one pose-refinement step (render, L1 + feature-cosine residual,
+              backward to the pose, Adam update) over 64 candidate poses of
+              the same scene at 960x540: the batched path (autotuned tile and
+              schedule, one launch per stage for all poses, the step captured
+              in a HIP graph) against the plain single-pose path looped over
+              the same poses (eager, no graph).
+  partitioned 8M Gaussians in 16 spatial partitions over 4x4 km, 16 query
+              poses, three coarse-to-fine levels (480x270, 960x540,
+              1920x1080) of 20 batched refinement steps each, every level a
+              captured graph; per-step latency p50/p99 and device memory use.
+  roofline    the blend kernel's algorithmic bytes per launch over its
+              event-timed duration, against HBM peak.
+  cpu_baseline the FP64 oracle on the host cores, on a bounded sample.
 
 python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-cpu]
+                [--no-fwd-bwd] [--no-partitioned]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,33 +37,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the blend kernel measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE, scaled by a plain copy's readings); valid only for the source it
+# was taken on, identified by a hash of the blend sources.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_fwd_1080p_1M_traffic.txt")
+BLEND_SOURCES = ("paper_2507_15683_amd/csrc/blend.hip", "paper_2507_15683_amd/csrc/hgsr_device.hpp")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--sort", default="bucket")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the renderer shards by pose with "
-              "no collective; run one process per GPU instead)", file=sys.stderr)
-        sys.exit(2)
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
-    import ctypes
 
+def blend_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in BLEND_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tile: int, feat_accum: str):
+    """HBM bytes per blend launch from the committed counter summary, or None
+    when it was taken on other sources or another kernel variant."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != blend_source_hash():
+            return None
+        if int(kv.get("tile", 0)) != tile or kv.get("feat_accum") != feat_accum:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def pct(xs, q):
     import numpy as np
-    import torch
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
-    import paper_2507_15683_amd as hg
-    import synth
 
-    def log(*a):
-        print(*a, file=sys.stderr, flush=True)
-
+def headline(hg, torch, synth, args):
+    """Config: 1M Gaussians, 1920x1080, one pose (forward only)."""
+    import ctypes
     log("bench: generating the 1M-Gaussian scene")
     sc, P, cam = synth.config2(0)
     scene = hg.GaussianScene.from_numpy(sc)
@@ -55,10 +91,20 @@ def main():
     r = hg.Renderer()
     out = r.alloc_outputs(scene, 1, K)
     log("bench: first render (sizes the workspace)")
-    r.render(scene, poses, K, tile=args.tile, sort=args.sort, out=out)
+    r.render(scene, poses, K, tile=16, sort=args.sort, out=out)
+    if args.tile:
+        tile, feat_accum = args.tile, ("valu" if args.feat == "auto" else args.feat)
+        opts = r.opts(tile=tile, sort=args.sort, feat_accum=feat_accum)
+        tuned = None
+    else:
+        tuned = r.autotune(scene, poses, K, out, sort=args.sort)
+        log("bench: autotuned", tuned)
+        tile, feat_accum = tuned["tile"], tuned["feat_accum"]
+        opts = r.opts(tile=0, sort=args.sort, schedule="auto")
+    r.render(scene, poses, K, tile=tile, sort=args.sort, schedule=tuned["schedule"] if tuned else "grid",
+             feat_accum=feat_accum, out=out)
     st = r.stats()
     log("bench: stats", st)
-    opts = r.opts(tile=args.tile, sort=args.sort)
     for _ in range(args.warmup):
         r.render_into(scene, poses, K, out, opts)
     torch.cuda.synchronize()
@@ -75,52 +121,352 @@ def main():
     t1 = time.perf_counter()
     lib.hgsr_profile_read(r.ctx, ms_acc, calls)
     lib.hgsr_profile_enable(r.ctx, 0)
-    assert r.check_overflow() == 0
+    if r.check_overflow() != 0:
+        raise RuntimeError("workspace overflow during the timed renders")
     ms = (t1 - t0) / args.steps * 1e3
     W, H, D = cam.width, cam.height, sc.feat_dim
-    mpix = W * H / (ms * 1e-3) / 1e6
     stage_ms = [ms_acc[k] / max(calls[k], 1) for k in range(3)]
+
+    # the same view with bf16 feature output
+    out16 = r.alloc_outputs(scene, 1, K, feat_bf16=True)
+    opts16 = r.opts(tile=0 if not args.tile else tile, sort=args.sort, schedule="auto" if not args.tile else "grid",
+                    feat_bf16=True, feat_accum="auto" if not args.tile else feat_accum)
+    for _ in range(args.warmup):
+        r.render_into(scene, poses, K, out16, opts16)
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.render_into(scene, poses, K, out16, opts16)
+    torch.cuda.synchronize()
+    b1 = time.perf_counter()
+    ms16 = (b1 - b0) / args.steps * 1e3
+
     # blend: algorithmic bytes per launch = per-pixel outputs (rgb 12 + depth 4
     # + alpha 4 + D*4 feature + 8 saved for the backward) + one read of every
     # visible splat (48 B record + 2*D feature)
     bytes_px = 12 + 4 + 4 + 4 * D + 8
     bytes_blend = W * H * bytes_px + st["visible"] * (48 + 2 * D)
     achieved = bytes_blend / (stage_ms[2] * 1e-3) / 1e9
+    traffic = measured_traffic(tile, feat_accum)
+    res = dict(ms=ms, mpix=W * H / (ms * 1e-3) / 1e6, ms16=ms16, stage_ms=stage_ms, tile=tile,
+               feat_accum=feat_accum, tuned=tuned, st=st, W=W, H=H, D=D, n=sc.n)
+    res["roofline"] = {"kernel": f"blend_fwd (tile {tile})", "bound": "hbm", "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": traffic, "bytes_per_launch": int(bytes_blend),
+                       "launch_us": round(stage_ms[2] * 1e3, 2)}
+    res["cpu_inputs"] = (sc, P, cam)
+    del out, out16, r
+    return res
+
+
+def refine_step_fns(hg, scene, K, lam_f=1.0):
+    def step(r, st, opts, stream):
+        r.render_into(scene, st["poses"], K, st["out"], opts, stream=stream)
+        hg.residual(st["out"]["rgb"], st["out"]["feat"], st["tgt_rgb"], st["tgt_feat"], lam_f=lam_f, out=st["res"],
+                    stream=stream)
+        r.backward(dict(rgb=st["res"][1], feat=st["res"][2]), want=("pose",), P=st["poses"].shape[0], scene=scene,
+                   grads=st["grads"], stream=stream)
+        hg.pose_adam(st["poses"], st["grads"]["pose"], st["m"], st["v"], st["step"], stream=stream)
+    return step
+
+
+def refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat):
+    NP = poses.shape[0]
+    st = dict(poses=poses, tgt_rgb=tgt_rgb, tgt_feat=tgt_feat,
+              m=torch.zeros((NP, 6), device="cuda"), v=torch.zeros((NP, 6), device="cuda"),
+              step=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    st["out"] = r.alloc_outputs(scene, NP, K)
+    st["res"] = (torch.empty(NP, device="cuda"), torch.empty((NP, 3, K.height, K.width), device="cuda"),
+                 torch.empty((NP, scene.feat_dim, K.height, K.width), device="cuda"))
+    st["grads"] = r.alloc_grads(scene, NP, ("pose",))
+    return st
+
+
+def reserve_headroom(r, NP, K, n, factor=1.5):
+    """Grow the workspace past the last render's needs so that poses moved by
+    the captured refinement steps still fit (nothing may allocate under
+    capture)."""
+    s = r.stats()
+    r.reserve(NP, K.width, K.height, s["tile"], int(factor * 2 * s["visible"] / NP) + 4096,
+              int(factor * s["keys"]) + 65536, n)
+
+
+def fwd_bwd(hg, torch, synth, args):
+    """64 candidate poses, 960x540, 1M Gaussians: batched + graph vs plain."""
+    log("bench: fwd+bwd, 64 poses at 960x540")
+    sc, P, cam, seed = synth.config3(0, with_seed=True)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    NP = P.shape[0]
+    rt = hg.Renderer()
+    q = rt.render(scene, torch.from_numpy(seed[None]).cuda(), K)
+    tgt_rgb = q["rgb"].expand(NP, -1, -1, -1).contiguous()
+    tgt_feat = q["feat"].expand(NP, -1, -1, -1).contiguous()
+    del q, rt
+    step_fn = refine_step_fns(hg, scene, K)
+    s = torch.cuda.Stream()
+
+    # batched: autotune, size, capture one step, replay
+    r = hg.Renderer()
+    st = refine_state(hg, torch, r, scene, K, torch.from_numpy(P).cuda(), tgt_rgb, tgt_feat)
+    tuned = r.autotune(scene, st["poses"], K, st["out"])
+    log("bench: autotuned (64 poses)", tuned)
+    opts = r.opts(tile=0, schedule="auto")
+    r.render(scene, st["poses"], K, tile=tuned["tile"], schedule=tuned["schedule"], feat_accum=tuned["feat_accum"],
+             out=st["out"])
+    reserve_headroom(r, NP, K, sc.n)
+    # forward-only batched throughput
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.fb_steps):
+        r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
+    e1.record(s)
+    s.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / args.fb_steps
+    with torch.cuda.stream(s):
+        step_fn(r, st, opts, s)
+    s.synchronize()
+    if r.check_overflow(s) != 0:
+        raise RuntimeError("workspace overflow in the batched warm-up step")
+    st["poses"].copy_(torch.from_numpy(P).cuda())
+    st["m"].zero_(); st["v"].zero_(); st["step"].zero_()
+    torch.cuda.synchronize()
+    r.graph_begin(s)
+    step_fn(r, st, opts, s)
+    r.graph_end()
+    r.graph_launch(2, s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    r.graph_launch(args.fb_steps, s)
+    e1.record(s)
+    s.synchronize()
+    t1 = time.perf_counter()
+    batched_ms = e0.elapsed_time(e1) / args.fb_steps
+    if r.check_overflow(s) != 0:
+        raise RuntimeError("workspace overflow during the captured refinement steps")
+    loss_b = st["res"][0].mean().item()
+    del st, r
+
+    # plain: one pose at a time, tile 16, grid schedule, eager
+    rp = hg.Renderer()
+    poses_p = torch.from_numpy(P).cuda()
+    per = []
+    for p in range(NP):
+        stp = refine_state(hg, torch, rp, scene, K, poses_p[p:p + 1], tgt_rgb[p:p + 1], tgt_feat[p:p + 1])
+        per.append(stp)
+    # size the workspace on every pose first
+    for p in range(NP):
+        rp.render(scene, per[p]["poses"], K, tile=16, out=per[p]["out"])
+    popts = rp.opts(tile=16, schedule="grid")
+    with torch.cuda.stream(s):
+        for p in range(NP):
+            step_fn(rp, per[p], popts, s)
+    s.synchronize()
+    e0.record(s)
+    with torch.cuda.stream(s):
+        for _ in range(args.plain_steps):
+            for p in range(NP):
+                step_fn(rp, per[p], popts, s)
+    e1.record(s)
+    s.synchronize()
+    plain_ms = e0.elapsed_time(e1) / args.plain_steps
+    if rp.check_overflow(s) != 0:
+        raise RuntimeError("workspace overflow in the plain loop")
+    del per, rp
+    W, H = cam.width, cam.height
+    return {"workload": "1M Gaussians, 64 candidate poses at 960x540 (fx 750), pose refinement step: render + "
+                        "L1/feature-cosine residual + backward to the pose + Adam",
+            "batched_graph_ms_per_step": round(batched_ms, 3), "plain_loop_ms_per_step": round(plain_ms, 3),
+            "speedup": round(plain_ms / batched_ms, 2), "batched_fwd_ms": round(fwd_ms, 3),
+            "batched_fwd_mpix_s": round(NP * W * H / (fwd_ms * 1e-3) / 1e6, 1),
+            "steps_timed": args.fb_steps, "plain_steps_timed": args.plain_steps, "autotuned": tuned,
+            "mean_loss_after": round(loss_b, 5)}
+
+
+def partitioned(hg, torch, synth, args):
+    """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
+    import numpy as np
+    log("bench: partitioned scene (8M Gaussians) generation")
+    sc, truth, start, cams = synth.config5(0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    NQ = truth.shape[0]
+    s = torch.cuda.Stream()
+    r = hg.Renderer()
+    poses = torch.from_numpy(start).cuda()
+    lat, per_level = [], []
+    free0, total = torch.cuda.mem_get_info()
+    t_start = time.perf_counter()
+    for lvl, cam in enumerate(cams):
+        K = hg.Intrinsics.of(cam)
+        step_fn = refine_step_fns(hg, scene, K)
+        tgt = r.render(scene, torch.from_numpy(truth).cuda(), K)
+        tgt_rgb, tgt_feat = tgt["rgb"].clone(), tgt["feat"].clone()
+        del tgt
+        st = refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat)
+        tuned = r.autotune(scene, poses, K, st["out"])
+        opts = r.opts(tile=0, schedule="auto")
+        r.render(scene, poses, K, tile=tuned["tile"], schedule=tuned["schedule"], feat_accum=tuned["feat_accum"],
+                 out=st["out"])
+        reserve_headroom(r, NQ, K, sc.n)
+        keep = poses.clone()
+        with torch.cuda.stream(s):
+            step_fn(r, st, opts, s)  # warm-up (then undone)
+        s.synchronize()
+        poses.copy_(keep)
+        st["m"].zero_(); st["v"].zero_(); st["step"].zero_()
+        torch.cuda.synchronize()
+        r.graph_begin(s)
+        step_fn(r, st, opts, s)
+        r.graph_end()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.part_iters + 1)]
+        ev[0].record(s)
+        for k in range(args.part_iters):
+            r.graph_launch(1, s)
+            ev[k + 1].record(s)
+        s.synchronize()
+        if r.check_overflow(s) != 0:
+            raise RuntimeError(f"workspace overflow at level {lvl}")
+        ll = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.part_iters)]
+        lat += ll
+        per_level.append({"size": f"{cam.width}x{cam.height}", "tile": tuned["tile"], "schedule": tuned["schedule"],
+                          "p50_ms": round(pct(ll, 50), 3), "p99_ms": round(pct(ll, 99), 3),
+                          "loss": round(st["res"][0].mean().item(), 5)})
+        log("bench: level", per_level[-1])
+        del st, tgt_rgb, tgt_feat
+    wall = time.perf_counter() - t_start
+    free1, _ = torch.cuda.mem_get_info()
+    fin = poses.cpu().numpy().astype(np.float64).reshape(NQ, 3, 4)
+    tr = truth.astype(np.float64).reshape(NQ, 3, 4)
+    s0 = start.astype(np.float64).reshape(NQ, 3, 4)
+    cpos = lambda T: -np.einsum("qji,qj->qi", T[:, :, :3], T[:, :, 3])
+    e0 = np.linalg.norm(cpos(s0) - cpos(tr), axis=1)
+    e1 = np.linalg.norm(cpos(fin) - cpos(tr), axis=1)
+    return {"workload": "8M Gaussians in 16 partitions over 4x4 km, 16 query poses, 3 levels (480x270, 960x540, "
+                        f"1920x1080) x {args.part_iters} captured fwd+bwd refinement steps",
+            "step_p50_ms": round(pct(lat, 50), 3), "step_p99_ms": round(pct(lat, 99), 3), "levels": per_level,
+            "device_mem_in_use_gb": round((total - free1) / 1e9, 2),
+            "device_mem_before_gb": round((total - free0) / 1e9, 2),
+            "torch_peak_allocated_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2),
+            "camera_centre_error_m": {"start_median": round(float(np.median(e0)), 3),
+                                      "final_median": round(float(np.median(e1)), 3)},
+            "wall_s": round(wall, 2)}
+
+
+def cpu_baseline(synth, sc, P, cam, budget_s):
+    """The FP64 oracle on the host cores: frames of the headline scene at the
+    headline pose and nearby poses until `budget_s` seconds have passed."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    poses = np.concatenate([P[:1], synth.perturb_poses(P[0], 63, 77, 2.0, 1.0)])
+    frames, tested, blended = 0, 0, 0
+    c0 = time.perf_counter()
+    while frames < len(poses):
+        ref = oracle.render(sc, poses[frames], cam, tile=16, margin=0)
+        tested += ref["stats"]["tested"]
+        blended += ref["stats"]["blended"]
+        frames += 1
+        if time.perf_counter() - c0 >= budget_s:
+            break
+    c1 = time.perf_counter()
+    W, H = cam.width, cam.height
+    return {"value": round(frames * W * H / (c1 - c0) / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{frames} full 1920x1080 frames of the headline scene (headline pose, then nearby poses), "
+                      "FP64 tiled oracle", "seconds": round(c1 - c0, 3),
+            "oracle_tested_pairs_per_frame": int(tested / frames), "oracle_blended_pairs_per_frame":
+                int(blended / frames)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle sample")
+    ap.add_argument("--tile", type=int, default=0, help="0: autotuned")
+    ap.add_argument("--sort", default="bucket")
+    ap.add_argument("--feat", choices=["auto", "valu", "mfma"], default="auto",
+                    help="feature accumulation with a fixed --tile (auto: the VALU)")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--no-partitioned", action="store_true")
+    ap.add_argument("--fb-steps", type=int, default=20)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--part-iters", type=int, default=20)
+    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned"], default=None,
+                    help="run one section and print its result alone (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (5 launches), to scale HBM counters")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 1 << 28  # 1 GiB of float32
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the renderer shards by pose with "
+              "no collective; run one process per GPU instead)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2507_15683_amd as hg
+    import synth
+
+    if args.only == "fwd_bwd":
+        print(json.dumps({"fwd_bwd": fwd_bwd(hg, torch, synth, args)}), flush=True)
+        return
+    if args.only == "partitioned":
+        print(json.dumps({"partitioned": partitioned(hg, torch, synth, args)}), flush=True)
+        return
+    if args.only == "headline":
+        args.no_fwd_bwd = args.no_partitioned = args.no_cpu = True
+    h = headline(hg, torch, synth, args)
     result = {
         "metric": "rendered Mpix/s at 1080p/1M Gaussians",
-        "value": round(mpix, 2),
+        "value": round(h["mpix"], 2),
         "unit": "Mpix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": round(h["ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1M Gaussians (SH3, 32-d bf16 features), 1920x1080, one pose, tile "
-                               f"{args.tile}, {args.sort} sort", "gaussians": sc.n, "width": W, "height": H,
-                   "feat_dim": D, "visible": st["visible"], "keys": st["keys"]},
-        "stages_ms": {"project": round(stage_ms[0], 4), "bin_sort": round(stage_ms[1], 4),
-                      "blend": round(stage_ms[2], 4)},
-        "roofline": {"kernel": "blend_fwd", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": int(bytes_blend)},
+        "config": {"workload": "1M Gaussians (SH3, 32-d bf16 features), 1920x1080, one pose, forward render "
+                               f"(tile {h['tile']}, {args.sort} sort)", "gaussians": h["n"], "width": h["W"],
+                   "height": h["H"], "feat_dim": h["D"], "visible": h["st"]["visible"], "keys": h["st"]["keys"],
+                   "autotuned": h["tuned"]},
+        "stages_ms": {"project": round(h["stage_ms"][0], 4), "bin_sort": round(h["stage_ms"][1], 4),
+                      "blend": round(h["stage_ms"][2], 4)},
+        "bf16_feature_out": {"ms_per_step": round(h["ms16"], 4),
+                             "value": round(h["W"] * h["H"] / (h["ms16"] * 1e-3) / 1e6, 2), "unit": "Mpix/s"},
+        "roofline": h["roofline"],
     }
+    torch.cuda.empty_cache()
+    if not args.no_fwd_bwd:
+        result["fwd_bwd"] = fwd_bwd(hg, torch, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_partitioned:
+        result["partitioned"] = partitioned(hg, torch, synth, args)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        import oracle
-        oracle.build(force=False)
-        log("bench: timing the CPU oracle on the same 1080p view")
-        c0 = time.perf_counter()
-        ref = oracle.render(sc, P[0], cam, tile=16, margin=0)
-        c1 = time.perf_counter()
-        result["cpu_baseline"] = {"value": round(W * H / (c1 - c0) / 1e6, 4), "unit": "Mpix/s",
-                                  "cores": oracle.num_threads(), "kind": "oracle",
-                                  "sample": "one full 1920x1080 frame of the same scene and pose (FP64, tiled)",
-                                  "seconds": round(c1 - c0, 3)}
-        result["config"]["oracle_tested_pairs"] = ref["stats"]["tested"]
-        result["config"]["oracle_blended_pairs"] = ref["stats"]["blended"]
+        log("bench: timing the CPU oracle")
+        sc, P, cam = h["cpu_inputs"]
+        result["cpu_baseline"] = cpu_baseline(synth, sc, P, cam, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -20,27 +20,26 @@
 
 namespace hgsr {
 
-template <int TILE>
-struct BackShape {
-  static constexpr int kThreads = TILE == 8 ? 64 : 256;
-  static constexpr int kPPT = TILE * TILE / kThreads;
-};
-
 template <int TILE, int D, bool FEATGRAD>
-__global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
-  constexpr int NT = BackShape<TILE>::kThreads;
-  constexpr int PPT = BackShape<TILE>::kPPT;
-  constexpr int DV = D / 8;
+__global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
+  using Sh = BlendShape<TILE>;
+  constexpr int NT = Sh::kThreads, NB = Sh::kBatch, NW = Sh::kWaves, BW = Sh::kBlockW, BH = Sh::kBlockH;
+  constexpr int PPT = Sh::kPPT;
+  constexpr int DV = D / 8;                             // 16-byte bf16 vectors per feature
   constexpr int DD = D > 0 ? D : 1;
-  __shared__ float4 s_geo[NT];
-  __shared__ float4 s_opz[NT];
-  __shared__ float4 s_col[NT];
-  __shared__ uint32_t s_rec[NT];
-  __shared__ uint4 s_feat[DV > 0 ? NT * DV : 1];
+  constexpr int PARTS = (DV >= NT / NB) ? NT / NB : 1;  // threads sharing one splat's feature load
+  __shared__ float4 s_geo[NB];
+  __shared__ float4 s_opz[NB];
+  __shared__ float4 s_col[NB];
+  __shared__ uint32_t s_rec[NB];
+  __shared__ float s_f[D > 0 ? NB * D : 1];  // features as FP32
+  __shared__ uint8_t s_mask[NB];
+  __shared__ uint16_t s_list[NW][NB];
+  __shared__ float s_g[NB][10];  // per staged splat: the workgroup's gradient sums
   __shared__ uint32_t s_max;
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int W = a.c.W, H = a.c.H;
   const int64_t HW = static_cast<int64_t>(W) * H;
   const int item = blockIdx.x;
@@ -48,17 +47,19 @@ __global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(Ba
   const int tile = item - pose * a.c.tiles_per_pose;
   const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;
   const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
+  const int bx0 = tx * TILE + (wave % Sh::kBlocksX) * BW, by0 = ty * TILE + (wave / Sh::kBlocksX) * BH;
 
   float pxf[PPT], pyf[PPT], T[PPT], Tf[PPT], S[PPT], gC[PPT][3], GZ[PPT], gT[PPT];
   float gF[PPT][DD];
   uint32_t last[PPT];
   if (tid == 0) s_max = 0;
+  for (int e = tid; e < NB * 10; e += NT) (&s_g[0][0])[e] = 0.f;
   __syncthreads();
   uint32_t my_max = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int li = tid + k * NT;
-    const int px = tx * TILE + (li % TILE), py = ty * TILE + (li / TILE);
+    const int li = lane + k * kWave;
+    const int px = bx0 + (li % BW), py = by0 + (li / BW);
     const bool inside = px < W && py < H;
     pxf[k] = static_cast<float>(px) + 0.5f;
     pyf[k] = static_cast<float>(py) + 0.5f;
@@ -99,51 +100,77 @@ __global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(Ba
     }
     my_max = max(my_max, last[k]);
   }
-  atomicMax(&s_max, my_max);
+  // list positions this wave must visit: below the largest saved length
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) my_max = max(my_max, static_cast<uint32_t>(__shfl_xor(my_max, off, kWave)));
+  const uint32_t wave_max = my_max;
+  if (lane == 0) atomicMax(&s_max, wave_max);
   __syncthreads();
   const uint32_t n_max = s_max;
   if (n_max == 0) return;
 
   // batches back to front; positions are relative to range.x
-  const int n_batches = static_cast<int>((n_max + NT - 1) / NT);
+  const int n_batches = static_cast<int>((n_max + NB - 1) / NB);
   for (int bi = n_batches - 1; bi >= 0; --bi) {
-    const uint32_t b0 = static_cast<uint32_t>(bi) * NT;
-    __syncthreads();
+    const uint32_t b0 = static_cast<uint32_t>(bi) * NB;
+    const int nb = static_cast<int>(min(static_cast<uint32_t>(NB), n_max - b0));
     {
-      const uint32_t pos = b0 + tid;
-      if (pos < n_max) {
-        const uint32_t r = a.list[range.x + pos];
+      const int e = tid % NB, part = tid / NB;
+      if (e < nb) {
+        const uint32_t r = a.list[range.x + b0 + e];
         const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
         const float4 g1 = sp[1];
-        s_geo[tid] = sp[0];
-        s_opz[tid] = g1;
-        s_col[tid] = sp[2];
-        s_rec[tid] = r;
-        if constexpr (DV > 0) {
-          const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(__float_as_uint(g1.w)) * DV;
+        if (part == 0) {
+          const float4 g0 = sp[0], g2 = sp[2];
+          s_geo[e] = g0;
+          s_opz[e] = g1;
+          s_col[e] = g2;
+          s_rec[e] = r;
+          float x0, x1, y0, y1;
+          splat_rect(g0, g1, g2.w, x0, x1, y0, y1);
+          uint8_t m = 0;
 #pragma unroll
-          for (int q = 0; q < DV; ++q) s_feat[tid * DV + q] = fv[q];
+          for (int w = 0; w < NW; ++w) {
+            const float wx0 = static_cast<float>(tx * TILE + (w % Sh::kBlocksX) * BW);
+            const float wy0 = static_cast<float>(ty * TILE + (w / Sh::kBlocksX) * BH);
+            if (x1 >= wx0 && x0 <= wx0 + (BW - 1) && y1 >= wy0 && y0 <= wy0 + (BH - 1)) m |= 1u << w;
+          }
+          s_mask[e] = m;
+        }
+        if constexpr (DV > 0) {
+          if (part < PARTS) {
+            constexpr int QV = DV / PARTS;
+            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) +
+                              static_cast<int64_t>(__float_as_uint(g1.w)) * DV + part * QV;
+#pragma unroll
+            for (int q = 0; q < QV; ++q) {
+              const uint4 f = fv[q];
+              float4* dst = reinterpret_cast<float4*>(&s_f[e * D + 8 * (part * QV + q)]);
+              dst[0] = make_float4(bf16_lo(f.x), bf16_hi(f.x), bf16_lo(f.y), bf16_hi(f.y));
+              dst[1] = make_float4(bf16_lo(f.z), bf16_hi(f.z), bf16_lo(f.w), bf16_hi(f.w));
+            }
+          }
         }
       }
     }
     __syncthreads();
-    const int nb = static_cast<int>(min(static_cast<uint32_t>(NT), n_max - b0));
-    for (int jj = nb - 1; jj >= 0; --jj) {
+    // compact the batch to the entries touching this wave's block and below
+    // its largest saved length (in list order)
+    int n_mine = 0;
+    for (int c0 = 0; c0 < nb; c0 += kWave) {
+      const int ce = c0 + lane;
+      const bool hit = ce < nb && b0 + ce < wave_max && ((s_mask[ce] >> wave) & 1u);
+      const uint64_t bal = __ballot(hit);
+      if (hit) s_list[wave][n_mine + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(ce);
+      n_mine += __popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int ii = n_mine - 1; ii >= 0; --ii) {
+      const int jj = s_list[wave][ii];
       const uint32_t pos = b0 + jj;
       const float4 geo = s_geo[jj];
       const float4 opz = s_opz[jj];
       const float4 col = s_col[jj];
-      float fv[DD];
-      if constexpr (DV > 0) {
-#pragma unroll
-        for (int q = 0; q < DV; ++q) {
-          const uint4 fq = s_feat[jj * DV + q];
-          fv[8 * q + 0] = bf16_lo(fq.x); fv[8 * q + 1] = bf16_hi(fq.x);
-          fv[8 * q + 2] = bf16_lo(fq.y); fv[8 * q + 3] = bf16_hi(fq.y);
-          fv[8 * q + 4] = bf16_lo(fq.z); fv[8 * q + 5] = bf16_hi(fq.z);
-          fv[8 * q + 6] = bf16_lo(fq.w); fv[8 * q + 7] = bf16_hi(fq.w);
-        }
-      }
       float g[10];
 #pragma unroll
       for (int q = 0; q < 10; ++q) g[q] = 0.f;
@@ -168,8 +195,15 @@ __global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(Ba
         const float w = alpha * Tj;
         float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
         if constexpr (D > 0) {
+          const float4* fq = reinterpret_cast<const float4*>(&s_f[jj * D]);
 #pragma unroll
-          for (int d = 0; d < D; ++d) h = fmaf(gF[k][d], fv[d], h);
+          for (int q = 0; q < D / 4; ++q) {
+            const float4 f = fq[q];
+            h = fmaf(gF[k][4 * q + 0], f.x, h);
+            h = fmaf(gF[k][4 * q + 1], f.y, h);
+            h = fmaf(gF[k][4 * q + 2], f.z, h);
+            h = fmaf(gF[k][4 * q + 3], f.w, h);
+          }
         }
         const float dA = Tj * h - (S[k] + gT[k] * Tf[k]) / om;
         S[k] = fmaf(w, h, S[k]);
@@ -193,21 +227,25 @@ __global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(Ba
         }
       }
       if (!__any(any)) continue;
-#pragma unroll
-      for (int q = 0; q < 10; ++q) g[q] = wave_sum(g[q]);
+      wave_add10(g, s_g[jj]);
       if constexpr (FEATGRAD) {
 #pragma unroll
         for (int d = 0; d < DD; ++d) gfe[d] = wave_sum(gfe[d]);
-      }
-      if (lane == 0) {
-        float* dst = a.g_rec + static_cast<int64_t>(s_rec[jj]) * kGradRecStride;
-#pragma unroll
-        for (int q = 0; q < 10; ++q) atomicAdd(dst + q, g[q]);
-        if constexpr (FEATGRAD) {
+        if (lane == 0) {
           float* fd = a.g_featvec + static_cast<int64_t>(__float_as_uint(opz.w)) * D;
 #pragma unroll
           for (int d = 0; d < DD; ++d) atomicAdd(fd + d, gfe[d]);
         }
+      }
+    }
+    __syncthreads();
+    // one global atomic per nonzero sum of the batch; clear for the next
+    for (int e = tid; e < nb * 10; e += NT) {
+      const int slot = e / 10, q = e - slot * 10;
+      const float v = s_g[slot][q];
+      if (v != 0.f) {
+        atomicAdd(a.g_rec + static_cast<int64_t>(s_rec[slot]) * kGradRecStride + q, v);
+        s_g[slot][q] = 0.f;
       }
     }
   }
@@ -215,7 +253,7 @@ __global__ __launch_bounds__(BackShape<TILE>::kThreads) void blend_bwd_kernel(Ba
 
 template <int TILE, int D>
 static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
-  constexpr int NT = BackShape<TILE>::kThreads;
+  constexpr int NT = BlendShape<TILE>::kThreads;
   if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true>), dim3(items), dim3(NT), 0, s, a);
   else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false>), dim3(items), dim3(NT), 0, s, a);
 }
@@ -223,7 +261,7 @@ static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
 template <int TILE>
 static void launch_bwd_t(const BackArgs& a, int items, hipStream_t s) {
   switch (a.D) {
-    case 0: hipLaunchKernelGGL((blend_bwd_kernel<TILE, 0, false>), dim3(items), dim3(BackShape<TILE>::kThreads), 0,
+    case 0: hipLaunchKernelGGL((blend_bwd_kernel<TILE, 0, false>), dim3(items), dim3(BlendShape<TILE>::kThreads), 0,
                                s, a); break;
     case 8: launch_bwd_td<TILE, 8>(a, items, s); break;
     case 16: launch_bwd_td<TILE, 16>(a, items, s); break;

@@ -158,46 +158,90 @@ __global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t* in, int6
   }
 }
 
-// Whole scan in one block, chunk after chunk (small inputs).
-__global__ __launch_bounds__(256) void scan_single_kernel(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges,
-                                                          uint32_t* total, uint64_t cap, int32_t* flags,
-                                                          int32_t flag_bit) {
-  __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_v[kScanChunk];
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += kScanChunk) {
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
-      s_v[k * 256 + threadIdx.x] = i < n ? in[i] : 0u;
+// One 1024-thread block scans up to kWideChunk values in a single pass: each
+// thread loads 16 consecutive values (four 16-byte loads, all in flight at
+// once), the block scans the per-thread sums, and each thread writes its 16
+// results (eight 16-byte stores for ranges).  One global round trip instead
+// of one per chunk.
+constexpr int kWideThreads = 1024;
+constexpr int kWideItems = 16;
+constexpr int64_t kWideChunk = static_cast<int64_t>(kWideThreads) * kWideItems;
+
+__global__ __launch_bounds__(1024) void scan_wide_kernel(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges,
+                                                        uint32_t* total, uint64_t cap, int32_t* flags,
+                                                        int32_t flag_bit) {
+  __shared__ uint32_t s_w[kWideThreads / kWave];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  const int64_t b = static_cast<int64_t>(t) * kWideItems;
+  const bool full = b + kWideItems <= n;
+  uint32_t v[kWideItems];
+  if (full && (reinterpret_cast<uintptr_t>(in) & 15) == 0) {
+    const uint4* p = reinterpret_cast<const uint4*>(in + b);
+#pragma unroll
+    for (int k = 0; k < kWideItems / 4; ++k) {
+      const uint4 q = p[k];
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
     }
-    __syncthreads();
-    uint32_t vals[kScanItems];
-    uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-      vals[k] = s_v[threadIdx.x * kScanItems + k];
-      sum += vals[k];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan256(sum, s_w, &tot) + carry;
-    for (int k = 0; k < kScanItems; ++k) {
-      s_v[threadIdx.x * kScanItems + k] = run;
-      run += vals[k];
-    }
-    __syncthreads();
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t i = base + static_cast<int64_t>(k) * 256 + threadIdx.x;
-      if (i < n) {
-        const uint32_t st = s_v[k * 256 + threadIdx.x];
-        if (ranges) ranges[i] = make_uint2(st, st + in[i]);
-        else out[i] = st;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kWideItems; ++k) v[k] = b + k < n ? in[b + k] : 0u;
+  }
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kWideItems; ++k) sum += v[k];
+  const uint32_t inc = wave_incl_scan(sum);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWideThreads / kWave; ++k) {
+    const uint32_t x = s_w[k];
+    before += k < w ? x : 0u;
+    tot += x;
+  }
+  uint32_t run = before + inc - sum;
+  if (ranges) {
+    if (full && (reinterpret_cast<uintptr_t>(ranges) & 15) == 0) {
+      uint4* q = reinterpret_cast<uint4*>(ranges + b);
+#pragma unroll
+      for (int k = 0; k < kWideItems / 2; ++k) {
+        const uint32_t s0 = run, e0 = s0 + v[2 * k], e1 = e0 + v[2 * k + 1];
+        q[k] = make_uint4(s0, e0, e0, e1);
+        run = e1;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kWideItems; ++k) {
+        if (b + k < n) ranges[b + k] = make_uint2(run, run + v[k]);
+        run += v[k];
       }
     }
-    carry += tot;
-    __syncthreads();
+  } else {
+    if (full && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      uint4* q = reinterpret_cast<uint4*>(out + b);
+#pragma unroll
+      for (int k = 0; k < kWideItems / 4; ++k) {
+        uint4 o;
+        o.x = run; run += v[4 * k];
+        o.y = run; run += v[4 * k + 1];
+        o.z = run; run += v[4 * k + 2];
+        o.w = run; run += v[4 * k + 3];
+        q[k] = o;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kWideItems; ++k) {
+        if (b + k < n) out[b + k] = run;
+        run += v[k];
+      }
+    }
   }
-  if (threadIdx.x == 0) {
-    if (total) *total = carry;
-    if (flags && static_cast<uint64_t>(carry) > cap) atomicOr(flags, flag_bit);
+  if (t == 0) {
+    if (total) *total = tot;
+    if (flags && static_cast<uint64_t>(tot) > cap) atomicOr(flags, flag_bit);
   }
 }
 
@@ -207,8 +251,9 @@ void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, ui
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s) {
   const int64_t nb = scan_block_count(n);
   if (nb == 0) return;
-  if (nb <= 16) {
-    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(256), 0, s, in, n, out, ranges, total, cap, flags, flag_bit);
+  if (n <= kWideChunk) {
+    hipLaunchKernelGGL(scan_wide_kernel, dim3(1), dim3(kWideThreads), 0, s, in, n, out, ranges, total, cap, flags,
+                       flag_bit);
     return;
   }
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, block_sums);
@@ -251,27 +296,70 @@ void launch_emit_bucket(const BinArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
 }
 
-// Short lists (<= 256 entries): one wave per tile (4 tiles per workgroup)
-// runs the register bitonic sort; used when the blend does not sort them
-// itself.
+// Short lists (<= 256 entries): one wave per tile (4 tiles per workgroup).
+// The wave copies the tile's keys to LDS and each entry's final position is
+// its rank, the number of keys below it (keys are unique: the same Gaussian
+// enters a tile once); the loop over the keys is uniform, each step one LDS
+// broadcast and a 64-bit compare, with no dependent shuffle chain.
+template <int RR>
+__device__ __forceinline__ void rank_keys(const uint64_t* sk, uint32_t n, const uint64_t* key, uint32_t* rank) {
+  uint32_t j = 0;
+  for (; j + 4 <= n; j += 4) {
+    const uint64_t k0 = sk[j], k1 = sk[j + 1], k2 = sk[j + 2], k3 = sk[j + 3];
+#pragma unroll
+    for (int q = 0; q < RR; ++q)
+      rank[q] += static_cast<uint32_t>(k0 < key[q]) + static_cast<uint32_t>(k1 < key[q]) +
+                 static_cast<uint32_t>(k2 < key[q]) + static_cast<uint32_t>(k3 < key[q]);
+  }
+  for (; j < n; ++j) {
+    const uint64_t k0 = sk[j];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) rank[q] += static_cast<uint32_t>(k0 < key[q]);
+  }
+}
+
 __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
+  __shared__ uint64_t s_k[4][kWaveSortCap];
   if (a.flags[0] & 3) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int tg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const int tg = blockIdx.x * 4 + w;
   if (tg >= a.n_tiles) return;
-  const uint2 r = a.ranges[tg];
+  uint2 r = a.ranges[tg];
+  r.x = __builtin_amdgcn_readfirstlane(r.x);  // one tile per wave: uniform
+  r.y = __builtin_amdgcn_readfirstlane(r.y);
   const uint32_t n = r.y - r.x;
   if (n <= 1 || n > static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) {
     if (n == 1 && lane == 0) a.list[r.x] = a.vals[r.x];
     return;
   }
+  const int R = static_cast<int>((n + kWave - 1) / kWave);  // keys per lane, 1..4
   uint64_t key[4];
-  uint32_t val[4];
-  const int R = wave_sort256(a.keys + r.x, a.vals + r.x, n, key, val);
+  uint32_t val[4], rank[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t e = q * kWave + lane;
-    if (q < R && e < n) a.list[r.x + e] = val[q];
+    key[q] = ~0ull;
+    val[q] = 0;
+    rank[q] = 0;
+    if (q < R && e < n) {
+      key[q] = a.keys[r.x + e];
+      val[q] = a.vals[r.x + e];
+      s_k[w][e] = key[q];
+    }
+  }
+  // the wave's own LDS writes complete before its reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  switch (R) {
+    case 1: rank_keys<1>(s_k[w], n, key, rank); break;
+    case 2: rank_keys<2>(s_k[w], n, key, rank); break;
+    default: rank_keys<4>(s_k[w], n, key, rank); break;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t e = q * kWave + lane;
+    if (q < R && e < n) a.list[r.x + rank[q]] = val[q];
   }
 }
 

@@ -20,44 +20,27 @@
 namespace hgsr {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
-template <int TILE>
-struct BlendShape {
-  static constexpr int kThreads = TILE == 8 ? 64 : 256;
-  static constexpr int kBatch = kThreads < 128 ? kThreads : 128;  // splats staged per round
-  static constexpr int kWaves = kThreads / kWave;
-  // a wave's pixel block: 8x8 (16x16 with 4 pixels per lane at tile 32)
-  static constexpr int kBlockW = TILE == 32 ? 16 : 8;
-  static constexpr int kBlockH = TILE * TILE / kWaves / kBlockW;
-  static constexpr int kPPT = kBlockW * kBlockH / kWave;  // pixels per lane
-  static constexpr int kBlocksX = TILE / kBlockW;
-};
-
-// Pixel-centre rectangle of a splat's support, padded; shared by the wave
-// culling of the forward and backward blends.
-__device__ __forceinline__ void splat_rect(const float4 geo, const float4 opz, float pmin, float& x0, float& x1,
-                                           float& y0, float& y1) {
-  const float det = geo.z * opz.x - geo.w * geo.w;
-  const float k2 = -2.f * pmin;
-  const float rx = 1.001f * sqrtf(fmaxf(k2 * opz.x / det, 0.f)) + 0.05f;
-  const float ry = 1.001f * sqrtf(fmaxf(k2 * geo.z / det, 0.f)) + 0.05f;
-  x0 = geo.x - rx - 0.5f;
-  x1 = geo.x + rx - 0.5f;
-  y0 = geo.y - ry - 0.5f;
-  y1 = geo.y + ry - 0.5f;
-}
+// Splats per matrix-core step of the feature sum (16 or 8).
+#ifndef HGSR_MF_GROUP
+#define HGSR_MF_GROUP 8
+#endif
+constexpr int kMfGroup = HGSR_MF_GROUP;
 
 template <int TILE, int D, bool BF16, bool MFK>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
   using S = BlendShape<TILE>;
   constexpr int NT = S::kThreads, NB = S::kBatch, NW = S::kWaves, BW = S::kBlockW, BH = S::kBlockH, PPT = S::kPPT;
-  constexpr bool LDS_F32 = D > 0 && D <= 32;            // features as FP32 in LDS
+  // 32 feature channels, one pixel per lane: the feature sum can run on the
+  // matrix cores, per 16 splats F^T[32 ch x 64 px] += Feat^T[32 x 16] W[16 x 64]
+  // with the FP32 weights split exactly into three bfloat16 parts
+  constexpr bool MF = MFK && D == 32 && PPT == 1;
+  constexpr bool LDS_F32 = D > 0 && D <= 32 && !MF;     // features as FP32 in LDS (else raw bf16)
   constexpr int FW = D == 0 ? 1 : (LDS_F32 ? D : D / 2);  // 32-bit words per feature vector
   constexpr int DV = D / 8;                              // 16-byte bf16 vectors per feature
   constexpr int PARTS = (DV >= NT / NB) ? NT / NB : 1;   // threads sharing one splat's feature load
-  // 32 feature channels, one pixel per lane: the feature sum runs on the
-  // matrix cores (F^T[32 ch x 64 px] += Feat^T[32 x 2 splats] W[2 x 64 px])
-  constexpr bool MF = MFK && D == 32 && PPT == 1;
   __shared__ float4 s_geo[NB];
   __shared__ float4 s_opz[NB];
   __shared__ float4 s_col[NB];
@@ -202,47 +185,101 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       }
       __builtin_amdgcn_wave_barrier();
       if constexpr (MF) {
-        // one splat for this wave's pixels: colour, depth and transmittance
-        // on the VALU; returns the pixel's blend weight (0 when not blended)
-        auto walk = [&](int jj) -> float {
-          if (done[0]) return 0.f;
-          const float4 geo = s_geo[jj];
-          const float4 opz = s_opz[jj];
-          const float dx = pxf[0] - geo.x, dy = pyf[0] - geo.y;
-          const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
-          if (power > 0.f || power < s_col[jj].w - kPreReject) return 0.f;
-          const float alpha = pair_alpha(opz.y, power);
-          if (alpha < kAlphaMin) return 0.f;
-          const float Tn = T[0] * (1.f - alpha);
-          if (Tn < kTMin) {
-            done[0] = true;
-            return 0.f;
-          }
-          const float w = alpha * T[0];
-          const float4 col = s_col[jj];
-          C[0][0] = fmaf(w, col.x, C[0][0]);
-          C[0][1] = fmaf(w, col.y, C[0][1]);
-          C[0][2] = fmaf(w, col.z, C[0][2]);
-          Z[0] = fmaf(w, opz.z, Z[0]);
-          T[0] = Tn;
-          used[0] = b0 + jj - range.x + 1;
-          return w;
-        };
-        for (int ii = 0; ii < n_mine; ii += 2) {
+        // MG splats per matrix step: 16 (32x32x16 bf16) or 8 (32x32x8 bf16)
+        constexpr int MG = kMfGroup, HG = MG / 2;
+        const int ch = lane & 31, half = lane >> 5;
+        for (int ii = 0; ii < n_mine; ii += MG) {
           if (__all(done[0] ? 1 : 0)) break;  // every lane of the wave has stopped (uniform)
-          const int jj0 = s_list[wave][ii];
-          const int jj1 = ii + 1 < n_mine ? static_cast<int>(s_list[wave][ii + 1]) : -1;
-          const float w0 = walk(jj0);
-          const float w1 = jj1 >= 0 ? walk(jj1) : 0.f;
-          if (__any(w0 != 0.f || w1 != 0.f)) {
-            // B operands: lanes 0-31 carry splat jj0's weights, lanes 32-63
-            // splat jj1's, for pixels 0-31 (bw0) and 32-63 (bw1)
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(w0), __float_as_uint(w1), false, false);
-            const float bw0 = __uint_as_float(sw[0]), bw1 = __uint_as_float(sw[1]);
-            const int jsel = lane < 32 ? jj0 : jj1;
-            const float av = jsel >= 0 ? __uint_as_float(s_fw[jsel * FW + (lane & 31)]) : 0.f;
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bw0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bw1, acc1, 0, 0, 0);
+          // colour, depth and transmittance on the VALU, in list order; wq[q]
+          // is this pixel's weight for the group's q-th splat (0 if not blended)
+          float wq[MG];
+          int jq[MG];
+          bool any_w = false;
+#pragma unroll
+          for (int q = 0; q < MG; ++q) {
+            const int i = ii + q;
+            const int jj = i < n_mine ? __builtin_amdgcn_readfirstlane(static_cast<int>(s_list[wave][i])) : -1;
+            jq[q] = jj;
+            float w = 0.f;
+            if (jj >= 0 && !done[0]) {
+              const float4 geo = s_geo[jj];
+              const float4 opz = s_opz[jj];
+              const float dx = pxf[0] - geo.x, dy = pyf[0] - geo.y;
+              const float power = pair_power(dx, dy, geo.z, geo.w, opz.x);
+              if (power <= 0.f && power >= s_col[jj].w - kPreReject) {
+                const float alpha = pair_alpha(opz.y, power);
+                if (alpha >= kAlphaMin) {
+                  const float Tn = T[0] * (1.f - alpha);
+                  if (Tn < kTMin) {
+                    done[0] = true;
+                  } else {
+                    w = alpha * T[0];
+                    const float4 col = s_col[jj];
+                    C[0][0] = fmaf(w, col.x, C[0][0]);
+                    C[0][1] = fmaf(w, col.y, C[0][1]);
+                    C[0][2] = fmaf(w, col.z, C[0][2]);
+                    Z[0] = fmaf(w, opz.z, Z[0]);
+                    T[0] = Tn;
+                    used[0] = b0 + jj - range.x + 1;
+                    any_w = true;
+                  }
+                }
+              }
+            }
+            wq[q] = w;
+          }
+          if (!__any(any_w ? 1 : 0)) continue;
+          // A: channel ch of splats HG*half + 0..HG-1 (raw bf16; a missing
+          // splat reads slot 0 and meets zero weights)
+          uint32_t ap[HG / 2];
+#pragma unroll
+          for (int t = 0; t < HG; t += 2) {
+            const int j0 = max(half ? jq[HG + t] : jq[t], 0), j1 = max(half ? jq[HG + 1 + t] : jq[t + 1], 0);
+            const uint32_t f0 = reinterpret_cast<const uint16_t*>(s_fw)[j0 * D + ch];
+            const uint32_t f1 = reinterpret_cast<const uint16_t*>(s_fw)[j1 * D + ch];
+            ap[t / 2] = f0 | (f1 << 16);
+          }
+          // B: weights of splats HG*half + t for pixel ch (acc0) or 32 + ch
+          // (acc1); one lane-half exchange gives both.  The FP32 weights go
+          // in as three exact bfloat16 parts (hi, mid, lo): each step feeds
+          // the top 8 significant bits and keeps the exact remainder.
+          float r0[HG], r1[HG];
+#pragma unroll
+          for (int t = 0; t < HG; ++t) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(wq[t]), __float_as_uint(wq[HG + t]),
+                                                             false, false);
+            r0[t] = __uint_as_float(sw[0]);
+            r1[t] = __uint_as_float(sw[1]);
+          }
+#pragma unroll
+          for (int part = 0; part < 3; ++part) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              float* r = side ? r1 : r0;
+              uint32_t bp[HG / 2];
+#pragma unroll
+              for (int t = 0; t < HG / 2; ++t) {
+                const uint32_t x = __float_as_uint(r[2 * t]) & 0xffff0000u;
+                const uint32_t y = __float_as_uint(r[2 * t + 1]) & 0xffff0000u;
+                bp[t] = (x >> 16) | y;
+                if (part < 2) {
+                  r[2 * t] -= __uint_as_float(x);
+                  r[2 * t + 1] -= __uint_as_float(y);
+                }
+              }
+              floatx16& acc = side ? acc1 : acc0;
+              if constexpr (MG == 16) {
+                bf16x8 av, bv;
+                __builtin_memcpy(&av, ap, 16);
+                __builtin_memcpy(&bv, bp, 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+              } else {
+                shortx4 av, bv;
+                __builtin_memcpy(&av, ap, 8);
+                __builtin_memcpy(&bv, bp, 8);
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+              }
+            }
           }
         }
       } else {

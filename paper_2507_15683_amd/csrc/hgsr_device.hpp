@@ -74,6 +74,51 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Rotate a value by n lanes within each row of 16 lanes (DPP row_ror).
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 | N, 0xf, 0xf, false));
+}
+
+// Sum over the row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  return v;
+}
+
+// Sums ten per-lane values over the wave and atomically adds total v to
+// dst[v] (dst in LDS or global memory).  A reduce-scatter: the lane-half
+// exchange (v_permlane32_swap) pairs value i with value 5 + i, so lanes 0-31
+// carry values 0-4 and lanes 32-63 values 5-9; the row exchange
+// (v_permlane16_swap) pairs them again, leaving three partial sums per lane
+// that a 16-lane DPP row sum completes.  Totals end in lanes 0, 16, 32, 48:
+// row r = lane / 16 holds values 5 (r / 2) + (r % 2), 5 (r / 2) + 2 + (r % 2)
+// and, for even rows, 5 (r / 2) + 4.
+__device__ __forceinline__ void wave_add10(const float g[10], float* dst) {
+  float b[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[i]), __float_as_uint(g[5 + i]), false, false);
+    b[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  }
+  const auto s0 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[0]), __float_as_uint(b[1]), false, false);
+  const auto s1 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[2]), __float_as_uint(b[3]), false, false);
+  const auto s2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[4]), __float_as_uint(b[4]), false, false);
+  const float c0 = row_sum16(__uint_as_float(s0[0]) + __uint_as_float(s0[1]));
+  const float c1 = row_sum16(__uint_as_float(s1[0]) + __uint_as_float(s1[1]));
+  const float c2 = row_sum16(__uint_as_float(s2[0]) + __uint_as_float(s2[1]));
+  const int lane = threadIdx.x & (kWave - 1);
+  if ((lane & 15) == 0) {
+    const int base = 5 * (lane >> 5), odd = (lane >> 4) & 1;
+    atomicAdd(dst + base + odd, c0);
+    atomicAdd(dst + base + 2 + odd, c1);
+    if (!odd) atomicAdd(dst + base + 4, c2);
+  }
+}
+
 // World covariance Sigma_w = R_q diag(exp(2 ls)) R_q^T, (w,x,y,z) quaternion
 // normalised here.  Returns xx, xy, xz, yy, yz, zz.
 __device__ __forceinline__ void cov3_from(const float4 q4, const float ls[3], float S[6]) {
@@ -149,6 +194,25 @@ __device__ __forceinline__ bool footprint(const float* P, const float mc[3], con
   f.px0 = static_cast<int>(x0); f.px1 = static_cast<int>(x1);
   f.py0 = static_cast<int>(y0); f.py1 = static_cast<int>(y1);
   return true;
+}
+
+// Conservative early test before the covariance is formed: the support
+// half-width footprint() finds, sqrt(k2 (a^T Sigma a + dilation)) with
+// a = row 0 of J R, is at most sqrt(k2 (|a|^2 s_max^2 + dilation)) where
+// |a|^2 = (fx/z)^2 (1 + xh^2) for a rotation R and s_max is the largest
+// scale (likewise for y).  Returns false only when that larger rectangle,
+// widened by 0.1% and one pixel for rounding, misses the image; such a
+// Gaussian fails footprint() too.
+__device__ __forceinline__ bool maybe_visible(const float mc[3], float s2max, float k2, const CamArgs& c) {
+  const float iz = 1.0f / mc[2];
+  const float xz = mc[0] * iz, yz = mc[1] * iz;
+  const float xh = fminf(fmaxf(xz, -c.limx), c.limx);
+  const float yh = fminf(fmaxf(yz, -c.limy), c.limy);
+  const float gx = c.fx * iz, gy = c.fy * iz;
+  const float rx = 1.001f * sqrtf(k2 * fmaf(gx * gx * fmaf(xh, xh, 1.f), s2max, kDilation)) + 1.f;
+  const float ry = 1.001f * sqrtf(k2 * fmaf(gy * gy * fmaf(yh, yh, 1.f), s2max, kDilation)) + 1.f;
+  const float u = fmaf(c.fx, xz, c.cx), v = fmaf(c.fy, yz, c.cy);
+  return u + rx >= 0.f && v + ry >= 0.f && u - rx <= static_cast<float>(c.W) && v - ry <= static_cast<float>(c.H);
 }
 
 // Real spherical harmonics up to degree 3 (Condon-Shortley phase, index
@@ -277,6 +341,32 @@ __device__ __forceinline__ int wave_sort256(const uint64_t* keys, const uint32_t
     }
   }
   return R;
+}
+
+template <int TILE>
+struct BlendShape {
+  static constexpr int kThreads = TILE == 8 ? 64 : 256;
+  static constexpr int kBatch = kThreads < 128 ? kThreads : 128;  // splats staged per round
+  static constexpr int kWaves = kThreads / kWave;
+  // a wave's pixel block: 8x8 (16x16 with 4 pixels per lane at tile 32)
+  static constexpr int kBlockW = TILE == 32 ? 16 : 8;
+  static constexpr int kBlockH = TILE * TILE / kWaves / kBlockW;
+  static constexpr int kPPT = kBlockW * kBlockH / kWave;  // pixels per lane
+  static constexpr int kBlocksX = TILE / kBlockW;
+};
+
+// Pixel-centre rectangle of a splat's support, padded; shared by the wave
+// culling of the forward and backward blends.
+__device__ __forceinline__ void splat_rect(const float4 geo, const float4 opz, float pmin, float& x0, float& x1,
+                                           float& y0, float& y1) {
+  const float det = geo.z * opz.x - geo.w * geo.w;
+  const float k2 = -2.f * pmin;
+  const float rx = 1.001f * sqrtf(fmaxf(k2 * opz.x / det, 0.f)) + 0.05f;
+  const float ry = 1.001f * sqrtf(fmaxf(k2 * geo.z / det, 0.f)) + 0.05f;
+  x0 = geo.x - rx - 0.5f;
+  x1 = geo.x + rx - 0.5f;
+  y0 = geo.y - ry - 0.5f;
+  y1 = geo.y + ry - 0.5f;
 }
 
 constexpr int kWaveSortCap = 256;   // lists this short are sorted by one wave

@@ -84,6 +84,8 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
 
   bool live = i < a.g.n;
   float mu[3] = {0.f, 0.f, 0.f}, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o = 0.f, k2 = 0.f;
+  float ls[3] = {0.f, 0.f, 0.f}, s2max = 0.f;
+  bool have_cov = false;  // the covariance is formed for the first pose that may see the Gaussian
   uint64_t pose_ok = ~0ull;
   if (live) {
     o = a.g.opac[i];
@@ -101,14 +103,17 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     mu[0] = a.g.means[3 * i];
     mu[1] = a.g.means[3 * i + 1];
     mu[2] = a.g.means[3 * i + 2];
-    const float4 q = reinterpret_cast<const float4*>(a.g.quats)[i];
-    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
-    cov3_from(q, ls, S);
+    ls[0] = a.g.log_scales[3 * i];
+    ls[1] = a.g.log_scales[3 * i + 1];
+    ls[2] = a.g.log_scales[3 * i + 2];
+    s2max = __expf(2.f * fmaxf(ls[0], fmaxf(ls[1], ls[2])));
     k2 = 2.f * __logf(255.f * o);
   }
   __syncthreads();
 
-  // phase 1: count visible poses per block
+  // phase 1: count visible poses per block; vis_mask keeps the result for
+  // phase 2
+  uint64_t vis_mask = 0;
   if (live) {
     for (int p = 0; p < a.P; ++p) {
       if (!((pose_ok >> p) & 1ull)) continue;
@@ -116,8 +121,16 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
       float mc[3];
       to_camera(T, mu, mc);
       if (!(mc[2] > a.c.near_z)) continue;
+      if (!maybe_visible(mc, s2max, k2, a.c)) continue;
+      if (!have_cov) {
+        cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
+        have_cov = true;
+      }
       Footprint f;
-      if (footprint(T, mc, S, k2, a.c, f)) atomicAdd(&s_cnt[p], 1u);
+      if (footprint(T, mc, S, k2, a.c, f)) {
+        atomicAdd(&s_cnt[p], 1u);
+        vis_mask |= 1ull << p;
+      }
     }
   }
   __syncthreads();
@@ -132,17 +145,17 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
   }
   __syncthreads();
 
-  // phase 2: write records
-  if (!live) return;
+  // phase 2: write records (footprints recomputed, same inputs and
+  // arithmetic as phase 1)
+  if (!vis_mask) return;
   for (int p = 0; p < a.P; ++p) {
-    if (!((pose_ok >> p) & 1ull)) continue;
+    if (!((vis_mask >> p) & 1ull)) continue;
     const int pg = a.pose_base + p;
     const float* T = a.poses + 12 * pg;
     float mc[3];
     to_camera(T, mu, mc);
-    if (!(mc[2] > a.c.near_z)) continue;
     Footprint f;
-    if (!footprint(T, mc, S, k2, a.c, f)) continue;
+    footprint(T, mc, S, k2, a.c, f);
     const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
     if (local >= sub_cap) {
       atomicOr(a.flags, 1);

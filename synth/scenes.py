@@ -302,14 +302,17 @@ def config2(k=0):
     return scene, pose[None], cam
 
 
-def config3(k=0, count=64):
+def config3(k=0, count=64, with_seed=False):
     """The config-2 scene seen by 64 poses perturbed from a seed pose by
-    N(0,5 m) and N(0,3 deg), rendered at 960x540 with fx=750."""
+    N(0,5 m) and N(0,3 deg), rendered at 960x540 with fx=750.  with_seed
+    also returns the seed (query) pose."""
     scene = config2_scene(k)
     rng = np.random.Generator(np.random.PCG64(3000 + k))
     seed_pose = _aerial_pose(rng, 30.0)
     poses = perturb_poses(seed_pose, count, 3000 + k + 1, 5.0, 3.0)
     cam = Camera(750.0, 750.0, 480.0, 270.0, 960, 540)
+    if with_seed:
+        return scene, poses, cam, seed_pose
     return scene, poses, cam
 
 

@@ -231,3 +231,55 @@ def test_config2_full_parity(hg, oracle_mod):
     f32 = to_np(out["feat"][0])
     fb = to_np(ob["feat"][0])
     assert np.all(np.abs(fb - f32) <= np.abs(f32) * 2.0 ** -8 + 1e-30)
+
+
+def test_partitioned_equals_unpartitioned(hg, oracle_mod):
+    """Per-pose partition culling changes no output: a partitioned scene
+    renders bitwise like the same Gaussians without partitions, for poses
+    that see one, several or no partitions."""
+    import copy
+    sc = synth.partitioned_scene(16_000, 200.0, 7, cells_per_side=4, sh_degree=1, feat_dim=8, boxes_per_km2=800,
+                                 per_box=20)
+    flat = copy.copy(sc)
+    flat.part_offsets = None
+    cam = synth.Camera(160.0, 160.0, 64.0, 48.0, 128, 96)
+    poses = np.stack([synth.down_pose((-75.0, -75.0), 40.0), synth.down_pose((0.0, 0.0), 80.0, (0.2, -0.1)),
+                      synth.down_pose((60.0, -25.0), 50.0, (0.0, 0.3), 1.0),
+                      synth.down_pose((5000.0, 5000.0), 80.0)])
+    log("case: 4 poses, partitioned vs flat")
+    a, r = _render(hg, sc, poses, cam, schedule="pose")
+    b, _ = _render(hg, flat, poses, cam, schedule="pose")
+    for k in ("rgb", "depth", "alpha", "feat"):
+        assert np.array_equal(to_np(a[k]), to_np(b[k])), k
+    assert to_np(a["alpha"][3]).max() == 0  # looks at nothing
+    ref = oracle_mod.render(sc, poses[1], cam)
+    parity(a, ref, p=1, label="partitioned/1", max_fragile_frac=0.05)
+
+
+def test_autotune_choice_and_cache(hg, tmp_path):
+    """The autotuner returns a valid choice, the renderer then uses it, and the
+    result equals the fixed default configuration (features within the
+    association-order difference of the matrix-core sum); a second tuner on
+    the same shape reads the cache file instead of timing."""
+    sc, P, cam = synth.tiny_scene(800, 31, width=96, height=72, feat_dim=32, sh_degree=2)
+    Ps = synth.perturb_poses(P[0], 6, 32, 1.0, 2.0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    r = hg.Renderer()
+    out = r.alloc_outputs(scene, len(Ps), K)
+    cache = str(tmp_path / "tune.jsonl")
+    log("case: autotune 6 poses")
+    res = r.autotune(scene, _poses(Ps), K, out, cache_path=cache)
+    log("tuned", res)
+    assert res["tile"] in (8, 16, 32) and res["schedule"] in ("grid", "pose", "tile")
+    assert res["feat_accum"] in ("valu", "mfma") and res["ms"] > 0
+    tuned = r.render(scene, _poses(Ps), K, tile=0, schedule="auto")
+    assert r.stats()["tile"] == res["tile"]
+    base, _ = _render(hg, sc, Ps, cam, tile=16, feat_accum="valu")
+    for k in ("rgb", "depth", "alpha"):
+        assert np.array_equal(to_np(tuned[k]), to_np(base[k])), k
+    assert np.abs(to_np(tuned["feat"]) - to_np(base["feat"])).max() < 1e-5
+    r2 = hg.Renderer()
+    res2 = r2.autotune(scene, _poses(Ps), K, out, cache_path=cache)
+    assert (res2["tile"], res2["schedule"], res2["feat_accum"]) == (res["tile"], res["schedule"], res["feat_accum"])
+    assert abs(res2["ms"] - res["ms"]) < 1e-4
