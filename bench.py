@@ -159,14 +159,16 @@ def headline(hg, torch, synth, args):
     return res
 
 
-def refine_step_fns(hg, scene, K, lam_f=1.0):
+def refine_step_fns(hg, scene, K, lam_f=1.0, lr_rho=1e-2, lr_phi=1e-3):
+    """One refinement step: render with the residual evaluated in the blend
+    (the feature map itself is not written), backward to the pose, Adam."""
     def step(r, st, opts, stream):
-        r.render_into(scene, st["poses"], K, st["out"], opts, stream=stream)
-        hg.residual(st["out"]["rgb"], st["out"]["feat"], st["tgt_rgb"], st["tgt_feat"], lam_f=lam_f, out=st["res"],
-                    stream=stream)
+        r.render_residual_into(scene, st["poses"], K, st["out"], opts, st["tgt_rgb"], st["tgt_feat"], st["res"],
+                               lam_f=lam_f, stream=stream)
         r.backward(dict(rgb=st["res"][1], feat=st["res"][2]), want=("pose",), P=st["poses"].shape[0], scene=scene,
                    grads=st["grads"], stream=stream)
-        hg.pose_adam(st["poses"], st["grads"]["pose"], st["m"], st["v"], st["step"], stream=stream)
+        hg.pose_adam(st["poses"], st["grads"]["pose"], st["m"], st["v"], st["step"], lr_rho=lr_rho, lr_phi=lr_phi,
+                     stream=stream)
     return step
 
 
@@ -176,6 +178,7 @@ def refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat):
               m=torch.zeros((NP, 6), device="cuda"), v=torch.zeros((NP, 6), device="cuda"),
               step=torch.zeros(1, dtype=torch.int32, device="cuda"))
     st["out"] = r.alloc_outputs(scene, NP, K)
+    st["out"]["feat"] = None  # the fused residual needs no feature map
     st["res"] = (torch.empty(NP, device="cuda"), torch.empty((NP, 3, K.height, K.width), device="cuda"),
                  torch.empty((NP, scene.feat_dim, K.height, K.width), device="cuda"))
     st["grads"] = r.alloc_grads(scene, NP, ("pose",))
@@ -200,8 +203,8 @@ def fwd_bwd(hg, torch, synth, args):
     NP = P.shape[0]
     rt = hg.Renderer()
     q = rt.render(scene, torch.from_numpy(seed[None]).cuda(), K)
-    tgt_rgb = q["rgb"].expand(NP, -1, -1, -1).contiguous()
-    tgt_feat = q["feat"].expand(NP, -1, -1, -1).contiguous()
+    # the query view, one target shared by all candidate poses
+    tgt_rgb, tgt_feat = q["rgb"].clone(), q["feat"].clone()
     del q, rt
     step_fn = refine_step_fns(hg, scene, K)
     s = torch.cuda.Stream()
@@ -209,23 +212,31 @@ def fwd_bwd(hg, torch, synth, args):
     # batched: autotune, size, capture one step, replay
     r = hg.Renderer()
     st = refine_state(hg, torch, r, scene, K, torch.from_numpy(P).cuda(), tgt_rgb, tgt_feat)
-    tuned = r.autotune(scene, st["poses"], K, st["out"])
-    log("bench: autotuned (64 poses)", tuned)
+    full = r.alloc_outputs(scene, NP, K)  # forward-only renders write every output
+    # forward-only batched throughput, at the tuning of the plain render
+    tuned_fwd = r.autotune(scene, st["poses"], K, full)
+    log("bench: autotuned forward (64 poses)", tuned_fwd)
     opts = r.opts(tile=0, schedule="auto")
-    r.render(scene, st["poses"], K, tile=tuned["tile"], schedule=tuned["schedule"], feat_accum=tuned["feat_accum"],
-             out=st["out"])
+    r.render(scene, st["poses"], K, tile=0, schedule="auto", out=full)
     reserve_headroom(r, NP, K, sc.n)
-    # forward-only batched throughput
     with torch.cuda.stream(s):
         for _ in range(3):
-            r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
+            r.render_into(scene, st["poses"], K, full, opts, stream=s)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(args.fb_steps):
-        r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
+        r.render_into(scene, st["poses"], K, full, opts, stream=s)
     e1.record(s)
     s.synchronize()
     fwd_ms = e0.elapsed_time(e1) / args.fb_steps
+    del full
+    # the refinement step's render (residual in the blend) is tuned on its own
+    tuned = r.autotune(scene, st["poses"], K, st["out"],
+                       residual=dict(rgb_target=tgt_rgb, feat_target=tgt_feat, res=st["res"]))
+    log("bench: autotuned refinement render (64 poses)", tuned)
+    r.render_residual(scene, st["poses"], K, tgt_rgb, tgt_feat, out=st["out"], res=st["res"], tile=0,
+                      schedule="auto")
+    reserve_headroom(r, NP, K, sc.n)
     with torch.cuda.stream(s):
         step_fn(r, st, opts, s)
     s.synchronize()
@@ -257,7 +268,7 @@ def fwd_bwd(hg, torch, synth, args):
     poses_p = torch.from_numpy(P).cuda()
     per = []
     for p in range(NP):
-        stp = refine_state(hg, torch, rp, scene, K, poses_p[p:p + 1], tgt_rgb[p:p + 1], tgt_feat[p:p + 1])
+        stp = refine_state(hg, torch, rp, scene, K, poses_p[p:p + 1], tgt_rgb, tgt_feat)
         per.append(stp)
     # size the workspace on every pose first
     for p in range(NP):
@@ -285,6 +296,7 @@ def fwd_bwd(hg, torch, synth, args):
             "speedup": round(plain_ms / batched_ms, 2), "batched_fwd_ms": round(fwd_ms, 3),
             "batched_fwd_mpix_s": round(NP * W * H / (fwd_ms * 1e-3) / 1e6, 1),
             "steps_timed": args.fb_steps, "plain_steps_timed": args.plain_steps, "autotuned": tuned,
+            "autotuned_forward": tuned_fwd,
             "mean_loss_after": round(loss_b, 5)}
 
 
@@ -303,15 +315,19 @@ def partitioned(hg, torch, synth, args):
     t_start = time.perf_counter()
     for lvl, cam in enumerate(cams):
         K = hg.Intrinsics.of(cam)
-        step_fn = refine_step_fns(hg, scene, K)
+        step_fn = refine_step_fns(hg, scene, K, lr_rho=args.part_lr_rho, lr_phi=args.part_lr_phi)
         tgt = r.render(scene, torch.from_numpy(truth).cuda(), K)
         tgt_rgb, tgt_feat = tgt["rgb"].clone(), tgt["feat"].clone()
         del tgt
         st = refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat)
-        tuned = r.autotune(scene, poses, K, st["out"])
+        full = r.alloc_outputs(scene, NQ, K)
+        r.render(scene, poses, K, out=full)  # sizes the workspace
+        del full
+        tuned = r.autotune(scene, poses, K, st["out"],
+                           residual=dict(rgb_target=tgt_rgb, feat_target=tgt_feat, res=st["res"]))
         opts = r.opts(tile=0, schedule="auto")
-        r.render(scene, poses, K, tile=tuned["tile"], schedule=tuned["schedule"], feat_accum=tuned["feat_accum"],
-                 out=st["out"])
+        r.render_residual(scene, poses, K, tgt_rgb, tgt_feat, out=st["out"], res=st["res"], tile=0,
+                          schedule="auto")
         reserve_headroom(r, NQ, K, sc.n)
         keep = poses.clone()
         with torch.cuda.stream(s):
@@ -399,6 +415,8 @@ def main():
     ap.add_argument("--fb-steps", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--part-iters", type=int, default=20)
+    ap.add_argument("--part-lr-rho", type=float, default=0.3, help="Adam step (m) of the partitioned refinement")
+    ap.add_argument("--part-lr-phi", type=float, default=4e-3, help="Adam step (rad) of the partitioned refinement")
     ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned"], default=None,
                     help="run one section and print its result alone (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -32,7 +32,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   __shared__ float4 s_opz[NB];
   __shared__ float4 s_col[NB];
   __shared__ uint32_t s_rec[NB];
-  __shared__ float s_f[D > 0 ? NB * D : 1];  // features as FP32
+  constexpr int FS = D + 4;  // padded slot stride (words): staging writes spread over banks
+  __shared__ float s_f[D > 0 ? NB * FS : 1];  // features as FP32
   __shared__ uint8_t s_mask[NB];
   __shared__ uint16_t s_list[NW][NB];
   __shared__ float s_g[NB][10];  // per staged splat: the workgroup's gradient sums
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
 #pragma unroll
             for (int q = 0; q < QV; ++q) {
               const uint4 f = fv[q];
-              float4* dst = reinterpret_cast<float4*>(&s_f[e * D + 8 * (part * QV + q)]);
+              float4* dst = reinterpret_cast<float4*>(&s_f[e * FS + 8 * (part * QV + q)]);
               dst[0] = make_float4(bf16_lo(f.x), bf16_hi(f.x), bf16_lo(f.y), bf16_hi(f.y));
               dst[1] = make_float4(bf16_lo(f.z), bf16_hi(f.z), bf16_lo(f.w), bf16_hi(f.w));
             }
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
         const float w = alpha * Tj;
         float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
         if constexpr (D > 0) {
-          const float4* fq = reinterpret_cast<const float4*>(&s_f[jj * D]);
+          const float4* fq = reinterpret_cast<const float4*>(&s_f[jj * FS]);
 #pragma unroll
           for (int q = 0; q < D / 4; ++q) {
             const float4 f = fq[q];

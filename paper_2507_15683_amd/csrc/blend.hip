@@ -2,9 +2,7 @@
 //
 // Each wave owns a square block of the tile (8x8 pixels at tile 8 and 16,
 // 16x16 with 4 pixels per lane at tile 32); compact blocks keep the lanes'
-// blend decisions coherent.  Tile lists up to `sort_cap` entries may arrive
-// unsorted and are then put in (depth, index) order by the workgroup's first
-// wave (a register bitonic sort).  The workgroup walks the tile's
+// blend decisions coherent.  The workgroup walks the tile's
 // depth-ordered list in batches: every thread stages one splat (geometry,
 // colour, FP32 feature vector) into LDS and marks which waves' blocks its
 // support rectangle touches; each wave then compacts the batch to the entries
@@ -13,7 +11,9 @@
 // are rejected before the exponential; the exact gate, clamp and stop tests
 // follow.  A pixel stops at the first splat that would take its transmittance
 // below 1e-4; the batch loop ends when every pixel of the tile has stopped.
-// Outputs are planar per pose.
+// Outputs are planar per pose.  With RES the epilogue also evaluates the
+// refinement residual against per-pixel targets from the FP32 accumulators
+// and writes its gradients (the feature map itself is then optional).
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -29,7 +29,7 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 #endif
 constexpr int kMfGroup = HGSR_MF_GROUP;
 
-template <int TILE, int D, bool BF16, bool MFK>
+template <int TILE, int D, bool BF16, bool MFK, bool RES>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
   using S = BlendShape<TILE>;
   constexpr int NT = S::kThreads, NB = S::kBatch, NW = S::kWaves, BW = S::kBlockW, BH = S::kBlockH, PPT = S::kPPT;
@@ -39,15 +39,18 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
   constexpr bool MF = MFK && D == 32 && PPT == 1;
   constexpr bool LDS_F32 = D > 0 && D <= 32 && !MF;     // features as FP32 in LDS (else raw bf16)
   constexpr int FW = D == 0 ? 1 : (LDS_F32 ? D : D / 2);  // 32-bit words per feature vector
+  // slot stride in words: padded by 4 so that the staging threads' 16-byte
+  // writes (one slot each) fall in different banks
+  constexpr int FS = D == 0 ? 1 : FW + 4;
   constexpr int DV = D / 8;                              // 16-byte bf16 vectors per feature
   constexpr int PARTS = (DV >= NT / NB) ? NT / NB : 1;   // threads sharing one splat's feature load
   __shared__ float4 s_geo[NB];
   __shared__ float4 s_opz[NB];
   __shared__ float4 s_col[NB];
-  __shared__ uint32_t s_fw[NB * FW];
+  __shared__ uint32_t s_fw[NB * FS];
   __shared__ uint8_t s_mask[NB];
   __shared__ uint16_t s_list[NW][NB];
-  __shared__ uint32_t s_order[kWaveSortCap];
+  __shared__ float s_lw[NW];
   __shared__ int s_item;
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
@@ -80,26 +83,6 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
     // this wave's pixel block
     const int bx0 = tx * TILE + (wave % S::kBlocksX) * BW, by0 = ty * TILE + (wave / S::kBlocksX) * BH;
-    // short unsorted lists are put in (depth, index) order here by wave 0
-    const uint32_t n_list = range.y - range.x;
-    const bool fused = n_list <= static_cast<uint32_t>(a.sort_cap);
-    if (fused && n_list > 0) {
-      if (wave == 0) {
-        uint64_t key[4];
-        uint32_t val[4];
-        const int R = wave_sort256(a.keys + range.x, a.vals + range.x, n_list, key, val);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t e = q * kWave + lane;
-          if (q < R && e < n_list) {
-            s_order[e] = val[q];
-            a.list_out[range.x + e] = val[q];
-          }
-        }
-      }
-      __syncthreads();
-    }
-
     float pxf[PPT], pyf[PPT], T[PPT], C[PPT][3], Z[PPT];
     float F[PPT][(D > 0 && !MF) ? D : 1];
     floatx16 acc0 = {}, acc1 = {};
@@ -131,7 +114,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       const int e = tid % NB, part = tid / NB;
       const uint32_t j = b0 + e;
       if (j < range.y) {
-        const uint32_t r = fused ? s_order[j - range.x] : a.list[j];
+        const uint32_t r = a.list[j];
         const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
         const float4 g1 = sp[1];
         if (part == 0) {
@@ -159,13 +142,13 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
 #pragma unroll
               for (int q = 0; q < QV; ++q) {
                 const uint4 f = fv[q];
-                uint4* dst = reinterpret_cast<uint4*>(&s_fw[e * FW + 8 * (part * QV + q)]);
+                uint4* dst = reinterpret_cast<uint4*>(&s_fw[e * FS + 8 * (part * QV + q)]);
                 dst[0] = make_uint4(f.x << 16, f.x & 0xffff0000u, f.y << 16, f.y & 0xffff0000u);
                 dst[1] = make_uint4(f.z << 16, f.z & 0xffff0000u, f.w << 16, f.w & 0xffff0000u);
               }
             } else {
 #pragma unroll
-              for (int q = 0; q < QV; ++q) reinterpret_cast<uint4*>(&s_fw[e * FW])[part * QV + q] = fv[q];
+              for (int q = 0; q < QV; ++q) reinterpret_cast<uint4*>(&s_fw[e * FS])[part * QV + q] = fv[q];
             }
           }
         }
@@ -235,8 +218,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
 #pragma unroll
           for (int t = 0; t < HG; t += 2) {
             const int j0 = max(half ? jq[HG + t] : jq[t], 0), j1 = max(half ? jq[HG + 1 + t] : jq[t + 1], 0);
-            const uint32_t f0 = reinterpret_cast<const uint16_t*>(s_fw)[j0 * D + ch];
-            const uint32_t f1 = reinterpret_cast<const uint16_t*>(s_fw)[j1 * D + ch];
+            const uint32_t f0 = reinterpret_cast<const uint16_t*>(s_fw)[j0 * 2 * FS + ch];
+            const uint32_t f1 = reinterpret_cast<const uint16_t*>(s_fw)[j1 * 2 * FS + ch];
             ap[t / 2] = f0 | (f1 << 16);
           }
           // B: weights of splats HG*half + t for pixel ch (acc0) or 32 + ch
@@ -313,7 +296,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
             Z[k] = fmaf(w, opz.z, Z[k]);
             if constexpr (D > 0) {
               if constexpr (LDS_F32) {
-                const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FW]);
+                const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FS]);
 #pragma unroll
                 for (int q = 0; q < D / 4; ++q) {
                   const float4 f = fq[q];
@@ -323,7 +306,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
                   F[k][4 * q + 3] = fmaf(w, f.w, F[k][4 * q + 3]);
                 }
               } else {
-                const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FW]);
+                const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FS]);
 #pragma unroll
                 for (int q = 0; q < D / 8; ++q) {
                   const uint4 f = fq[q];
@@ -346,14 +329,53 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     }
 
     const int64_t pbase = static_cast<int64_t>(pose) * HW;
+    float lsum = 0.f;  // this lane's residual terms (RES)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       if (!inside[k]) continue;
       const int64_t o = pbase + pix[k];
       const int64_t o3 = static_cast<int64_t>(pose) * 3 * HW + pix[k];
-      a.rgb[o3] = fmaf(T[k], a.bg[0], C[k][0]);
-      a.rgb[o3 + HW] = fmaf(T[k], a.bg[1], C[k][1]);
-      a.rgb[o3 + 2 * HW] = fmaf(T[k], a.bg[2], C[k][2]);
+      const float out_rgb[3] = {fmaf(T[k], a.bg[0], C[k][0]), fmaf(T[k], a.bg[1], C[k][1]),
+                                fmaf(T[k], a.bg[2], C[k][2])};
+      a.rgb[o3] = out_rgb[0];
+      a.rgb[o3 + HW] = out_rgb[1];
+      a.rgb[o3 + 2 * HW] = out_rgb[2];
+      if constexpr (RES) {
+        // L1 colour term and feature cosine term, as the residual kernel
+        // computes them, from this pixel's FP32 values
+        const float inv = a.res_inv_hw;
+        const int64_t tp = static_cast<int64_t>(pose) * a.res_t_stride;  // target image of this pose
+        const int64_t t3 = tp * 3 * HW + pix[k];
+        float l = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float d = out_rgb[ch] - a.res_rgb_t[t3 + ch * HW];
+          l += fabsf(d);
+          a.res_g_rgb[o3 + ch * HW] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+        }
+        if constexpr (D > 0 && !MF) {
+          const int64_t of = static_cast<int64_t>(pose) * D * HW + pix[k];
+          const int64_t tf = tp * D * HW + pix[k];
+          float dot = 0.f, na = 0.f, nb = 0.f;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const float t = a.res_feat_t[tf + d * HW];
+            dot = fmaf(F[k][d], t, dot);
+            na = fmaf(F[k][d], F[k][d], na);
+            nb = fmaf(t, t, nb);
+          }
+          na = sqrtf(na);
+          nb = sqrtf(nb);
+          const float n = na * nb + kCosEps;
+          const float cosv = dot / n;
+          l += a.res_lam * (1.f - cosv);
+          const float s1 = -a.res_lam * inv / n;
+          const float s2 = na > 0.f ? a.res_lam * inv * dot * nb / (n * n * na) : 0.f;
+#pragma unroll
+          for (int d = 0; d < D; ++d) a.res_g_feat[of + d * HW] = s1 * a.res_feat_t[tf + d * HW] + s2 * F[k][d];
+        }
+        lsum += l * inv;
+      }
       const float A = 1.f - T[k];
       a.alpha[o] = A;
       a.depth[o] = A > 0.f ? Z[k] / A : 0.f;
@@ -398,6 +420,18 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
         }
       }
     }
+    if constexpr (RES) {
+      // this tile's loss share, summed in a fixed order (waves, then lanes)
+      lsum = wave_sum(lsum);
+      if (lane == 0) s_lw[wave] = lsum;
+      __syncthreads();
+      if (tid == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += s_lw[w];
+        a.res_part[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile] = t;
+      }
+    }
     if (persistent) __syncthreads();
   }
 }
@@ -405,10 +439,12 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
 template <int TILE, int D, bool BF16>
 static void launch_t(const BlendArgs& a, int n_ctas, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
-  if (D == 32 && TILE != 32 && a.feat_mfma)
-    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, true>), dim3(n_ctas), dim3(NT), 0, s, a);
+  if (a.res_loss)
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false, true>), dim3(n_ctas), dim3(NT), 0, s, a);
+  else if (D == 32 && TILE != 32 && a.feat_mfma)
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, true, false>), dim3(n_ctas), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false>), dim3(n_ctas), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false, false>), dim3(n_ctas), dim3(NT), 0, s, a);
 }
 
 template <int TILE, int D>
@@ -426,6 +462,26 @@ static void launch_tile(const BlendArgs& a, int D, bool bf16, int n_ctas, hipStr
     case 32: launch_td<TILE, 32>(a, bf16, n_ctas, s); break;
     default: launch_td<TILE, 64>(a, bf16, n_ctas, s); break;
   }
+}
+
+// Per-pose loss from the per-tile shares, in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* part, int32_t tiles_per_pose, float* loss) {
+  __shared__ float s_r[256];
+  const int pose = blockIdx.x;
+  const float* p = part + static_cast<int64_t>(pose) * tiles_per_pose;
+  float v = 0.f;
+  for (int t = threadIdx.x; t < tiles_per_pose; t += 256) v += p[t];
+  s_r[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) s_r[threadIdx.x] += s_r[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[pose] = s_r[0];
+}
+
+void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(P), dim3(256), 0, s, part, tiles_per_pose, loss);
 }
 
 void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipStream_t s) {

@@ -16,6 +16,7 @@ constexpr float kDilation = 0.3f;           // screen-space low-pass, px^2
 constexpr float kGuard = 1.3f;              // Jacobian guard band, x field of view
 constexpr float kRectPad = 5e-4f;           // support rectangle padding, px
 constexpr float kPreReject = 1e-3f;         // exponent margin below the gate for the early reject
+constexpr float kCosEps = 1e-8f;     // added to |F| |F*| in the feature cosine
 constexpr int kMaxPoses = 64;               // poses per projection launch
 constexpr int kSub = 32;                    // record sub-segments (and counters) per pose
 constexpr int kWave = 64;

@@ -76,7 +76,7 @@ struct hgsr_ctx {
 
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
-      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg;
+      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -245,6 +245,7 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
   TRY(ensure(c, c->finalT, npix * sizeof(float)));
   TRY(ensure(c, c->nused, npix * sizeof(uint32_t)));
   TRY(ensure(c, c->part_vis, std::max(P, 1) * sizeof(uint64_t)));
+  TRY(ensure(c, c->loss_part, ntile * sizeof(float)));
   if (lsd) {
     TRY(ensure(c, c->rec_keys, nrec * sizeof(uint32_t)));
     TRY(ensure(c, c->rec_offsets, nrec * sizeof(uint32_t)));
@@ -293,7 +294,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg};
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -323,9 +324,9 @@ hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, 
   return HGSR_OK;
 }
 
-hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                        hgsr_stream stream) {
+static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                               const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                               const hgsr_residual_io* res, hgsr_stream stream) {
   if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
   TRY(check_gaussians(g));
   TRY(check_intrinsics(K));
@@ -341,6 +342,12 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     return fail(HGSR_ERR_INVALID_ARG, "bad sort_mode");
   if (opts->feat_accum < HGSR_FEAT_AUTO || opts->feat_accum > HGSR_FEAT_MFMA)
     return fail(HGSR_ERR_INVALID_ARG, "bad feat_accum");
+  if (res) {
+    if (!res->rgb_target || !res->loss || !res->grad_rgb)
+      return fail(HGSR_ERR_INVALID_ARG, "residual needs rgb_target, loss and grad_rgb");
+    if (g->feat_dim > 0 && (!res->feat_target || !res->grad_feat))
+      return fail(HGSR_ERR_INVALID_ARG, "residual with features needs feat_target and grad_feat");
+  }
   const bool lsd = opts->sort_mode == HGSR_SORT_LSD;
   const float near_z = opts->near_z > 0.f ? opts->near_z : 0.2f;
   const CamArgs cam = make_cam(*K, tile, near_z);
@@ -401,7 +408,6 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   ba.flags = misc + kFlags;
   uint32_t* total = reinterpret_cast<uint32_t*>(misc + kTotalKeys);
   const uint32_t* sorted = nullptr;
-  int blend_sort_cap = 0;
   if (!lsd) {
     launch_scan(c->tile_count.as<uint32_t>(), ntile, nullptr, c->ranges.as<uint2>(), c->scan_tmp.as<uint32_t>(), total,
                 c->key_cap, misc + kFlags, 2, s);
@@ -450,14 +456,10 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   bl.P = P;
   bl.ranges = c->ranges.as<uint2>();
   bl.list = sorted;
-  bl.keys = c->keys0.as<uint64_t>();
-  bl.vals = c->vals0.as<uint32_t>();
-  bl.list_out = c->list.as<uint32_t>();
-  bl.sort_cap = blend_sort_cap;
   {
     int fa = opts->feat_accum;
     if (fa == HGSR_FEAT_AUTO) fa = c->tuned_feat ? c->tuned_feat : HGSR_FEAT_VALU;
-    bl.feat_mfma = fa == HGSR_FEAT_MFMA ? 1 : 0;
+    bl.feat_mfma = fa == HGSR_FEAT_MFMA && !res ? 1 : 0;
   }
   bl.recs = c->recs.as<Splat>();
   bl.feat = g->feat;
@@ -472,9 +474,19 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   bl.n_items = static_cast<int32_t>(ntile);
   bl.queue = reinterpret_cast<uint32_t*>(misc + kQueue);
   bl.flags = misc + kFlags;
+  bl.res_rgb_t = res ? res->rgb_target : nullptr;
+  bl.res_feat_t = res ? res->feat_target : nullptr;
+  bl.res_lam = res ? res->lam_f : 0.f;
+  bl.res_t_stride = res && res->shared_target ? 0 : 1;
+  bl.res_inv_hw = 1.f / static_cast<float>(static_cast<int64_t>(K->width) * K->height);
+  bl.res_loss = res ? res->loss : nullptr;
+  bl.res_part = c->loss_part.as<float>();
+  bl.res_g_rgb = res ? res->grad_rgb : nullptr;
+  bl.res_g_feat = res ? res->grad_feat : nullptr;
   int n_ctas = static_cast<int>(ntile);
   if (sched != HGSR_SCHED_GRID) n_ctas = static_cast<int>(std::min<int64_t>(ntile, 8ll * c->n_cu));
   launch_blend_fwd(bl, g->feat_dim, opts->feat_out_bf16 != 0, n_ctas, s);
+  if (res) launch_loss_reduce(c->loss_part.as<float>(), cam.tiles_per_pose, P, res->loss, s);
   HIP_TRY(hipGetLastError());
   hipEvent_t e3 = stamp(c, s);
   mark(c, 0, e0, e1);
@@ -492,6 +504,19 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   c->cam = cam;
   c->sorted = sorted;
   return HGSR_OK;
+}
+
+hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream) {
+  return render_impl(c, g, poses, P, K, opts, out, nullptr, stream);
+}
+
+hgsr_status hgsr_render_residual(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                                 const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                                 const hgsr_residual_io* res, hgsr_stream stream) {
+  if (!res) return fail(HGSR_ERR_INVALID_ARG, "res is NULL");
+  return render_impl(c, g, poses, P, K, opts, out, res, stream);
 }
 
 hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream stream) {
@@ -768,13 +793,20 @@ hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, 
 
 hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream) {
+                          const hgsr_residual_io* res, const char* cache_path, hgsr_tune_result* result,
+                          hgsr_stream stream) {
   if (!c || !g || !K || !opts || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   if (c->capturing) return fail(HGSR_ERR_STATE, "cannot autotune while capturing");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // the call being tuned: a plain render, or a render with the residual
+  auto run = [&](const hgsr_opts* o) {
+    return res ? hgsr_render_residual(c, g, poses, P, K, o, out, res, stream)
+               : hgsr_render(c, g, poses, P, K, o, out, stream);
+  };
   char key[256];
-  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d\"", K->width, K->height, P,
-           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode);
+  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d/res%d\"", K->width, K->height, P,
+           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode,
+           res ? (res->shared_target ? 2 : 1) : 0);
   // cached answer?
   if (cache_path) {
     FILE* f = fopen(cache_path, "r");
@@ -817,20 +849,20 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     for (int sc : scheds)
       for (int fa : feats) {
       if (P == 1 && sc == HGSR_SCHED_TILE_MAJOR) continue;
-      if (fa == HGSR_FEAT_MFMA && (g->feat_dim != 32 || t == 32)) continue;
+      if (fa == HGSR_FEAT_MFMA && (g->feat_dim != 32 || t == 32 || res)) continue;
       hgsr_opts o = *opts;
       o.tile = t;
       o.schedule = sc;
       o.feat_accum = fa;
       for (int tries = 0; tries < 6; ++tries) {
-        TRY(hgsr_render(c, g, poses, P, K, &o, out, stream));
+        TRY(run(&o));
         int32_t ovf = 0;
         TRY(hgsr_check_overflow(c, &ovf, stream));
         if (!ovf) break;
       }
       const int reps = 5;
       HIP_TRY(hipEventRecord(a, s));
-      for (int r = 0; r < reps; ++r) TRY(hgsr_render(c, g, poses, P, K, &o, out, stream));
+      for (int r = 0; r < reps; ++r) TRY(run(&o));
       HIP_TRY(hipEventRecord(b, s));
       HIP_TRY(hipEventSynchronize(b));
       float ms = 0.f;

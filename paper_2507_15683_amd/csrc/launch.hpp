@@ -67,11 +67,7 @@ struct BlendArgs {
   CamArgs c;
   int32_t P;
   const uint2* ranges;
-  const uint32_t* list;      // sorted record indices (lists the blend does not sort itself)
-  const uint64_t* keys;      // unsorted (depth bits << 32 | gid) keys, when the blend sorts
-  const uint32_t* vals;      // their record indices
-  uint32_t* list_out;        // where the blend stores the lists it sorted (for the backward)
-  int32_t sort_cap;          // lists up to this length are sorted by the blend; 0 = none
+  const uint32_t* list;      // per-tile record indices in (depth, index) order
   int32_t feat_mfma;         // accumulate 32 feature channels on the matrix cores
   const Splat* recs;
   const uint16_t* feat;      // n x D bf16
@@ -86,6 +82,16 @@ struct BlendArgs {
   int32_t n_items;
   uint32_t* queue;
   const int32_t* flags;
+  // refinement residual in the epilogue (res_loss != null)
+  const float* res_rgb_t;     // target of pose p at p * res_t_stride images
+  const float* res_feat_t;
+  int32_t res_t_stride;       // 1: a target per pose; 0: one shared target
+  float res_lam;
+  float res_inv_hw;
+  float* res_loss;            // non-null selects the residual epilogue
+  float* res_part;            // per (pose, tile) loss shares, summed afterwards
+  float* res_g_rgb;
+  float* res_g_feat;
 };
 
 struct BackArgs {
@@ -153,6 +159,7 @@ void launch_ranges_from_sorted(const uint64_t* keys, const uint32_t* total, uint
                                int32_t n_tiles, const int32_t* flags, hipStream_t s);
 
 // blend.hip
+void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, float* loss, hipStream_t s);
 void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipStream_t s);
 
 // backward.hip

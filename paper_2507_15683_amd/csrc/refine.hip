@@ -6,8 +6,6 @@
 
 namespace hgsr {
 
-constexpr float kCosEps = 1e-8f;
-
 template <int D, bool BF16>
 __global__ __launch_bounds__(256) void residual_kernel(const float* rgb, const void* feat, const float* rgb_t,
                                                        const float* feat_t, int P, int64_t HW, float lam_f,
