@@ -160,13 +160,12 @@ def headline(hg, torch, synth, args):
 
 
 def refine_step_fns(hg, scene, K, lam_f=1.0, lr_rho=1e-2, lr_phi=1e-3):
-    """One refinement step: render with the residual evaluated in the blend
-    (the feature map itself is not written), backward to the pose, Adam."""
+    """One refinement step: render, the residual's gradient formed inside the
+    blend backward (no gradient images), backward to the pose, Adam."""
     def step(r, st, opts, stream):
-        r.render_residual_into(scene, st["poses"], K, st["out"], opts, st["tgt_rgb"], st["tgt_feat"], st["res"],
-                               lam_f=lam_f, stream=stream)
-        r.backward(dict(rgb=st["res"][1], feat=st["res"][2]), want=("pose",), P=st["poses"].shape[0], scene=scene,
-                   grads=st["grads"], stream=stream)
+        r.render_into(scene, st["poses"], K, st["out"], opts, stream=stream)
+        r.residual_backward(st["tgt_rgb"], st["tgt_feat"], lam_f=lam_f, loss=st["loss"], grads=st["grads"],
+                            P=st["poses"].shape[0], scene=scene, stream=stream)
         hg.pose_adam(st["poses"], st["grads"]["pose"], st["m"], st["v"], st["step"], lr_rho=lr_rho, lr_phi=lr_phi,
                      stream=stream)
     return step
@@ -178,9 +177,7 @@ def refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat):
               m=torch.zeros((NP, 6), device="cuda"), v=torch.zeros((NP, 6), device="cuda"),
               step=torch.zeros(1, dtype=torch.int32, device="cuda"))
     st["out"] = r.alloc_outputs(scene, NP, K)
-    st["out"]["feat"] = None  # the fused residual needs no feature map
-    st["res"] = (torch.empty(NP, device="cuda"), torch.empty((NP, 3, K.height, K.width), device="cuda"),
-                 torch.empty((NP, scene.feat_dim, K.height, K.width), device="cuda"))
+    st["loss"] = torch.empty(NP, device="cuda")
     st["grads"] = r.alloc_grads(scene, NP, ("pose",))
     return st
 
@@ -212,31 +209,22 @@ def fwd_bwd(hg, torch, synth, args):
     # batched: autotune, size, capture one step, replay
     r = hg.Renderer()
     st = refine_state(hg, torch, r, scene, K, torch.from_numpy(P).cuda(), tgt_rgb, tgt_feat)
-    full = r.alloc_outputs(scene, NP, K)  # forward-only renders write every output
-    # forward-only batched throughput, at the tuning of the plain render
-    tuned_fwd = r.autotune(scene, st["poses"], K, full)
-    log("bench: autotuned forward (64 poses)", tuned_fwd)
+    tuned = r.autotune(scene, st["poses"], K, st["out"])
+    log("bench: autotuned (64 poses)", tuned)
     opts = r.opts(tile=0, schedule="auto")
-    r.render(scene, st["poses"], K, tile=0, schedule="auto", out=full)
+    r.render(scene, st["poses"], K, tile=0, schedule="auto", out=st["out"])
     reserve_headroom(r, NP, K, sc.n)
+    # forward-only batched throughput
     with torch.cuda.stream(s):
         for _ in range(3):
-            r.render_into(scene, st["poses"], K, full, opts, stream=s)
+            r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(args.fb_steps):
-        r.render_into(scene, st["poses"], K, full, opts, stream=s)
+        r.render_into(scene, st["poses"], K, st["out"], opts, stream=s)
     e1.record(s)
     s.synchronize()
     fwd_ms = e0.elapsed_time(e1) / args.fb_steps
-    del full
-    # the refinement step's render (residual in the blend) is tuned on its own
-    tuned = r.autotune(scene, st["poses"], K, st["out"],
-                       residual=dict(rgb_target=tgt_rgb, feat_target=tgt_feat, res=st["res"]))
-    log("bench: autotuned refinement render (64 poses)", tuned)
-    r.render_residual(scene, st["poses"], K, tgt_rgb, tgt_feat, out=st["out"], res=st["res"], tile=0,
-                      schedule="auto")
-    reserve_headroom(r, NP, K, sc.n)
     with torch.cuda.stream(s):
         step_fn(r, st, opts, s)
     s.synchronize()
@@ -260,7 +248,7 @@ def fwd_bwd(hg, torch, synth, args):
     batched_ms = e0.elapsed_time(e1) / args.fb_steps
     if r.check_overflow(s) != 0:
         raise RuntimeError("workspace overflow during the captured refinement steps")
-    loss_b = st["res"][0].mean().item()
+    loss_b = st["loss"].mean().item()
     del st, r
 
     # plain: one pose at a time, tile 16, grid schedule, eager
@@ -296,7 +284,6 @@ def fwd_bwd(hg, torch, synth, args):
             "speedup": round(plain_ms / batched_ms, 2), "batched_fwd_ms": round(fwd_ms, 3),
             "batched_fwd_mpix_s": round(NP * W * H / (fwd_ms * 1e-3) / 1e6, 1),
             "steps_timed": args.fb_steps, "plain_steps_timed": args.plain_steps, "autotuned": tuned,
-            "autotuned_forward": tuned_fwd,
             "mean_loss_after": round(loss_b, 5)}
 
 
@@ -320,14 +307,9 @@ def partitioned(hg, torch, synth, args):
         tgt_rgb, tgt_feat = tgt["rgb"].clone(), tgt["feat"].clone()
         del tgt
         st = refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat)
-        full = r.alloc_outputs(scene, NQ, K)
-        r.render(scene, poses, K, out=full)  # sizes the workspace
-        del full
-        tuned = r.autotune(scene, poses, K, st["out"],
-                           residual=dict(rgb_target=tgt_rgb, feat_target=tgt_feat, res=st["res"]))
+        tuned = r.autotune(scene, poses, K, st["out"])
         opts = r.opts(tile=0, schedule="auto")
-        r.render_residual(scene, poses, K, tgt_rgb, tgt_feat, out=st["out"], res=st["res"], tile=0,
-                          schedule="auto")
+        r.render(scene, poses, K, tile=0, schedule="auto", out=st["out"])
         reserve_headroom(r, NQ, K, sc.n)
         keep = poses.clone()
         with torch.cuda.stream(s):
@@ -351,7 +333,7 @@ def partitioned(hg, torch, synth, args):
         lat += ll
         per_level.append({"size": f"{cam.width}x{cam.height}", "tile": tuned["tile"], "schedule": tuned["schedule"],
                           "p50_ms": round(pct(ll, 50), 3), "p99_ms": round(pct(ll, 99), 3),
-                          "loss": round(st["res"][0].mean().item(), 5)})
+                          "loss": round(st["loss"].mean().item(), 5)})
         log("bench: level", per_level[-1])
         del st, tgt_rgb, tgt_feat
     wall = time.perf_counter() - t_start

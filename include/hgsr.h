@@ -206,37 +206,6 @@ hgsr_status hgsr_render(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* pos
                         const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
                         hgsr_stream stream);
 
-/* Targets and outputs of the refinement residual evaluated inside a render
- * (hgsr_render_residual); the residual is the one hgsr_residual defines.
- * All device pointers: rgb_target 3 x H x W and feat_target D x H x W per
- * target image, grad_rgb P x 3 x H x W and grad_feat P x D x H x W (feature
- * pointers may be NULL when D == 0), loss P floats (overwritten).  lam_f
- * weighs the feature term.  shared_target = 0: one target image per pose;
- * nonzero: every pose is compared with the same single target (the
- * candidate poses of one query). */
-typedef struct {
-  const float* rgb_target;
-  const float* feat_target;
-  float lam_f;
-  int32_t shared_target;
-  float* loss;
-  float* grad_rgb;
-  float* grad_feat;
-} hgsr_residual_io;
-
-/* hgsr_render and hgsr_residual in one pass (the dense refinement step of
- * Sec. 3.4 renders at the current pose and compares with the query): the
- * blend's epilogue computes each pixel's residual terms and gradients from
- * its FP32 accumulators, so the feature map need not be written and read
- * back.  out->feat may be NULL (feature map not written); rgb, depth and
- * alpha are written as by hgsr_render.  The feature sum runs on the VALU
- * whatever opts->feat_accum says.  Results equal hgsr_render followed by
- * hgsr_residual on FP32 outputs, except for the order in which the loss
- * is summed.  hgsr_render_backward then applies to this render. */
-hgsr_status hgsr_render_residual(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
-                                 const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                                 const hgsr_residual_io* res, hgsr_stream stream);
-
 /* Backward of the last hgsr_render on this context: replays each pixel's
  * blend in reverse from the saved final transmittance and writes the
  * requested gradients.  The forward's inputs and its depth/alpha outputs
@@ -253,6 +222,31 @@ hgsr_status hgsr_render_backward(hgsr_ctx* ctx, const hgsr_grad_outputs* grad_ou
 hgsr_status hgsr_residual(const float* rgb, const void* feat, int32_t feat_bf16, const float* rgb_target,
                           const float* feat_target, int32_t P, int32_t H, int32_t W, int32_t D, float lam_f,
                           float* loss, float* grad_rgb, float* grad_feat, hgsr_stream stream);
+
+/* Targets of the refinement residual (the one hgsr_residual defines), as
+ * device pointers: rgb_target 3 x H x W and feat_target D x H x W per target
+ * image (feat_target NULL when D == 0).  shared_target = 0: one target
+ * image per pose; nonzero: every pose is compared with the same single
+ * target (the candidate poses of one query).  lam_f weighs the feature
+ * term. */
+typedef struct {
+  const float* rgb_target;
+  const float* feat_target;
+  float lam_f;
+  int32_t shared_target;
+} hgsr_residual_targets;
+
+/* Gradient of the refinement residual of the last hgsr_render on this
+ * context (Sec. 3.4: the dense stage refines the pose by comparing renders
+ * with the query), without materialising dL/d(outputs): the blend backward
+ * forms each pixel's residual gradient from the render's rgb and feature
+ * outputs (which must still hold that render's values) and the targets, then
+ * replays the blend as hgsr_render_backward does.  Writes loss (device, P
+ * floats, overwritten; summed per tile, then per pose, in a fixed order) and
+ * the requested gradients; equal to hgsr_residual followed by
+ * hgsr_render_backward up to the order in which the loss is summed. */
+hgsr_status hgsr_residual_backward(hgsr_ctx* ctx, const hgsr_residual_targets* targets, float* loss,
+                                   const hgsr_grads* grads, hgsr_stream stream);
 
 /* One Adam step on the pose tangents and the left update T <- Exp(-step) T.
  * poses P x 12 (updated in place), grad P x 6, m and v P x 6 (state),
@@ -297,13 +291,10 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges,
  * the context's default (opts->tile == 0, opts->schedule == HGSR_SCHED_AUTO,
  * opts->feat_accum == HGSR_FEAT_AUTO) and append it to the JSON-lines cache
  * file `cache_path` (host string, may be NULL), which later calls on the same
- * shape read instead of timing.  With `res` non-NULL the call timed is
- * hgsr_render_residual with those targets (the refinement step's render).
- * Synchronises `stream`. */
+ * shape read instead of timing.  Synchronises `stream`. */
 hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                          const hgsr_residual_io* res, const char* cache_path, hgsr_tune_result* result,
-                          hgsr_stream stream);
+                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream);
 
 /* Stage timing.  While enabled, hgsr_render records HIP events on its
  * stream around its stages (0: projection, 1: tile binning and sort,

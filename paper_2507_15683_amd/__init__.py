@@ -165,56 +165,6 @@ class Renderer:
         check(self.lib.hgsr_render(self.ctx, ctypes.byref(g), _ptr(poses), P, ctypes.byref(kc), ctypes.byref(opts),
                                    ctypes.byref(o), _stream_ptr(stream)), "hgsr_render")
 
-    def render_residual_into(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict,
-                             opts: _lib.Opts, rgb_target: torch.Tensor, feat_target: Optional[torch.Tensor],
-                             res: tuple, lam_f: float = 1.0, stream=None):
-        """Enqueue one render with the refinement residual evaluated in the
-        blend: res = (loss (P,), grad_rgb (P,3,H,W), grad_feat (P,D,H,W) or
-        None) are written; out["feat"] may be None (not written).  Targets
-        are (P,3,H,W)/(P,D,H,W), or (1,3,H,W)/(1,D,H,W) shared by all poses."""
-        if poses.dtype != torch.float32 or not poses.is_contiguous() or poses.shape[-1] != 12:
-            raise ValueError("poses must be a contiguous float32 (P, 12) device tensor")
-        P = poses.shape[0]
-        g = scene.c()
-        o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out.get("feat")))
-        kc = K.c()
-        loss, g_rgb, g_feat = res
-        shared = int(rgb_target.shape[0] == 1 and P > 1)
-        if not shared and rgb_target.shape[0] != P:
-            raise ValueError("targets must hold one image per pose or a single shared one")
-        rio = _lib.ResidualIO(_ptr(rgb_target), _ptr(feat_target), lam_f, shared, _ptr(loss), _ptr(g_rgb),
-                              _ptr(g_feat))
-        self._keep = (scene, poses, out)
-        self._keep_res = (rgb_target, feat_target, res)
-        check(self.lib.hgsr_render_residual(self.ctx, ctypes.byref(g), _ptr(poses), P, ctypes.byref(kc),
-                                            ctypes.byref(opts), ctypes.byref(o), ctypes.byref(rio),
-                                            _stream_ptr(stream)), "hgsr_render_residual")
-
-    def render_residual(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, rgb_target: torch.Tensor,
-                        feat_target: Optional[torch.Tensor] = None, lam_f: float = 1.0, out: Optional[dict] = None,
-                        res: Optional[tuple] = None, write_feat: bool = False, stream=None, **opt_kw):
-        """Render with the residual evaluated in the blend; returns (out,
-        (loss, grad_rgb, grad_feat)).  Synchronises to check the workspace
-        and re-renders after growing it if needed."""
-        if poses.dim() == 1:
-            poses = poses[None]
-        P = poses.shape[0]
-        if out is None:
-            out = self.alloc_outputs(scene, P, K)
-            if not write_feat:
-                out["feat"] = None
-        if res is None:
-            dev = scene.means.device
-            res = (torch.empty(P, dtype=torch.float32, device=dev), torch.empty_like(out["rgb"]),
-                   torch.empty((P, scene.feat_dim, K.height, K.width), dtype=torch.float32, device=dev)
-                   if scene.feat_dim else None)
-        opts = self.opts(**opt_kw)
-        for _ in range(6):
-            self.render_residual_into(scene, poses, K, out, opts, rgb_target, feat_target, res, lam_f, stream)
-            if self.check_overflow(stream) == 0:
-                return out, res
-        raise HgsrError(3, "render_residual: workspace kept overflowing")
-
     def check_overflow(self, stream=None) -> int:
         f = ctypes.c_int32(0)
         check(self.lib.hgsr_check_overflow(self.ctx, ctypes.byref(f), _stream_ptr(stream)), "hgsr_check_overflow")
@@ -281,28 +231,44 @@ class Renderer:
               "hgsr_render_backward")
         return grads
 
+    def residual_backward(self, rgb_target: torch.Tensor, feat_target: Optional[torch.Tensor] = None,
+                          lam_f: float = 1.0, want=("pose",), loss: Optional[torch.Tensor] = None,
+                          grads: Optional[dict] = None, P: Optional[int] = None,
+                          scene: Optional[GaussianScene] = None, stream=None):
+        """Loss and gradients of the refinement residual of the last render
+        against targets ((P,3,H,W)/(P,D,H,W), or a single (1,...) target
+        shared by all poses), formed inside the blend backward.  The last
+        render's rgb and (FP32 or bf16) feature outputs must be unchanged.
+        Returns (loss (P,), grads dict)."""
+        scene = scene if scene is not None else self._keep[0]
+        P = P if P is not None else self._keep[1].shape[0]
+        if grads is None:
+            grads = self.alloc_grads(scene, P, want)
+        if loss is None:
+            loss = torch.empty(P, dtype=torch.float32, device=scene.means.device)
+        shared = int(rgb_target.shape[0] == 1 and P > 1)
+        if not shared and rgb_target.shape[0] != P:
+            raise ValueError("targets must hold one image per pose or a single shared one")
+        rt = _lib.ResidualTargets(_ptr(_f32(rgb_target)), _ptr(_f32(feat_target)), lam_f, shared)
+        gr = _lib.Grads(*[_ptr(grads.get(k)) for k in ("pose", "means", "opacities", "log_scales", "quats", "sh",
+                                                      "feat")])
+        self._keep_grad = (rgb_target, feat_target, loss, grads)
+        check(self.lib.hgsr_residual_backward(self.ctx, ctypes.byref(rt), _ptr(loss), ctypes.byref(gr),
+                                              _stream_ptr(stream)), "hgsr_residual_backward")
+        return loss, grads
+
     def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
-                 feat_bf16=False, cache_path: Optional[str] = None, residual: Optional[dict] = None,
-                 stream=None) -> dict:
+                 feat_bf16=False, cache_path: Optional[str] = None, stream=None) -> dict:
         """Time tile sizes 8/16/32, the blend schedules and the feature
         accumulations on this input; the winner becomes this renderer's
-        default for tile=0 / schedule="auto" / feat_accum="auto".  With
-        residual = dict(rgb_target, feat_target, res[, lam_f]) the render
-        timed is the one with the residual in the blend."""
+        default for tile=0 / schedule="auto" / feat_accum="auto"."""
         g = scene.c()
         kc = K.c()
         opts = self.opts(16, sort, "grid", feat_bf16=feat_bf16)
-        o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out.get("feat")))
-        rio = None
-        if residual is not None:
-            loss, g_rgb, g_feat = residual["res"]
-            rt = residual["rgb_target"]
-            shared = int(rt.shape[0] == 1 and poses.shape[0] > 1)
-            rio = _lib.ResidualIO(_ptr(rt), _ptr(residual.get("feat_target")), residual.get("lam_f", 1.0), shared,
-                                  _ptr(loss), _ptr(g_rgb), _ptr(g_feat))
+        o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["feat"]))
         res = _lib.TuneResult()
         check(self.lib.hgsr_autotune(self.ctx, ctypes.byref(g), _ptr(poses), poses.shape[0], ctypes.byref(kc),
-                                     ctypes.byref(opts), ctypes.byref(o), None if rio is None else ctypes.byref(rio),
+                                     ctypes.byref(opts), ctypes.byref(o),
                                      None if cache_path is None else cache_path.encode(), ctypes.byref(res),
                                      _stream_ptr(stream)), "hgsr_autotune")
         return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule],

@@ -57,9 +57,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("tile", I32), ("schedule", I32), ("feat_accum", I32), ("ms", F32)]
 
 
-class ResidualIO(ctypes.Structure):
-    _fields_ = [("rgb_target", P_), ("feat_target", P_), ("lam_f", F32), ("shared_target", I32), ("loss", P_),
-                ("grad_rgb", P_), ("grad_feat", P_)]
+class ResidualTargets(ctypes.Structure):
+    _fields_ = [("rgb_target", P_), ("feat_target", P_), ("lam_f", F32), ("shared_target", I32)]
 
 
 # (name, argtypes) for every entry point declared in include/hgsr.h
@@ -69,9 +68,8 @@ SIGNATURES = {
     "hgsr_reserve": [P_, I32, I32, I32, I32, I64, I64, I64],
     "hgsr_render": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
                     ctypes.POINTER(Outputs), P_],
-    "hgsr_render_residual": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics),
-                             ctypes.POINTER(Opts), ctypes.POINTER(Outputs), ctypes.POINTER(ResidualIO), P_],
     "hgsr_render_backward": [P_, ctypes.POINTER(GradOutputs), ctypes.POINTER(Grads), P_],
+    "hgsr_residual_backward": [P_, ctypes.POINTER(ResidualTargets), P_, ctypes.POINTER(Grads), P_],
     "hgsr_residual": [P_, P_, I32, P_, P_, I32, I32, I32, I32, F32, P_, P_, P_, P_],
     "hgsr_pose_adam": [P_, P_, P_, P_, P_, I32, F32, F32, F32, F32, F32, P_],
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
@@ -83,8 +81,7 @@ SIGNATURES = {
     "hgsr_stats": [P_, ctypes.POINTER(RenderStats), P_],
     "hgsr_debug_tile_lists": [P_, I32, P_, P_, I64, ctypes.POINTER(I64), P_],
     "hgsr_autotune": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
-                      ctypes.POINTER(Outputs), ctypes.POINTER(ResidualIO), ctypes.c_char_p, ctypes.POINTER(TuneResult),
-                      P_],
+                      ctypes.POINTER(Outputs), ctypes.c_char_p, ctypes.POINTER(TuneResult), P_],
     "hgsr_profile_enable": [P_, I32],
     "hgsr_profile_read": [P_, P_, P_],
     "hgsr_last_error": [],

@@ -20,7 +20,7 @@
 
 namespace hgsr {
 
-template <int TILE, int D, bool FEATGRAD>
+template <int TILE, int D, bool FEATGRAD, bool RES>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
   using Sh = BlendShape<TILE>;
   constexpr int NT = Sh::kThreads, NB = Sh::kBatch, NW = Sh::kWaves, BW = Sh::kBlockW, BH = Sh::kBlockH;
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   __shared__ uint16_t s_list[NW][NB];
   __shared__ float s_g[NB][10];  // per staged splat: the workgroup's gradient sums
   __shared__ uint32_t s_max;
+  __shared__ float s_lw[NW];
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   for (int e = tid; e < NB * 10; e += NT) (&s_g[0][0])[e] = 0.f;
   __syncthreads();
   uint32_t my_max = 0;
+  float lsum = 0.f;  // this lane's residual terms (RES)
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int li = lane + k * kWave;
@@ -78,7 +80,46 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
     Tf[k] = T[k] = a.final_T[o];
     const float A = 1.f - Tf[k];
     float gtv = 0.f;
-    if (a.g_rgb) {
+    if constexpr (RES) {
+      // the residual's gradient at this pixel (the definition the residual
+      // kernel evaluates), from the forward's outputs and the target
+      const float inv = a.res_inv_hw;
+      const int64_t o3 = static_cast<int64_t>(pose) * 3 * HW + pix;
+      const int64_t tp = static_cast<int64_t>(pose) * a.res_t_stride;
+      float l = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float d = a.fwd_rgb[o3 + ch * HW] - a.res_rgb_t[tp * 3 * HW + pix + ch * HW];
+        l += fabsf(d);
+        gC[k][ch] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+      }
+      gtv = gC[k][0] * a.bg[0] + gC[k][1] * a.bg[1] + gC[k][2] * a.bg[2];
+      if constexpr (D > 0) {
+        const int64_t of = static_cast<int64_t>(pose) * D * HW + pix;
+        const int64_t tf = tp * D * HW + pix;
+        float t[D];
+        float dot = 0.f, na = 0.f, nb = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          gF[k][d] = a.fwd_feat_bf16 ? bf16_lo(static_cast<const uint16_t*>(a.fwd_feat)[of + d * HW])
+                                     : static_cast<const float*>(a.fwd_feat)[of + d * HW];
+          t[d] = a.res_feat_t[tf + d * HW];
+          dot = fmaf(gF[k][d], t[d], dot);
+          na = fmaf(gF[k][d], gF[k][d], na);
+          nb = fmaf(t[d], t[d], nb);
+        }
+        na = sqrtf(na);
+        nb = sqrtf(nb);
+        const float n = na * nb + kCosEps;
+        const float cosv = dot / n;
+        l += a.res_lam * (1.f - cosv);
+        const float s1 = -a.res_lam * inv / n;
+        const float s2 = na > 0.f ? a.res_lam * inv * dot * nb / (n * n * na) : 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) gF[k][d] = s1 * t[d] + s2 * gF[k][d];
+      }
+      lsum += l * inv;
+    } else if (a.g_rgb) {
       const int64_t o3 = static_cast<int64_t>(pose) * 3 * HW + pix;
       gC[k][0] = a.g_rgb[o3];
       gC[k][1] = a.g_rgb[o3 + HW];
@@ -92,7 +133,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
     }
     if (a.g_alpha) gtv -= a.g_alpha[o];
     gT[k] = gtv;
-    if constexpr (D > 0) {
+    if constexpr (D > 0 && !RES) {
       if (a.g_feat) {
         const int64_t of = static_cast<int64_t>(pose) * D * HW + pix;
 #pragma unroll
@@ -106,7 +147,20 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   for (int off = 32; off > 0; off >>= 1) my_max = max(my_max, static_cast<uint32_t>(__shfl_xor(my_max, off, kWave)));
   const uint32_t wave_max = my_max;
   if (lane == 0) atomicMax(&s_max, wave_max);
+  if constexpr (RES) {
+    // this tile's loss share, summed in a fixed order (lanes, then waves)
+    lsum = wave_sum(lsum);
+    if (lane == 0) s_lw[wave] = lsum;
+  }
   __syncthreads();
+  if constexpr (RES) {
+    if (tid == 0) {
+      float t = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += s_lw[w];
+      a.res_part[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile] = t;
+    }
+  }
   const uint32_t n_max = s_max;
   if (n_max == 0) return;
 
@@ -252,18 +306,42 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   }
 }
 
+// Per-pose loss from the per-tile shares, in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* part, int32_t tiles_per_pose, float* loss) {
+  __shared__ float s_r[256];
+  const int pose = blockIdx.x;
+  const float* p = part + static_cast<int64_t>(pose) * tiles_per_pose;
+  float v = 0.f;
+  for (int t = threadIdx.x; t < tiles_per_pose; t += 256) v += p[t];
+  s_r[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) s_r[threadIdx.x] += s_r[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[pose] = s_r[0];
+}
+
+void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(P), dim3(256), 0, s, part, tiles_per_pose, loss);
+}
+
 template <int TILE, int D>
 static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
-  if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true>), dim3(items), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false>), dim3(items), dim3(NT), 0, s, a);
+  if (a.res_rgb_t) {
+    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true>), dim3(items), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true>), dim3(items), dim3(NT), 0, s, a);
+  } else {
+    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, false>), dim3(items), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false>), dim3(items), dim3(NT), 0, s, a);
+  }
 }
 
 template <int TILE>
 static void launch_bwd_t(const BackArgs& a, int items, hipStream_t s) {
   switch (a.D) {
-    case 0: hipLaunchKernelGGL((blend_bwd_kernel<TILE, 0, false>), dim3(items), dim3(BlendShape<TILE>::kThreads), 0,
-                               s, a); break;
+    case 0: launch_bwd_td<TILE, 0>(a, items, s); break;
     case 8: launch_bwd_td<TILE, 8>(a, items, s); break;
     case 16: launch_bwd_td<TILE, 16>(a, items, s); break;
     case 32: launch_bwd_td<TILE, 32>(a, items, s); break;

@@ -11,9 +11,7 @@
 // are rejected before the exponential; the exact gate, clamp and stop tests
 // follow.  A pixel stops at the first splat that would take its transmittance
 // below 1e-4; the batch loop ends when every pixel of the tile has stopped.
-// Outputs are planar per pose.  With RES the epilogue also evaluates the
-// refinement residual against per-pixel targets from the FP32 accumulators
-// and writes its gradients (the feature map itself is then optional).
+// Outputs are planar per pose.
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -29,7 +27,7 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 #endif
 constexpr int kMfGroup = HGSR_MF_GROUP;
 
-template <int TILE, int D, bool BF16, bool MFK, bool RES>
+template <int TILE, int D, bool BF16, bool MFK>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
   using S = BlendShape<TILE>;
   constexpr int NT = S::kThreads, NB = S::kBatch, NW = S::kWaves, BW = S::kBlockW, BH = S::kBlockH, PPT = S::kPPT;
@@ -50,7 +48,6 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
   __shared__ uint32_t s_fw[NB * FS];
   __shared__ uint8_t s_mask[NB];
   __shared__ uint16_t s_list[NW][NB];
-  __shared__ float s_lw[NW];
   __shared__ int s_item;
   if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
@@ -329,53 +326,14 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
     }
 
     const int64_t pbase = static_cast<int64_t>(pose) * HW;
-    float lsum = 0.f;  // this lane's residual terms (RES)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       if (!inside[k]) continue;
       const int64_t o = pbase + pix[k];
       const int64_t o3 = static_cast<int64_t>(pose) * 3 * HW + pix[k];
-      const float out_rgb[3] = {fmaf(T[k], a.bg[0], C[k][0]), fmaf(T[k], a.bg[1], C[k][1]),
-                                fmaf(T[k], a.bg[2], C[k][2])};
-      a.rgb[o3] = out_rgb[0];
-      a.rgb[o3 + HW] = out_rgb[1];
-      a.rgb[o3 + 2 * HW] = out_rgb[2];
-      if constexpr (RES) {
-        // L1 colour term and feature cosine term, as the residual kernel
-        // computes them, from this pixel's FP32 values
-        const float inv = a.res_inv_hw;
-        const int64_t tp = static_cast<int64_t>(pose) * a.res_t_stride;  // target image of this pose
-        const int64_t t3 = tp * 3 * HW + pix[k];
-        float l = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float d = out_rgb[ch] - a.res_rgb_t[t3 + ch * HW];
-          l += fabsf(d);
-          a.res_g_rgb[o3 + ch * HW] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
-        }
-        if constexpr (D > 0 && !MF) {
-          const int64_t of = static_cast<int64_t>(pose) * D * HW + pix[k];
-          const int64_t tf = tp * D * HW + pix[k];
-          float dot = 0.f, na = 0.f, nb = 0.f;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const float t = a.res_feat_t[tf + d * HW];
-            dot = fmaf(F[k][d], t, dot);
-            na = fmaf(F[k][d], F[k][d], na);
-            nb = fmaf(t, t, nb);
-          }
-          na = sqrtf(na);
-          nb = sqrtf(nb);
-          const float n = na * nb + kCosEps;
-          const float cosv = dot / n;
-          l += a.res_lam * (1.f - cosv);
-          const float s1 = -a.res_lam * inv / n;
-          const float s2 = na > 0.f ? a.res_lam * inv * dot * nb / (n * n * na) : 0.f;
-#pragma unroll
-          for (int d = 0; d < D; ++d) a.res_g_feat[of + d * HW] = s1 * a.res_feat_t[tf + d * HW] + s2 * F[k][d];
-        }
-        lsum += l * inv;
-      }
+      a.rgb[o3] = fmaf(T[k], a.bg[0], C[k][0]);
+      a.rgb[o3 + HW] = fmaf(T[k], a.bg[1], C[k][1]);
+      a.rgb[o3 + 2 * HW] = fmaf(T[k], a.bg[2], C[k][2]);
       const float A = 1.f - T[k];
       a.alpha[o] = A;
       a.depth[o] = A > 0.f ? Z[k] / A : 0.f;
@@ -420,18 +378,6 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
         }
       }
     }
-    if constexpr (RES) {
-      // this tile's loss share, summed in a fixed order (waves, then lanes)
-      lsum = wave_sum(lsum);
-      if (lane == 0) s_lw[wave] = lsum;
-      __syncthreads();
-      if (tid == 0) {
-        float t = 0.f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) t += s_lw[w];
-        a.res_part[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile] = t;
-      }
-    }
     if (persistent) __syncthreads();
   }
 }
@@ -439,12 +385,10 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
 template <int TILE, int D, bool BF16>
 static void launch_t(const BlendArgs& a, int n_ctas, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
-  if (a.res_loss)
-    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false, true>), dim3(n_ctas), dim3(NT), 0, s, a);
-  else if (D == 32 && TILE != 32 && a.feat_mfma)
-    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, true, false>), dim3(n_ctas), dim3(NT), 0, s, a);
+  if (D == 32 && TILE != 32 && a.feat_mfma)
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, true>), dim3(n_ctas), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false, false>), dim3(n_ctas), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((blend_fwd_kernel<TILE, D, BF16, false>), dim3(n_ctas), dim3(NT), 0, s, a);
 }
 
 template <int TILE, int D>
@@ -462,26 +406,6 @@ static void launch_tile(const BlendArgs& a, int D, bool bf16, int n_ctas, hipStr
     case 32: launch_td<TILE, 32>(a, bf16, n_ctas, s); break;
     default: launch_td<TILE, 64>(a, bf16, n_ctas, s); break;
   }
-}
-
-// Per-pose loss from the per-tile shares, in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* part, int32_t tiles_per_pose, float* loss) {
-  __shared__ float s_r[256];
-  const int pose = blockIdx.x;
-  const float* p = part + static_cast<int64_t>(pose) * tiles_per_pose;
-  float v = 0.f;
-  for (int t = threadIdx.x; t < tiles_per_pose; t += 256) v += p[t];
-  s_r[threadIdx.x] = v;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) s_r[threadIdx.x] += s_r[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) loss[pose] = s_r[0];
-}
-
-void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(P), dim3(256), 0, s, part, tiles_per_pose, loss);
 }
 
 void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipStream_t s) {

@@ -324,9 +324,9 @@ hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, 
   return HGSR_OK;
 }
 
-static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                               const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                               const hgsr_residual_io* res, hgsr_stream stream) {
+hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream) {
   if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
   TRY(check_gaussians(g));
   TRY(check_intrinsics(K));
@@ -342,12 +342,6 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
     return fail(HGSR_ERR_INVALID_ARG, "bad sort_mode");
   if (opts->feat_accum < HGSR_FEAT_AUTO || opts->feat_accum > HGSR_FEAT_MFMA)
     return fail(HGSR_ERR_INVALID_ARG, "bad feat_accum");
-  if (res) {
-    if (!res->rgb_target || !res->loss || !res->grad_rgb)
-      return fail(HGSR_ERR_INVALID_ARG, "residual needs rgb_target, loss and grad_rgb");
-    if (g->feat_dim > 0 && (!res->feat_target || !res->grad_feat))
-      return fail(HGSR_ERR_INVALID_ARG, "residual with features needs feat_target and grad_feat");
-  }
   const bool lsd = opts->sort_mode == HGSR_SORT_LSD;
   const float near_z = opts->near_z > 0.f ? opts->near_z : 0.2f;
   const CamArgs cam = make_cam(*K, tile, near_z);
@@ -459,7 +453,7 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   {
     int fa = opts->feat_accum;
     if (fa == HGSR_FEAT_AUTO) fa = c->tuned_feat ? c->tuned_feat : HGSR_FEAT_VALU;
-    bl.feat_mfma = fa == HGSR_FEAT_MFMA && !res ? 1 : 0;
+    bl.feat_mfma = fa == HGSR_FEAT_MFMA ? 1 : 0;
   }
   bl.recs = c->recs.as<Splat>();
   bl.feat = g->feat;
@@ -474,19 +468,9 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   bl.n_items = static_cast<int32_t>(ntile);
   bl.queue = reinterpret_cast<uint32_t*>(misc + kQueue);
   bl.flags = misc + kFlags;
-  bl.res_rgb_t = res ? res->rgb_target : nullptr;
-  bl.res_feat_t = res ? res->feat_target : nullptr;
-  bl.res_lam = res ? res->lam_f : 0.f;
-  bl.res_t_stride = res && res->shared_target ? 0 : 1;
-  bl.res_inv_hw = 1.f / static_cast<float>(static_cast<int64_t>(K->width) * K->height);
-  bl.res_loss = res ? res->loss : nullptr;
-  bl.res_part = c->loss_part.as<float>();
-  bl.res_g_rgb = res ? res->grad_rgb : nullptr;
-  bl.res_g_feat = res ? res->grad_feat : nullptr;
   int n_ctas = static_cast<int>(ntile);
   if (sched != HGSR_SCHED_GRID) n_ctas = static_cast<int>(std::min<int64_t>(ntile, 8ll * c->n_cu));
   launch_blend_fwd(bl, g->feat_dim, opts->feat_out_bf16 != 0, n_ctas, s);
-  if (res) launch_loss_reduce(c->loss_part.as<float>(), cam.tiles_per_pose, P, res->loss, s);
   HIP_TRY(hipGetLastError());
   hipEvent_t e3 = stamp(c, s);
   mark(c, 0, e0, e1);
@@ -506,18 +490,6 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   return HGSR_OK;
 }
 
-hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                        hgsr_stream stream) {
-  return render_impl(c, g, poses, P, K, opts, out, nullptr, stream);
-}
-
-hgsr_status hgsr_render_residual(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                                 const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                                 const hgsr_residual_io* res, hgsr_stream stream) {
-  if (!res) return fail(HGSR_ERR_INVALID_ARG, "res is NULL");
-  return render_impl(c, g, poses, P, K, opts, out, res, stream);
-}
 
 hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream stream) {
   if (!c || !overflowed) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
@@ -701,13 +673,23 @@ hgsr_status hgsr_profile_read(hgsr_ctx* c, double* ms, int64_t* calls) {
   return HGSR_OK;
 }
 
-hgsr_status hgsr_render_backward(hgsr_ctx* c, const hgsr_grad_outputs* go, const hgsr_grads* gr,
-                                 hgsr_stream stream) {
-  if (!c || !go || !gr) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+// Backward of the last render for dL/d(outputs) given (go) or formed from
+// the residual against targets (rt, with the loss written to `loss`).
+static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const hgsr_residual_targets* rt,
+                                 float* loss, const hgsr_grads* gr, hgsr_stream stream) {
+  if (!c || !(go || rt) || !gr) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   if (!c->have_render) return fail(HGSR_ERR_STATE, "backward before any render");
   const int D = c->g.feat_dim;
+  static const hgsr_grad_outputs none = {nullptr, nullptr, nullptr, nullptr};
+  if (!go) go = &none;
   if ((go->feat || gr->feat) && D == 0) return fail(HGSR_ERR_INVALID_ARG, "feature gradients need feat_dim > 0");
   if (go->depth && !c->out.depth) return fail(HGSR_ERR_STATE, "depth gradient needs the forward depth");
+  if (rt) {
+    if (!rt->rgb_target || !loss) return fail(HGSR_ERR_INVALID_ARG, "residual needs rgb_target and loss");
+    if (!c->out.rgb) return fail(HGSR_ERR_STATE, "residual needs the forward rgb");
+    if (D > 0 && (!rt->feat_target || !c->out.feat))
+      return fail(HGSR_ERR_INVALID_ARG, "residual with features needs feat_target and the forward feature map");
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int P = c->P;
   const int64_t n = c->g.n;
@@ -742,7 +724,17 @@ hgsr_status hgsr_render_backward(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   b.g_rec = c->grad_rec.as<float>();
   b.g_featvec = gr->feat;
   b.flags = misc + kFlags;
+  b.fwd_rgb = c->out.rgb;
+  b.fwd_feat = c->out.feat;
+  b.fwd_feat_bf16 = c->opts.feat_out_bf16 != 0;
+  b.res_rgb_t = rt ? rt->rgb_target : nullptr;
+  b.res_feat_t = rt ? rt->feat_target : nullptr;
+  b.res_t_stride = rt && rt->shared_target ? 0 : 1;
+  b.res_lam = rt ? rt->lam_f : 0.f;
+  b.res_inv_hw = 1.f / static_cast<float>(static_cast<int64_t>(c->cam.W) * c->cam.H);
+  b.res_part = c->loss_part.as<float>();
   launch_blend_bwd(b, s);
+  if (rt) launch_loss_reduce(c->loss_part.as<float>(), c->cam.tiles_per_pose, P, loss, s);
   hipEvent_t e1 = stamp(c, s);
   ProjBackArgs pb;
   pb.g = make_gauss(c->g);
@@ -766,6 +758,18 @@ hgsr_status hgsr_render_backward(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   mark(c, 3, e0, e1);
   mark(c, 4, e1, e2);
   return HGSR_OK;
+}
+
+hgsr_status hgsr_render_backward(hgsr_ctx* c, const hgsr_grad_outputs* go, const hgsr_grads* gr,
+                                 hgsr_stream stream) {
+  if (!go) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  return backward_impl(c, go, nullptr, nullptr, gr, stream);
+}
+
+hgsr_status hgsr_residual_backward(hgsr_ctx* c, const hgsr_residual_targets* t, float* loss, const hgsr_grads* gr,
+                                   hgsr_stream stream) {
+  if (!t) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  return backward_impl(c, nullptr, t, loss, gr, stream);
 }
 
 hgsr_status hgsr_residual(const float* rgb, const void* feat, int32_t feat_bf16, const float* rgb_target,
@@ -793,20 +797,14 @@ hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, 
 
 hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                          const hgsr_residual_io* res, const char* cache_path, hgsr_tune_result* result,
-                          hgsr_stream stream) {
+                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream) {
   if (!c || !g || !K || !opts || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   if (c->capturing) return fail(HGSR_ERR_STATE, "cannot autotune while capturing");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // the call being tuned: a plain render, or a render with the residual
-  auto run = [&](const hgsr_opts* o) {
-    return res ? hgsr_render_residual(c, g, poses, P, K, o, out, res, stream)
-               : hgsr_render(c, g, poses, P, K, o, out, stream);
-  };
+  auto run = [&](const hgsr_opts* o) { return hgsr_render(c, g, poses, P, K, o, out, stream); };
   char key[256];
-  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d/res%d\"", K->width, K->height, P,
-           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode,
-           res ? (res->shared_target ? 2 : 1) : 0);
+  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d\"", K->width, K->height, P,
+           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode);
   // cached answer?
   if (cache_path) {
     FILE* f = fopen(cache_path, "r");
@@ -849,7 +847,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     for (int sc : scheds)
       for (int fa : feats) {
       if (P == 1 && sc == HGSR_SCHED_TILE_MAJOR) continue;
-      if (fa == HGSR_FEAT_MFMA && (g->feat_dim != 32 || t == 32 || res)) continue;
+      if (fa == HGSR_FEAT_MFMA && (g->feat_dim != 32 || t == 32)) continue;
       hgsr_opts o = *opts;
       o.tile = t;
       o.schedule = sc;

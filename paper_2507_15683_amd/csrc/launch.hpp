@@ -82,16 +82,6 @@ struct BlendArgs {
   int32_t n_items;
   uint32_t* queue;
   const int32_t* flags;
-  // refinement residual in the epilogue (res_loss != null)
-  const float* res_rgb_t;     // target of pose p at p * res_t_stride images
-  const float* res_feat_t;
-  int32_t res_t_stride;       // 1: a target per pose; 0: one shared target
-  float res_lam;
-  float res_inv_hw;
-  float* res_loss;            // non-null selects the residual epilogue
-  float* res_part;            // per (pose, tile) loss shares, summed afterwards
-  float* res_g_rgb;
-  float* res_g_feat;
 };
 
 struct BackArgs {
@@ -113,6 +103,18 @@ struct BackArgs {
   float* g_rec;              // per record: du dv da db dc do dz dr dg db (+2 pad)
   float* g_featvec;          // n x D or null
   const int32_t* flags;
+  // refinement residual formed per pixel in place of g_rgb / g_feat
+  // (res_rgb_t != null): from the forward's rgb and feature outputs and the
+  // targets; the per-(pose, tile) loss shares go to res_part
+  const float* fwd_rgb;
+  const void* fwd_feat;
+  int32_t fwd_feat_bf16;
+  const float* res_rgb_t;
+  const float* res_feat_t;
+  int32_t res_t_stride;      // 1: a target per pose; 0: one shared target
+  float res_lam;
+  float res_inv_hw;
+  float* res_part;
 };
 
 struct ProjBackArgs {

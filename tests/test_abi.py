@@ -51,7 +51,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Intrinsics) == 24
     assert ctypes.sizeof(_lib.Opts) == 4 * 3 + 12 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(_lib.TuneResult) == 16
-    assert ctypes.sizeof(_lib.ResidualIO) == 48
+    assert ctypes.sizeof(_lib.ResidualTargets) == 24
     assert ctypes.sizeof(_lib.Outputs) == 32
     assert ctypes.sizeof(_lib.Grads) == 56
 

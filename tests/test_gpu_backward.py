@@ -314,43 +314,34 @@ def test_graph_replay_matches_eager(hg):
     assert int(to_np(st1["step"])[0]) == 5
 
 
-@pytest.mark.parametrize("D,tile", [(32, 16), (8, 8), (0, 32)])
-def test_fused_residual_matches_separate(hg, orc, D, tile):
-    """Render with the residual evaluated in the blend epilogue equals a render
-    followed by the residual kernel: same outputs and colour gradients bitwise,
-    feature gradients to rounding, loss up to summation order; the backward
-    after either gives the same pose gradients."""
+@pytest.mark.parametrize("D,tile,bf16", [(32, 16, False), (8, 8, False), (0, 32, False), (32, 8, True)])
+def test_residual_backward_matches_separate(hg, orc, D, tile, bf16):
+    """The residual formed inside the blend backward equals the residual
+    kernel followed by the plain backward: loss up to summation order, pose
+    and mean gradients to float-atomic rounding."""
     import torch
     sc, P, cam = synth.tiny_scene(500, 40 + D, width=83, height=61, feat_dim=D, sh_degree=1)
     Ps = synth.perturb_poses(P[0], 3, 41, 1.0, 2.0)
     tg = synth.perturb_poses(P[0], 3, 42, 1.0, 2.0)
     scene = hg.GaussianScene.from_numpy(sc)
     K = hg.Intrinsics.of(cam)
-    rt = hg.Renderer()
-    tgt = rt.render(scene, _t(tg), K)
+    tgt = hg.Renderer().render(scene, _t(tg), K)
     tgt = {k: (None if v is None else v.clone()) for k, v in tgt.items()}
-    log(f"case: fused residual D={D} tile={tile}")
-    ra = hg.Renderer()
-    a = ra.render(scene, _t(Ps), K, tile=tile)
-    la, ga_rgb, ga_feat = hg.residual(a["rgb"], a["feat"], tgt["rgb"], tgt["feat"])
-    pa = ra.backward(dict(rgb=ga_rgb, feat=ga_feat), want=("pose",))["pose"]
-    rb = hg.Renderer()
-    out, res = rb.render_residual(scene, _t(Ps), K, tgt["rgb"], tgt["feat"], tile=tile)
-    assert out["feat"] is None
-    for k in ("rgb", "depth", "alpha"):
-        assert np.array_equal(to_np(a[k]), to_np(out[k])), k
-    assert np.array_equal(to_np(ga_rgb), to_np(res[1]))
-    if D:
-        gf_a, gf_b = to_np(ga_feat), to_np(res[2])
-        assert np.abs(gf_a - gf_b).max() <= 1e-6 * np.abs(gf_a).max()
-    assert np.allclose(to_np(la), to_np(res[0]), rtol=1e-5, atol=0)
-    pb = rb.backward(dict(rgb=res[1], feat=res[2]), want=("pose",))["pose"]
-    assert _rel(to_np(pb), to_np(pa)) < 1e-5
+    log(f"case: residual backward D={D} tile={tile} bf16={bf16}")
+    r = hg.Renderer()
+    a = r.render(scene, _t(Ps), K, tile=tile, feat_bf16=bf16)
+    la, g_rgb, g_feat = hg.residual(a["rgb"], a["feat"], tgt["rgb"], tgt["feat"])
+    ga = r.backward(dict(rgb=g_rgb, feat=g_feat), want=("pose", "means"))
+    ga = {k: to_np(v).copy() for k, v in ga.items()}
+    lb, gb = r.residual_backward(tgt["rgb"], tgt["feat"], want=("pose", "means"))
+    assert np.allclose(to_np(la), to_np(lb), rtol=1e-5, atol=0)
+    assert _rel(to_np(gb["pose"]), ga["pose"]) < 1e-5
+    assert _rel(to_np(gb["means"]), ga["means"]) < 1e-5
 
 
-def test_fused_residual_shared_target(hg):
+def test_residual_backward_shared_target(hg):
     """One target shared by all poses gives what the same target replicated
-    per pose gives, bitwise."""
+    per pose gives (loss bitwise, gradients to float-atomic rounding)."""
     sc, P, cam = synth.tiny_scene(400, 50, width=70, height=52, feat_dim=16, sh_degree=1)
     Ps = synth.perturb_poses(P[0], 4, 51, 1.0, 2.0)
     scene = hg.GaussianScene.from_numpy(sc)
@@ -360,16 +351,10 @@ def test_fused_residual_shared_target(hg):
     rep_rgb = one_rgb.expand(4, -1, -1, -1).contiguous()
     rep_feat = one_feat.expand(4, -1, -1, -1).contiguous()
     log("case: shared vs replicated target")
-    _, ra = hg.Renderer().render_residual(scene, _t(Ps), K, one_rgb, one_feat)
-    _, rb = hg.Renderer().render_residual(scene, _t(Ps), K, rep_rgb, rep_feat)
-    for x, y in zip(ra, rb):
-        assert np.array_equal(to_np(x), to_np(y))
-    log("case: autotune the residual render")
     r = hg.Renderer()
-    out, res = r.render_residual(scene, _t(Ps), K, one_rgb, one_feat)
-    tuned = r.autotune(scene, _t(Ps), K, out, residual=dict(rgb_target=one_rgb, feat_target=one_feat, res=res))
-    log("tuned", tuned)
-    assert tuned["feat_accum"] == "valu" and tuned["tile"] in (8, 16, 32)
-    _, rc = r.render_residual(scene, _t(Ps), K, one_rgb, one_feat, out=out, tile=0, schedule="auto")
-    assert np.array_equal(to_np(rc[1]), to_np(ra[1])) and np.array_equal(to_np(rc[2]), to_np(ra[2]))
-    assert np.allclose(to_np(rc[0]), to_np(ra[0]), rtol=1e-5, atol=0)
+    r.render(scene, _t(Ps), K)
+    la, ga = r.residual_backward(one_rgb, one_feat)
+    la, pa = to_np(la).copy(), to_np(ga["pose"]).copy()
+    lb, gb = r.residual_backward(rep_rgb, rep_feat)
+    assert np.array_equal(la, to_np(lb))
+    assert _rel(to_np(gb["pose"]), pa) < 1e-6
