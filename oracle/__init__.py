@@ -63,6 +63,7 @@ def _load():
         lib.orc_render_frozen.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P]
         lib.orc_tile_lists.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P, ctypes.c_int64, P, P]
         lib.orc_sh_basis.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P]
+        lib.orc_min_q_box.argtypes = [P, ctypes.c_int64, P]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -174,6 +175,17 @@ def tile_lists(scene, pose, cam, tile: int = 16, edge_px: float = 1e-3, near: fl
     lib.orc_tile_lists(ctypes.byref(b.s), _ptr(pose64), ctypes.byref(b.c), tile, edge_px, _ptr(offsets), _ptr(ids),
                        ids.shape[0], _ptr(edge), _ptr(total))
     return offsets, ids[: int(total[0])], edge.astype(bool)
+
+
+def min_q_box(rows: np.ndarray) -> np.ndarray:
+    """Smallest conic distance a dx^2 + 2 b dx dy + c dy^2 of rectangles to
+    means: rows (n, 9) [a, b, c, u, v, x0, x1, y0, y1]."""
+    lib = _load()
+    r = np.zeros((len(rows), 10))
+    r[:, :9] = rows
+    out = np.zeros(len(rows))
+    lib.orc_min_q_box(_ptr(r), len(rows), _ptr(out))
+    return out
 
 
 def sh_basis(degree: int, dirs: np.ndarray) -> np.ndarray:

@@ -41,6 +41,7 @@
 // blended Gaussians) lies within an FP32 error bound of flipping.
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -160,6 +161,27 @@ struct Pose {
   double R[3][3];
   double t[3];
 };
+
+// Smallest conic distance q(p - mean) = a dx^2 + 2 b dx dy + c dy^2 over the
+// rectangle [x0, x1] x [y0, y1].  q is convex: 0 when the mean lies inside,
+// otherwise the minimum lies on an edge, where q is a one-variable quadratic
+// minimised at its stationary point clamped to the edge.
+double min_q_box(double a, double b, double c, double u, double v, double x0, double x1, double y0, double y1) {
+  if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return 0.0;
+  auto q = [&](double dx, double dy) { return a * dx * dx + 2.0 * b * dx * dy + c * dy * dy; };
+  double best = std::numeric_limits<double>::infinity();
+  for (double xe : {x0, x1}) {  // edges x = xe
+    const double dx = xe - u;
+    const double dy = std::min(std::max(-b * dx / c, y0 - v), y1 - v);
+    best = std::min(best, q(dx, dy));
+  }
+  for (double ye : {y0, y1}) {  // edges y = ye
+    const double dy = ye - v;
+    const double dx = std::min(std::max(-b * dy / a, x0 - u), x1 - u);
+    best = std::min(best, q(dx, dy));
+  }
+  return best;
+}
 
 Pose make_pose(const double* p) {
   Pose P;
@@ -396,6 +418,18 @@ void store_pixel(const PixelOut& po, const double* f, int D, int64_t pix, int64_
     for (int k = 0; k < D; ++k) feat[k * HW + pix] = f[k];
 }
 
+// Tile listing rule: a visible Gaussian is listed in the tiles of its pixel
+// rectangle (step 7) whose rectangle of pixel centres (clipped to the image,
+// grown by `grow` px on each side) meets the support ellipse q <= k^2,
+// k^2 = 2 ln(255 o).  Every pixel where the Gaussian passes the 1/255 gate
+// lies in such a tile, so the tiled render equals the per-pixel definition.
+bool tile_meets(const Proj& g, int tx, int ty, int tile, int W, int H, double grow) {
+  const double x0 = tx * tile + 0.5 - grow, x1 = std::min((tx + 1) * tile, W) - 0.5 + grow;
+  const double y0 = ty * tile + 0.5 - grow, y1 = std::min((ty + 1) * tile, H) - 0.5 + grow;
+  const double k2 = 2.0 * std::log(255.0 * g.o);
+  return min_q_box(g.conic[0], g.conic[1], g.conic[2], g.u, g.v, x0, x1, y0, y1) <= k2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -422,8 +456,9 @@ int orc_project(const orc_scene* s, const double* pose, const orc_camera* cam, d
 }
 
 // Render one pose.  mode 0: brute force (global (z, i) sort, every visible
-// Gaussian tested at every pixel); mode 1: tiled (per-tile lists from the
-// support rectangle grown by `margin_px` whole pixels).
+// Gaussian tested at every pixel); mode 1: tiled (per-tile lists by the tile
+// listing rule, with the pixel rectangle and the tiles' centre rectangles
+// grown by `margin_px` pixels).
 // Outputs (caller-allocated): rgb 3xHxW, depth HxW, alpha HxW, feat DxHxW (or
 // null), finalT HxW, nblend HxW, fragile HxW (any may be null except rgb, depth,
 // alpha).  stats[4] = {visible, keys, tested pairs, blended pairs}.
@@ -474,6 +509,7 @@ int orc_render(const orc_scene* s, const double* pose, const orc_camera* cam, in
       const int y0 = std::max(0, g.py0 - margin_px), y1 = std::min(H - 1, g.py1 + margin_px);
       for (int ty = y0 / tile; ty <= y1 / tile; ++ty)
         for (int tx = x0 / tile; tx <= x1 / tile; ++tx) {
+          if (!tile_meets(g, tx, ty, tile, W, H, static_cast<double>(margin_px))) continue;
           bins[static_cast<size_t>(ty) * ntx + tx].push_back(static_cast<int32_t>(i));
           ++keys;
         }
@@ -561,10 +597,11 @@ int orc_render_frozen(const orc_scene* s, const double* pose, const orc_camera* 
   return 0;
 }
 
-// Per-tile candidate lists in (z, i) order (support rectangle of step 7, no
+// Per-tile candidate lists in (z, i) order (the tile listing rule, no
 // margin).  offsets: ntiles + 1 entries; ids: capacity `cap` (may be null to
 // query the total, returned in *total).  edge[i] = 1 when Gaussian i's tile set
-// changes if any rectangle bound moves by up to `edge_px` pixels.
+// changes if any pixel-rectangle bound, or the centre rectangle of any tile
+// it may reach, moves by up to `edge_px` pixels.
 int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam, int32_t tile, double edge_px,
                    int64_t* offsets, int32_t* ids, int64_t cap, uint8_t* edge, int64_t* total) {
   const Pose P = make_pose(pose);
@@ -594,11 +631,18 @@ int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam
       tiles_of(g.bx0 + edge_px, g.bx1 - edge_px, g.by0 + edge_px, g.by1 - edge_px, lo);
       tiles_of(g.bx0 - edge_px, g.bx1 + edge_px, g.by0 - edge_px, g.by1 + edge_px, hi);
       if (lo[0] != hi[0] || lo[1] != hi[1] || lo[2] != hi[2] || lo[3] != hi[3]) edge[i] = 1;
+      for (int ty = std::max(hi[2], 0); ty <= hi[3] && !edge[i]; ++ty)
+        for (int tx = std::max(hi[0], 0); tx <= hi[1]; ++tx)
+          if (tile_meets(g, tx, ty, tile, W, H, edge_px) != tile_meets(g, tx, ty, tile, W, H, -edge_px)) {
+            edge[i] = 1;
+            break;
+          }
     }
     if (!g.visible) continue;
     for (int ty = g.py0 / tile; ty <= g.py1 / tile; ++ty)
       for (int tx = g.px0 / tile; tx <= g.px1 / tile; ++tx)
-        bins[static_cast<size_t>(ty) * ntx + tx].push_back(static_cast<int32_t>(i));
+        if (tile_meets(g, tx, ty, tile, W, H, 0.0))
+          bins[static_cast<size_t>(ty) * ntx + tx].push_back(static_cast<int32_t>(i));
   }
   int64_t acc = 0;
   for (size_t b = 0; b < bins.size(); ++b) {
@@ -612,6 +656,16 @@ int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam
   if (offsets) offsets[bins.size()] = acc;
   *total = acc;
   return (ids && acc > cap) ? 2 : 0;
+}
+
+// Smallest conic distance over rectangles (tests): rows of 10 doubles
+// [a, b, c, u, v, x0, x1, y0, y1, unused] -> out[i].
+int orc_min_q_box(const double* rows, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double* r = rows + 10 * i;
+    out[i] = min_q_box(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8]);
+  }
+  return 0;
 }
 
 // Real SH basis values at unit directions (tests): dirs n x 3, out n x (deg+1)^2.

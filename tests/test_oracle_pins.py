@@ -381,21 +381,75 @@ def test_view_dependent_colour_uses_camera_centre(oracle_lib):
 
 
 # ------------------------------------------------------------------ tile lists
-def test_tile_lists_match_rectangles(oracle_lib):
+def test_tile_lists_follow_the_listing_rule(oracle_lib):
+    """A visible Gaussian is listed in a tile of its pixel rectangle exactly
+    when the tile's rectangle of pixel centres meets its support ellipse
+    q <= 2 ln(255 o); checked here by brute force on a 1/40 px grid of each
+    such rectangle (grid minimum vs the listing decision), in (z, index)
+    order.  Listing must also be a subset of the rectangle rule."""
     sc, P, cam = synth.tiny_scene(180, 13)
     tile = 16
     p = oracle_lib.project(sc, P[0], cam)
     off, ids, edge = oracle_lib.tile_lists(sc, P[0], cam, tile)
     ntx = (cam.width + tile - 1) // tile
     nty = (cam.height + tile - 1) // tile
+    k2 = 2.0 * np.log(255.0 * p["o"])
+    dropped = 0
     for ty in range(nty):
         for tx in range(ntx):
             b = ty * ntx + tx
-            got = ids[off[b]:off[b + 1]]
-            want = [i for i in range(sc.n) if p["visible"][i] and p["px0"][i] // tile <= tx <= p["px1"][i] // tile
+            got = list(ids[off[b]:off[b + 1]])
+            rect = [i for i in range(sc.n) if p["visible"][i] and p["px0"][i] // tile <= tx <= p["px1"][i] // tile
                     and p["py0"][i] // tile <= ty <= p["py1"][i] // tile]
+            assert set(got) <= set(rect)
+            xs = np.arange(tx * tile + 0.5, min((tx + 1) * tile, cam.width) - 0.5 + 1e-9, 1 / 40)
+            ys = np.arange(ty * tile + 0.5, min((ty + 1) * tile, cam.height) - 0.5 + 1e-9, 1 / 40)
+            X, Y = np.meshgrid(xs, ys)
+            want = []
+            for i in rect:
+                a, bb, c = p["conic_a"][i], p["conic_b"][i], p["conic_c"][i]
+                dx, dy = X - p["u"][i], Y - p["v"][i]
+                qmin = (a * dx * dx + 2 * bb * dx * dy + c * dy * dy).min()
+                # grid spacing bound: |grad q| * spacing / sqrt(2) at most
+                slack = 2 * np.sqrt(max(a, c) * k2[i]) * np.sqrt(max(a, c)) / 40
+                if qmin <= k2[i]:
+                    want.append(i)
+                else:
+                    assert i not in got or qmin <= k2[i] + slack, (tx, ty, i)
+                    if i in got:
+                        want.append(i)
+            dropped += len(rect) - len(got)
             want.sort(key=lambda i: (p["z"][i], i))
-            assert list(got) == want
+            assert got == want, (tx, ty)
+    assert dropped > 0  # the rule is tighter than the rectangle on this scene
+
+
+def test_min_q_box_closed_forms_and_grid(oracle_lib):
+    rng = np.random.default_rng(5)
+    # mean inside -> 0; isotropic axis-aligned -> a * squared distance
+    assert oracle_lib.min_q_box(np.array([[2.0, 0.3, 1.0, 5.0, 5.0, 4.0, 6.0, 4.5, 5.5]]))[0] == 0.0
+    r = oracle_lib.min_q_box(np.array([[0.5, 0.0, 0.5, 0.0, 0.0, 3.0, 4.0, -1.0, 1.0]]))[0]
+    assert abs(r - 0.5 * 9.0) < 1e-15
+    r = oracle_lib.min_q_box(np.array([[0.5, 0.0, 0.5, 0.0, 0.0, 3.0, 4.0, 4.0, 6.0]]))[0]
+    assert abs(r - 0.5 * 25.0) < 1e-15
+    rows = []
+    for _ in range(200):
+        L = rng.normal(size=(2, 2))
+        S = L @ L.T + 0.1 * np.eye(2)
+        a, b, c = S[0, 0], S[0, 1], S[1, 1]
+        u, v = rng.uniform(-5, 5, 2)
+        x0, y0 = rng.uniform(-6, 4, 2)
+        x1, y1 = x0 + rng.uniform(0.1, 3), y0 + rng.uniform(0.1, 3)
+        rows.append([a, b, c, u, v, x0, x1, y0, y1])
+    rows = np.array(rows)
+    got = oracle_lib.min_q_box(rows)
+    for row, g in zip(rows, got):
+        a, b, c, u, v, x0, x1, y0, y1 = row
+        X, Y = np.meshgrid(np.linspace(x0, x1, 401), np.linspace(y0, y1, 401))
+        dx, dy = X - u, Y - v
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        assert g <= q.min() + 1e-12  # never above any point of the rectangle
+        assert q.min() - g <= 1e-3 * (1 + q.min())  # and at the grid's resolution
 
 
 # ------------------------------------------------------------------ pose tangent and residual
