@@ -423,11 +423,12 @@ void store_pixel(const PixelOut& po, const double* f, int D, int64_t pix, int64_
 // grown by `grow` px on each side) meets the support ellipse q <= k^2,
 // k^2 = 2 ln(255 o).  Every pixel where the Gaussian passes the 1/255 gate
 // lies in such a tile, so the tiled render equals the per-pixel definition.
-bool tile_meets(const Proj& g, int tx, int ty, int tile, int W, int H, double grow) {
+// slack widens the threshold to k^2 (1 + slack) + 10 slack (edge tests).
+bool tile_meets(const Proj& g, int tx, int ty, int tile, int W, int H, double grow, double slack = 0.0) {
   const double x0 = tx * tile + 0.5 - grow, x1 = std::min((tx + 1) * tile, W) - 0.5 + grow;
   const double y0 = ty * tile + 0.5 - grow, y1 = std::min((ty + 1) * tile, H) - 0.5 + grow;
   const double k2 = 2.0 * std::log(255.0 * g.o);
-  return min_q_box(g.conic[0], g.conic[1], g.conic[2], g.u, g.v, x0, x1, y0, y1) <= k2;
+  return min_q_box(g.conic[0], g.conic[1], g.conic[2], g.u, g.v, x0, x1, y0, y1) <= k2 * (1.0 + slack) + 10.0 * slack;
 }
 
 }  // namespace
@@ -601,7 +602,8 @@ int orc_render_frozen(const orc_scene* s, const double* pose, const orc_camera* 
 // margin).  offsets: ntiles + 1 entries; ids: capacity `cap` (may be null to
 // query the total, returned in *total).  edge[i] = 1 when Gaussian i's tile set
 // changes if any pixel-rectangle bound, or the centre rectangle of any tile
-// it may reach, moves by up to `edge_px` pixels.
+// it may reach, moves by up to `edge_px` pixels, or the ellipse threshold by
+// a relative 2e-5 (+2e-4).
 int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam, int32_t tile, double edge_px,
                    int64_t* offsets, int32_t* ids, int64_t cap, uint8_t* edge, int64_t* total) {
   const Pose P = make_pose(pose);
@@ -633,7 +635,7 @@ int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam
       if (lo[0] != hi[0] || lo[1] != hi[1] || lo[2] != hi[2] || lo[3] != hi[3]) edge[i] = 1;
       for (int ty = std::max(hi[2], 0); ty <= hi[3] && !edge[i]; ++ty)
         for (int tx = std::max(hi[0], 0); tx <= hi[1]; ++tx)
-          if (tile_meets(g, tx, ty, tile, W, H, edge_px) != tile_meets(g, tx, ty, tile, W, H, -edge_px)) {
+          if (tile_meets(g, tx, ty, tile, W, H, edge_px, 2e-5) != tile_meets(g, tx, ty, tile, W, H, -edge_px)) {
             edge[i] = 1;
             break;
           }

@@ -172,25 +172,16 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
     {
       const int e = tid % NB, part = tid / NB;
       if (e < nb) {
-        const uint32_t r = a.list[range.x + b0 + e];
+        const uint32_t lv = a.list[range.x + b0 + e];
+        const uint32_t r = lv & kRecMask;
         const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
         const float4 g1 = sp[1];
         if (part == 0) {
-          const float4 g0 = sp[0], g2 = sp[2];
-          s_geo[e] = g0;
+          s_geo[e] = sp[0];
           s_opz[e] = g1;
-          s_col[e] = g2;
+          s_col[e] = sp[2];
           s_rec[e] = r;
-          float x0, x1, y0, y1;
-          splat_rect(g0, g1, g2.w, x0, x1, y0, y1);
-          uint8_t m = 0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) {
-            const float wx0 = static_cast<float>(tx * TILE + (w % Sh::kBlocksX) * BW);
-            const float wy0 = static_cast<float>(ty * TILE + (w / Sh::kBlocksX) * BH);
-            if (x1 >= wx0 && x0 <= wx0 + (BW - 1) && y1 >= wy0 && y0 <= wy0 + (BH - 1)) m |= 1u << w;
-          }
-          s_mask[e] = m;
+          s_mask[e] = static_cast<uint8_t>(lv >> kRecBits);  // waves whose block the support meets
         }
         if constexpr (DV > 0) {
           if (part < PARTS) {

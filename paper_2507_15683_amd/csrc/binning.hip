@@ -275,18 +275,27 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
   const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
   const uint2 r = a.rects[idx];
-  const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];  // cc, o, z, gid
+  const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+  const float4 geo = rp[0], hdr = rp[1];  // u, v, ca, cb | cc, o, z, gid
+  const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
   const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
   const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
-  const int nx = tx1 - tx0 + 1, ntl = nx * (ty1 - ty0 + 1);
   const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
-  for (int q = static_cast<int>(sub); q < ntl; q += kEmitLanes) {
-    const int ty = ty0 + q / nx, tx = tx0 + q % nx;
-    const int64_t tg = tbase + ty * a.c.ntx + tx;
-    const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
-    if (pos < a.key_cap) {
-      a.keys[pos] = key;
-      a.vals[pos] = static_cast<uint32_t>(idx);
+  // the record's tiles row by row (the projection counted the same spans);
+  // the kEmitLanes lanes of a record take every kEmitLanes-th tile in order
+  int q = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    int ta, tb;
+    row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+    const int first = ta + ((static_cast<int>(sub) - q) % kEmitLanes + kEmitLanes) % kEmitLanes;
+    if (tb >= ta) q += tb - ta + 1;
+    for (int tx = first; tx <= tb; tx += kEmitLanes) {
+      const int64_t tg = tbase + ty * a.c.ntx + tx;
+      const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
+      if (pos < a.key_cap) {
+        a.keys[pos] = key;
+        a.vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+      }
     }
   }
 }
@@ -506,18 +515,27 @@ __global__ __launch_bounds__(256) void emit_lsd_kernel(BinArgs a, const uint32_t
   if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
   const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
   const uint2 r = a.rects[idx];
-  const float4 hdr = reinterpret_cast<const float4*>(a.recs + idx)[1];
+  const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+  const float4 geo = rp[0], hdr = rp[1];
+  const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
   const uint32_t zb = zbits(hdr.z), gid = __float_as_uint(hdr.w);
   const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
   uint64_t pos = rec_offsets[idx];
   const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-      if (pos >= a.key_cap) continue;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    int ta, tb;
+    row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+    for (int tx = ta; tx <= tb; ++tx) {
+      if (pos >= a.key_cap) {
+        ++pos;
+        continue;
+      }
       keys[pos] = (static_cast<uint64_t>(tbase + ty * a.c.ntx + tx) << 32) | zb;
       gids[pos] = gid;
-      vals[pos] = static_cast<uint32_t>(idx);
+      vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+      ++pos;
     }
+  }
 }
 
 void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,

@@ -356,19 +356,102 @@ struct BlendShape {
   static constexpr int kBlocksX = TILE / kBlockW;
 };
 
-// Pixel-centre rectangle of a splat's support, padded; shared by the wave
-// culling of the forward and backward blends.
-__device__ __forceinline__ void splat_rect(const float4 geo, const float4 opz, float pmin, float& x0, float& x1,
-                                           float& y0, float& y1) {
-  const float det = geo.z * opz.x - geo.w * geo.w;
-  const float k2 = -2.f * pmin;
-  const float rx = 1.001f * sqrtf(fmaxf(k2 * opz.x / det, 0.f)) + 0.05f;
-  const float ry = 1.001f * sqrtf(fmaxf(k2 * geo.z / det, 0.f)) + 0.05f;
-  x0 = geo.x - rx - 0.5f;
-  x1 = geo.x + rx - 0.5f;
-  y0 = geo.y - ry - 0.5f;
-  y1 = geo.y + ry - 0.5f;
+// Smallest conic distance q(p - mean) = a dx^2 + 2 b dx dy + c dy^2 over the
+// rectangle [x0, x1] x [y0, y1] (ia = 1/a, ic = 1/c).  q is convex: 0 when
+// the mean is inside, otherwise the smallest of the four edge minima, each a
+// one-variable quadratic minimised at its clamped stationary point.
+__device__ __forceinline__ float min_q_box(float a, float b, float c, float ia, float ic, float u, float v, float x0,
+                                           float x1, float y0, float y1) {
+  if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return 0.f;
+  float best = 3.4e38f;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float dx = (e ? x1 : x0) - u;
+    const float dy = fminf(fmaxf(-b * dx * ic, y0 - v), y1 - v);
+    best = fminf(best, fmaf(a * dx, dx, fmaf(2.f * b * dx, dy, c * dy * dy)));
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float dy = (e ? y1 : y0) - v;
+    const float dx = fminf(fmaxf(-b * dy * ia, x0 - u), x1 - u);
+    best = fminf(best, fmaf(a * dx, dx, fmaf(2.f * b * dx, dy, c * dy * dy)));
+  }
+  return best;
 }
+
+// Listing margins, wider than FP32 rounding of the mean (1e-4 px at 2000 px)
+// and of q: rectangles grow by kListGrow px, the threshold k^2 by a relative
+// kListSlack plus 10 kListSlack.
+constexpr float kListGrow = 5e-4f;
+constexpr float kListSlack = 1e-5f;
+
+// Whether a splat (mean u, v; conic a, b, c; k2 = 2 ln(255 o)) meets the
+// rectangle of pixel centres [x0 + 0.5, x1 - 0.5] x [y0 + 0.5, y1 - 0.5]
+// (pixel-edge coordinates x0..x1, y0..y1), with the listing margins.
+struct SplatShape {
+  float u, v, a, b, c, ia, ic, thr;
+};
+__device__ __forceinline__ SplatShape splat_shape(float u, float v, float a, float b, float c, float k2) {
+  return SplatShape{u, v, a, b, c, 1.f / a, 1.f / c, fmaf(k2, kListSlack, k2) + 10.f * kListSlack};
+}
+__device__ __forceinline__ bool meets_centres(const SplatShape& s, float x0, float x1, float y0, float y1) {
+  return min_q_box(s.a, s.b, s.c, s.ia, s.ic, s.u, s.v, x0 + (0.5f - kListGrow), x1 - (0.5f - kListGrow),
+                   y0 + (0.5f - kListGrow), y1 - (0.5f - kListGrow)) <= s.thr;
+}
+// Tiles of row ty whose pixel-centre rectangles meet the support ellipse:
+// [*ta, *tb] within [tx0, tx1] (empty when *ta > *tb).  Equivalent to
+// tile_meets on each tile of the row, at two square roots per row: within
+// the row's band of pixel-centre y the ellipse's x-extent is an interval,
+// whose right end x_r(dy) = (-b dy + sqrt(a thr - det dy^2)) / a is concave
+// in dy with its maximum at dy = -b sqrt(thr / (c det)) (and the left end
+// mirrors it), so both ends are evaluated at that point clamped to the band.
+__device__ __forceinline__ void row_span(const SplatShape& s, int ty, int tile, int W, int H, int tx0, int tx1,
+                                         int* ta, int* tb) {
+  const float det = s.a * s.c - s.b * s.b;
+  const float ymax = sqrtf(s.a * s.thr / det);
+  const float lo = fmaxf(static_cast<float>(ty * tile) + (0.5f - kListGrow) - s.v, -ymax);
+  const float hi = fminf(static_cast<float>(min((ty + 1) * tile, H)) - (0.5f - kListGrow) - s.v, ymax);
+  if (!(lo <= hi)) {
+    *ta = 1;
+    *tb = 0;
+    return;
+  }
+  const float dyr = -s.b * sqrtf(s.thr / (s.c * det));
+  const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
+  const float xr = s.u + (-s.b * dr + sqrtf(fmaxf(s.a * s.thr - det * dr * dr, 0.f))) * s.ia;
+  const float xl = s.u + (-s.b * dl - sqrtf(fmaxf(s.a * s.thr - det * dl * dl, 0.f))) * s.ia;
+  const float inv = 1.f / static_cast<float>(tile);
+  int a = static_cast<int>(ceilf((xl + (0.5f - kListGrow)) * inv - 1.f));
+  int b = static_cast<int>(floorf((xr - (0.5f - kListGrow)) * inv));
+  if (xl > static_cast<float>(W) - (0.5f - kListGrow)) b = -1;  // right of the last pixel centre
+  *ta = max(a, tx0);
+  *tb = min(b, tx1);
+}
+
+// Tile-list entries carry the record index in the low kRecBits bits and, in
+// the top four, which of the tile's blend blocks (the waves' pixel blocks:
+// one 8x8 block at tile 8, 2 x 2 blocks of tile/2 otherwise) the splat's
+// support meets, so the blend stages no geometry test.
+constexpr int kRecBits = 28;
+constexpr uint32_t kRecMask = (1u << kRecBits) - 1u;
+__device__ __forceinline__ uint32_t block_mask(const SplatShape& s, int tx, int ty, int tile) {
+  if (tile == 8) return 1u;
+  const int h = tile / 2;
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float x0 = static_cast<float>(tx * tile + (w & 1) * h), y0 = static_cast<float>(ty * tile + (w >> 1) * h);
+    if (meets_centres(s, x0, x0 + h, y0, y0 + h)) m |= 1u << w;
+  }
+  return m;
+}
+
+// Tile (tx, ty) of a camera: its pixel-centre rectangle clipped to the image.
+__device__ __forceinline__ bool tile_meets(const SplatShape& s, int tx, int ty, int tile, int W, int H) {
+  return meets_centres(s, static_cast<float>(tx * tile), static_cast<float>(min((tx + 1) * tile, W)),
+                       static_cast<float>(ty * tile), static_cast<float>(min((ty + 1) * tile, H)));
+}
+
 
 constexpr int kWaveSortCap = 256;   // lists this short are sorted by one wave
 

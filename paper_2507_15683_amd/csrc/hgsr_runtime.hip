@@ -229,6 +229,8 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
   const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
   const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
   const int64_t npix = static_cast<int64_t>(P) * cam.W * cam.H;
+  if (nrec > static_cast<int64_t>(kRecMask))
+    return fail(HGSR_ERR_INVALID_ARG, "too many (pose, Gaussian) records for one render: split the poses");
   TRY(ensure(c, c->recs, nrec * sizeof(Splat)));
   TRY(ensure(c, c->rects, nrec * sizeof(uint2)));
   TRY(ensure(c, c->pose_count, static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
@@ -573,7 +575,7 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* c, int32_t pose, uint32_t* ranges, u
     ranges[2 * t] = static_cast<uint32_t>(k);
     for (uint32_t e = rg[t].x; e < rg[t].y; ++e, ++k) {
       if (gids && k < cap) {
-        const int64_t r = static_cast<int64_t>(idx[e - lo]) - base;
+        const int64_t r = static_cast<int64_t>(idx[e - lo] & kRecMask) - base;
         gids[k] = (r >= 0 && r < nrec) ? recs[r].gid : 0xffffffffu;
       }
     }
