@@ -237,7 +237,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
         if (alpha < kAlphaMin) continue;
         any = true;
         const float om = 1.f - alpha;
-        const float Tj = T[k] / om;
+        const float iom = __builtin_amdgcn_rcpf(om);  // 1/(1 - alpha), alpha <= 0.99
+        const float Tj = T[k] * iom;
         const float w = alpha * Tj;
         float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
         if constexpr (D > 0) {
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
             h = fmaf(gF[k][4 * q + 3], f.w, h);
           }
         }
-        const float dA = Tj * h - (S[k] + gT[k] * Tf[k]) / om;
+        const float dA = Tj * h - (S[k] + gT[k] * Tf[k]) * iom;
         S[k] = fmaf(w, h, S[k]);
         T[k] = Tj;
         g[7] += w * gC[k][0];

@@ -262,6 +262,39 @@ void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, ui
                      ranges);
 }
 
+// ------------------------------------------------------------ tile counts
+// One thread per record: the tiles of its pixel rectangle that the support
+// ellipse meets (row spans), counted per (pose, tile) for the bucket path and
+// per record for the LSD path.  The emit kernels walk the same spans.
+__global__ __launch_bounds__(256) void count_tiles_kernel(BinArgs a, uint32_t* tile_count, uint32_t* rec_keys) {
+  if (a.flags[0] & 1) return;
+  const int pose = blockIdx.y;
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
+  const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+  const uint2 r = a.rects[idx];
+  const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+  const float4 geo = rp[0], hdr = rp[1];
+  const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+  const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+  uint32_t* tc = tile_count ? tile_count + static_cast<int64_t>(pose) * a.c.tiles_per_pose : nullptr;
+  uint32_t ntiles = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    int ta, tb;
+    row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+    for (int tx = ta; tx <= tb; ++tx) {
+      ++ntiles;
+      if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+    }
+  }
+  if (rec_keys) rec_keys[idx] = ntiles;
+}
+
+void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_keys, hipStream_t s) {
+  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+  hipLaunchKernelGGL(count_tiles_kernel, grid, dim3(256), 0, s, a, tile_count, rec_keys);
+}
+
 // ------------------------------------------------------------ bucket path
 // Four threads per record, each claiming slots in every fourth overlapped
 // tile's bucket (enough waves in flight to hide the atomics' latency).

@@ -209,6 +209,8 @@ hgsr_status check_intrinsics(const hgsr_intrinsics* K) {
 
 // Records per pose: a multiple of the sub-segment count, with sub-segments
 // half again as large as an even split (block-to-counter imbalance).
+constexpr int kCountInProjectPoses = 4;
+
 uint32_t round_rec_cap(int64_t r) {
   int64_t sub = (r + kSub - 1) / kSub;
   sub += sub / 2 + 64;
@@ -368,6 +370,10 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
 
   hipEvent_t e0 = stamp(c, s);
   const GaussArgs ga = make_gauss(*g);
+  // Tile counts: inside the projection for few poses (its latency hides the
+  // atomics), in a kernel of one thread per record for many (the
+  // projection's per-pose loop would diverge on them).
+  const bool count_in_project = P <= kCountInProjectPoses;
   if (g->n_parts > 0) launch_partition_cull(poses, P, g->part_bounds, g->n_parts, cam, c->part_vis.as<uint64_t>(), s);
 
   if (g->n > 0) {
@@ -380,11 +386,11 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
       pa.pose_base = p0;
       pa.recs = c->recs.as<Splat>();
       pa.rects = c->rects.as<uint2>();
-      pa.rec_keys = lsd ? c->rec_keys.as<uint32_t>() : nullptr;
       pa.pose_count = pose_count;
       pa.rec_cap = c->rec_cap;
-      pa.tile_count = lsd ? nullptr : c->tile_count.as<uint32_t>();
       pa.part_vis = g->n_parts > 0 ? c->part_vis.as<uint64_t>() : nullptr;
+      pa.tile_count = count_in_project && !lsd ? c->tile_count.as<uint32_t>() : nullptr;
+      pa.rec_keys = count_in_project && lsd ? c->rec_keys.as<uint32_t>() : nullptr;
       pa.flags = misc + kFlags;
       launch_project(pa, s);
     }
@@ -404,6 +410,9 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   ba.flags = misc + kFlags;
   uint32_t* total = reinterpret_cast<uint32_t*>(misc + kTotalKeys);
   const uint32_t* sorted = nullptr;
+  if (!count_in_project)
+    launch_count_tiles(ba, lsd ? nullptr : c->tile_count.as<uint32_t>(), lsd ? c->rec_keys.as<uint32_t>() : nullptr,
+                       s);
   if (!lsd) {
     launch_scan(c->tile_count.as<uint32_t>(), ntile, nullptr, c->ranges.as<uint2>(), c->scan_tmp.as<uint32_t>(), total,
                 c->key_cap, misc + kFlags, 2, s);

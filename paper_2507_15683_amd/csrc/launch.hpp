@@ -16,10 +16,12 @@ struct ProjectArgs {
   int32_t pose_base;         // first pose of this launch
   Splat* recs;               // P_total x rec_cap
   uint2* rects;              // tile rectangle per record (tx0 | tx1 << 16, ty0 | ty1 << 16)
-  uint32_t* rec_keys;        // entries per record (LSD path) or null
   uint32_t* pose_count;      // P x kSub sub-segment counters (may exceed rec_cap / kSub)
   uint32_t rec_cap;          // records per pose (a multiple of kSub)
-  uint32_t* tile_count;      // entries per (pose, tile) (bucket path) or null
+  // tile counts taken here for few poses (else count_tiles_kernel): per
+  // (pose, tile) for the bucket path, per record for the LSD path, or null
+  uint32_t* tile_count;
+  uint32_t* rec_keys;
   const uint64_t* part_vis;  // per pose: partitions that may be visible, or null
   int32_t* flags;            // [0]: overflow bits
 };
@@ -152,6 +154,8 @@ void launch_clear4(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t*
 int64_t scan_block_count(int64_t n);
 void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, uint32_t* block_sums,
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s);
+// tile_count (bucket) or rec_keys (LSD): the other may be null
+void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_keys, hipStream_t s);
 void launch_emit_bucket(const BinArgs& a, hipStream_t s);
 void launch_tile_sort(const TileSortArgs& a, bool short_lists, hipStream_t s);
 void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,

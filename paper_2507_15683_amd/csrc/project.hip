@@ -184,20 +184,22 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     const int ty0 = f.py0 >> a.c.tile_shift, ty1 = f.py1 >> a.c.tile_shift;
     a.rects[idx] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
                               static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
-    // tiles of the rectangle whose pixel centres the support ellipse meets
-    // (the emit kernels apply the same test to the stored record)
-    const SplatShape shp = splat_shape(sp.u, sp.v, sp.ca, sp.cb, sp.cc, -2.f * sp.pmin);
-    uint32_t ntiles = 0;
-    uint32_t* tc = a.tile_count ? a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose : nullptr;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-      int ta, tb;
-      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
-      for (int tx = ta; tx <= tb; ++tx) {
-        ++ntiles;
-        if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+    // few poses: the record's tiles are counted here (row spans of the same
+    // stored values count_tiles_kernel would read); many poses: there
+    if (a.tile_count || a.rec_keys) {
+      const SplatShape shp = splat_shape(sp.u, sp.v, sp.ca, sp.cb, sp.cc, -2.f * sp.pmin);
+      uint32_t ntiles = 0;
+      uint32_t* tc = a.tile_count ? a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose : nullptr;
+      for (int ty = ty0; ty <= ty1; ++ty) {
+        int ta, tb;
+        row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+        for (int tx = ta; tx <= tb; ++tx) {
+          ++ntiles;
+          if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+        }
       }
+      if (a.rec_keys) a.rec_keys[idx] = ntiles;
     }
-    if (a.rec_keys) a.rec_keys[idx] = ntiles;
   }
 }
 
