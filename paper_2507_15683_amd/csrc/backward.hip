@@ -44,7 +44,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int W = a.c.W, H = a.c.H;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int item = blockIdx.x;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pose = item / a.c.tiles_per_pose;
   const int tile = item - pose * a.c.tiles_per_pose;
   const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;

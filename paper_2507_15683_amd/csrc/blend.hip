@@ -66,7 +66,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       if (item >= a.n_items) break;
     } else {
       if (iter > 0) break;
-      item = blockIdx.x;
+      item = xcd_item(blockIdx.x, gridDim.x);
     }
     int pose, tile;
     if (a.schedule == kSchedTileMajor) {

@@ -453,6 +453,20 @@ __device__ __forceinline__ bool tile_meets(const SplatShape& s, int tx, int ty, 
 }
 
 
+// MI355X dispatches workgroup i of a launch to accelerator die (XCD)
+// i % kXcds, and each XCD has its own L2.  Renumbering the workgroups so that
+// each XCD takes one contiguous range of (pose, tile) items keeps
+// horizontally adjacent tiles -- which write the two halves of the same
+// output cache lines and read many of the same splats -- in one L2.  The map
+// is a permutation of [0, n), so results do not depend on the dispatch
+// order.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int x = b % kXcds, k = b / kXcds;
+  const int per = n / kXcds, rem = n % kXcds;
+  return x * per + min(x, rem) + k;
+}
+
 constexpr int kWaveSortCap = 256;   // lists this short are sorted by one wave
 
 // Tile-id bits of a pose-major tile index (for key packing).
