@@ -7,7 +7,8 @@ binding) never imports, links or calls it, and the two share no code.
 The arithmetic lives in `hgsr_oracle.cpp` (plain C++, double precision,
 OpenMP over tiles/rows); this module marshals numpy arrays to it.  The pose
 exponential and the refinement residual used by the finite-difference checks
-are in `se3.py` and `loss.py`.
+are in `se3.py` and `loss.py`; significance scoring with the render
+visibility check is in `significance.py`.
 """
 from __future__ import annotations
 
@@ -64,6 +65,7 @@ def _load():
         lib.orc_tile_lists.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P, ctypes.c_int64, P, P]
         lib.orc_sh_basis.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P]
         lib.orc_min_q_box.argtypes = [P, ctypes.c_int64, P]
+        lib.orc_contrib.argtypes = [P, P, P, ctypes.c_int32, P, P, P]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -119,12 +121,14 @@ def project(scene, pose, cam, near=0.2) -> dict:
 
 
 def render(scene, pose, cam, mode: str = "tiled", tile: int = 16, margin: int = 1, near: float = 0.2,
-           bg=(0.0, 0.0, 0.0), want_lists: bool = False, list_cap: int = 256) -> dict:
+           bg=(0.0, 0.0, 0.0), want_lists: bool = False, list_cap: int = 256, overrides=None) -> dict:
     """Render one pose in FP64.  Returns rgb (3,H,W), depth (H,W), alpha (H,W),
     feat (D,H,W) or None, T (H,W), nblend (H,W), fragile (H,W) bool, stats
-    {visible, keys, tested, blended}, and lists (H*W, list_cap) when asked."""
+    {visible, keys, tested, blended}, and lists (H*W, list_cap) when asked.
+    overrides: optional float64 arrays replacing scene parameters (as in
+    render_frozen)."""
     lib = _load()
-    b = _Bound(scene, cam, near, bg)
+    b = _Bound(scene, cam, near, bg, overrides)
     H, W, D = cam.height, cam.width, b.s.feat_dim
     rgb = np.zeros((3, H, W)); depth = np.zeros((H, W)); alpha = np.zeros((H, W))
     feat = np.zeros((D, H, W)) if D else None
@@ -175,6 +179,18 @@ def tile_lists(scene, pose, cam, tile: int = 16, edge_px: float = 1e-3, near: fl
     lib.orc_tile_lists(ctypes.byref(b.s), _ptr(pose64), ctypes.byref(b.c), tile, edge_px, _ptr(offsets), _ptr(ids),
                        ids.shape[0], _ptr(edge), _ptr(total))
     return offsets, ids[: int(total[0])], edge.astype(bool)
+
+
+def contrib(scene, pose, cam, tile: int = 16, near: float = 0.2):
+    """Per-Gaussian render visibility of one pose: (contrib, robust, touched)
+    boolean (N,) arrays -- blended at some pixel; blended at some non-fragile
+    pixel; reached by the walk of some fragile pixel."""
+    lib = _load()
+    b = _Bound(scene, cam, near)
+    n = scene.means.shape[0]
+    c = np.zeros(n, dtype=np.uint8); r = np.zeros(n, dtype=np.uint8); t = np.zeros(n, dtype=np.uint8)
+    lib.orc_contrib(ctypes.byref(b.s), _ptr(_pose64(pose)), ctypes.byref(b.c), tile, _ptr(c), _ptr(r), _ptr(t))
+    return c.astype(bool), r.astype(bool), t.astype(bool)
 
 
 def min_q_box(rows: np.ndarray) -> np.ndarray:

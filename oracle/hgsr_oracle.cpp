@@ -330,7 +330,7 @@ struct PixelOut {
 // blended Gaussians in order.  Returns the number of tested pairs.
 int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<Proj>& pr,
                    const int32_t* order, int64_t count, int px, int py, PixelOut& out, double* feat_out,
-                   int32_t* list_out, int32_t list_cap, bool* list_overflow) {
+                   int32_t* list_out, int32_t list_cap, bool* list_overflow, int64_t* walked = nullptr) {
   const int D = s.feat_dim;
   double T = 1.0, C[3] = {0, 0, 0}, Z = 0.0;
   for (int k = 0; k < D; ++k) feat_out[k] = 0.0;
@@ -341,6 +341,7 @@ int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<
   bool stopped = false;
   int64_t tested = 0;
   const double pxc = px + 0.5, pyc = py + 0.5;
+  if (walked) *walked = count;
   for (int64_t j = 0; j < count; ++j) {
     const int32_t gi = order[j];
     const Proj& g = pr[gi];
@@ -370,7 +371,10 @@ int64_t walk_pixel(const orc_scene& s, const orc_camera& cam, const std::vector<
     if (prev_z >= 0.0 && std::fabs(g.z - prev_z) <= ez + prev_ez) frag = true;
     prev_z = g.z;
     prev_ez = ez;
-    if (stopped) break;  // only the next gate-passing Gaussian matters after a stop
+    if (stopped) {  // only the next gate-passing Gaussian matters after a stop
+      if (walked) *walked = j + 1;
+      break;
+    }
     const double Tn = T * (1.0 - alpha);
     lnT_err += (alpha / (1.0 - alpha)) * dln + 4 * kEps32;
     if (std::fabs(std::log(Tn / kTMin)) <= 2.0 * lnT_err) frag = true;
@@ -658,6 +662,69 @@ int orc_tile_lists(const orc_scene* s, const double* pose, const orc_camera* cam
   if (offsets) offsets[bins.size()] = acc;
   *total = acc;
   return (ids && acc > cap) ? 2 : 0;
+}
+
+// Which Gaussians contribute to the rendered image (the render-gradient
+// visibility check of Sec. 3.2 and its algorithm: after rendering and a
+// backward pass of the summed RGB, a Gaussian is visible where its mean
+// receives a nonzero gradient, i.e. where it is blended, with weight
+// alpha T > 0, at one pixel at least).  Per Gaussian i:
+//   contrib[i]  = 1 if it is blended at some pixel;
+//   robust[i]   = 1 if it is blended at some pixel that is not fragile;
+//   touched[i]  = 1 if some fragile pixel's walk reached it (tested it before
+//                 the walk ended).
+// A Gaussian with robust = 0 and touched = 1 may be decided either way by an
+// FP32 renderer; every other Gaussian's contrib is fixed.  Tiled walk, lists by
+// the tile listing rule (equal to the brute-force walk).
+int orc_contrib(const orc_scene* s, const double* pose, const orc_camera* cam, int32_t tile, uint8_t* contrib,
+                uint8_t* robust, uint8_t* touched) {
+  const Pose P = make_pose(pose);
+  const int W = cam->width, H = cam->height, D = s->feat_dim;
+  const int ntx = (W + tile - 1) / tile, nty = (H + tile - 1) / tile;
+  std::vector<Proj> pr(s->n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < s->n; ++i) pr[i] = project(*s, i, P, *cam, false);
+  std::vector<std::vector<int32_t>> bins(static_cast<size_t>(ntx) * nty);
+  for (int64_t i = 0; i < s->n; ++i) {
+    contrib[i] = robust[i] = touched[i] = 0;
+    const Proj& g = pr[i];
+    if (!g.visible) continue;
+    for (int ty = g.py0 / tile; ty <= g.py1 / tile; ++ty)
+      for (int tx = g.px0 / tile; tx <= g.px1 / tile; ++tx)
+        if (tile_meets(g, tx, ty, tile, W, H, 0.0))
+          bins[static_cast<size_t>(ty) * ntx + tx].push_back(static_cast<int32_t>(i));
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < static_cast<int64_t>(bins.size()); ++b) {
+    std::vector<int32_t>& lst = bins[b];
+    std::sort(lst.begin(), lst.end(), [&](int32_t a, int32_t c) { return z_index_less(pr, a, c); });
+    const int tx = static_cast<int>(b % ntx), ty = static_cast<int>(b / ntx);
+    std::vector<double> f(D > 0 ? D : 1);
+    std::vector<int32_t> blended(lst.size() + 1);
+    for (int py = ty * tile; py < std::min(H, (ty + 1) * tile); ++py)
+      for (int px = tx * tile; px < std::min(W, (tx + 1) * tile); ++px) {
+        PixelOut po;
+        bool ovf = false;
+        int64_t walked = 0;
+        walk_pixel(*s, *cam, pr, lst.data(), static_cast<int64_t>(lst.size()), px, py, po, f.data(), blended.data(),
+                   static_cast<int32_t>(blended.size()), &ovf, &walked);
+        for (int32_t k = 0; k < po.nblend; ++k) {
+          const int32_t gi = blended[k];
+#pragma omp atomic write
+          contrib[gi] = 1;
+          if (!po.fragile) {
+#pragma omp atomic write
+            robust[gi] = 1;
+          }
+        }
+        if (po.fragile)
+          for (int64_t j = 0; j < walked; ++j) {
+#pragma omp atomic write
+            touched[lst[j]] = 1;
+          }
+      }
+  }
+  return 0;
 }
 
 // Smallest conic distance over rectangles (tests): rows of 10 doubles
