@@ -287,6 +287,88 @@ def fwd_bwd(hg, torch, synth, args):
             "mean_loss_after": round(loss_b, 5)}
 
 
+def significance(hg, torch, synth, args):
+    """Significance scoring (Sec. 3.2, Eq. 4-6): the 1M-Gaussian scene against
+    64 training views at 960x540 with 32-channel FP32 maps at image
+    resolution, one call per batch of 64 views."""
+    import ctypes
+    log("bench: significance scoring, 64 views at 960x540")
+    sc, P, cam = synth.config3(0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    NP, W, H, D, n = P.shape[0], cam.width, cam.height, sc.feat_dim, sc.n
+    poses = torch.from_numpy(P).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3100)
+    maps = torch.randn((NP, D, H, W), generator=gen, device="cuda", dtype=torch.float32)
+    r = hg.Renderer()
+    first = r.significance(scene, poses, K, maps, tile=16)       # sizes the workspace
+    pairs = int(first["vis_count"].sum().item())
+    st = r.stats()
+    reserve_headroom(r, NP, K, n, factor=1.1)
+    del first
+    ssum = torch.zeros(n, dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    opts = r.opts(tile=16)
+    s = torch.cuda.Stream()
+    lib = r.lib
+    ms_acc = (ctypes.c_double * 6)()
+    calls = (ctypes.c_int64 * 6)()
+    out = {}
+    for layout in ("planar", "interleaved"):
+        m = maps if layout == "planar" else maps.permute(0, 2, 3, 1).contiguous()
+        for _ in range(2):
+            r.significance_into(scene, poses, K, m, ssum, cnt, opts, layout=layout, stream=s)
+        s.synchronize()
+        lib.hgsr_profile_enable(r.ctx, 1)
+        lib.hgsr_profile_read(r.ctx, ms_acc, calls)  # reset
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.sig_steps):
+            r.significance_into(scene, poses, K, m, ssum, cnt, opts, layout=layout, stream=s)
+        e1.record(s)
+        s.synchronize()
+        lib.hgsr_profile_read(r.ctx, ms_acc, calls)
+        lib.hgsr_profile_enable(r.ctx, 0)
+        if r.check_overflow(s) != 0:
+            raise RuntimeError("workspace overflow during the timed scoring calls")
+        # the profiled events sit between the stages and slow them slightly;
+        # the batch time comes from an unprofiled run
+        e0.record(s)
+        for _ in range(args.sig_steps):
+            r.significance_into(scene, poses, K, m, ssum, cnt, opts, layout=layout, stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1) / args.sig_steps
+        stage = {k: ms_acc[i] / max(calls[i], 1) for k, i in (("project", 0), ("bin_sort", 1), ("visibility_walk", 2),
+                                                             ("score", 5))}
+        out[layout] = dict(ms=ms, stage=stage)
+        if layout == "interleaved":
+            del m
+    del maps
+    pl, il = out["planar"], out["interleaved"]
+    # scoring pass: algorithmic bytes = the P x n visibility bytes, each
+    # Gaussian's mean, feature vector and running sum/count once (12 + 2D + 16),
+    # and one D-float map vector per visible (view, Gaussian) pair
+    score_bytes = NP * n + n * (12 + 2 * D + 16) + pairs * 4 * D
+    walk_bytes = NP * n + st["keys"] * 4 + st["visible"] * 48   # flags written, list read, records read
+    rl = []
+    for name, lay in (("planar", pl), ("interleaved", il)):
+        t = lay["stage"]["score"] * 1e-3
+        rl.append({"kernel": f"score ({name} maps)", "bound": "hbm", "achieved": round(score_bytes / t / 1e9, 1),
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(score_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                   "bytes_per_launch": int(score_bytes), "launch_us": round(lay["stage"]["score"] * 1e3, 2)})
+    return {"workload": "1M Gaussians (32-d features) scored against 64 views at 960x540, 32-channel FP32 maps at "
+                        "image resolution: visibility walk + Eq. 4 cosine at the projected mean + per-Gaussian sums",
+            "ms_per_batch": round(pl["ms"], 3), "views_per_s": round(NP / (pl["ms"] * 1e-3), 1),
+            "mpix_per_s": round(NP * W * H / (pl["ms"] * 1e-3) / 1e6, 1),
+            "interleaved_ms_per_batch": round(il["ms"], 3),
+            "stages_ms": {k: round(v, 4) for k, v in pl["stage"].items()},
+            "interleaved_stages_ms": {k: round(v, 4) for k, v in il["stage"].items()},
+            "visible_pairs": pairs, "records": st["visible"], "tile_entries": st["keys"],
+            "walk_bytes_per_launch": int(walk_bytes), "roofline_score": rl, "steps_timed": args.sig_steps}
+
+
 def partitioned(hg, torch, synth, args):
     """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
     import numpy as np
@@ -394,12 +476,14 @@ def main():
                     help="feature accumulation with a fixed --tile (auto: the VALU)")
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-partitioned", action="store_true")
+    ap.add_argument("--no-significance", action="store_true")
+    ap.add_argument("--sig-steps", type=int, default=10)
     ap.add_argument("--fb-steps", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--part-iters", type=int, default=20)
     ap.add_argument("--part-lr-rho", type=float, default=0.3, help="Adam step (m) of the partitioned refinement")
     ap.add_argument("--part-lr-phi", type=float, default=4e-3, help="Adam step (rad) of the partitioned refinement")
-    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned"], default=None,
+    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance"], default=None,
                     help="run one section and print its result alone (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (5 launches), to scale HBM counters")
@@ -430,8 +514,11 @@ def main():
     if args.only == "partitioned":
         print(json.dumps({"partitioned": partitioned(hg, torch, synth, args)}), flush=True)
         return
+    if args.only == "significance":
+        print(json.dumps({"significance": significance(hg, torch, synth, args)}), flush=True)
+        return
     if args.only == "headline":
-        args.no_fwd_bwd = args.no_partitioned = args.no_cpu = True
+        args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_cpu = True
     h = headline(hg, torch, synth, args)
     result = {
         "metric": "rendered Mpix/s at 1080p/1M Gaussians",
@@ -462,6 +549,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_partitioned:
         result["partitioned"] = partitioned(hg, torch, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_significance:
+        result["significance"] = significance(hg, torch, synth, args)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("bench: timing the CPU oracle")

@@ -255,6 +255,47 @@ hgsr_status hgsr_residual_backward(hgsr_ctx* ctx, const hgsr_residual_targets* t
 hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step_count, int32_t P,
                            float lr_rho, float lr_phi, float beta1, float beta2, float eps, hgsr_stream stream);
 
+/* 2D feature maps of the views scored by hgsr_significance (device, FP32):
+ * one D x height x width map per view, D = the scene's feature_dim.  The
+ * map covers the image: the projected mean (U, V) reads the cell
+ * (floor(U width / W), floor(V height / H)) that contains it (nearest, no
+ * interpolation).  layout HGSR_MAP_PLANAR: view-major, then channel, row,
+ * column (P x D x height x width, the layout of the rendered feature maps);
+ * HGSR_MAP_INTERLEAVED: P x height x width x D (one contiguous vector per
+ * cell). */
+enum { HGSR_MAP_PLANAR = 0, HGSR_MAP_INTERLEAVED = 1 };
+typedef struct {
+  const float* maps;
+  int32_t width;
+  int32_t height;
+  int32_t layout;
+} hgsr_feature_maps;
+
+/* Significance scoring (Sec. 3.2, Eq. 4-6) of every Gaussian against P
+ * training views with poses `poses` (device, P x 12) and 2D feature maps
+ * `maps`.  For each view the call renders the visibility of the render-mask
+ * algorithm of Sec. 3.2: a Gaussian j is visible when it is blended (weight
+ * alpha T > 0, the condition under which its mean receives a gradient from
+ * the rendered RGB) at one pixel at least, and its projected mean (U, V) =
+ * K (X/Z) lies in [0, W) x [0, H).  For each visible j it adds
+ *   cos_j = F_j . F^t(U, V) / (|F_j| |F^t(U, V)| + 1e-8)      (Eq. 4)
+ * to score_sum[j] (Eq. 5) and 1 to vis_count[j] (device, n floats and n
+ * uint32, accumulated: the caller zeroes them once and calls once per batch
+ * of views).  Views are added in order, so results do not depend on
+ * scheduling.  visible (device, P x n bytes, or NULL) receives the mask per
+ * view (1 = visible).  The Gaussians' features must be present
+ * (feature_dim > 0).  Uses the context's workspace: a following
+ * hgsr_render_backward is refused until the next hgsr_render.  Overflow is
+ * reported as for hgsr_render (the sums are then undefined). */
+hgsr_status hgsr_significance(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
+                              const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_feature_maps* maps,
+                              float* score_sum, uint32_t* vis_count, uint8_t* visible, hgsr_stream stream);
+
+/* Final significance score S(g_j) = score_sum[j] / vis_count[j] (Eq. 6), 0
+ * where vis_count[j] == 0 (device, n floats). */
+hgsr_status hgsr_significance_final(const float* score_sum, const uint32_t* vis_count, int64_t n, float* score,
+                                    hgsr_stream stream);
+
 /* Fill part_bounds (device, n_parts x 6) with a box containing, for every
  * Gaussian of each partition, the ball of radius 3.33 x its largest scale
  * around its mean (the 1/255 support of the most opaque Gaussian). */
@@ -298,8 +339,10 @@ hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* p
 
 /* Stage timing.  While enabled, hgsr_render records HIP events on its
  * stream around its stages (0: projection, 1: tile binning and sort,
- * 2: blend) and hgsr_render_backward around its stages (3: blend backward,
- * 4: projection backward); nothing is recorded while a graph is captured.
+ * 2: blend), hgsr_render_backward around its stages (3: blend backward,
+ * 4: projection backward) and hgsr_significance around stages 0 and 1, its
+ * visibility walk (2) and its scoring pass (5); nothing is recorded while a
+ * graph is captured.
  * hgsr_profile_read synchronises, returns the milliseconds accumulated per
  * stage (host array of 6 doubles) and the number of timed calls per stage
  * (host array of 6 int64, may be NULL), and resets the accumulators. */

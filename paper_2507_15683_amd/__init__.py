@@ -257,6 +257,64 @@ class Renderer:
                                               _stream_ptr(stream)), "hgsr_residual_backward")
         return loss, grads
 
+    def significance_into(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, maps: torch.Tensor,
+                          score_sum: torch.Tensor, vis_count: torch.Tensor, opts: _lib.Opts,
+                          visible: Optional[torch.Tensor] = None, layout: str = "planar", stream=None):
+        """Enqueue one batch of significance scoring (Sec. 3.2, Eq. 4-5): maps
+        (P, D, Hf, Wf) planar or (P, Hf, Wf, D) interleaved float32; adds to
+        score_sum (N,) float32 and vis_count (N,) int32; visible (P, N) uint8
+        or None.  No synchronisation."""
+        if poses.dtype != torch.float32 or not poses.is_contiguous() or poses.shape[-1] != 12:
+            raise ValueError("poses must be a contiguous float32 (P, 12) device tensor")
+        if maps.dtype != torch.float32 or not maps.is_contiguous() or maps.dim() != 4:
+            raise ValueError("maps must be a contiguous float32 4-D device tensor")
+        P = poses.shape[0]
+        inter = layout == "interleaved"
+        D = maps.shape[3] if inter else maps.shape[1]
+        Hf, Wf = (maps.shape[1], maps.shape[2]) if inter else (maps.shape[2], maps.shape[3])
+        if maps.shape[0] != P or D != scene.feat_dim:
+            raise ValueError("maps must hold one D-channel map per pose, D = the scene's feature_dim")
+        if score_sum.dtype != torch.float32 or vis_count.dtype != torch.int32:
+            raise ValueError("score_sum must be float32 and vis_count int32")
+        if visible is not None and (visible.dtype != torch.uint8 or visible.numel() != P * scene.n):
+            raise ValueError("visible must be a (P, N) uint8 tensor")
+        g = scene.c()
+        kc = K.c()
+        fm = _lib.FeatureMaps(_ptr(maps), Wf, Hf, _lib.MAP_INTERLEAVED if inter else _lib.MAP_PLANAR)
+        self._keep = (scene, poses, maps)
+        check(self.lib.hgsr_significance(self.ctx, ctypes.byref(g), _ptr(poses), P, ctypes.byref(kc),
+                                         ctypes.byref(opts), ctypes.byref(fm), _ptr(score_sum), _ptr(vis_count),
+                                         _ptr(visible), _stream_ptr(stream)), "hgsr_significance")
+
+    def significance(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, maps: torch.Tensor,
+                     score_sum: Optional[torch.Tensor] = None, vis_count: Optional[torch.Tensor] = None,
+                     want_visible: bool = False, layout: str = "planar", tile=16, sort="bucket", near=0.2,
+                     stream=None) -> dict:
+        """Score the Gaussians against P views and return dict(score_sum,
+        vis_count, score (Eq. 6), visible (P, N) uint8 or None).  Pass
+        score_sum / vis_count to accumulate over batches of views.  The call
+        synchronises; after a workspace overflow it restores the sums, grows
+        the workspace and scores the batch again."""
+        if poses.dim() == 1:
+            poses = poses[None]
+        dev = scene.means.device
+        n = scene.n
+        if score_sum is None:
+            score_sum = torch.zeros(n, dtype=torch.float32, device=dev)
+        if vis_count is None:
+            vis_count = torch.zeros(n, dtype=torch.int32, device=dev)
+        visible = torch.empty((poses.shape[0], n), dtype=torch.uint8, device=dev) if want_visible else None
+        opts = self.opts(tile, sort, "grid", near=near)
+        s0, c0 = score_sum.clone(), vis_count.clone()
+        for _ in range(6):
+            self.significance_into(scene, poses, K, maps, score_sum, vis_count, opts, visible, layout, stream)
+            if self.check_overflow(stream) == 0:
+                score = significance_final(score_sum, vis_count, stream=stream)
+                return dict(score_sum=score_sum, vis_count=vis_count, score=score, visible=visible)
+            score_sum.copy_(s0)
+            vis_count.copy_(c0)
+        raise HgsrError(3, "significance: workspace kept overflowing")
+
     def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
                  feat_bf16=False, cache_path: Optional[str] = None, stream=None) -> dict:
         """Time tile sizes 8/16/32, the blend schedules and the feature
@@ -281,8 +339,8 @@ class Renderer:
         ms = (ctypes.c_double * 6)()
         calls = (ctypes.c_int64 * 6)()
         check(self.lib.hgsr_profile_read(self.ctx, ms, calls), "hgsr_profile_read")
-        names = ["project", "bin_sort", "blend", "blend_bwd", "project_bwd", "unused"]
-        return {names[k]: (ms[k], calls[k]) for k in range(5)}
+        names = ["project", "bin_sort", "blend", "blend_bwd", "project_bwd", "score"]
+        return {names[k]: (ms[k], calls[k]) for k in range(6)}
 
     # graph capture
     def graph_begin(self, stream):
@@ -365,6 +423,16 @@ def residual(rgb, feat, rgb_t, feat_t, lam_f=1.0, out=None, stream=None):
                             _ptr(rgb_t), _ptr(feat_t), P, H, W, D, lam_f, _ptr(loss), _ptr(g_rgb), _ptr(g_feat),
                             _stream_ptr(stream)), "hgsr_residual")
     return loss, g_rgb, g_feat
+
+
+def significance_final(score_sum: torch.Tensor, vis_count: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    """S(g_j) = score_sum / vis_count (Eq. 6), 0 where the count is 0."""
+    if out is None:
+        out = torch.empty_like(score_sum)
+    check(_lib.load().hgsr_significance_final(_ptr(score_sum), _ptr(vis_count), score_sum.numel(), _ptr(out),
+                                         _stream_ptr(stream)), "hgsr_significance_final")
+    return out
 
 
 def pose_adam(poses, grad, m, v, step, lr_rho=1e-2, lr_phi=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):

@@ -61,6 +61,12 @@ class ResidualTargets(ctypes.Structure):
     _fields_ = [("rgb_target", P_), ("feat_target", P_), ("lam_f", F32), ("shared_target", I32)]
 
 
+class FeatureMaps(ctypes.Structure):
+    _fields_ = [("maps", P_), ("width", I32), ("height", I32), ("layout", I32)]
+
+
+MAP_PLANAR, MAP_INTERLEAVED = 0, 1
+
 # (name, argtypes) for every entry point declared in include/hgsr.h
 SIGNATURES = {
     "hgsr_ctx_create": [ctypes.POINTER(P_), I64, I64],
@@ -72,6 +78,9 @@ SIGNATURES = {
     "hgsr_residual_backward": [P_, ctypes.POINTER(ResidualTargets), P_, ctypes.POINTER(Grads), P_],
     "hgsr_residual": [P_, P_, I32, P_, P_, I32, I32, I32, I32, F32, P_, P_, P_, P_],
     "hgsr_pose_adam": [P_, P_, P_, P_, P_, I32, F32, F32, F32, F32, F32, P_],
+    "hgsr_significance": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
+                          ctypes.POINTER(FeatureMaps), P_, P_, P_, P_],
+    "hgsr_significance_final": [P_, P_, I64, P_, P_],
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],

@@ -76,11 +76,12 @@ struct hgsr_ctx {
 
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
-      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part;
+      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
-  bool have_render = false;
+  bool have_lists = false;   // records and tile lists of the last call (render or scoring)
+  bool have_render = false;  // ... and that call was a render (the backward's input)
   hgsr_gaussians g{};
   const float* poses = nullptr;
   int32_t P = 0;
@@ -261,98 +262,45 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
   return HGSR_OK;
 }
 
-}  // namespace
+// Options of a render-like call resolved against the context's defaults.
+struct Resolved {
+  int tile, sched;
+  bool lsd;
+  CamArgs cam;
+};
 
-extern "C" {
-
-const char* hgsr_last_error(void) { return g_err.c_str(); }
-const char* hgsr_version(void) { return "hgsr 0.1 gfx950"; }
-
-hgsr_status hgsr_ctx_create(hgsr_ctx** out, int64_t record_hint, int64_t key_hint) {
-  if (!out) return fail(HGSR_ERR_INVALID_ARG, "ctx out-pointer is NULL");
-  hgsr_ctx* c = new hgsr_ctx();
-  HIP_TRY(hipGetDevice(&c->device));
-  int cu = 0;
-  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0) c->n_cu = cu;
-  c->rec_hint = record_hint;
-  c->key_hint = key_hint;
-  hgsr_status st = ensure(c, c->misc, kMiscWords * sizeof(int32_t));
-  if (st != HGSR_OK) {
-    delete c;
-    return st;
-  }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_misc), kMiscWords * sizeof(int32_t), hipHostMallocDefault) !=
-      hipSuccess) {
-    delete c;
-    return fail(HGSR_ERR_HIP, "hipHostMalloc failed");
-  }
-  HIP_TRY(hipMemset(c->misc.p, 0, kMiscWords * sizeof(int32_t)));
-  *out = c;
-  return HGSR_OK;
-}
-
-hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
-  if (!c) return HGSR_OK;
-  if (c->exec) (void)hipGraphExecDestroy(c->exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
-                &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
-                &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part};
-  for (Buf* b : all)
-    if (b->p) (void)hipFree(b->p);
-  if (c->h_misc) (void)hipHostFree(c->h_misc);
-  for (auto& m : c->marks) {
-    c->pool.push_back(m.a);
-    c->pool.push_back(m.b);
-  }
-  std::sort(c->pool.begin(), c->pool.end());
-  c->pool.erase(std::unique(c->pool.begin(), c->pool.end()), c->pool.end());
-  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
-  delete c;
-  return HGSR_OK;
-}
-
-hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, int32_t tile,
-                         int64_t records_per_pose, int64_t keys, int64_t n_gaussians) {
-  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
-  if (P <= 0 || width <= 0 || height <= 0 || !(tile == 8 || tile == 16 || tile == 32))
-    return fail(HGSR_ERR_INVALID_ARG, "bad reserve arguments");
-  if (records_per_pose > 0 && round_rec_cap(records_per_pose) > c->rec_cap) c->rec_cap = round_rec_cap(records_per_pose);
-  if (keys > 0 && static_cast<uint64_t>(keys) > c->key_cap) c->key_cap = static_cast<uint64_t>(keys);
-  hgsr_intrinsics K{1.f, 1.f, 0.f, 0.f, width, height};
-  const CamArgs cam = make_cam(K, tile, 0.2f);
-  // size every buffer either sort path may use
-  TRY(size_workspace(c, P, cam, n_gaussians, true));
-  TRY(ensure(c, c->grad_rec, static_cast<size_t>(P) * c->rec_cap * kGradRecStride * sizeof(float)));
-  return HGSR_OK;
-}
-
-hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                        hgsr_stream stream) {
+hgsr_status resolve(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                    const hgsr_opts* opts, Resolved* r) {
   if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
   TRY(check_gaussians(g));
   TRY(check_intrinsics(K));
-  if (!opts || !out) return fail(HGSR_ERR_INVALID_ARG, "opts/out is NULL");
+  if (!opts) return fail(HGSR_ERR_INVALID_ARG, "opts is NULL");
   if (P <= 0 || P > 4096 || !poses) return fail(HGSR_ERR_INVALID_ARG, "need 1..4096 poses and a pose pointer");
-  if (!out->rgb || !out->depth || !out->alpha) return fail(HGSR_ERR_INVALID_ARG, "rgb, depth and alpha are required");
-  int tile = opts->tile ? opts->tile : (c->tuned_tile ? c->tuned_tile : 16);
-  if (!(tile == 8 || tile == 16 || tile == 32)) return fail(HGSR_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
-  int sched = opts->schedule;
-  if (sched == HGSR_SCHED_AUTO) sched = c->tuned_sched >= 0 ? c->tuned_sched : HGSR_SCHED_GRID;
-  if (sched < 0 || sched > 2) return fail(HGSR_ERR_INVALID_ARG, "bad schedule");
+  r->tile = opts->tile ? opts->tile : (c->tuned_tile ? c->tuned_tile : 16);
+  if (!(r->tile == 8 || r->tile == 16 || r->tile == 32)) return fail(HGSR_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
+  r->sched = opts->schedule;
+  if (r->sched == HGSR_SCHED_AUTO) r->sched = c->tuned_sched >= 0 ? c->tuned_sched : HGSR_SCHED_GRID;
+  if (r->sched < 0 || r->sched > 2) return fail(HGSR_ERR_INVALID_ARG, "bad schedule");
   if (!(opts->sort_mode == HGSR_SORT_BUCKET || opts->sort_mode == HGSR_SORT_LSD))
     return fail(HGSR_ERR_INVALID_ARG, "bad sort_mode");
   if (opts->feat_accum < HGSR_FEAT_AUTO || opts->feat_accum > HGSR_FEAT_MFMA)
     return fail(HGSR_ERR_INVALID_ARG, "bad feat_accum");
-  const bool lsd = opts->sort_mode == HGSR_SORT_LSD;
+  r->lsd = opts->sort_mode == HGSR_SORT_LSD;
   const float near_z = opts->near_z > 0.f ? opts->near_z : 0.2f;
-  const CamArgs cam = make_cam(*K, tile, near_z);
-  if (static_cast<int64_t>(P) * cam.tiles_per_pose >= (1ll << 31))
+  r->cam = make_cam(*K, r->tile, near_z);
+  if (static_cast<int64_t>(P) * r->cam.tiles_per_pose >= (1ll << 31))
     return fail(HGSR_ERR_INVALID_ARG, "too many (pose, tile) items");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return HGSR_OK;
+}
 
+// Projection, tile binning and the per-tile depth sort of P poses: on
+// return (enqueued on s) the context holds the records, the per-tile ranges
+// and the sorted per-tile lists (*sorted_out).  Stages 0 and 1 of the
+// profile.
+hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P, const hgsr_opts* opts,
+                        const Resolved& rs, hipStream_t s, const uint32_t** sorted_out) {
+  const bool lsd = rs.lsd;
+  const CamArgs& cam = rs.cam;
   TRY(size_workspace(c, P, cam, g->n, lsd));
   int32_t* misc = c->misc.as<int32_t>();
   uint32_t* pose_count = c->pose_count.as<uint32_t>();
@@ -456,6 +404,95 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   }
 
   hipEvent_t e2 = stamp(c, s);
+  mark(c, 0, e0, e1);
+  mark(c, 1, e1, e2);
+  *sorted_out = sorted;
+  return HGSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hgsr_last_error(void) { return g_err.c_str(); }
+const char* hgsr_version(void) { return "hgsr 0.1 gfx950"; }
+
+hgsr_status hgsr_ctx_create(hgsr_ctx** out, int64_t record_hint, int64_t key_hint) {
+  if (!out) return fail(HGSR_ERR_INVALID_ARG, "ctx out-pointer is NULL");
+  hgsr_ctx* c = new hgsr_ctx();
+  HIP_TRY(hipGetDevice(&c->device));
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0) c->n_cu = cu;
+  c->rec_hint = record_hint;
+  c->key_hint = key_hint;
+  hgsr_status st = ensure(c, c->misc, kMiscWords * sizeof(int32_t));
+  if (st != HGSR_OK) {
+    delete c;
+    return st;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_misc), kMiscWords * sizeof(int32_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return fail(HGSR_ERR_HIP, "hipHostMalloc failed");
+  }
+  HIP_TRY(hipMemset(c->misc.p, 0, kMiscWords * sizeof(int32_t)));
+  *out = c;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
+  if (!c) return HGSR_OK;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
+                &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
+                &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis};
+  for (Buf* b : all)
+    if (b->p) (void)hipFree(b->p);
+  if (c->h_misc) (void)hipHostFree(c->h_misc);
+  for (auto& m : c->marks) {
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  std::sort(c->pool.begin(), c->pool.end());
+  c->pool.erase(std::unique(c->pool.begin(), c->pool.end()), c->pool.end());
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, int32_t tile,
+                         int64_t records_per_pose, int64_t keys, int64_t n_gaussians) {
+  if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
+  if (P <= 0 || width <= 0 || height <= 0 || !(tile == 8 || tile == 16 || tile == 32))
+    return fail(HGSR_ERR_INVALID_ARG, "bad reserve arguments");
+  if (records_per_pose > 0 && round_rec_cap(records_per_pose) > c->rec_cap) c->rec_cap = round_rec_cap(records_per_pose);
+  if (keys > 0 && static_cast<uint64_t>(keys) > c->key_cap) c->key_cap = static_cast<uint64_t>(keys);
+  hgsr_intrinsics K{1.f, 1.f, 0.f, 0.f, width, height};
+  const CamArgs cam = make_cam(K, tile, 0.2f);
+  // size every buffer either sort path may use
+  TRY(size_workspace(c, P, cam, n_gaussians, true));
+  TRY(ensure(c, c->grad_rec, static_cast<size_t>(P) * c->rec_cap * kGradRecStride * sizeof(float)));
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream) {
+  Resolved rs;
+  TRY(resolve(c, g, poses, P, K, opts, &rs));
+  if (!out) return fail(HGSR_ERR_INVALID_ARG, "out is NULL");
+  if (!out->rgb || !out->depth || !out->alpha) return fail(HGSR_ERR_INVALID_ARG, "rgb, depth and alpha are required");
+  const int tile = rs.tile, sched = rs.sched;
+  const CamArgs cam = rs.cam;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t* sorted = nullptr;
+  TRY(build_lists(c, g, poses, P, opts, rs, s, &sorted));
+  int32_t* misc = c->misc.as<int32_t>();
+  const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
+
+  hipEvent_t e2 = stamp(c, s);
   BlendArgs bl;
   bl.c = cam;
   bl.P = P;
@@ -484,10 +521,9 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   launch_blend_fwd(bl, g->feat_dim, opts->feat_out_bf16 != 0, n_ctas, s);
   HIP_TRY(hipGetLastError());
   hipEvent_t e3 = stamp(c, s);
-  mark(c, 0, e0, e1);
-  mark(c, 1, e1, e2);
   mark(c, 2, e2, e3);
 
+  c->have_lists = true;
   c->have_render = true;
   c->g = *g;
   c->poses = poses;
@@ -502,12 +538,95 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
 }
 
 
+hgsr_status hgsr_significance(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                              const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_feature_maps* maps,
+                              float* score_sum, uint32_t* vis_count, uint8_t* visible, hgsr_stream stream) {
+  Resolved rs;
+  TRY(resolve(c, g, poses, P, K, opts, &rs));
+  if (g->feat_dim <= 0) return fail(HGSR_ERR_INVALID_ARG, "significance scoring needs the Gaussians' features");
+  if (!maps || !maps->maps) return fail(HGSR_ERR_INVALID_ARG, "feature maps are NULL");
+  if (maps->width <= 0 || maps->height <= 0 || maps->width > 16384 || maps->height > 16384)
+    return fail(HGSR_ERR_INVALID_ARG, "feature map size %dx%d out of range", maps->width, maps->height);
+  if (maps->layout != HGSR_MAP_PLANAR && maps->layout != HGSR_MAP_INTERLEAVED)
+    return fail(HGSR_ERR_INVALID_ARG, "bad feature map layout");
+  if (maps->layout == HGSR_MAP_INTERLEAVED && !aligned16(maps->maps))
+    return fail(HGSR_ERR_INVALID_ARG, "interleaved maps must be 16-byte aligned");
+  if (g->n > 0 && (!score_sum || !vis_count)) return fail(HGSR_ERR_INVALID_ARG, "score_sum/vis_count are NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t n = g->n;
+  // per (Gaussian, view) blended flags, Gaussian-major with rows of P
+  // rounded up to 16 bytes; cleared by a kernel (capturable)
+  const int64_t vis_stride = (static_cast<int64_t>(P) + 15) / 16 * 16;
+  const int64_t nvis = vis_stride * n;
+  TRY(ensure(c, c->vis, static_cast<size_t>(nvis) + 16));
+  const uint32_t* sorted = nullptr;
+  TRY(build_lists(c, g, poses, P, opts, rs, s, &sorted));
+  launch_fill_u32(c->vis.as<uint32_t>(), 0u, nvis / 4, s);
+  int32_t* misc = c->misc.as<int32_t>();
+  hipEvent_t e2 = stamp(c, s);
+  ContribArgs ca;
+  ca.c = rs.cam;
+  ca.ranges = c->ranges.as<uint2>();
+  ca.list = sorted;
+  ca.recs = c->recs.as<Splat>();
+  ca.vis = c->vis.as<uint8_t>();
+  ca.vis_stride = vis_stride;
+  ca.flags = misc + kFlags;
+  launch_contrib(ca, static_cast<int>(static_cast<int64_t>(P) * rs.cam.tiles_per_pose), s);
+  hipEvent_t e3 = stamp(c, s);
+  ScoreArgs sa;
+  sa.c = rs.cam;
+  sa.poses = poses;
+  sa.P = P;
+  sa.means = g->means;
+  sa.feat = g->feat;
+  sa.D = g->feat_dim;
+  sa.n = n;
+  sa.vis = c->vis.as<uint8_t>();
+  sa.vis_stride = vis_stride;
+  sa.maps = maps->maps;
+  sa.map_w = maps->width;
+  sa.map_h = maps->height;
+  sa.map_layout = maps->layout;
+  sa.score_sum = score_sum;
+  sa.vis_count = vis_count;
+  sa.visible = visible;
+  sa.flags = misc + kFlags;
+  launch_score(sa, s);
+  HIP_TRY(hipGetLastError());
+  hipEvent_t e4 = stamp(c, s);
+  mark(c, 2, e2, e3);
+  mark(c, 5, e3, e4);
+
+  c->have_lists = true;
+  c->have_render = false;
+  c->g = *g;
+  c->poses = poses;
+  c->P = P;
+  c->K = *K;
+  c->opts = *opts;
+  c->opts.tile = rs.tile;
+  c->cam = rs.cam;
+  c->sorted = sorted;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_significance_final(const float* score_sum, const uint32_t* vis_count, int64_t n, float* score,
+                                    hgsr_stream stream) {
+  if (n < 0) return fail(HGSR_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return HGSR_OK;
+  if (!score_sum || !vis_count || !score) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  launch_score_final(score_sum, vis_count, n, score, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
 hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream stream) {
   if (!c || !overflowed) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   std::vector<uint32_t> counts(std::max(c->P, 1) * kSub, 0);
-  if (c->have_render)
+  if (c->have_lists)
     HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, static_cast<size_t>(c->P) * kSub * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -530,7 +649,7 @@ hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream st
 
 hgsr_status hgsr_stats(hgsr_ctx* c, hgsr_render_stats* out, hgsr_stream stream) {
   if (!c || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
-  if (!c->have_render) return fail(HGSR_ERR_STATE, "no render yet");
+  if (!c->have_lists) return fail(HGSR_ERR_STATE, "no render yet");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t ntile = static_cast<int64_t>(c->P) * c->cam.tiles_per_pose;
   std::vector<uint32_t> counts(static_cast<size_t>(c->P) * kSub);
@@ -552,7 +671,7 @@ hgsr_status hgsr_stats(hgsr_ctx* c, hgsr_render_stats* out, hgsr_stream stream) 
 hgsr_status hgsr_debug_tile_lists(hgsr_ctx* c, int32_t pose, uint32_t* ranges, uint32_t* gids, int64_t cap,
                                   int64_t* n, hgsr_stream stream) {
   if (!c || !ranges || !n) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
-  if (!c->have_render) return fail(HGSR_ERR_STATE, "no render yet");
+  if (!c->have_lists) return fail(HGSR_ERR_STATE, "no render yet");
   if (pose < 0 || pose >= c->P) return fail(HGSR_ERR_INVALID_ARG, "pose out of range");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int tiles = c->cam.tiles_per_pose;

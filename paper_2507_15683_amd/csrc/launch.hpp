@@ -139,6 +139,38 @@ struct ProjBackArgs {
 
 constexpr int kGradRecStride = 12;
 
+// Significance scoring: which Gaussians a view blends (vis: n rows of
+// vis_stride bytes, one per view, vis_stride = P rounded up to 16; cleared
+// before the walk), then per Gaussian the feature cosine at its projected
+// mean summed over the views.
+struct ContribArgs {
+  CamArgs c;
+  const uint2* ranges;
+  const uint32_t* list;
+  const Splat* recs;
+  uint8_t* vis;
+  int64_t vis_stride;
+  const int32_t* flags;
+};
+
+struct ScoreArgs {
+  CamArgs c;
+  const float* poses;
+  int32_t P;
+  const float* means;
+  const uint16_t* feat;
+  int32_t D;
+  int64_t n;
+  const uint8_t* vis;
+  int64_t vis_stride;
+  const float* maps;
+  int32_t map_w, map_h, map_layout;
+  float* score_sum;
+  uint32_t* vis_count;
+  uint8_t* visible;
+  const int32_t* flags;
+};
+
 // project.hip
 void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s);
 void launch_partition_cull(const float* poses, int P, const float* bounds, int n_parts, const CamArgs& c,
@@ -172,6 +204,11 @@ void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipS
 void launch_blend_bwd(const BackArgs& a, hipStream_t s);
 void launch_project_bwd(const ProjBackArgs& a, hipStream_t s);
 void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap, int P, hipStream_t s);
+
+// score.hip
+void launch_contrib(const ContribArgs& a, int n_items, hipStream_t s);
+void launch_score(const ScoreArgs& a, hipStream_t s);
+void launch_score_final(const float* sum, const uint32_t* count, int64_t n, float* score, hipStream_t s);
 
 // refine.hip
 void launch_residual(const float* rgb, const void* feat, int feat_bf16, const float* rgb_t, const float* feat_t,

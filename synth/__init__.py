@@ -22,4 +22,5 @@ from .scenes import (  # noqa: F401
     tiny_scene,
     f32_to_bf16_bits,
     bf16_bits_to_f32,
+    feature_maps,
 )

@@ -384,3 +384,14 @@ def tiny_scene(n, seed, width=64, height=48, sh_degree=0, feat_dim=0, extent=Non
     P[:, 3] = -P[:, :3] @ C
     cam = Camera(float(fx), float(fx), width / 2.0, height / 2.0, width, height)
     return scene, P.reshape(12).astype(np.float32)[None], cam
+
+
+def feature_maps(count, dim, height, width, seed, layout="planar") -> np.ndarray:
+    """`count` 2D feature maps of `dim` channels (the training views' image
+    features that Gaussians are scored against): N(0, 1) float32, planar
+    (count, dim, height, width) or interleaved (count, height, width, dim)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = rng.standard_normal((count, dim, height, width), dtype=np.float32)
+    if layout == "interleaved":
+        m = np.ascontiguousarray(m.transpose(0, 2, 3, 1))
+    return m

@@ -54,6 +54,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.ResidualTargets) == 24
     assert ctypes.sizeof(_lib.Outputs) == 32
     assert ctypes.sizeof(_lib.Grads) == 56
+    assert ctypes.sizeof(_lib.FeatureMaps) == 8 + 3 * 4 + 4   # pointer, width, height, layout, tail padding
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -76,3 +77,8 @@ def test_invalid_arguments_rejected_on_host(lib):
     g2.sh_degree = 0
     g2.feat_dim = 12
     assert L.hgsr_validate(ctypes.byref(g2), None) == 1
+    # significance scoring: NULL ctx, negative n, NULL outputs
+    assert L.hgsr_significance(None, None, None, 1, None, None, None, None, None, None, None) == 1
+    assert L.hgsr_significance_final(None, None, -1, None, None) == 1
+    assert L.hgsr_significance_final(None, None, 5, None, None) == 1
+    assert L.hgsr_significance_final(None, None, 0, None, None) == 0   # nothing to do

@@ -1,0 +1,246 @@
+"""GPU significance scoring (Sec. 3.2, Eq. 4-6) through the C ABI against the
+FP64 oracle: per-view visibility (render-gradient check and image bounds),
+visibility counts and cosine sums, element by element; exactness of
+batching, accumulation and tile size; the GPU visibility against the support
+of the GPU backward's mean gradient; edge cases; the 1M-Gaussian, 64-view
+workload on sampled views."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+SUM_TOL = 1e-5        # absolute, per view term (FP32 cosine of unit-scale vectors)
+MAX_EXEMPT = 0.03     # fraction of (view, Gaussian) pairs FP32 may decide either way
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2507_15683_amd as hg
+    return hg
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import oracle
+    oracle.build(force=False)
+    from oracle import significance
+    return significance
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+def _compare(res, ref, P, label):
+    """Element-wise parity of a GPU scoring result with the oracle's."""
+    vis = res["visible"].cpu().numpy().astype(bool)
+    ex = ref["exempt"]
+    ok = ~ex
+    bad_vis = ok & (vis != ref["visible"])
+    log(label, "pairs", ex.size, "exempt", int(ex.sum()), "visible(oracle)", int(ref["visible"].sum()),
+        "visible(gpu)", int(vis.sum()), "mismatch", int(bad_vis.sum()))
+    assert not bad_vis.any(), (label, np.argwhere(bad_vis)[:8])
+    assert ex.mean() <= MAX_EXEMPT, (label, ex.mean())
+    clean = ~ex.any(axis=0)
+    cnt = res["vis_count"].cpu().numpy().astype(np.int64)
+    ssum = res["score_sum"].cpu().numpy().astype(np.float64)
+    score = res["score"].cpu().numpy().astype(np.float64)
+    assert np.array_equal(cnt[clean], ref["count"][clean]), label
+    d_sum = np.abs(ssum - ref["score_sum"])[clean]
+    d_sc = np.abs(score - ref["score"])[clean]
+    log(label, "gaussians", clean.size, "clean", int(clean.sum()), "max |d sum|", float(d_sum.max(initial=0)),
+        "max |d score|", float(d_sc.max(initial=0)))
+    assert (d_sum <= SUM_TOL * np.maximum(ref["count"][clean], 1)).all(), label
+    assert (d_sc <= SUM_TOL).all(), label
+    assert (score[cnt == 0] == 0).all()
+
+
+def _views(P0, count, seed, sigma_t=2.0, sigma_r=3.0):
+    """float32 poses: the GPU and the oracle read the same values."""
+    v = synth.perturb_poses(np.asarray(P0, np.float64).reshape(12), count, seed, sigma_t, sigma_r)
+    return np.ascontiguousarray(v, dtype=np.float32)
+
+
+def test_terrain_256x192_parity(hg, sg):
+    """20k Gaussians (32-d features) on the small terrain, 4 views at
+    256x192, maps at image resolution, tile 16."""
+    log("case: terrain 20k, 4 views 256x192, planar maps 256x192")
+    base, P0, cam = synth.config1(0)
+    sc = synth.terrain_scene(20_000, 200.0, 1000, sh_degree=0, feat_dim=32)
+    poses = _views(P0[0], 4, 11)
+    maps = synth.feature_maps(4, 32, cam.height, cam.width, 12)
+    ref = sg.significance(sc, poses, cam, maps, tile=16)
+    r = hg.Renderer()
+    res = r.significance(hg.GaussianScene.from_numpy(sc), _t(poses), hg.Intrinsics.of(cam),
+                         _t(maps), want_visible=True, tile=16)
+    _compare(res, ref, 4, "terrain")
+    assert ref["count"].sum() > 1000
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ragged_parity(hg, sg, seed):
+    """Ragged image sizes, every tile size, feature widths 8/16/32/64, maps
+    on non-divisor grids, both map layouts, SH degrees 0-3."""
+    D = [8, 16, 64, 32][seed]
+    W, H = 67 + 11 * seed, 45 + 7 * seed
+    sc, P0, cam = synth.tiny_scene(150 + 60 * seed, 400 + seed, width=W, height=H, sh_degree=seed % 4, feat_dim=D)
+    poses = _views(P0[0], 3, 410 + seed, 1.0, 4.0)
+    Hf, Wf = [(7, 13), (H, W), (5, 9), (H // 2, W // 3)][seed]
+    maps = synth.feature_maps(3, D, Hf, Wf, 420 + seed)
+    ref = sg.significance(sc, poses, cam, maps, tile=16)
+    gsc = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    pt = _t(poses)
+    for tile in (8, 16, 32):
+        for layout in ("planar", "interleaved"):
+            m = maps if layout == "planar" else np.ascontiguousarray(maps.transpose(0, 2, 3, 1))
+            log(f"case: ragged seed {seed} D {D} {W}x{H} maps {Wf}x{Hf} tile {tile} {layout}")
+            res = hg.Renderer().significance(gsc, pt, K, _t(m), want_visible=True, layout=layout, tile=tile)
+            _compare(res, ref, 3, f"ragged{seed}/t{tile}/{layout}")
+
+
+def test_batching_accumulation_and_tiles_are_exact(hg):
+    """One call over P views equals P calls of one view accumulated, for
+    every tile size, bit for bit (each Gaussian's sum runs in view order in
+    one thread either way; the visibility decisions do not depend on the
+    tile size)."""
+    import torch
+    sc, P0, cam = synth.tiny_scene(900, 77, width=160, height=120, feat_dim=32)
+    poses = _views(P0[0], 5, 78, 2.0, 5.0)
+    maps = _t(synth.feature_maps(5, 32, 60, 80, 79))
+    gsc = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    pt = _t(poses)
+    r = hg.Renderer()
+    ref = r.significance(gsc, pt, K, maps, want_visible=True, tile=16)
+    for tile in (8, 32):
+        o = r.significance(gsc, pt, K, maps, want_visible=True, tile=tile)
+        for k in ("score_sum", "vis_count", "visible"):
+            assert torch.equal(o[k], ref[k]), (tile, k)
+    s = torch.zeros(sc.n, dtype=torch.float32, device="cuda")
+    c = torch.zeros(sc.n, dtype=torch.int32, device="cuda")
+    for p in range(5):
+        o = r.significance(gsc, pt[p:p + 1].contiguous(), K, maps[p:p + 1].contiguous(), score_sum=s, vis_count=c,
+                           want_visible=True, tile=16)
+        assert torch.equal(o["visible"][0], ref["visible"][p])
+    assert torch.equal(s, ref["score_sum"]) and torch.equal(c, ref["vis_count"])
+    assert torch.equal(hg.significance_final(s, c), ref["score"])
+    log("batched == accumulated single views, tiles 8/16/32 identical; visible pairs",
+        int(ref["visible"].sum().item()))
+
+
+def test_visibility_is_the_support_of_the_gpu_mean_gradient(hg, sg):
+    """The render-mask algorithm literally: render, back-propagate the summed
+    RGB, mark the Gaussians whose mean gradient is nonzero.  On the GPU this
+    set, restricted to means inside the image, equals the scoring pass's
+    visibility (opacities below the 0.99 clamp, where a blended Gaussian's
+    alpha has no gradient)."""
+    import torch
+    sc, P0, cam = synth.tiny_scene(2000, 55, width=192, height=128, feat_dim=16)
+    sc.opacities[:] = np.minimum(sc.opacities, 0.95)
+    gsc = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    pt = _t(P0.astype(np.float32))
+    r = hg.Renderer()
+    out = r.render(gsc, pt, K, tile=16)
+    g = r.backward({"rgb": torch.ones_like(out["rgb"])}, want=("means",))
+    grad_nz = (g["means"].abs().sum(dim=1) > 0).cpu().numpy()
+    maps = _t(synth.feature_maps(1, 16, 32, 48, 56))
+    res = r.significance(gsc, pt, K, maps, want_visible=True, tile=16)
+    vis = res["visible"][0].cpu().numpy().astype(bool)
+    U, V, _ = sg.project_means(sc.means, P0[0], cam)
+    with np.errstate(invalid="ignore"):
+        inside = (U >= 0) & (U < cam.width) & (V >= 0) & (V < cam.height)
+        far = (np.minimum(np.abs(U), np.abs(cam.width - U)) > 1e-3) & \
+              (np.minimum(np.abs(V), np.abs(cam.height - V)) > 1e-3)
+    want = grad_nz & inside
+    mism = (vis != want) & far
+    log("gradient support", int(grad_nz.sum()), "visible", int(vis.sum()), "mismatch", int(mism.sum()))
+    assert vis.sum() > 100
+    assert not mism.any(), np.nonzero(mism)[0][:8]
+
+
+def test_edge_cases(hg, sg):
+    """Empty scene; a view that sees nothing; a single-cell map; a scene
+    without features and mismatched maps are refused."""
+    import torch
+    r = hg.Renderer()
+    sc, P0, cam = synth.tiny_scene(300, 91, feat_dim=8)
+    K = hg.Intrinsics.of(cam)
+    # empty scene
+    empty = sc.subset(np.zeros(0, dtype=np.int64))
+    res = r.significance(hg.GaussianScene.from_numpy(empty), _t(P0.astype(np.float32)), K,
+                         _t(synth.feature_maps(1, 8, 4, 4, 1)), want_visible=True)
+    assert res["score_sum"].numel() == 0
+    # a view looking away from the scene (camera turned upwards)
+    P = np.asarray(P0[0], np.float64).reshape(3, 4)
+    C = -P[:, :3].T @ P[:, 3]                           # camera centre, kept
+    away = np.empty((3, 4))
+    away[:, :3] = np.diag([1.0, -1.0, -1.0]) @ P[:, :3]  # turned 180 degrees about its x axis
+    away[:, 3] = -away[:, :3] @ C
+    gsc = hg.GaussianScene.from_numpy(sc)
+    res = r.significance(gsc, _t(away.reshape(1, 12).astype(np.float32)), K, _t(synth.feature_maps(1, 8, 4, 4, 2)),
+                         want_visible=True)
+    assert int(res["vis_count"].sum()) == 0 and int(res["visible"].sum()) == 0
+    assert float(res["score"].abs().sum()) == 0.0
+    # single-cell map: every visible Gaussian reads the same vector
+    maps = synth.feature_maps(1, 8, 1, 1, 3)
+    res = r.significance(gsc, _t(P0.astype(np.float32)), K, _t(maps), want_visible=True)
+    ref = sg.significance(sc, P0.astype(np.float64), cam, maps)
+    _compare(res, ref, 1, "single-cell")
+    # refused: no features; D mismatch
+    nofeat = synth.tiny_scene(50, 92)[0]
+    with pytest.raises(Exception):
+        r.significance(hg.GaussianScene.from_numpy(nofeat), _t(P0.astype(np.float32)), K,
+                       _t(synth.feature_maps(1, 8, 4, 4, 4)))
+    with pytest.raises(ValueError):
+        r.significance(gsc, _t(P0.astype(np.float32)), K, _t(synth.feature_maps(1, 16, 4, 4, 5)))
+    torch.cuda.synchronize()
+
+
+def test_full_size_64_views_sampled(hg, sg):
+    """The 1M-Gaussian scene (SH3, 32-d features) scored against its 64
+    views at 960x540 (maps at 480x270) in one call, as the benchmark runs it:
+    the visibility of views 0, 31 and 63 against the oracle's, and every
+    Gaussian's count and sum against the oracle's cosines over the views the
+    GPU marked visible."""
+    import torch
+    log("case: 1M Gaussians, 64 views 960x540, planar maps 480x270")
+    sc, poses, cam = synth.config3(0)
+    maps = synth.feature_maps(64, 32, 270, 480, 3100)
+    r = hg.Renderer()
+    res = r.significance(hg.GaussianScene.from_numpy(sc), _t(poses), hg.Intrinsics.of(cam),
+                         _t(maps), want_visible=True, tile=16)
+    vis = res["visible"].cpu().numpy().astype(bool)
+    for p in (0, 31, 63):
+        t = sg.view_terms(sc, poses[p], cam, maps[p], tile=16)
+        ok = ~t["exempt"]
+        bad = ok & (vis[p] != t["visible"])
+        log(f"view {p}: visible gpu {int(vis[p].sum())} oracle {int(t['visible'].sum())} "
+            f"exempt {int(t['exempt'].sum())} mismatch {int(bad.sum())}")
+        assert not bad.any()
+        assert t["exempt"].mean() <= MAX_EXEMPT
+    feat64 = sg.bf16_to_f64(sc.feat)
+    want = np.zeros(sc.n)
+    shaky = np.zeros(sc.n, dtype=bool)
+    for p in range(64):
+        U, V, _ = sg.project_means(sc.means, poses[p], cam)
+        cos, inside, near = sg.sample_cosines(feat64, U, V, maps[p], cam.width, cam.height)
+        m = vis[p]
+        shaky |= m & (near | ~inside)
+        want[m & inside] += cos[m & inside]
+    cnt = res["vis_count"].cpu().numpy()
+    assert np.array_equal(cnt, vis.sum(axis=0))
+    d = np.abs(res["score_sum"].cpu().numpy().astype(np.float64) - want)[~shaky]
+    log("full size: visible pairs", int(vis.sum()), "gaussians seen", int((cnt > 0).sum()),
+        "shaky", int(shaky.sum()), "max |d sum|", float(d.max(initial=0)))
+    assert (d <= SUM_TOL * np.maximum(cnt[~shaky], 1)).all()
+    assert vis.sum() > 1_000_000
+    torch.cuda.synchronize()
