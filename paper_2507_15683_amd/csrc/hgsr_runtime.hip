@@ -76,7 +76,7 @@ struct hgsr_ctx {
 
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
-      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis;
+      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -236,7 +236,9 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
     return fail(HGSR_ERR_INVALID_ARG, "too many (pose, Gaussian) records for one render: split the poses");
   TRY(ensure(c, c->recs, nrec * sizeof(Splat)));
   TRY(ensure(c, c->rects, nrec * sizeof(uint2)));
-  TRY(ensure(c, c->pose_count, static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
+  // record sub-segment counters, then the cull pass's candidate counters
+  TRY(ensure(c, c->pose_count, 2 * static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
+  TRY(ensure(c, c->cand, nrec * sizeof(uint32_t)));
   TRY(ensure(c, c->tile_count, ntile * sizeof(uint32_t)));
   TRY(ensure(c, c->tile_cursor, ntile * sizeof(uint32_t)));
   TRY(ensure(c, c->ranges, ntile * sizeof(uint2)));
@@ -310,38 +312,43 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   // clear flags and counters (a kernel, not a memset, so the sequence can be
   // captured and replayed)
   if (!lsd)
-    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, static_cast<int64_t>(P) * kSub,
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, 2 * static_cast<int64_t>(P) * kSub,
                   c->tile_count.as<uint32_t>(), ntile, c->tile_cursor.as<uint32_t>(), ntile, s);
   else
-    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, static_cast<int64_t>(P) * kSub,
+    launch_clear4(reinterpret_cast<uint32_t*>(misc), 3, pose_count, 2 * static_cast<int64_t>(P) * kSub,
                   c->rec_keys.as<uint32_t>(), nrec, nullptr, 0, s);
 
   hipEvent_t e0 = stamp(c, s);
   const GaussArgs ga = make_gauss(*g);
-  // Tile counts: inside the projection for few poses (its latency hides the
-  // atomics), in a kernel of one thread per record for many (the
-  // projection's per-pose loop would diverge on them).
+  // Few poses: one fused projection pass that also takes the tile counts
+  // (its latency hides the atomics).  Many poses: a cull pass and a dense
+  // pass over the candidate (pose, Gaussian) pairs, then the counts in a
+  // kernel of one thread per record.
   const bool count_in_project = P <= kCountInProjectPoses;
   if (g->n_parts > 0) launch_partition_cull(poses, P, g->part_bounds, g->n_parts, cam, c->part_vis.as<uint64_t>(), s);
 
   if (g->n > 0) {
+    ProjectArgs pa;
+    pa.g = ga;
+    pa.c = cam;
+    pa.poses = poses;
+    pa.recs = c->recs.as<Splat>();
+    pa.rects = c->rects.as<uint2>();
+    pa.pose_count = pose_count;
+    pa.rec_cap = c->rec_cap;
+    pa.part_vis = g->n_parts > 0 ? c->part_vis.as<uint64_t>() : nullptr;
+    pa.tile_count = count_in_project && !lsd ? c->tile_count.as<uint32_t>() : nullptr;
+    pa.rec_keys = count_in_project && lsd ? c->rec_keys.as<uint32_t>() : nullptr;
+    pa.cand = c->cand.as<uint32_t>();
+    pa.cand_count = pose_count + static_cast<int64_t>(P) * kSub;
+    pa.flags = misc + kFlags;
     for (int p0 = 0; p0 < P; p0 += kMaxPoses) {
-      ProjectArgs pa;
-      pa.g = ga;
-      pa.c = cam;
-      pa.poses = poses;
       pa.P = std::min(kMaxPoses, P - p0);
       pa.pose_base = p0;
-      pa.recs = c->recs.as<Splat>();
-      pa.rects = c->rects.as<uint2>();
-      pa.pose_count = pose_count;
-      pa.rec_cap = c->rec_cap;
-      pa.part_vis = g->n_parts > 0 ? c->part_vis.as<uint64_t>() : nullptr;
-      pa.tile_count = count_in_project && !lsd ? c->tile_count.as<uint32_t>() : nullptr;
-      pa.rec_keys = count_in_project && lsd ? c->rec_keys.as<uint32_t>() : nullptr;
-      pa.flags = misc + kFlags;
-      launch_project(pa, s);
+      if (count_in_project) launch_project(pa, s);
+      else launch_cull(pa, s);
     }
+    if (!count_in_project) launch_splat(pa, P, s);
   }
 
   hipEvent_t e1 = stamp(c, s);
@@ -447,7 +454,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis};
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -625,9 +632,10 @@ hgsr_status hgsr_check_overflow(hgsr_ctx* c, int32_t* overflowed, hgsr_stream st
   if (!c || !overflowed) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(c->h_misc, c->misc.p, kMiscWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  std::vector<uint32_t> counts(std::max(c->P, 1) * kSub, 0);
+  // record and candidate sub-segment counters (both may exceed their capacity)
+  std::vector<uint32_t> counts(2 * std::max(c->P, 1) * kSub, 0);
   if (c->have_lists)
-    HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, static_cast<size_t>(c->P) * kSub * sizeof(uint32_t),
+    HIP_TRY(hipMemcpyAsync(counts.data(), c->pose_count.p, 2 * static_cast<size_t>(c->P) * kSub * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int32_t f = c->h_misc[kFlags];

@@ -23,6 +23,10 @@ struct ProjectArgs {
   uint32_t* tile_count;
   uint32_t* rec_keys;
   const uint64_t* part_vis;  // per pose: partitions that may be visible, or null
+  // candidate (pose, Gaussian) pairs of the cull pass: per pose kSub
+  // sub-segments of rec_cap / kSub Gaussian indices, with their counters
+  uint32_t* cand;
+  uint32_t* cand_count;
   int32_t* flags;            // [0]: overflow bits
 };
 
@@ -175,7 +179,12 @@ struct ScoreArgs {
 void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s);
 void launch_partition_cull(const float* poses, int P, const float* bounds, int n_parts, const CamArgs& c,
                            uint64_t* vis, hipStream_t s);
+// few poses: the fused pass per launch of up to kMaxPoses poses; many
+// poses: the cull pass per launch of up to kMaxPoses poses, then the splat
+// pass once for all
 void launch_project(const ProjectArgs& a, hipStream_t s);
+void launch_cull(const ProjectArgs& a, hipStream_t s);
+void launch_splat(const ProjectArgs& a, int P_total, hipStream_t s);
 void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s);
 
 // binning.hip

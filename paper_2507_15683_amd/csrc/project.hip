@@ -69,11 +69,14 @@ __global__ void partition_cull_kernel(const float* poses, int P, const float* bo
 }
 
 // ------------------------------------------------------------ projection
-// One thread per Gaussian, looping over the launch's poses (the Gaussian's
-// parameters are read once for all poses).  Visible (pose, Gaussian) pairs
-// are compacted per pose: phase 1 counts them per block in LDS, one global
-// atomic per (block, pose) reserves a range of that pose's record segment,
-// phase 2 recomputes the footprint and writes the records.
+// Few poses: one fused pass.  One thread per Gaussian, looping over the
+// launch's poses (the Gaussian's parameters are read once for all poses).
+// Visible (pose, Gaussian) pairs are compacted per pose: phase 1 counts them
+// per block in LDS, one global atomic per (block, pose) reserves a range of
+// that pose's record segment, phase 2 recomputes the footprint and writes the
+// records.  With many poses the lanes of a wave rarely share a visible pose,
+// so the expensive footprint runs on a few lanes per wave; the two passes
+// below (cull, then one thread per candidate) keep those lanes dense.
 template <int DEG>
 __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
   __shared__ uint32_t s_cnt[kMaxPoses];
@@ -203,6 +206,176 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
   }
 }
 
+// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.
+//
+// cull_kernel: one thread per Gaussian, looping over the launch's poses,
+// applies the opacity, partition, near-plane and conservative footprint
+// tests (maybe_visible: no covariance is formed) and appends the Gaussian's
+// index to the candidate list of every pose that may see it.  Per block and
+// pose the candidates are counted in LDS and one global atomic reserves a
+// range of one of the pose's kSub candidate sub-segments.
+//
+// splat_kernel: one thread per candidate (pose, Gaussian): the EWA
+// footprint with the exact support test, the SH colour, and the record;
+// a block holds candidates of one pose sub-segment, so one LDS count and
+// one global atomic per block reserve its records.
+__global__ __launch_bounds__(256) void cull_kernel(ProjectArgs a) {
+  __shared__ uint32_t s_cnt[kMaxPoses];
+  __shared__ uint32_t s_base[kMaxPoses];
+  const int tid = threadIdx.x;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
+
+  bool live = i < a.g.n;
+  float mu[3] = {0.f, 0.f, 0.f}, o = 0.f, k2 = 0.f, s2max = 0.f;
+  uint64_t pose_ok = ~0ull;
+  if (live) {
+    o = a.g.opac[i];
+    live = o >= kAlphaMin;  // also false for NaN
+    if (live && a.g.n_parts > 0) {
+      int part = 0;
+      while (part + 1 < a.g.n_parts && a.g.part_offsets[part + 1] <= i) ++part;
+      pose_ok = 0;
+      for (int p = 0; p < a.P; ++p)
+        if ((a.part_vis[a.pose_base + p] >> part) & 1ull) pose_ok |= (1ull << p);
+      live = pose_ok != 0;
+    }
+  }
+  if (live) {
+    mu[0] = a.g.means[3 * i];
+    mu[1] = a.g.means[3 * i + 1];
+    mu[2] = a.g.means[3 * i + 2];
+    const float l0 = a.g.log_scales[3 * i], l1 = a.g.log_scales[3 * i + 1], l2 = a.g.log_scales[3 * i + 2];
+    s2max = __expf(2.f * fmaxf(l0, fmaxf(l1, l2)));
+    k2 = 2.f * __logf(255.f * o);
+  }
+  __syncthreads();
+  uint64_t cand = 0;
+  if (live) {
+    for (int p = 0; p < a.P; ++p) {
+      if (!((pose_ok >> p) & 1ull)) continue;
+      const float* T = a.poses + 12 * (a.pose_base + p);
+      float mc[3];
+      to_camera(T, mu, mc);
+      if (!(mc[2] > a.c.near_z)) continue;
+      if (!maybe_visible(mc, s2max, k2, a.c)) continue;
+      atomicAdd(&s_cnt[p], 1u);
+      cand |= 1ull << p;
+    }
+  }
+  __syncthreads();
+  const int sub = static_cast<int>(blockIdx.x % kSub);
+  const uint32_t sub_cap = a.rec_cap / kSub;
+  for (int p = tid; p < a.P; p += 256) {
+    const uint32_t cnt = s_cnt[p];
+    s_base[p] = cnt ? atomicAdd(&a.cand_count[(a.pose_base + p) * kSub + sub], cnt) : 0u;
+    s_cnt[p] = 0;
+  }
+  __syncthreads();
+  while (cand) {
+    const int p = __builtin_ctzll(cand);
+    cand &= cand - 1ull;
+    const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
+    if (local >= sub_cap) {
+      atomicOr(a.flags, 1);
+      continue;
+    }
+    a.cand[static_cast<int64_t>(a.pose_base + p) * a.rec_cap + sub * sub_cap + local] = static_cast<uint32_t>(i);
+  }
+}
+
+// Candidates per splat block.
+constexpr int kSplatBlock = 256;
+
+template <int DEG>
+__global__ __launch_bounds__(kSplatBlock) void splat_kernel(ProjectArgs a) {
+  __shared__ uint32_t s_cnt, s_base;
+  const int tid = threadIdx.x;
+  const uint32_t sub_cap = a.rec_cap / kSub;
+  const int chunks = static_cast<int>((sub_cap + kSplatBlock - 1) / kSplatBlock);
+  // block -> (pose, candidate sub-segment, chunk of kSplatBlock candidates)
+  const int chunk = static_cast<int>(blockIdx.x % chunks);
+  const int csub = static_cast<int>((blockIdx.x / chunks) % kSub);
+  const int pg = static_cast<int>(blockIdx.x / (chunks * kSub));
+  const uint32_t n_cand = min(a.cand_count[pg * kSub + csub], sub_cap);
+  const uint32_t first = static_cast<uint32_t>(chunk) * kSplatBlock;
+  if (first >= n_cand) return;  // uniform: the whole block leaves
+  if (tid == 0) s_cnt = 0;
+  const uint32_t c = first + tid;
+  bool vis = false;
+  int64_t i = 0;
+  float mu[3], mc[3], o = 0.f, k2 = 0.f;
+  Footprint f;
+  const float* T = a.poses + 12 * pg;
+  if (c < n_cand) {
+    i = a.cand[static_cast<int64_t>(pg) * a.rec_cap + csub * sub_cap + c];
+    o = a.g.opac[i];
+    mu[0] = a.g.means[3 * i];
+    mu[1] = a.g.means[3 * i + 1];
+    mu[2] = a.g.means[3 * i + 2];
+    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+    k2 = 2.f * __logf(255.f * o);
+    float S[6];
+    cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
+    to_camera(T, mu, mc);
+    vis = footprint(T, mc, S, k2, a.c, f);
+  }
+  __syncthreads();
+  uint32_t local = 0;
+  if (vis) local = atomicAdd(&s_cnt, 1u);
+  __syncthreads();
+  // records go to one of the pose's kSub record sub-segments, picked by
+  // block index, so that the reservation atomics spread over kSub addresses
+  const int sub = static_cast<int>(blockIdx.x % kSub);
+  if (tid == 0) s_base = s_cnt ? atomicAdd(&a.pose_count[pg * kSub + sub], s_cnt) : 0u;
+  __syncthreads();
+  if (!vis) return;
+  local += s_base;
+  if (local >= sub_cap) {
+    atomicOr(a.flags, 1);
+    return;
+  }
+  const uint32_t slot = sub * sub_cap + local;
+  // view direction from the camera centre C = -R^T t
+  const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
+  const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
+  const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
+  float dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
+  const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= inv; dy *= inv; dz *= inv;
+  float rgb[3];
+  sh_colour_raw<DEG>(a.g.sh, i, dx, dy, dz, rgb);
+  const int64_t idx = static_cast<int64_t>(pg) * a.rec_cap + slot;
+  Splat sp;
+  sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
+  sp.cc = f.cc; sp.o = o; sp.z = mc[2]; sp.gid = static_cast<uint32_t>(i);
+  sp.r = fmaxf(rgb[0], 0.f); sp.g = fmaxf(rgb[1], 0.f); sp.b = fmaxf(rgb[2], 0.f);
+  sp.pmin = -0.5f * k2;
+  float4* dst = reinterpret_cast<float4*>(a.recs + idx);
+  const float4* src = reinterpret_cast<const float4*>(&sp);
+  dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
+  const int tx0 = f.px0 >> a.c.tile_shift, tx1 = f.px1 >> a.c.tile_shift;
+  const int ty0 = f.py0 >> a.c.tile_shift, ty1 = f.py1 >> a.c.tile_shift;
+  a.rects[idx] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
+                            static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
+  // few poses: the record's tiles are counted here (row spans of the same
+  // stored values count_tiles_kernel would read); many poses: there
+  if (a.tile_count || a.rec_keys) {
+    const SplatShape shp = splat_shape(sp.u, sp.v, sp.ca, sp.cb, sp.cc, -2.f * sp.pmin);
+    uint32_t ntiles = 0;
+    uint32_t* tc = a.tile_count ? a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose : nullptr;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      for (int tx = ta; tx <= tb; ++tx) {
+        ++ntiles;
+        if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+      }
+    }
+    if (a.rec_keys) a.rec_keys[idx] = ntiles;
+  }
+}
+
 // ------------------------------------------------------------ validation
 __global__ void validate_kernel(GaussArgs g, int32_t* bad) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -242,6 +415,23 @@ void launch_project(const ProjectArgs& a, hipStream_t s) {
     case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, a); break;
+  }
+}
+
+void launch_cull(const ProjectArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((a.g.n + 255) / 256));
+  hipLaunchKernelGGL(cull_kernel, grid, dim3(256), 0, s, a);
+}
+
+void launch_splat(const ProjectArgs& a, int P_total, hipStream_t s) {
+  const int64_t chunks = (a.rec_cap / kSub + kSplatBlock - 1) / kSplatBlock;
+  const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(P_total) * kSub * chunks));
+  const dim3 block(kSplatBlock);
+  switch (a.g.sh_degree) {
+    case 0: hipLaunchKernelGGL(splat_kernel<0>, grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(splat_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(splat_kernel<2>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(splat_kernel<3>, grid, block, 0, s, a); break;
   }
 }
 
