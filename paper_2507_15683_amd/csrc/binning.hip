@@ -263,6 +263,9 @@ void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, ui
 }
 
 // ------------------------------------------------------------ tile counts
+// Largest per-pose tile count whose counters fit an LDS copy (64 KB).
+constexpr int kLdsTileMax = 16384;
+
 // One thread per record: the tiles of its pixel rectangle that the support
 // ellipse meets (row spans), counted per (pose, tile) for the bucket path and
 // per record for the LSD path.  The emit kernels walk the same spans.
@@ -290,7 +293,49 @@ __global__ __launch_bounds__(256) void count_tiles_kernel(BinArgs a, uint32_t* t
   if (rec_keys) rec_keys[idx] = ntiles;
 }
 
+// Many poses (bucket path): a workgroup takes a run of kRecPerBlock record
+// slots of one pose and counts their tile entries in an LDS copy of that
+// pose's tile counters, then adds each nonzero counter to global memory once
+// (one global atomic per (workgroup, tile) instead of one per entry).
+constexpr uint32_t kRecPerBlock = 4096;
+
+__global__ __launch_bounds__(256) void count_tiles_lds_kernel(BinArgs a, uint32_t* tile_count) {
+  extern __shared__ uint32_t s_hist[];  // tiles_per_pose counters
+  if (a.flags[0] & 1) return;
+  const int pose = blockIdx.y;
+  const int T = a.c.tiles_per_pose;
+  for (int t = threadIdx.x; t < T; t += 256) s_hist[t] = 0;
+  __syncthreads();
+  const uint32_t s0 = blockIdx.x * kRecPerBlock, s1 = min(s0 + kRecPerBlock, a.rec_cap);
+  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
+    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
+    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+    const uint2 r = a.rects[idx];
+    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+    const float4 geo = rp[0], hdr = rp[1];
+    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      for (int tx = ta; tx <= tb; ++tx) atomicAdd(&s_hist[ty * a.c.ntx + tx], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* tc = tile_count + static_cast<int64_t>(pose) * T;
+  for (int t = threadIdx.x; t < T; t += 256) {
+    const uint32_t c = s_hist[t];
+    if (c) atomicAdd(&tc[t], c);
+  }
+}
+
 void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_keys, hipStream_t s) {
+  if (tile_count && !rec_keys && a.c.tiles_per_pose <= kLdsTileMax) {
+    const dim3 grid((a.rec_cap + kRecPerBlock - 1) / kRecPerBlock, a.P);
+    hipLaunchKernelGGL(count_tiles_lds_kernel, grid, dim3(256), a.c.tiles_per_pose * sizeof(uint32_t), s, a,
+                       tile_count);
+    return;
+  }
   const dim3 grid((a.rec_cap + 255) / 256, a.P);
   hipLaunchKernelGGL(count_tiles_kernel, grid, dim3(256), 0, s, a, tile_count, rec_keys);
 }
@@ -333,7 +378,67 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   }
 }
 
-void launch_emit_bucket(const BinArgs& a, hipStream_t s) {
+// Many poses: the same run of record slots as count_tiles_lds_kernel counts
+// its entries per tile in LDS, reserves each tile's range with one global
+// atomic, and places its entries from LDS cursors.
+__global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
+  extern __shared__ uint32_t s_pos[];  // per tile: count, then next position
+  if (a.flags[0] & 1) return;
+  const int pose = blockIdx.y;
+  const int T = a.c.tiles_per_pose;
+  for (int t = threadIdx.x; t < T; t += 256) s_pos[t] = 0;
+  __syncthreads();
+  const uint32_t s0 = blockIdx.x * kRecPerBlock, s1 = min(s0 + kRecPerBlock, a.rec_cap);
+  const int64_t tbase = static_cast<int64_t>(pose) * T;
+  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
+    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
+    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+    const uint2 r = a.rects[idx];
+    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+    const float4 geo = rp[0], hdr = rp[1];
+    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      for (int tx = ta; tx <= tb; ++tx) atomicAdd(&s_pos[ty * a.c.ntx + tx], 1u);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < T; t += 256) {
+    const uint32_t c = s_pos[t];
+    if (c) s_pos[t] = a.ranges[tbase + t].x + atomicAdd(&a.tile_cursor[tbase + t], c);
+  }
+  __syncthreads();
+  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
+    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
+    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+    const uint2 r = a.rects[idx];
+    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+    const float4 geo = rp[0], hdr = rp[1];  // u, v, ca, cb | cc, o, z, gid
+    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+    const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      for (int tx = ta; tx <= tb; ++tx) {
+        const uint64_t pos = atomicAdd(&s_pos[ty * a.c.ntx + tx], 1u);
+        if (pos < a.key_cap) {
+          a.keys[pos] = key;
+          a.vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+        }
+      }
+    }
+  }
+}
+
+void launch_emit_bucket(const BinArgs& a, bool lds, hipStream_t s) {
+  if (lds && a.c.tiles_per_pose <= kLdsTileMax) {
+    const dim3 grid((a.rec_cap + kRecPerBlock - 1) / kRecPerBlock, a.P);
+    hipLaunchKernelGGL(emit_bucket_lds_kernel, grid, dim3(256), a.c.tiles_per_pose * sizeof(uint32_t), s, a);
+    return;
+  }
   const dim3 grid((a.rec_cap * kEmitLanes + 255) / 256, a.P);
   hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
 }

@@ -373,7 +373,7 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
                 c->key_cap, misc + kFlags, 2, s);
     ba.keys = c->keys0.as<uint64_t>();
     ba.vals = c->vals0.as<uint32_t>();
-    launch_emit_bucket(ba, s);
+    launch_emit_bucket(ba, !count_in_project, s);
     TileSortArgs ta;
     ta.n_tiles = static_cast<int32_t>(ntile);
     ta.ranges = c->ranges.as<uint2>();

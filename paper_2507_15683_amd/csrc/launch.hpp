@@ -197,7 +197,9 @@ void launch_scan(const uint32_t* in, int64_t n, uint32_t* out, uint2* ranges, ui
                  uint32_t* total, uint64_t cap, int32_t* flags, int32_t flag_bit, hipStream_t s);
 // tile_count (bucket) or rec_keys (LSD): the other may be null
 void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_keys, hipStream_t s);
-void launch_emit_bucket(const BinArgs& a, hipStream_t s);
+// lds: the per-workgroup LDS counters (many poses; the count kernel uses
+// them whenever it runs on the bucket path)
+void launch_emit_bucket(const BinArgs& a, bool lds, hipStream_t s);
 void launch_tile_sort(const TileSortArgs& a, bool short_lists, hipStream_t s);
 void launch_emit_lsd(const BinArgs& a, const uint32_t* rec_offsets, uint64_t* keys, uint32_t* gids,
                      uint32_t* vals, hipStream_t s);
