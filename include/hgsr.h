@@ -117,7 +117,10 @@ enum { HGSR_SCHED_GRID = 0, HGSR_SCHED_POSE_MAJOR = 1, HGSR_SCHED_TILE_MAJOR = 2
  * HGSR_FEAT_AUTO (the autotuned choice, else the VALU), HGSR_FEAT_VALU
  * (per-pixel FMAs in blend order) or HGSR_FEAT_MFMA (per batch, a 32x2 by
  * 2x64 FP32 matrix-core product of features and per-pixel weights; the same
- * sum in another association order). */
+ * sum in another association order).  HGSR_FEAT_MFMA also moves the
+ * backward's per-pair feature term (the pixel's feature gradient dotted with
+ * the splat's feature) onto the matrix cores, per group of 32 splats; the
+ * other settings keep it on the VALU. */
 enum { HGSR_FEAT_AUTO = 0, HGSR_FEAT_VALU = 1, HGSR_FEAT_MFMA = 2 };
 
 typedef struct {

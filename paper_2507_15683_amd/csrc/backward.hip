@@ -20,7 +20,21 @@
 
 namespace hgsr {
 
-template <int TILE, int D, bool FEATGRAD, bool RES>
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// Splats per matrix-core group of the feature term (MFH).
+constexpr int kHGroup = 32;
+
+// MFH: the feature part of h_j = gF . f_j for a group of 32 splats and the
+// wave's 64 pixels is one matrix product H[32 x 64] = F[32 x 32] gF[32 x 64],
+// run as v_mfma_f32_32x32x8_bf16 (channels in four steps of 8, pixels in two
+// blocks of 32).  F is the splats' stored bf16 features (exact); the FP32
+// pixel gradient gF enters as three bf16 parts (top, middle and last 8
+// significant bits), so the products are exact and only the summation order
+// differs from the FP32 dot product.  H goes to LDS, where the walk reads its
+// pixel's value of each splat.
+template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
   using Sh = BlendShape<TILE>;
   constexpr int NT = Sh::kThreads, NB = Sh::kBatch, NW = Sh::kWaves, BW = Sh::kBlockW, BH = Sh::kBlockH;
@@ -28,12 +42,16 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   constexpr int DV = D / 8;                             // 16-byte bf16 vectors per feature
   constexpr int DD = D > 0 ? D : 1;
   constexpr int PARTS = (DV >= NT / NB) ? NT / NB : 1;  // threads sharing one splat's feature load
+  constexpr bool MF = MFH && D == 32 && PPT == 1 && !FEATGRAD;
   __shared__ float4 s_geo[NB];
   __shared__ float4 s_opz[NB];
   __shared__ float4 s_col[NB];
   __shared__ uint32_t s_rec[NB];
   constexpr int FS = D + 4;  // padded slot stride (words): staging writes spread over banks
-  __shared__ float s_f[D > 0 ? NB * FS : 1];  // features as FP32
+  __shared__ float s_f[(D > 0 && !MF) ? NB * FS : 1];  // features as FP32
+  constexpr int FBS = 20;    // MF: raw bf16 feature slot (16 words + 4 of padding)
+  __shared__ uint32_t s_fb[MF ? NB * FBS : 1];
+  __shared__ float s_h[MF ? NW : 1][MF ? kHGroup : 1][MF ? kWave : 1];  // MF: H per wave
   __shared__ uint8_t s_mask[NB];
   __shared__ uint16_t s_list[NW][NB];
   __shared__ float s_g[NB][10];  // per staged splat: the workgroup's gradient sums
@@ -191,9 +209,13 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
 #pragma unroll
             for (int q = 0; q < QV; ++q) {
               const uint4 f = fv[q];
-              float4* dst = reinterpret_cast<float4*>(&s_f[e * FS + 8 * (part * QV + q)]);
-              dst[0] = make_float4(bf16_lo(f.x), bf16_hi(f.x), bf16_lo(f.y), bf16_hi(f.y));
-              dst[1] = make_float4(bf16_lo(f.z), bf16_hi(f.z), bf16_lo(f.w), bf16_hi(f.w));
+              if constexpr (MF) {
+                reinterpret_cast<uint4*>(&s_fb[e * FBS])[part * QV + q] = f;
+              } else {
+                float4* dst = reinterpret_cast<float4*>(&s_f[e * FS + 8 * (part * QV + q)]);
+                dst[0] = make_float4(bf16_lo(f.x), bf16_hi(f.x), bf16_lo(f.y), bf16_hi(f.y));
+                dst[1] = make_float4(bf16_lo(f.z), bf16_hi(f.z), bf16_lo(f.w), bf16_hi(f.w));
+              }
             }
           }
         }
@@ -212,6 +234,72 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
     }
     __builtin_amdgcn_wave_barrier();
     for (int ii = n_mine - 1; ii >= 0; --ii) {
+      if constexpr (MF) {
+        if (ii == n_mine - 1 || (ii + 1) % kHGroup == 0) {
+          // H for the group of compacted entries [g0, g0 + 32) holding ii
+          const int g0 = ii / kHGroup * kHGroup;
+          const int row = lane & 31, half = lane >> 5;
+          const int e = g0 + row;
+          const int js = e < n_mine ? static_cast<int>(s_list[wave][e]) : -1;
+          floatx16 acc0 = {}, acc1 = {};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            uint2 av = make_uint2(0u, 0u);
+            if (js >= 0) av = *reinterpret_cast<const uint2*>(&s_fb[js * FBS + 4 * ks + 2 * half]);
+            shortx4 A;
+            __builtin_memcpy(&A, &av, 8);
+            // B: this lane's pixel gradient, channels 8 ks .. 8 ks + 7, split
+            // into three exact bf16 parts; lane l supplies channels
+            // 8 ks + 4 (l / 32) + 0..3 of pixel l % 32 (block 0) and of pixel
+            // 32 + l % 32 (block 1): its own half of the channels for its own
+            // block, the partner lane's (l ^ 32) for the other, exchanged with
+            // one lane-half swap per word
+            float r[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              r[c] = gF[0][8 * ks + c];
+              // keeps the split inside the group loop (recomputed per group)
+              // instead of hoisted into 48 live registers for the whole walk
+              asm volatile("" : "+v"(r[c]));
+            }
+#pragma unroll
+            for (int part = 0; part < 3; ++part) {
+              uint32_t hw[4];  // bf16 pairs: channels (0,1) (2,3) (4,5) (6,7)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const uint32_t x = __float_as_uint(r[2 * c]) & 0xffff0000u;
+                const uint32_t y = __float_as_uint(r[2 * c + 1]) & 0xffff0000u;
+                hw[c] = (x >> 16) | y;
+                if (part < 2) {
+                  r[2 * c] -= __uint_as_float(x);
+                  r[2 * c + 1] -= __uint_as_float(y);
+                }
+              }
+              uint32_t b0w[2], b1w[2];
+#pragma unroll
+              for (int w = 0; w < 2; ++w) {
+                const auto sw = __builtin_amdgcn_permlane32_swap(hw[w], hw[2 + w], false, false);
+                b0w[w] = sw[0];
+                b1w[w] = sw[1];
+              }
+              shortx4 B0, B1;
+              __builtin_memcpy(&B0, b0w, 8);
+              __builtin_memcpy(&B1, b1w, 8);
+              acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B0, acc0, 0, 0, 0);
+              acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B1, acc1, 0, 0, 0);
+            }
+          }
+          // accumulator layout: lane l, register r holds row 8 (r/4) + 4 (l/32)
+          // + r%4 (group entry) of column l % 32 (pixel, + 32 for acc1)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int hr = 8 * (r / 4) + 4 * half + (r % 4);
+            s_h[MF ? wave : 0][hr][row] = acc0[r];
+            s_h[MF ? wave : 0][hr][32 + row] = acc1[r];
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
       const int jj = s_list[wave][ii];
       const uint32_t pos = b0 + jj;
       const float4 geo = s_geo[jj];
@@ -241,7 +329,9 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
         const float Tj = T[k] * iom;
         const float w = alpha * Tj;
         float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
-        if constexpr (D > 0) {
+        if constexpr (MF) {
+          h += s_h[MF ? wave : 0][ii % kHGroup][lane];
+        } else if constexpr (D > 0) {
           const float4* fq = reinterpret_cast<const float4*>(&s_f[jj * FS]);
 #pragma unroll
           for (int q = 0; q < D / 4; ++q) {
@@ -321,12 +411,18 @@ void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, fl
 template <int TILE, int D>
 static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
+  // the feature term on the matrix cores: 32 channels, one pixel per lane,
+  // no per-Gaussian feature gradient
+  constexpr bool MFOK = D == 32 && BlendShape<TILE>::kPPT == 1;
+  const bool mf = MFOK && a.feat_mfma && !a.g_featvec;
   if (a.res_rgb_t) {
-    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true>), dim3(items), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true>), dim3(items), dim3(NT), 0, s, a);
+    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true, false>), dim3(items), dim3(NT), 0, s, a);
+    else if (mf) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, MFOK>), dim3(items), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, false>), dim3(items), dim3(NT), 0, s, a);
   } else {
-    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, false>), dim3(items), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false>), dim3(items), dim3(NT), 0, s, a);
+    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, false, false>), dim3(items), dim3(NT), 0, s, a);
+    else if (mf) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, MFOK>), dim3(items), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, false>), dim3(items), dim3(NT), 0, s, a);
   }
 }
 

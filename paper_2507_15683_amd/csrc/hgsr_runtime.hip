@@ -846,6 +846,11 @@ static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   BackArgs b;
   b.c = c->cam;
   b.P = P;
+  // the backward's feature term on the matrix cores only when the render
+  // asked for the matrix-core feature sum (measured slower than the VALU dot
+  // product on the refinement workload: the per-group matrix products and
+  // their LDS staging outweigh the 32 FMAs per visited pair)
+  b.feat_mfma = c->opts.feat_accum == HGSR_FEAT_MFMA ? 1 : 0;
   b.ranges = c->ranges.as<uint2>();
   b.list = c->sorted;
   b.recs = c->recs.as<Splat>();

@@ -93,6 +93,7 @@ struct BlendArgs {
 struct BackArgs {
   CamArgs c;
   int32_t P;
+  int32_t feat_mfma;         // feature term of h on the matrix cores (D 32, one pixel per lane)
   const uint2* ranges;
   const uint32_t* list;
   const Splat* recs;

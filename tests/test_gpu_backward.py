@@ -358,3 +358,39 @@ def test_residual_backward_shared_target(hg):
     lb, gb = r.residual_backward(rep_rgb, rep_feat)
     assert np.array_equal(la, to_np(lb))
     assert _rel(to_np(gb["pose"]), pa) < 1e-6
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_matrix_core_feature_term_matches_valu(hg, orc, tile):
+    """The backward's feature term h = gF . f on the matrix cores (bf16 parts
+    of the FP32 pixel gradient, exact products) gives the gradients of the
+    per-pixel FP32 dot product up to summation order (and the forward's
+    matrix-core feature sum, |delta| <= 1e-7), with the residual formed in the
+    prologue and with dL/dfeat images."""
+    import torch
+    sc, P, cam = synth.tiny_scene(700, 60 + tile, width=97, height=70, feat_dim=32, sh_degree=2)
+    Ps = synth.perturb_poses(P[0], 3, 61, 1.0, 2.0)
+    tg = synth.perturb_poses(P[0], 3, 62, 1.0, 2.0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    tgt = hg.Renderer().render(scene, _t(tg), K)
+    tgt = {k: (None if v is None else v.clone()) for k, v in tgt.items()}
+    log(f"case: matrix-core feature term, tile {tile}")
+    res = {}
+    # "mfma": the feature sum of the forward and the feature term of the
+    # backward on the matrix cores; "valu": both on the VALU
+    for fa in ("valu", "mfma"):
+        r = hg.Renderer()
+        out = r.render(scene, _t(Ps), K, tile=tile, feat_accum=fa)
+        lb, gb = r.residual_backward(tgt["rgb"], tgt["feat"], want=("pose", "means", "opacities"))
+        _, g_rgb, g_feat = hg.residual(out["rgb"], out["feat"], tgt["rgb"], tgt["feat"])
+        gp = r.backward(dict(rgb=g_rgb, feat=g_feat), want=("pose", "means", "opacities"))
+        res[fa] = ({k: to_np(v).copy() for k, v in gb.items()}, {k: to_np(v).copy() for k, v in gp.items()},
+                   to_np(lb).copy())
+        torch.cuda.synchronize()
+    for which in (0, 1):
+        for k in ("pose", "means", "opacities"):
+            rel = _rel(res["mfma"][which][k], res["valu"][which][k])
+            log(which, k, rel)
+            assert rel < 1e-5, (which, k, rel)
+    np.testing.assert_allclose(res["mfma"][2], res["valu"][2], rtol=1e-6, atol=0)
