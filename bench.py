@@ -390,6 +390,43 @@ def significance(hg, torch, synth, args):
             "walk_bytes_per_launch": int(walk_bytes), "roofline_score": rl, "steps_timed": args.sig_steps}
 
 
+def matching(hg, torch, synth, args):
+    """Coarse-to-fine probabilistic mutual matching (Sec. 3.4, Eq. 11) at the
+    1080p sizes: 135 x 240 coarse positions (1/8), 1080 x 1920 fine maps,
+    32-channel bf16 features; the render a shifted, noisy copy of the query."""
+    import numpy as np
+    log("bench: matching, 135x240 coarse / 1080x1920 fine")
+    Hc, Wc, D = 135, 240, 32
+    q_c, r_c, q_f, r_f = synth.matching_maps(D, Hc, Wc, seed=9000, shift=(11, -6), noise=0.3)
+    bf = lambda b: torch.from_numpy(b.view(np.int16)).cuda().view(torch.bfloat16)
+    qc, rc, qf, rf = bf(q_c), bf(r_c), bf(q_f), bf(r_f)
+    r = hg.Renderer()
+    s = torch.cuda.Stream()
+    out = r.match(qc, rc, qf, rf, stream=s)
+    s.synchronize()
+    for _ in range(2):
+        r.match(qc, rc, qf, rf, out=out, stream=s)
+    s.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.match_steps):
+        r.match(qc, rc, qf, rf, out=out, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / args.match_steps
+    K = int(out["n_coarse"].cpu().numpy().view(np.uint32)[0])
+    n_fine = int((out["fine_query"][: 64 * K] >= 0).sum().item())
+    N = Hc * Wc
+    # the two coarse passes each form the N x N cosine matrix on the matrix
+    # cores (2 N^2 D flops per pass)
+    tflops = 2 * 2 * N * N * D / (ms * 1e-3) / 1e12
+    return {"workload": "coarse-to-fine probabilistic mutual matching, 135x240 coarse positions (1920x1080 / 8), "
+                        "1080x1920 fine maps, 32-channel bf16 features, tau 0.1",
+            "ms_per_call": round(ms, 3), "coarse_pairs_per_s": round(N * N / (ms * 1e-3), 1),
+            "coarse_correspondences": K, "fine_correspondences": n_fine,
+            "coarse_matrix_tflop_s": round(tflops, 1), "steps_timed": args.match_steps}
+
+
 def partitioned(hg, torch, synth, args):
     """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
     import numpy as np
@@ -498,13 +535,16 @@ def main():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-partitioned", action="store_true")
     ap.add_argument("--no-significance", action="store_true")
+    ap.add_argument("--no-matching", action="store_true")
+    ap.add_argument("--match-steps", type=int, default=10)
     ap.add_argument("--sig-steps", type=int, default=10)
     ap.add_argument("--fb-steps", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--part-iters", type=int, default=20)
     ap.add_argument("--part-lr-rho", type=float, default=0.3, help="Adam step (m) of the partitioned refinement")
     ap.add_argument("--part-lr-phi", type=float, default=4e-3, help="Adam step (rad) of the partitioned refinement")
-    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance"], default=None,
+    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance", "matching"],
+                    default=None,
                     help="run one section and print its result alone (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (5 launches), to scale HBM counters")
@@ -538,8 +578,11 @@ def main():
     if args.only == "significance":
         print(json.dumps({"significance": significance(hg, torch, synth, args)}), flush=True)
         return
+    if args.only == "matching":
+        print(json.dumps({"matching": matching(hg, torch, synth, args)}), flush=True)
+        return
     if args.only == "headline":
-        args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_cpu = True
+        args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_matching = args.no_cpu = True
     h = headline(hg, torch, synth, args)
     result = {
         "metric": "rendered Mpix/s at 1080p/1M Gaussians",
@@ -576,6 +619,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_significance:
         result["significance"] = significance(hg, torch, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_matching:
+        result["matching"] = matching(hg, torch, synth, args)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("bench: timing the CPU oracle")

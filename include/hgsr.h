@@ -299,6 +299,54 @@ hgsr_status hgsr_significance(hgsr_ctx* ctx, const hgsr_gaussians* g, const floa
 hgsr_status hgsr_significance_final(const float* score_sum, const uint32_t* vis_count, int64_t n, float* score,
                                     hgsr_stream stream);
 
+/* Query and rendered feature maps for hgsr_match (device, bfloat16 bits,
+ * planar D x H x W).  The coarse maps are coarse_width x coarse_height
+ * positions; the fine maps, when given, 8 times that in each direction
+ * (the window w = H_f / H_c = 8 of Sec. 3.4).  D: 8, 16, 32 or 64. */
+typedef struct {
+  const uint16_t* query_coarse;
+  const uint16_t* render_coarse;
+  const uint16_t* query_fine;   /* NULL: coarse level only */
+  const uint16_t* render_fine;
+  int32_t D;
+  int32_t coarse_width;
+  int32_t coarse_height;
+} hgsr_match_maps;
+
+/* Outputs of hgsr_match (device, caller-allocated).  n_coarse: one uint32,
+ * the number of coarse correspondences K.  coarse_query / coarse_render /
+ * coarse_p: capacity coarse_width x coarse_height entries; entry k < K is
+ * the k-th correspondence in query order: the query's and the render's
+ * coarse position (row-major index) and its probability P.  fine_query /
+ * fine_render / fine_p (needed when fine maps are given): capacity
+ * coarse_width x coarse_height x 64; slot 64 k + t describes query window
+ * position t (row-major in the 8 x 8 window) of coarse correspondence k: its
+ * fine position and the matched rendered fine position (row-major indices
+ * in the fine maps) and P, or -1, -1, 0 when position t has no mutual
+ * match.  Slots of k >= K are left unchanged. */
+typedef struct {
+  uint32_t* n_coarse;
+  int32_t* coarse_query;
+  int32_t* coarse_render;
+  float* coarse_p;
+  int32_t* fine_query;
+  int32_t* fine_render;
+  float* fine_p;
+} hgsr_match_out;
+
+/* Coarse-to-fine probabilistic mutual matching of a query's feature maps
+ * with rendered ones (Sec. 3.4, Eq. 11).  Coarse level: M_ij = cosine of
+ * query position i and rendered position j (a.b / (|a| |b| + 1e-8)),
+ * P = softmax over j of M/tau times softmax over i of M/tau (element by
+ * element), and (i, j) is a correspondence when j maximises row i of P and
+ * i maximises column j (ties: lowest index).  Fine level: the same on the
+ * 8 x 8 fine windows of coarse cell i in the query and cell j in the render,
+ * for every coarse correspondence.  tau_coarse and tau_fine must be at least
+ * 1/40.  The M matrix is never stored; the workspace grows with the number
+ * of coarse positions.  Asynchronous on `stream`. */
+hgsr_status hgsr_match(hgsr_ctx* ctx, const hgsr_match_maps* maps, float tau_coarse, float tau_fine,
+                       const hgsr_match_out* out, hgsr_stream stream);
+
 /* Fill part_bounds (device, n_parts x 6) with a box containing, for every
  * Gaussian of each partition, the ball of radius 3.33 x its largest scale
  * around its mean (the 1/255 support of the most opaque Gaussian). */

@@ -315,6 +315,42 @@ class Renderer:
             vis_count.copy_(c0)
         raise HgsrError(3, "significance: workspace kept overflowing")
 
+    def match(self, q_coarse: torch.Tensor, r_coarse: torch.Tensor, q_fine: Optional[torch.Tensor] = None,
+              r_fine: Optional[torch.Tensor] = None, tau_coarse: float = 0.1, tau_fine: float = 0.1,
+              out: Optional[dict] = None, stream=None) -> dict:
+        """Coarse-to-fine probabilistic mutual matching (Sec. 3.4, Eq. 11) of
+        query and rendered bf16 feature maps (D, Hc, Wc) and, optionally,
+        (D, 8 Hc, 8 Wc).  Returns dict(n_coarse (1,) uint32 -- read it after
+        synchronising --, coarse_query, coarse_render, coarse_p, fine_query,
+        fine_render, fine_p) on the device (see hgsr_match_out)."""
+        for t in (q_coarse, r_coarse, q_fine, r_fine):
+            if t is not None and (t.dtype != torch.bfloat16 or not t.is_contiguous() or t.dim() != 3):
+                raise ValueError("feature maps must be contiguous bfloat16 (D, H, W) device tensors")
+        D, Hc, Wc = q_coarse.shape
+        if r_coarse.shape != q_coarse.shape:
+            raise ValueError("query and rendered coarse maps must have the same shape")
+        if (q_fine is None) != (r_fine is None):
+            raise ValueError("give both fine maps or neither")
+        if q_fine is not None and (q_fine.shape != (D, 8 * Hc, 8 * Wc) or r_fine.shape != q_fine.shape):
+            raise ValueError("fine maps must be (D, 8 Hc, 8 Wc)")
+        dev = q_coarse.device
+        N = Hc * Wc
+        if out is None:
+            out = dict(n_coarse=torch.zeros(1, dtype=torch.int32, device=dev),
+                       coarse_query=torch.empty(N, dtype=torch.int32, device=dev),
+                       coarse_render=torch.empty(N, dtype=torch.int32, device=dev),
+                       coarse_p=torch.empty(N, dtype=torch.float32, device=dev),
+                       fine_query=torch.empty(N * 64 if q_fine is not None else 0, dtype=torch.int32, device=dev),
+                       fine_render=torch.empty(N * 64 if q_fine is not None else 0, dtype=torch.int32, device=dev),
+                       fine_p=torch.empty(N * 64 if q_fine is not None else 0, dtype=torch.float32, device=dev))
+        mm = _lib.MatchMaps(_ptr(q_coarse), _ptr(r_coarse), _ptr(q_fine), _ptr(r_fine), D, Wc, Hc)
+        mo = _lib.MatchOut(*[_ptr(out[k]) for k in ("n_coarse", "coarse_query", "coarse_render", "coarse_p",
+                                                     "fine_query", "fine_render", "fine_p")])
+        self._keep_match = (q_coarse, r_coarse, q_fine, r_fine, out)
+        check(self.lib.hgsr_match(self.ctx, ctypes.byref(mm), tau_coarse, tau_fine, ctypes.byref(mo),
+                                  _stream_ptr(stream)), "hgsr_match")
+        return out
+
     def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
                  feat_bf16=False, cache_path: Optional[str] = None, stream=None) -> dict:
         """Time tile sizes 8/16/32, the blend schedules and the feature

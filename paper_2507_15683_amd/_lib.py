@@ -67,6 +67,16 @@ class FeatureMaps(ctypes.Structure):
 
 MAP_PLANAR, MAP_INTERLEAVED = 0, 1
 
+
+class MatchMaps(ctypes.Structure):
+    _fields_ = [("query_coarse", P_), ("render_coarse", P_), ("query_fine", P_), ("render_fine", P_), ("D", I32),
+                ("coarse_width", I32), ("coarse_height", I32)]
+
+
+class MatchOut(ctypes.Structure):
+    _fields_ = [("n_coarse", P_), ("coarse_query", P_), ("coarse_render", P_), ("coarse_p", P_),
+                ("fine_query", P_), ("fine_render", P_), ("fine_p", P_)]
+
 # (name, argtypes) for every entry point declared in include/hgsr.h
 SIGNATURES = {
     "hgsr_ctx_create": [ctypes.POINTER(P_), I64, I64],
@@ -81,6 +91,7 @@ SIGNATURES = {
     "hgsr_significance": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
                           ctypes.POINTER(FeatureMaps), P_, P_, P_, P_],
     "hgsr_significance_final": [P_, P_, I64, P_, P_],
+    "hgsr_match": [P_, ctypes.POINTER(MatchMaps), F32, F32, ctypes.POINTER(MatchOut), P_],
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],

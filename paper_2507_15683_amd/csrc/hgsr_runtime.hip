@@ -76,7 +76,8 @@ struct hgsr_ctx {
 
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
-      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand;
+      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
+      match;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -454,7 +455,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand};
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -615,6 +616,70 @@ hgsr_status hgsr_significance(hgsr_ctx* c, const hgsr_gaussians* g, const float*
   c->opts.tile = rs.tile;
   c->cam = rs.cam;
   c->sorted = sorted;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_match(hgsr_ctx* c, const hgsr_match_maps* m, float tau_coarse, float tau_fine,
+                       const hgsr_match_out* out, hgsr_stream stream) {
+  if (!c || !m || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  const int D = m->D;
+  if (!(D == 8 || D == 16 || D == 32 || D == 64)) return fail(HGSR_ERR_INVALID_ARG, "D must be 8, 16, 32 or 64");
+  if (m->coarse_width <= 0 || m->coarse_height <= 0 || m->coarse_width > 2048 || m->coarse_height > 2048)
+    return fail(HGSR_ERR_INVALID_ARG, "coarse size %dx%d out of range", m->coarse_width, m->coarse_height);
+  if (!m->query_coarse || !m->render_coarse) return fail(HGSR_ERR_INVALID_ARG, "coarse maps are NULL");
+  if ((m->query_fine == nullptr) != (m->render_fine == nullptr))
+    return fail(HGSR_ERR_INVALID_ARG, "give both fine maps or neither");
+  if (!(tau_coarse >= 0.025f) || !(tau_fine >= 0.025f) || !std::isfinite(tau_coarse) || !std::isfinite(tau_fine))
+    return fail(HGSR_ERR_INVALID_ARG, "temperatures must be finite and at least 1/40");
+  if (!out->n_coarse || !out->coarse_query || !out->coarse_render || !out->coarse_p)
+    return fail(HGSR_ERR_INVALID_ARG, "coarse outputs are NULL");
+  if (m->query_fine && (!out->fine_query || !out->fine_render || !out->fine_p))
+    return fail(HGSR_ERR_INVALID_ARG, "fine outputs are NULL");
+  const int64_t N = static_cast<int64_t>(m->coarse_width) * m->coarse_height;
+  const int64_t n_rb = (N + kMatchRowBlock - 1) / kMatchRowBlock;
+  // workspace: vectors, norms, sums, partials, log-sum-exps, winners, flags
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t b_vec = al(N * D * 2), b_f = al(N * 4), b_part = al(n_rb * N * 4);
+  const int64_t b_scan = al((scan_block_count(N) + 16) * 4);
+  const int64_t total = 2 * b_vec + 8 * b_f + 2 * b_part + b_scan;
+  TRY(ensure(c, c->match, static_cast<size_t>(total)));
+  char* w = c->match.as<char>();
+  MatchLaunch L;
+  L.q_coarse = m->query_coarse;
+  L.r_coarse = m->render_coarse;
+  L.q_fine = m->query_fine;
+  L.r_fine = m->render_fine;
+  L.D = D;
+  L.Hc = m->coarse_height;
+  L.Wc = m->coarse_width;
+  L.nq = static_cast<int32_t>(N);
+  L.nr = static_cast<int32_t>(N);
+  L.tau_coarse = tau_coarse;
+  L.tau_fine = tau_fine;
+  L.qvec = reinterpret_cast<uint16_t*>(w); w += b_vec;
+  L.rvec = reinterpret_cast<uint16_t*>(w); w += b_vec;
+  L.qnorm = reinterpret_cast<float*>(w); w += b_f;
+  L.rnorm = reinterpret_cast<float*>(w); w += b_f;
+  L.row_sum = reinterpret_cast<float*>(w); w += b_f;
+  L.row_lse = reinterpret_cast<float*>(w); w += b_f;
+  L.col_lse = reinterpret_cast<float*>(w); w += b_f;
+  L.row_arg = reinterpret_cast<int32_t*>(w); w += b_f;
+  L.col_arg = reinterpret_cast<int32_t*>(w); w += b_f;
+  L.flag = reinterpret_cast<uint32_t*>(w); w += b_f;
+  L.col_part = reinterpret_cast<float*>(w); w += b_part;
+  L.colp_idx = reinterpret_cast<int32_t*>(w); w += b_part;
+  L.scan_tmp = reinterpret_cast<uint32_t*>(w); w += b_scan;
+  L.offs = reinterpret_cast<uint32_t*>(L.row_sum);  // the row sums are consumed before the scan writes
+  L.n_coarse = out->n_coarse;
+  L.out_cq = out->coarse_query;
+  L.out_cr = out->coarse_render;
+  L.out_cp = out->coarse_p;
+  L.out_fq = out->fine_query;
+  L.out_fr = out->fine_render;
+  L.out_fp = out->fine_p;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  launch_match(L, s);
+  HIP_TRY(hipGetLastError());
   return HGSR_OK;
 }
 

@@ -217,6 +217,41 @@ void launch_blend_bwd(const BackArgs& a, hipStream_t s);
 void launch_project_bwd(const ProjBackArgs& a, hipStream_t s);
 void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap, int P, hipStream_t s);
 
+// match.hip: coarse-to-fine probabilistic mutual matching
+struct MatchLaunch {
+  const uint16_t* q_coarse;
+  const uint16_t* r_coarse;
+  const uint16_t* q_fine;   // null: coarse level only
+  const uint16_t* r_fine;
+  int32_t D, Hc, Wc, nq, nr;
+  float tau_coarse, tau_fine;
+  // workspace
+  uint16_t* qvec;           // nq x D
+  uint16_t* rvec;           // nr x D
+  float* qnorm;
+  float* rnorm;
+  float* row_sum;           // nq
+  float* col_part;          // row blocks x nr
+  float* row_lse;           // nq
+  float* col_lse;           // nr
+  int32_t* row_arg;         // nq
+  int32_t* col_arg;         // nr
+  int32_t* colp_idx;        // row blocks x nr
+  uint32_t* flag;           // nq
+  uint32_t* offs;           // nq
+  uint32_t* scan_tmp;
+  // outputs
+  uint32_t* n_coarse;
+  int32_t* out_cq;
+  int32_t* out_cr;
+  float* out_cp;
+  int32_t* out_fq;
+  int32_t* out_fr;
+  float* out_fp;
+};
+constexpr int kMatchRowBlock = 128;
+void launch_match(const MatchLaunch& L, hipStream_t s);
+
 // score.hip
 void launch_contrib(const ContribArgs& a, int n_items, hipStream_t s);
 void launch_score(const ScoreArgs& a, hipStream_t s);

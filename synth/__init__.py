@@ -23,4 +23,5 @@ from .scenes import (  # noqa: F401
     f32_to_bf16_bits,
     bf16_bits_to_f32,
     feature_maps,
+    matching_maps,
 )

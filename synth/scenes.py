@@ -395,3 +395,24 @@ def feature_maps(count, dim, height, width, seed, layout="planar") -> np.ndarray
     if layout == "interleaved":
         m = np.ascontiguousarray(m.transpose(0, 2, 3, 1))
     return m
+
+
+def matching_maps(dim, coarse_h, coarse_w, seed, shift=(3, 5), noise=0.3):
+    """Query and rendered feature maps for coarse-to-fine matching, as bf16
+    bits: fine maps (dim, 8 coarse_h, 8 coarse_w) of N(0, 1) features, the
+    rendered one the query's moved by `shift` = (dx, dy) fine pixels plus
+    N(0, noise) (fresh features where it moves in from outside), and coarse
+    maps that are the fine maps' 8 x 8 means.  Returns (q_coarse, r_coarse,
+    q_fine, r_fine)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Hf, Wf = 8 * coarse_h, 8 * coarse_w
+    q = rng.standard_normal((dim, Hf, Wf), dtype=np.float32)
+    r = rng.standard_normal((dim, Hf, Wf), dtype=np.float32)
+    dx, dy = shift
+    ys = slice(max(dy, 0), Hf + min(dy, 0))
+    xs = slice(max(dx, 0), Wf + min(dx, 0))
+    ys_src = slice(max(-dy, 0), Hf + min(-dy, 0))
+    xs_src = slice(max(-dx, 0), Wf + min(-dx, 0))
+    r[:, ys, xs] = q[:, ys_src, xs_src] + noise * rng.standard_normal(q[:, ys_src, xs_src].shape, dtype=np.float32)
+    pool = lambda f: f.reshape(dim, coarse_h, 8, coarse_w, 8).mean(axis=(2, 4))
+    return (f32_to_bf16_bits(pool(q)), f32_to_bf16_bits(pool(r)), f32_to_bf16_bits(q), f32_to_bf16_bits(r))

@@ -55,6 +55,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Outputs) == 32
     assert ctypes.sizeof(_lib.Grads) == 56
     assert ctypes.sizeof(_lib.FeatureMaps) == 8 + 3 * 4 + 4   # pointer, width, height, layout, tail padding
+    assert ctypes.sizeof(_lib.MatchMaps) == 4 * 8 + 3 * 4 + 4  # 4 pointers, D, width, height, tail padding
+    assert ctypes.sizeof(_lib.MatchOut) == 7 * 8
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -82,3 +84,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert L.hgsr_significance_final(None, None, -1, None, None) == 1
     assert L.hgsr_significance_final(None, None, 5, None, None) == 1
     assert L.hgsr_significance_final(None, None, 0, None, None) == 0   # nothing to do
+    # matching: NULL arguments, bad D, temperatures below 1/40
+    assert L.hgsr_match(None, None, 0.1, 0.1, None, None) == 1
+    mm = _lib.MatchMaps()
+    mo = _lib.MatchOut()
+    mm.D = 12
+    assert L.hgsr_match(ctypes.c_void_p(1), ctypes.byref(mm), 0.1, 0.1, ctypes.byref(mo), None) == 1
+    mm.D, mm.coarse_width, mm.coarse_height = 32, 4, 4
+    mm.query_coarse = mm.render_coarse = 16
+    assert L.hgsr_match(ctypes.c_void_p(1), ctypes.byref(mm), 0.01, 0.1, ctypes.byref(mo), None) == 1
