@@ -637,11 +637,12 @@ hgsr_status hgsr_match(hgsr_ctx* c, const hgsr_match_maps* m, float tau_coarse, 
     return fail(HGSR_ERR_INVALID_ARG, "fine outputs are NULL");
   const int64_t N = static_cast<int64_t>(m->coarse_width) * m->coarse_height;
   const int64_t n_rb = (N + kMatchRowBlock - 1) / kMatchRowBlock;
-  // workspace: vectors, norms, sums, partials, log-sum-exps, winners, flags
+  // workspace: vectors, norms, partials, log-sum-exps, winners, flags
+  const int n_split = match_splits(static_cast<int>(N));
   auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
-  const int64_t b_vec = al(N * D * 2), b_f = al(N * 4), b_part = al(n_rb * N * 4);
+  const int64_t b_vec = al(N * D * 2), b_f = al(N * 4), b_part = al(n_rb * N * 4), b_rpart = al(n_split * N * 4);
   const int64_t b_scan = al((scan_block_count(N) + 16) * 4);
-  const int64_t total = 2 * b_vec + 8 * b_f + 2 * b_part + b_scan;
+  const int64_t total = 2 * b_vec + 8 * b_f + 2 * b_part + 2 * b_rpart + b_scan;
   TRY(ensure(c, c->match, static_cast<size_t>(total)));
   char* w = c->match.as<char>();
   MatchLaunch L;
@@ -656,20 +657,22 @@ hgsr_status hgsr_match(hgsr_ctx* c, const hgsr_match_maps* m, float tau_coarse, 
   L.nr = static_cast<int32_t>(N);
   L.tau_coarse = tau_coarse;
   L.tau_fine = tau_fine;
+  L.n_split = n_split;
   L.qvec = reinterpret_cast<uint16_t*>(w); w += b_vec;
   L.rvec = reinterpret_cast<uint16_t*>(w); w += b_vec;
   L.qnorm = reinterpret_cast<float*>(w); w += b_f;
   L.rnorm = reinterpret_cast<float*>(w); w += b_f;
-  L.row_sum = reinterpret_cast<float*>(w); w += b_f;
   L.row_lse = reinterpret_cast<float*>(w); w += b_f;
   L.col_lse = reinterpret_cast<float*>(w); w += b_f;
   L.row_arg = reinterpret_cast<int32_t*>(w); w += b_f;
   L.col_arg = reinterpret_cast<int32_t*>(w); w += b_f;
   L.flag = reinterpret_cast<uint32_t*>(w); w += b_f;
+  L.offs = reinterpret_cast<uint32_t*>(w); w += b_f;
   L.col_part = reinterpret_cast<float*>(w); w += b_part;
   L.colp_idx = reinterpret_cast<int32_t*>(w); w += b_part;
+  L.row_part = reinterpret_cast<float*>(w); w += b_rpart;
+  L.rowp_idx = reinterpret_cast<int32_t*>(w); w += b_rpart;
   L.scan_tmp = reinterpret_cast<uint32_t*>(w); w += b_scan;
-  L.offs = reinterpret_cast<uint32_t*>(L.row_sum);  // the row sums are consumed before the scan writes
   L.n_coarse = out->n_coarse;
   L.out_cq = out->coarse_query;
   L.out_cr = out->coarse_render;

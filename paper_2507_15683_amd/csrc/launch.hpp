@@ -230,13 +230,15 @@ struct MatchLaunch {
   uint16_t* rvec;           // nr x D
   float* qnorm;
   float* rnorm;
-  float* row_sum;           // nq
+  int32_t n_split;          // column ranges per row block (match_splits)
+  float* row_part;          // n_split x nq
+  int32_t* rowp_idx;        // n_split x nq
   float* col_part;          // row blocks x nr
+  int32_t* colp_idx;        // row blocks x nr
   float* row_lse;           // nq
   float* col_lse;           // nr
   int32_t* row_arg;         // nq
   int32_t* col_arg;         // nr
-  int32_t* colp_idx;        // row blocks x nr
   uint32_t* flag;           // nq
   uint32_t* offs;           // nq
   uint32_t* scan_tmp;
@@ -250,6 +252,7 @@ struct MatchLaunch {
   float* out_fp;
 };
 constexpr int kMatchRowBlock = 128;
+int match_splits(int nq);
 void launch_match(const MatchLaunch& L, hipStream_t s);
 
 // score.hip

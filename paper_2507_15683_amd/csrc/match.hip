@@ -51,48 +51,37 @@ __global__ void match_prep_kernel(const uint16_t* map, int D, int64_t n, uint16_
   norm[p] = sqrtf(ss);
 }
 
-// The tile product: acc[r] = Q_i . R_j for this lane's 16 rows
-// i = 8 (r/4) + 4 (lane/32) + r%4 of the wave's 32 and column j = lane % 32
-// of the tile.  A operands (the wave's rows) are loaded once by the caller.
-template <int D>
-__device__ __forceinline__ floatx16 tile_dot(const uint2 (&aop)[D / 8], const uint16_t* rvec, int col, int nr,
-                                             int half) {
-  floatx16 acc = {};
-#pragma unroll
-  for (int ks = 0; ks < D / 8; ++ks) {
-    uint2 bv = make_uint2(0u, 0u);
-    if (col < nr) bv = *reinterpret_cast<const uint2*>(rvec + static_cast<int64_t>(col) * D + 8 * ks + 4 * half);
-    shortx4 A, B;
-    __builtin_memcpy(&A, &aop[ks], 8);
-    __builtin_memcpy(&B, &bv, 8);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
 struct MatchArgs {
   const uint16_t* qvec;
   const uint16_t* rvec;
   const float* qnorm;
   const float* rnorm;
   int32_t nq, nr;
+  int32_t n_split;     // column ranges per row block (grid y)
+  int32_t split_cols;  // columns per range (a multiple of 128)
   float inv_tau;       // 1 / tau
-  float* row_sum;      // stats: sum_j exp(S_ij - 1/tau)
-  float* col_part;     // stats: per (row block, column) partial sums
+  float* row_part;     // stats: per (range, row) sums; argmax: per (range, row) best values
+  int32_t* rowp_idx;   // argmax: per (range, row) best column
+  float* col_part;     // stats: per (row block, column) sums; argmax: best values
+  int32_t* colp_idx;   // argmax: per (row block, column) best row
   const float* row_lse;  // argmax: a_i
   const float* col_lse;  // argmax: b_j
-  int32_t* row_arg;    // argmax: best column per row
-  float* colp_val;     // argmax: per (row block, column) best value
-  int32_t* colp_idx;   //          and its row
 };
 
+constexpr int kTilesPerRound = 2;  // column tiles of 32 per LDS combine
+
+// Stats (ARGMAX false) or argmax (true) over the column range
+// [blockIdx.y * split_cols, + split_cols) for the workgroup's 128 rows.
 template <int D, bool ARGMAX>
 __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
-  __shared__ float s_cv[4][32];
-  __shared__ int32_t s_ci[4][32];
+  constexpr int RC = 32 * kTilesPerRound;  // columns per round
+  __shared__ float s_cv[4][RC];
+  __shared__ int32_t s_ci[4][RC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, cl = lane & 31;
-  const int rb = blockIdx.x;
+  const int rb = blockIdx.x, sp = blockIdx.y;
   const int row0 = rb * kRowBlock + wave * 32;
+  const int c_begin = sp * a.split_cols;
+  const int c_end = min(a.nr, c_begin + a.split_cols);
   // A operands: row row0 + cl, channels 8 ks + 4 half .. + 3
   uint2 aop[D / 8];
 #pragma unroll
@@ -109,61 +98,81 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
     const int i = row0 + 8 * (r / 4) + 4 * half + (r % 4);
     rv[r] = i < a.nq;
     nq[r] = rv[r] ? a.qnorm[i] : 1.f;
-    rs[r] = 0.f;
+    rs[r] = ARGMAX ? -INFINITY : 0.f;  // stats: sum; argmax: best value of 2 S - b
     ra[r] = ARGMAX && rv[r] ? a.row_lse[i] : 0.f;
     ri[r] = -1;
-    if (ARGMAX) rs[r] = -INFINITY;  // best value of 2 S - b
   }
   const float k1 = kLog2e * a.inv_tau;
-  for (int c0 = 0; c0 < a.nr; c0 += 32) {
-    const int col = c0 + cl;
-    const bool cv = col < a.nr;
-    const floatx16 acc = tile_dot<D>(aop, a.rvec, col, a.nr, half);
-    const float nr = cv ? a.rnorm[col] : 1.f;
-    const float cb = ARGMAX && cv ? a.col_lse[col] : 0.f;
-    float cacc = ARGMAX ? -INFINITY : 0.f;
-    int32_t cidx = -1;
+  const float two_tau = 2.f * a.inv_tau;
+  for (int c0 = c_begin; c0 < c_end; c0 += RC) {
+    // this round's B operands, all loads in flight before the first product
+    uint2 bop[kTilesPerRound][D / 8];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float m = acc[r] * __builtin_amdgcn_rcpf(fmaf(nq[r], nr, kCosEps));  // cosine
-      const bool ok = rv[r] && cv;
+    for (int t = 0; t < kTilesPerRound; ++t) {
+      const int col = c0 + 32 * t + cl;
+#pragma unroll
+      for (int ks = 0; ks < D / 8; ++ks) {
+        bop[t][ks] = make_uint2(0u, 0u);
+        if (col < c_end)
+          bop[t][ks] = *reinterpret_cast<const uint2*>(a.rvec + static_cast<int64_t>(col) * D + 8 * ks + 4 * half);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kTilesPerRound; ++t) {
+      const int col = c0 + 32 * t + cl;
+      const bool cv = col < c_end;
+      floatx16 acc = {};
+#pragma unroll
+      for (int ks = 0; ks < D / 8; ++ks) {
+        shortx4 A, B;
+        __builtin_memcpy(&A, &aop[ks], 8);
+        __builtin_memcpy(&B, &bop[t][ks], 8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, acc, 0, 0, 0);
+      }
+      const float nr = cv ? a.rnorm[col] : 1.f;
+      const float cb = ARGMAX && cv ? a.col_lse[col] : 0.f;
+      float cacc = ARGMAX ? -INFINITY : 0.f;
+      int32_t cidx = -1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float m = acc[r] * __builtin_amdgcn_rcpf(fmaf(nq[r], nr, kCosEps));  // cosine
+        const bool ok = rv[r] && cv;
+        if constexpr (!ARGMAX) {
+          // exp(S - 1/tau) = 2^((m - 1) log2(e) / tau)
+          const float e = ok ? __builtin_amdgcn_exp2f(fmaf(m, k1, -k1)) : 0.f;
+          rs[r] += e;
+          cacc += e;
+        } else {
+          const float vr = fmaf(m, two_tau, -cb);     // row i's objective 2 S - b at column j
+          const float vc = fmaf(m, two_tau, -ra[r]);  // column j's objective 2 S - a at row i
+          if (ok && vr > rs[r]) {       // a lane's columns arrive in increasing order
+            rs[r] = vr;
+            ri[r] = col;
+          }
+          if (ok && vc > cacc) {        // a lane's rows increase with r
+            cacc = vc;
+            cidx = row0 + 8 * (r / 4) + 4 * half + (r % 4);
+          }
+        }
+      }
+      // the column over this wave's 32 rows: combine the two lane halves
       if constexpr (!ARGMAX) {
-        // exp(S - 1/tau) = 2^((m - 1) log2(e) / tau)
-        const float e = ok ? __builtin_amdgcn_exp2f(fmaf(m, k1, -k1)) : 0.f;
-        rs[r] += e;
-        cacc += e;
+        cacc += __shfl_xor(cacc, 32, 64);
       } else {
-        const float s2 = 2.f * m * a.inv_tau;
-        const float vr = s2 - cb;       // row i's objective at column j
-        const float vc = s2 - ra[r];    // column j's objective at row i
-        if (ok && vr > rs[r]) {         // columns arrive in increasing order per lane
-          rs[r] = vr;
-          ri[r] = col;
-        }
-        const int i = row0 + 8 * (r / 4) + 4 * half + (r % 4);
-        if (ok && vc > cacc) {          // rows increase with r within a lane
-          cacc = vc;
-          cidx = i;
+        const float ov = __shfl_xor(cacc, 32, 64);
+        const int32_t oi = __shfl_xor(cidx, 32, 64);
+        if (oi >= 0 && (cidx < 0 || ov > cacc || (ov == cacc && oi < cidx))) {
+          cacc = ov;
+          cidx = oi;
         }
       }
-    }
-    // the column over this wave's 32 rows: combine the two lane halves
-    if constexpr (!ARGMAX) {
-      cacc += __shfl_xor(cacc, 32, 64);
-    } else {
-      const float ov = __shfl_xor(cacc, 32, 64);
-      const int32_t oi = __shfl_xor(cidx, 32, 64);
-      if (ov > cacc || (ov == cacc && oi >= 0 && (cidx < 0 || oi < cidx))) {
-        cacc = ov;
-        cidx = oi;
+      if (half == 0) {
+        s_cv[wave][32 * t + cl] = cacc;
+        s_ci[wave][32 * t + cl] = cidx;
       }
-    }
-    if (half == 0) {
-      s_cv[wave][cl] = cacc;
-      s_ci[wave][cl] = cidx;
     }
     __syncthreads();
-    if (tid < 32 && c0 + tid < a.nr) {
+    if (tid < RC && c0 + tid < c_end) {
       const int64_t o = static_cast<int64_t>(rb) * a.nr + c0 + tid;
       if constexpr (!ARGMAX) {
         a.col_part[o] = s_cv[0][tid] + s_cv[1][tid] + s_cv[2][tid] + s_cv[3][tid];
@@ -177,13 +186,13 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
             bi = s_ci[w][tid];
           }
         }
-        a.colp_val[o] = bv;
+        a.col_part[o] = bv;
         a.colp_idx[o] = bi;
       }
     }
     __syncthreads();
   }
-  // rows: combine the 32 lanes of each half (columns cl + 32 t)
+  // rows: combine the 32 lanes of each half (the lanes hold different columns)
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     float v = rs[r];
@@ -201,39 +210,70 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
     }
     const int i = row0 + 8 * (r / 4) + 4 * half + (r % 4);
     if (cl == 0 && rv[r]) {
-      if constexpr (!ARGMAX) a.row_sum[i] = v;
-      else a.row_arg[i] = idx;
+      a.row_part[static_cast<int64_t>(sp) * a.nq + i] = v;
+      if constexpr (ARGMAX) a.rowp_idx[static_cast<int64_t>(sp) * a.nq + i] = idx;
     }
   }
 }
 
-// Row and column log-sum-exps: a_i = 1/tau + log(row sum), b_j likewise from
-// the partials (summed over the row blocks in order).
-__global__ void match_lse_kernel(MatchArgs a, int n_rb, float* row_lse, float* col_lse) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < a.nq) row_lse[t] = a.inv_tau + __logf(a.row_sum[t]);
-  if (t < a.nr) {
-    float s = 0.f;
-    for (int b = 0; b < n_rb; ++b) s += a.col_part[static_cast<int64_t>(b) * a.nr + t];
-    col_lse[t] = a.inv_tau + __logf(s);
-  }
-}
-
-// Column winners from the per-row-block partials, then the mutual flags.
-__global__ void match_colarg_kernel(MatchArgs a, int n_rb, int32_t* col_arg) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= a.nr) return;
-  float bv = -INFINITY;
+// Reductions of the partials, 8 threads per row or column (partials k, k+8,
+// ...; then combined in a fixed order): the log-sum-exps
+// a_i = 1/tau + log(sum), b_j likewise (STATS), or the best column per row
+// and best row per column (ties: lowest index).
+template <bool STATS>
+__global__ __launch_bounds__(256) void match_reduce_kernel(MatchArgs a, int n_rb, float* row_lse, float* col_lse,
+                                                           int32_t* row_arg, int32_t* col_arg) {
+  __shared__ float s_v[32][8];
+  __shared__ int32_t s_i[32][8];
+  const int part = threadIdx.x & 7, slot = threadIdx.x >> 3;
+  const int64_t u = static_cast<int64_t>(blockIdx.x) * 32 + slot;  // rows first, then columns
+  const bool is_row = u < a.nq;
+  const int64_t x = is_row ? u : u - a.nq;
+  const bool live = is_row || x < a.nr;
+  const int n = is_row ? a.n_split : n_rb;
+  const int64_t stride = is_row ? a.nq : a.nr;
+  const float* vals = is_row ? a.row_part : a.col_part;
+  const int32_t* idxs = is_row ? a.rowp_idx : a.colp_idx;
+  float v = STATS ? 0.f : -INFINITY;
   int32_t bi = -1;
-  for (int b = 0; b < n_rb; ++b) {  // row blocks hold increasing rows
-    const int64_t o = static_cast<int64_t>(b) * a.nr + j;
-    const int32_t i = a.colp_idx[o];
-    if (i >= 0 && a.colp_val[o] > bv) {
-      bv = a.colp_val[o];
-      bi = i;
+  if (live) {
+    for (int k = part; k < n; k += 8) {
+      const float w = vals[k * stride + x];
+      if constexpr (STATS) {
+        v += w;
+      } else {
+        const int32_t wi = idxs[k * stride + x];  // partials in increasing index order
+        if (wi >= 0 && (bi < 0 || w > v)) {
+          v = w;
+          bi = wi;
+        }
+      }
     }
   }
-  col_arg[j] = bi;
+  s_v[slot][part] = v;
+  s_i[slot][part] = bi;
+  __syncthreads();
+  if (part == 0 && live) {
+    float t = STATS ? 0.f : -INFINITY;
+    int32_t ti = -1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if constexpr (STATS) {
+        t += s_v[slot][q];
+      } else {
+        const int32_t qi = s_i[slot][q];
+        if (qi >= 0 && (ti < 0 || s_v[slot][q] > t || (s_v[slot][q] == t && qi < ti))) {
+          t = s_v[slot][q];
+          ti = qi;
+        }
+      }
+    }
+    if constexpr (STATS) {
+      (is_row ? row_lse : col_lse)[x] = a.inv_tau + __logf(t);
+    } else {
+      (is_row ? row_arg : col_arg)[x] = ti;
+    }
+  }
 }
 
 __global__ void match_flag_kernel(const int32_t* row_arg, const int32_t* col_arg, int nq, uint32_t* flag) {
@@ -245,11 +285,12 @@ __global__ void match_flag_kernel(const int32_t* row_arg, const int32_t* col_arg
 
 // P_ij of each correspondence (the cosine recomputed in FP32), compacted.
 template <int D>
-__global__ void match_emit_kernel(MatchArgs a, const uint32_t* flag, const uint32_t* offs, const float* row_lse,
-                                  const float* col_lse, int32_t* out_q, int32_t* out_r, float* out_p) {
+__global__ void match_emit_kernel(MatchArgs a, const int32_t* row_arg, const uint32_t* flag, const uint32_t* offs,
+                                  const float* row_lse, const float* col_lse, int32_t* out_q, int32_t* out_r,
+                                  float* out_p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.nq || !flag[i]) return;
-  const int32_t j = a.row_arg[i];
+  const int32_t j = row_arg[i];
   float dot = 0.f;
   for (int d = 0; d < D; ++d) {
     const float x = __uint_as_float(static_cast<uint32_t>(a.qvec[static_cast<int64_t>(i) * D + d]) << 16);
@@ -282,7 +323,8 @@ struct FineArgs {
 template <int D>
 __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
   constexpr int WW = 64, w = 8;
-  __shared__ float s_r[WW][D + 1];   // render window vectors (FP32)
+  constexpr int RS = D + 4;            // row stride: 16-byte aligned rows
+  __shared__ float s_r[WW * RS];       // render window vectors (FP32)
   __shared__ float s_m[WW][WW + 1];  // the window's cosines [query][render]
   __shared__ float s_rn[WW];
   __shared__ float s_cl[WW];         // column log-sum-exps
@@ -303,7 +345,7 @@ __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
     q[d] = __uint_as_float(static_cast<uint32_t>(a.qf[d * a.plane + qpix]) << 16);
     qq = fmaf(q[d], q[d], qq);
     const float rv = __uint_as_float(static_cast<uint32_t>(a.rf[d * a.plane + rpix]) << 16);
-    s_r[t][d] = rv;
+    s_r[t * RS + d] = rv;
     rr = fmaf(rv, rv, rr);
   }
   const float nq = sqrtf(qq);
@@ -313,9 +355,16 @@ __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
   float mx = -INFINITY;
   for (int j = 0; j < WW; ++j) {
     float dot = 0.f;
+    const float4* rj = reinterpret_cast<const float4*>(&s_r[j * RS]);  // the same address in every lane
 #pragma unroll
-    for (int d = 0; d < D; ++d) dot = fmaf(q[d], s_r[j][d], dot);
-    const float m = dot / fmaf(nq, s_rn[j], kCosEps);
+    for (int d4 = 0; d4 < D / 4; ++d4) {
+      const float4 v = rj[d4];
+      dot = fmaf(q[4 * d4 + 0], v.x, dot);
+      dot = fmaf(q[4 * d4 + 1], v.y, dot);
+      dot = fmaf(q[4 * d4 + 2], v.z, dot);
+      dot = fmaf(q[4 * d4 + 3], v.w, dot);
+    }
+    const float m = dot * __builtin_amdgcn_rcpf(fmaf(nq, s_rn[j], kCosEps));
     s_m[t][j] = m;
     mx = fmaxf(mx, m);
   }
@@ -368,6 +417,30 @@ __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
 }
 
 // ------------------------------------------------------------ launchers
+int match_splits(int nq) {
+  // enough workgroups to fill the chip: about 2048 (row block, column range)
+  const int n_rb = (nq + kRowBlock - 1) / kRowBlock;
+  int sp = (2048 + n_rb - 1) / n_rb;
+  return sp < 1 ? 1 : (sp > 32 ? 32 : sp);
+}
+
+template <int D>
+static void launch_passes(MatchArgs a, const MatchLaunch& L, int n_rb, hipStream_t s) {
+  const dim3 grid(n_rb, a.n_split);
+  const int nred = (a.nq + a.nr + 31) / 32;
+  hipLaunchKernelGGL((match_pass_kernel<D, false>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(match_reduce_kernel<true>, dim3(nred), dim3(256), 0, s, a, n_rb, L.row_lse, L.col_lse,
+                     L.row_arg, L.col_arg);
+  hipLaunchKernelGGL((match_pass_kernel<D, true>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(match_reduce_kernel<false>, dim3(nred), dim3(256), 0, s, a, n_rb, L.row_lse, L.col_lse,
+                     L.row_arg, L.col_arg);
+  hipLaunchKernelGGL(match_flag_kernel, dim3((a.nq + 255) / 256), dim3(256), 0, s, L.row_arg, L.col_arg, a.nq,
+                     L.flag);
+  launch_scan(L.flag, a.nq, L.offs, nullptr, L.scan_tmp, L.n_coarse, ~0ull, nullptr, 0, s);
+  hipLaunchKernelGGL((match_emit_kernel<D>), dim3((a.nq + 255) / 256), dim3(256), 0, s, a, L.row_arg, L.flag,
+                     L.offs, L.row_lse, L.col_lse, L.out_cq, L.out_cr, L.out_cp);
+}
+
 void launch_match(const MatchLaunch& L, hipStream_t s) {
   const int nq = L.nq, nr = L.nr, D = L.D;
   const int n_rb = (nq + kRowBlock - 1) / kRowBlock;
@@ -382,40 +455,22 @@ void launch_match(const MatchLaunch& L, hipStream_t s) {
   a.rnorm = L.rnorm;
   a.nq = nq;
   a.nr = nr;
+  a.n_split = L.n_split;
+  const int tiles = (nr + 31) / 32;
+  const int per = (tiles + a.n_split - 1) / a.n_split;
+  a.split_cols = (per + kTilesPerRound - 1) / kTilesPerRound * kTilesPerRound * 32;
   a.inv_tau = 1.f / L.tau_coarse;
-  a.row_sum = L.row_sum;
+  a.row_part = L.row_part;
+  a.rowp_idx = L.rowp_idx;
   a.col_part = L.col_part;
+  a.colp_idx = L.colp_idx;
   a.row_lse = L.row_lse;
   a.col_lse = L.col_lse;
-  a.row_arg = L.row_arg;
-  a.colp_val = L.col_part;  // the stats partials are dead once reduced
-  a.colp_idx = L.colp_idx;
   switch (D) {
-    case 8: hipLaunchKernelGGL((match_pass_kernel<8, false>), dim3(n_rb), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((match_pass_kernel<16, false>), dim3(n_rb), dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((match_pass_kernel<64, false>), dim3(n_rb), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((match_pass_kernel<32, false>), dim3(n_rb), dim3(256), 0, s, a); break;
-  }
-  const int nmax = nq > nr ? nq : nr;
-  hipLaunchKernelGGL(match_lse_kernel, dim3((nmax + 255) / 256), dim3(256), 0, s, a, n_rb, L.row_lse, L.col_lse);
-  switch (D) {
-    case 8: hipLaunchKernelGGL((match_pass_kernel<8, true>), dim3(n_rb), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((match_pass_kernel<16, true>), dim3(n_rb), dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((match_pass_kernel<64, true>), dim3(n_rb), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((match_pass_kernel<32, true>), dim3(n_rb), dim3(256), 0, s, a); break;
-  }
-  hipLaunchKernelGGL(match_colarg_kernel, dim3((nr + 255) / 256), dim3(256), 0, s, a, n_rb, L.col_arg);
-  hipLaunchKernelGGL(match_flag_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, L.row_arg, L.col_arg, nq, L.flag);
-  launch_scan(L.flag, nq, L.offs, nullptr, L.scan_tmp, L.n_coarse, ~0ull, nullptr, 0, s);
-  switch (D) {
-    case 8: hipLaunchKernelGGL((match_emit_kernel<8>), dim3((nq + 255) / 256), dim3(256), 0, s, a, L.flag, L.offs,
-                               L.row_lse, L.col_lse, L.out_cq, L.out_cr, L.out_cp); break;
-    case 16: hipLaunchKernelGGL((match_emit_kernel<16>), dim3((nq + 255) / 256), dim3(256), 0, s, a, L.flag, L.offs,
-                                L.row_lse, L.col_lse, L.out_cq, L.out_cr, L.out_cp); break;
-    case 64: hipLaunchKernelGGL((match_emit_kernel<64>), dim3((nq + 255) / 256), dim3(256), 0, s, a, L.flag, L.offs,
-                                L.row_lse, L.col_lse, L.out_cq, L.out_cr, L.out_cp); break;
-    default: hipLaunchKernelGGL((match_emit_kernel<32>), dim3((nq + 255) / 256), dim3(256), 0, s, a, L.flag, L.offs,
-                                L.row_lse, L.col_lse, L.out_cq, L.out_cr, L.out_cp); break;
+    case 8: launch_passes<8>(a, L, n_rb, s); break;
+    case 16: launch_passes<16>(a, L, n_rb, s); break;
+    case 64: launch_passes<64>(a, L, n_rb, s); break;
+    default: launch_passes<32>(a, L, n_rb, s); break;
   }
   if (!L.q_fine) return;
   FineArgs f;
