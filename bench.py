@@ -230,7 +230,7 @@ def fwd_bwd(hg, torch, synth, args):
     # batched: autotune, size, capture one step, replay
     r = hg.Renderer()
     st = refine_state(hg, torch, r, scene, K, torch.from_numpy(P).cuda(), tgt_rgb, tgt_feat)
-    tuned = r.autotune(scene, st["poses"], K, st["out"])
+    tuned = r.autotune(scene, st["poses"], K, st["out"], with_backward=True)
     log("bench: autotuned (64 poses)", tuned)
     opts = r.opts(tile=0, schedule="auto")
     r.render(scene, st["poses"], K, tile=0, schedule="auto", out=st["out"])
@@ -447,7 +447,7 @@ def partitioned(hg, torch, synth, args):
         tgt_rgb, tgt_feat = tgt["rgb"].clone(), tgt["feat"].clone()
         del tgt
         st = refine_state(hg, torch, r, scene, K, poses, tgt_rgb, tgt_feat)
-        tuned = r.autotune(scene, poses, K, st["out"])
+        tuned = r.autotune(scene, poses, K, st["out"], with_backward=True)
         opts = r.opts(tile=0, schedule="auto")
         r.render(scene, poses, K, tile=0, schedule="auto", out=st["out"])
         reserve_headroom(r, NQ, K, sc.n)

@@ -383,10 +383,14 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges,
  * the context's default (opts->tile == 0, opts->schedule == HGSR_SCHED_AUTO,
  * opts->feat_accum == HGSR_FEAT_AUTO) and append it to the JSON-lines cache
  * file `cache_path` (host string, may be NULL), which later calls on the same
- * shape read instead of timing.  Synchronises `stream`. */
+ * shape read instead of timing.  with_backward != 0 times each render
+ * followed by the pose backward (dL/drgb and, for FP32 feature maps,
+ * dL/dfeat taken as the rendered maps themselves), the cost of a refinement
+ * step, instead of the render alone.  Synchronises `stream`. */
 hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream);
+                          int32_t with_backward, const char* cache_path, hgsr_tune_result* result,
+                          hgsr_stream stream);
 
 /* Stage timing.  While enabled, hgsr_render records HIP events on its
  * stream around its stages (0: projection, 1: tile binning and sort,

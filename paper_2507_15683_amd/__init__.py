@@ -352,17 +352,20 @@ class Renderer:
         return out
 
     def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
-                 feat_bf16=False, cache_path: Optional[str] = None, stream=None) -> dict:
+                 feat_bf16=False, with_backward: bool = False, cache_path: Optional[str] = None,
+                 stream=None) -> dict:
         """Time tile sizes 8/16/32, the blend schedules and the feature
-        accumulations on this input; the winner becomes this renderer's
-        default for tile=0 / schedule="auto" / feat_accum="auto"."""
+        accumulations on this input (with_backward: each render followed by
+        the pose backward, the cost of a refinement step); the winner becomes
+        this renderer's default for tile=0 / schedule="auto" /
+        feat_accum="auto"."""
         g = scene.c()
         kc = K.c()
         opts = self.opts(16, sort, "grid", feat_bf16=feat_bf16)
         o = _lib.Outputs(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["feat"]))
         res = _lib.TuneResult()
         check(self.lib.hgsr_autotune(self.ctx, ctypes.byref(g), _ptr(poses), poses.shape[0], ctypes.byref(kc),
-                                     ctypes.byref(opts), ctypes.byref(o),
+                                     ctypes.byref(opts), ctypes.byref(o), int(with_backward),
                                      None if cache_path is None else cache_path.encode(), ctypes.byref(res),
                                      _stream_ptr(stream)), "hgsr_autotune")
         return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule],

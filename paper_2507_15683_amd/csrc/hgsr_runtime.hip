@@ -77,7 +77,7 @@ struct hgsr_ctx {
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
       gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
-      match;
+      match, tune;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -455,7 +455,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match};
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match, &c->tune};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -1008,14 +1008,27 @@ hgsr_status hgsr_pose_adam(float* poses, const float* grad, float* m, float* v, 
 
 hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
                           const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                          const char* cache_path, hgsr_tune_result* result, hgsr_stream stream) {
+                          int32_t with_backward, const char* cache_path, hgsr_tune_result* result,
+                          hgsr_stream stream) {
   if (!c || !g || !K || !opts || !out) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   if (c->capturing) return fail(HGSR_ERR_STATE, "cannot autotune while capturing");
+  if (P <= 0) return fail(HGSR_ERR_INVALID_ARG, "need at least one pose");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  auto run = [&](const hgsr_opts* o) { return hgsr_render(c, g, poses, P, K, o, out, stream); };
+  if (with_backward) TRY(ensure(c, c->tune, static_cast<size_t>(P) * 6 * sizeof(float)));
+  auto run = [&](const hgsr_opts* o) -> hgsr_status {
+    TRY(hgsr_render(c, g, poses, P, K, o, out, stream));
+    if (!with_backward) return HGSR_OK;
+    // the refinement step's backward: pose gradient of a loss whose output
+    // gradients are the rendered maps themselves (nonzero, right shapes)
+    const bool f32feat = g->feat_dim > 0 && out->feat && !o->feat_out_bf16;
+    const hgsr_grad_outputs go = {out->rgb, nullptr, nullptr, f32feat ? static_cast<const float*>(out->feat) : nullptr};
+    hgsr_grads gr{};
+    gr.pose = c->tune.as<float>();
+    return hgsr_render_backward(c, &go, &gr, stream);
+  };
   char key[256];
-  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d\"", K->width, K->height, P,
-           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode);
+  snprintf(key, sizeof(key), "\"key\": \"gfx950/%dx%d/P%d/n%lld/D%d/sh%d/sort%d/bwd%d\"", K->width, K->height, P,
+           static_cast<long long>(g->n), g->feat_dim, g->sh_degree, opts->sort_mode, with_backward ? 1 : 0);
   // cached answer?
   if (cache_path) {
     FILE* f = fopen(cache_path, "r");

@@ -283,3 +283,13 @@ def test_autotune_choice_and_cache(hg, tmp_path):
     res2 = r2.autotune(scene, _poses(Ps), K, out, cache_path=cache)
     assert (res2["tile"], res2["schedule"], res2["feat_accum"]) == (res["tile"], res["schedule"], res["feat_accum"])
     assert abs(res2["ms"] - res["ms"]) < 1e-4
+    # tuned on the refinement step's cost (render + pose backward): its own
+    # cache entry, and a time that includes the backward
+    rb = hg.Renderer()
+    resb = rb.autotune(scene, _poses(Ps), K, out, with_backward=True, cache_path=cache)
+    log("tuned with backward", resb)
+    assert resb["tile"] in (8, 16, 32) and resb["ms"] > res["ms"]
+    rb2 = hg.Renderer()
+    resb2 = rb2.autotune(scene, _poses(Ps), K, out, with_backward=True, cache_path=cache)
+    assert (resb2["tile"], resb2["schedule"]) == (resb["tile"], resb["schedule"])
+    assert abs(resb2["ms"] - resb["ms"]) < 1e-4
