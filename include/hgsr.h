@@ -347,6 +347,67 @@ typedef struct {
 hgsr_status hgsr_match(hgsr_ctx* ctx, const hgsr_match_maps* maps, float tau_coarse, float tau_fine,
                        const hgsr_match_out* out, hgsr_stream stream);
 
+/* A 2D-3D pose problem for hgsr_pnp (device arrays): query pixel coordinates
+ * p2d (n x 2, pixel centres at +0.5) and world points x3d (n x 3), e.g. the
+ * fine correspondences with hgsr_backproject's points; samples (n_hyp x 3)
+ * are the RANSAC draws, indices into the n correspondences (given by the
+ * caller, so that runs are reproducible); tau the inlier threshold in
+ * pixels; gn_iters Gauss-Newton steps per hypothesis, refine_iters steps of
+ * the final refinement. */
+typedef struct {
+  const float* p2d;
+  const float* x3d;
+  int64_t n;
+  const int32_t* samples;
+  int32_t n_hyp;
+  float tau;
+  int32_t gn_iters;
+  int32_t refine_iters;
+} hgsr_pnp_problem;
+
+/* Results of hgsr_pnp (device, caller-allocated): pose (12 floats, the
+ * refined world -> camera [R|t]); best (1 int32, the winning hypothesis, -1
+ * when no sample was valid); counts (n_hyp int32: inliers per hypothesis, -1
+ * for a degenerate sample); hyp_poses (n_hyp x 12, or NULL); inliers (n
+ * bytes, or NULL: 1 for the final pose's inliers); n_inliers (1 int32). */
+typedef struct {
+  float* pose;
+  int32_t* best;
+  int32_t* counts;
+  float* hyp_poses;
+  uint8_t* inliers;
+  int32_t* n_inliers;
+} hgsr_pnp_result;
+
+/* Pose from 2D-3D correspondences (Sec. 3.4, Eq. 10): argmin over [R|t] of
+ * sum_i rho(|p_i - pi(K [R|t] X_i)|, tau), rho the truncated quadratic
+ * min(e^2, tau^2), by RANSAC.  Each sample of 3 correspondences is solved by
+ * gn_iters Gauss-Newton steps from the prior pose pose0 (device, 12 floats:
+ * the render pose) with the left update T <- Exp(delta) T; a sample with a
+ * singular normal matrix is invalid; every hypothesis is scored by its
+ * number of correspondences with positive depth and reprojection error
+ * below tau (ties: lowest index); the best is refined by refine_iters
+ * Gauss-Newton steps on its inlier set, re-taken before every step.
+ * Everything runs on the device (capturable). */
+hgsr_status hgsr_pnp(hgsr_ctx* ctx, const hgsr_pnp_problem* problem, const hgsr_intrinsics* K, const float* pose0,
+                     const hgsr_pnp_result* result, hgsr_stream stream);
+
+/* World points of rendered pixels (Sec. 3.4 lifts the rendered matches with
+ * the rendered depth): x3d[i] = R^T (d K^-1 [u, v, 1]^T - t) for pixel pix[i]
+ * (row-major index into the width x height depth map, centre (u, v) =
+ * (x + 0.5, y + 0.5)), its depth d and the render pose [R|t] (device, 12
+ * floats).  Out-of-range pixels give (0, 0, 0). */
+hgsr_status hgsr_backproject(const float* depth, int32_t width, int32_t height, const float* pose,
+                             const hgsr_intrinsics* K, const int32_t* pix, int64_t n, float* x3d,
+                             hgsr_stream stream);
+
+/* Pose consistency verification (Algorithm 2): for the n dense results
+ * poses (device, n x 12), the rotation angle of R_i R_{i+1}^T (trace clamped
+ * to [-1, 3]) for every consecutive pair; reliable (device int32) is 1 when
+ * none exceeds tau_deg; max_angle (device float, or NULL) the largest. */
+hgsr_status hgsr_pose_consistency(const float* poses, int32_t n, float tau_deg, int32_t* reliable,
+                                  float* max_angle, hgsr_stream stream);
+
 /* Fill part_bounds (device, n_parts x 6) with a box containing, for every
  * Gaussian of each partition, the ball of radius 3.33 x its largest scale
  * around its mean (the 1/255 support of the most opaque Gaussian). */

@@ -129,6 +129,10 @@ def pnp_ransac(p2d, X3d, K, pose0, samples, tau=2.0, gn_iters=10, refine_iters=1
         e = errors(T, K, X, p)
         hyp_err[h] = e
         counts[h] = int((e < tau).sum())
+    if not valid.any():          # no hypothesis: the prior pose, no refinement
+        inl = errors(T0, K, X, p) < tau
+        return dict(pose=T0[:3, :].copy(), best=-1, counts=np.where(valid, counts, -1), valid=valid, hyps=hyps,
+                    inliers=inl, hyp_err=hyp_err)
     best = int(np.argmax(np.where(valid, counts, -1)))
     T = np.eye(4)
     T[:3, :] = hyps[best]
@@ -139,8 +143,8 @@ def pnp_ransac(p2d, X3d, K, pose0, samples, tau=2.0, gn_iters=10, refine_iters=1
             break
         T = Tn
     inl = errors(T, K, X, p) < tau
-    return dict(pose=T[:3, :].copy(), best=best, counts=counts, valid=valid, hyps=hyps, inliers=inl,
-                hyp_err=hyp_err)
+    return dict(pose=T[:3, :].copy(), best=best, counts=np.where(valid, counts, -1), valid=valid, hyps=hyps,
+                inliers=inl, hyp_err=hyp_err)
 
 
 def rotation_angle_deg(T1, T2) -> float:

@@ -351,6 +351,38 @@ class Renderer:
                                   _stream_ptr(stream)), "hgsr_match")
         return out
 
+    def pnp(self, p2d: torch.Tensor, x3d: torch.Tensor, K: Intrinsics, pose0: torch.Tensor, samples: torch.Tensor,
+            tau: float = 2.0, gn_iters: int = 10, refine_iters: int = 10, want_hyps: bool = False,
+            want_inliers: bool = True, stream=None) -> dict:
+        """Pose from 2D-3D correspondences (Sec. 3.4, Eq. 10) by RANSAC over
+        the given 3-point samples and truncated-quadratic refinement, on the
+        device.  p2d (n, 2), x3d (n, 3), pose0 (12,) float32; samples
+        (n_hyp, 3) int32.  Returns dict(pose (12,), best, counts (n_hyp,),
+        n_inliers, inliers (n,) uint8 or None, hyp_poses or None)."""
+        for t, shp in ((p2d, 2), (x3d, 3)):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != shp:
+                raise ValueError("p2d must be (n, 2) and x3d (n, 3) contiguous float32 device tensors")
+        if p2d.shape[0] != x3d.shape[0]:
+            raise ValueError("p2d and x3d must hold the same number of correspondences")
+        if samples.dtype != torch.int32 or not samples.is_contiguous() or samples.dim() != 2 or samples.shape[1] != 3:
+            raise ValueError("samples must be a contiguous (n_hyp, 3) int32 device tensor")
+        dev = p2d.device
+        n, H = p2d.shape[0], samples.shape[0]
+        out = dict(pose=torch.empty(12, dtype=torch.float32, device=dev),
+                   best=torch.empty(1, dtype=torch.int32, device=dev),
+                   counts=torch.empty(H, dtype=torch.int32, device=dev),
+                   n_inliers=torch.empty(1, dtype=torch.int32, device=dev),
+                   inliers=torch.empty(n, dtype=torch.uint8, device=dev) if want_inliers else None,
+                   hyp_poses=torch.empty((H, 12), dtype=torch.float32, device=dev) if want_hyps else None)
+        pose0 = _f32(pose0).reshape(12).contiguous()
+        pb = _lib.PnpProblem(_ptr(p2d), _ptr(x3d), n, _ptr(samples), H, tau, gn_iters, refine_iters)
+        pr = _lib.PnpResult(*[_ptr(out[k]) for k in ("pose", "best", "counts", "hyp_poses", "inliers", "n_inliers")])
+        kc = K.c()
+        self._keep_pnp = (p2d, x3d, samples, pose0, out)
+        check(self.lib.hgsr_pnp(self.ctx, ctypes.byref(pb), ctypes.byref(kc), _ptr(pose0), ctypes.byref(pr),
+                                _stream_ptr(stream)), "hgsr_pnp")
+        return out
+
     def autotune(self, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics, out: dict, sort="bucket",
                  feat_bf16=False, with_backward: bool = False, cache_path: Optional[str] = None,
                  stream=None) -> dict:
@@ -472,6 +504,32 @@ def significance_final(score_sum: torch.Tensor, vis_count: torch.Tensor, out: Op
     check(_lib.load().hgsr_significance_final(_ptr(score_sum), _ptr(vis_count), score_sum.numel(), _ptr(out),
                                          _stream_ptr(stream)), "hgsr_significance_final")
     return out
+
+
+def backproject(depth: torch.Tensor, pose: torch.Tensor, K: Intrinsics, pix: torch.Tensor,
+                out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """World points (n, 3) of rendered pixels pix (n,) int32 (row-major in
+    the (H, W) depth map) under the render pose (12,)."""
+    H, W = depth.shape[-2:]
+    n = pix.numel()
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=depth.device)
+    pose = _f32(pose).reshape(12).contiguous()
+    kc = K.c()
+    check(_lib.load().hgsr_backproject(_ptr(_f32(depth)), W, H, _ptr(pose), ctypes.byref(kc), _ptr(pix), n,
+                                       _ptr(out), _stream_ptr(stream)), "hgsr_backproject")
+    return out
+
+
+def pose_consistency(poses: torch.Tensor, tau_deg: float = 20.0, stream=None):
+    """Algorithm 2 over consecutive dense results poses (n, 12): returns
+    (reliable (1,) int32, max_angle (1,) float32) on the device."""
+    poses = _f32(poses).contiguous()
+    rel = torch.empty(1, dtype=torch.int32, device=poses.device)
+    ang = torch.empty(1, dtype=torch.float32, device=poses.device)
+    check(_lib.load().hgsr_pose_consistency(_ptr(poses), poses.shape[0], tau_deg, _ptr(rel), _ptr(ang),
+                                            _stream_ptr(stream)), "hgsr_pose_consistency")
+    return rel, ang
 
 
 def pose_adam(poses, grad, m, v, step, lr_rho=1e-2, lr_phi=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):

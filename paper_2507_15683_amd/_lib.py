@@ -77,6 +77,16 @@ class MatchOut(ctypes.Structure):
     _fields_ = [("n_coarse", P_), ("coarse_query", P_), ("coarse_render", P_), ("coarse_p", P_),
                 ("fine_query", P_), ("fine_render", P_), ("fine_p", P_)]
 
+class PnpProblem(ctypes.Structure):
+    _fields_ = [("p2d", P_), ("x3d", P_), ("n", I64), ("samples", P_), ("n_hyp", I32), ("tau", F32),
+                ("gn_iters", I32), ("refine_iters", I32)]
+
+
+class PnpResult(ctypes.Structure):
+    _fields_ = [("pose", P_), ("best", P_), ("counts", P_), ("hyp_poses", P_), ("inliers", P_),
+                ("n_inliers", P_)]
+
+
 # (name, argtypes) for every entry point declared in include/hgsr.h
 SIGNATURES = {
     "hgsr_ctx_create": [ctypes.POINTER(P_), I64, I64],
@@ -92,6 +102,9 @@ SIGNATURES = {
                           ctypes.POINTER(FeatureMaps), P_, P_, P_, P_],
     "hgsr_significance_final": [P_, P_, I64, P_, P_],
     "hgsr_match": [P_, ctypes.POINTER(MatchMaps), F32, F32, ctypes.POINTER(MatchOut), P_],
+    "hgsr_pnp": [P_, ctypes.POINTER(PnpProblem), ctypes.POINTER(Intrinsics), P_, ctypes.POINTER(PnpResult), P_],
+    "hgsr_backproject": [P_, I32, I32, P_, ctypes.POINTER(Intrinsics), P_, I64, P_, P_],
+    "hgsr_pose_consistency": [P_, I32, F32, P_, P_, P_],
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],

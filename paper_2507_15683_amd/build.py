@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgsr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["project.hip", "binning.hip", "blend.hip", "backward.hip", "refine.hip", "score.hip", "match.hip",
+SOURCES = ["project.hip", "binning.hip", "blend.hip", "backward.hip", "refine.hip", "score.hip", "match.hip", "pnp.hip",
            "hgsr_runtime.hip"]
 
 # No packed-FP32 instructions; no FMA contraction (forward and reverse replay

@@ -77,7 +77,7 @@ struct hgsr_ctx {
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
       gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
-      match, tune;
+      match, tune, pnp;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -455,7 +455,8 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
-                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match, &c->tune};
+                &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match, &c->tune,
+                &c->pnp};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -682,6 +683,77 @@ hgsr_status hgsr_match(hgsr_ctx* c, const hgsr_match_maps* m, float tau_coarse, 
   L.out_fp = out->fine_p;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   launch_match(L, s);
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pnp(hgsr_ctx* c, const hgsr_pnp_problem* pb, const hgsr_intrinsics* K, const float* pose0,
+                     const hgsr_pnp_result* res, hgsr_stream stream) {
+  if (!c || !pb || !res || !pose0) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  TRY(check_intrinsics(K));
+  if (pb->n < 0 || pb->n > (1ll << 31)) return fail(HGSR_ERR_INVALID_ARG, "n out of range");
+  if (pb->n > 0 && (!pb->p2d || !pb->x3d)) return fail(HGSR_ERR_INVALID_ARG, "correspondences are NULL");
+  if (pb->n_hyp < 1 || pb->n_hyp > (1 << 20) || !pb->samples)
+    return fail(HGSR_ERR_INVALID_ARG, "need 1..2^20 samples");
+  if (!(pb->tau > 0.f) || !std::isfinite(pb->tau)) return fail(HGSR_ERR_INVALID_ARG, "tau must be positive");
+  if (pb->gn_iters < 0 || pb->gn_iters > 100 || pb->refine_iters < 0 || pb->refine_iters > 100)
+    return fail(HGSR_ERR_INVALID_ARG, "iteration counts must be 0..100");
+  if (!res->pose || !res->best || !res->counts || !res->n_inliers)
+    return fail(HGSR_ERR_INVALID_ARG, "pose, best, counts and n_inliers are required");
+  const int nb = pnp_normal_blocks(pb->n);
+  const size_t b_hyp = res->hyp_poses ? 0 : (static_cast<size_t>(pb->n_hyp) * 12 * sizeof(float) + 255) / 256 * 256;
+  const size_t b_T = 256, b_state = 256, b_part = (static_cast<size_t>(nb) * 28 * sizeof(float) + 255) / 256 * 256;
+  TRY(ensure(c, c->pnp, b_hyp + b_T + b_state + b_part));
+  char* w = c->pnp.as<char>();
+  PnpArgs a;
+  a.p2d = pb->p2d;
+  a.x3d = pb->x3d;
+  a.n = pb->n;
+  a.samples = pb->samples;
+  a.n_hyp = pb->n_hyp;
+  a.tau = pb->tau;
+  a.gn_iters = pb->gn_iters;
+  a.refine_iters = pb->refine_iters;
+  a.fx = K->fx;
+  a.fy = K->fy;
+  a.cx = K->cx;
+  a.cy = K->cy;
+  a.pose0 = pose0;
+  a.hyp = res->hyp_poses ? res->hyp_poses : reinterpret_cast<float*>(w);
+  w += b_hyp;
+  a.T = reinterpret_cast<float*>(w); w += b_T;
+  a.state = reinterpret_cast<int32_t*>(w); w += b_state;
+  a.part = reinterpret_cast<float*>(w); w += b_part;
+  a.counts = res->counts;
+  a.best = res->best;
+  a.inliers = res->inliers;
+  a.n_inliers = res->n_inliers;
+  a.pose_out = res->pose;
+  launch_pnp(a, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_backproject(const float* depth, int32_t width, int32_t height, const float* pose,
+                             const hgsr_intrinsics* K, const int32_t* pix, int64_t n, float* x3d,
+                             hgsr_stream stream) {
+  TRY(check_intrinsics(K));
+  if (width <= 0 || height <= 0 || static_cast<int64_t>(width) * height >= (1ll << 31))
+    return fail(HGSR_ERR_INVALID_ARG, "depth map size out of range");
+  if (n < 0 || n >= (1ll << 31)) return fail(HGSR_ERR_INVALID_ARG, "n out of range");
+  if (n == 0) return HGSR_OK;
+  if (!depth || !pose || !pix || !x3d) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  launch_backproject(depth, width, height, pose, K->fx, K->fy, K->cx, K->cy, pix, static_cast<int>(n), x3d,
+                     reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pose_consistency(const float* poses, int32_t n, float tau_deg, int32_t* reliable,
+                                  float* max_angle, hgsr_stream stream) {
+  if (n < 1 || !poses || !reliable) return fail(HGSR_ERR_INVALID_ARG, "need n >= 1 poses and a result pointer");
+  if (!(tau_deg >= 0.f)) return fail(HGSR_ERR_INVALID_ARG, "tau_deg must be non-negative");
+  launch_pose_consistency(poses, n, tau_deg, reliable, max_angle, reinterpret_cast<hipStream_t>(stream));
   HIP_TRY(hipGetLastError());
   return HGSR_OK;
 }

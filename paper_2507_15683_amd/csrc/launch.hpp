@@ -255,6 +255,34 @@ constexpr int kMatchRowBlock = 128;
 int match_splits(int nq);
 void launch_match(const MatchLaunch& L, hipStream_t s);
 
+// pnp.hip: 2D-3D pose solve (RANSAC over given 3-point samples, refinement)
+struct PnpArgs {
+  const float* p2d;         // n x 2
+  const float* x3d;         // n x 3
+  int64_t n;
+  const int32_t* samples;   // n_hyp x 3
+  int32_t n_hyp;
+  float tau;
+  int32_t gn_iters, refine_iters;
+  float fx, fy, cx, cy;
+  const float* pose0;       // 12
+  float* hyp;               // n_hyp x 12
+  int32_t* counts;          // n_hyp (-1: invalid sample)
+  int32_t* best;            // 1
+  float* T;                 // 12: the pose being refined
+  int32_t* state;           // 1: refinement running
+  float* part;              // normal-equation partials, pnp_normal_blocks(n) x 28
+  uint8_t* inliers;         // n or null
+  int32_t* n_inliers;       // 1
+  float* pose_out;          // 12
+};
+int pnp_normal_blocks(int64_t n);
+void launch_pnp(const PnpArgs& a, hipStream_t s);
+void launch_backproject(const float* depth, int W, int H, const float* pose, float fx, float fy, float cx, float cy,
+                        const int32_t* pix, int n, float* x3d, hipStream_t s);
+void launch_pose_consistency(const float* poses, int n, float tau_deg, int32_t* reliable, float* max_angle,
+                             hipStream_t s);
+
 // score.hip
 void launch_contrib(const ContribArgs& a, int n_items, hipStream_t s);
 void launch_score(const ScoreArgs& a, hipStream_t s);

@@ -57,6 +57,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.FeatureMaps) == 8 + 3 * 4 + 4   # pointer, width, height, layout, tail padding
     assert ctypes.sizeof(_lib.MatchMaps) == 4 * 8 + 3 * 4 + 4  # 4 pointers, D, width, height, tail padding
     assert ctypes.sizeof(_lib.MatchOut) == 7 * 8
+    assert ctypes.sizeof(_lib.PnpProblem) == 4 * 8 + 4 * 4     # 2 ptrs, n, samples, n_hyp, tau, 2 counts
+    assert ctypes.sizeof(_lib.PnpResult) == 6 * 8
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -93,3 +95,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     mm.D, mm.coarse_width, mm.coarse_height = 32, 4, 4
     mm.query_coarse = mm.render_coarse = 16
     assert L.hgsr_match(ctypes.c_void_p(1), ctypes.byref(mm), 0.01, 0.1, ctypes.byref(mo), None) == 1
+    # pose solve, back-projection, consistency: argument checks
+    assert L.hgsr_pnp(None, None, None, None, None, None) == 1
+    pp = _lib.PnpProblem()
+    pr = _lib.PnpResult()
+    kk = _lib.Intrinsics(100.0, 100.0, 32.0, 24.0, 64, 48)
+    pp.n, pp.n_hyp, pp.tau = 10, 0, 2.0
+    assert L.hgsr_pnp(ctypes.c_void_p(1), ctypes.byref(pp), ctypes.byref(kk), ctypes.c_void_p(16),
+                      ctypes.byref(pr), None) == 1   # NULL arrays / no samples
+    assert L.hgsr_backproject(None, 64, 48, None, ctypes.byref(kk), None, 0, None, None) == 0   # nothing to do
+    assert L.hgsr_backproject(None, 64, 48, None, ctypes.byref(kk), None, 5, None, None) == 1
+    assert L.hgsr_pose_consistency(None, 3, 20.0, None, None, None) == 1
