@@ -427,6 +427,51 @@ def matching(hg, torch, synth, args):
             "coarse_matrix_tflop_s": round(tflops, 1), "steps_timed": args.match_steps}
 
 
+def pose_solve(hg, torch, synth, args):
+    """The dense stage's pose solve (Sec. 3.4, Eq. 10) at the size of the
+    1080p matching output: 640k 2D-3D correspondences (half of them outliers,
+    the inliers with 0.5 px noise) seen at 1920x1080, f = 1500, from 100-300 m,
+    1024 RANSAC samples of 3, 10 Gauss-Newton steps per hypothesis and 10
+    refinement steps from a prior 2 m / 1.2 degrees away."""
+    import numpy as np
+    log("bench: pose solve, 640k correspondences, 1024 hypotheses")
+    n, H = 640_000, 1024
+    cam = synth.Camera(1500.0, 1500.0, 960.0, 540.0, 1920, 1080)
+    rng = np.random.Generator(np.random.PCG64(4242))
+    pose = synth.down_pose((10.0, -20.0), 200.0, (0.2, -0.1), 0.4).reshape(3, 4).astype(np.float64)
+    u = rng.uniform(0, cam.width, n)
+    v = rng.uniform(0, cam.height, n)
+    d = rng.uniform(150.0, 260.0, n)
+    Xc = np.stack([d * (u - cam.cx) / cam.fx, d * (v - cam.cy) / cam.fy, d], 1)
+    X = (Xc - pose[:, 3]) @ pose[:, :3]
+    p = np.stack([u, v], 1) + rng.normal(0.0, 0.5, (n, 2))
+    out = rng.random(n) < 0.5
+    p[out] = np.stack([rng.uniform(0, cam.width, out.sum()), rng.uniform(0, cam.height, out.sum())], 1)
+    prior = synth.perturb_poses(pose.reshape(12).astype(np.float32), 1, 4243, 1.2, 0.7)[0]
+    samples = rng.integers(0, n, (H, 3)).astype(np.int32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    p2d, x3d, pr, smp = t(p.astype(np.float32)), t(X.astype(np.float32)), t(prior), t(samples)
+    K = hg.Intrinsics.of(cam)
+    r = hg.Renderer()
+    s = torch.cuda.Stream()
+    res = r.pnp(p2d, x3d, K, pr, smp, stream=s)
+    s.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.pnp_steps):
+        r.pnp(p2d, x3d, K, pr, smp, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / args.pnp_steps
+    got = res["pose"].cpu().numpy().reshape(3, 4).astype(np.float64)
+    C = lambda P: -P[:, :3].T @ P[:, 3]
+    return {"workload": "2D-3D pose solve, 640k correspondences (50% outliers, 0.5 px noise), 1920x1080 f=1500, "
+                        "1024 RANSAC samples x 10 Gauss-Newton steps, 10 refinement steps, tau 2 px",
+            "ms_per_call": round(ms, 3), "hypothesis_evaluations_per_s": round(n * H / (ms * 1e-3), 1),
+            "inliers": int(res["n_inliers"].cpu().numpy()[0]), "true_inliers": int((~out).sum()),
+            "centre_error_m": round(float(np.linalg.norm(C(got) - C(pose))), 5), "steps_timed": args.pnp_steps}
+
+
 def partitioned(hg, torch, synth, args):
     """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
     import numpy as np
@@ -537,13 +582,15 @@ def main():
     ap.add_argument("--no-significance", action="store_true")
     ap.add_argument("--no-matching", action="store_true")
     ap.add_argument("--match-steps", type=int, default=10)
+    ap.add_argument("--no-pose-solve", action="store_true")
+    ap.add_argument("--pnp-steps", type=int, default=10)
     ap.add_argument("--sig-steps", type=int, default=10)
     ap.add_argument("--fb-steps", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--part-iters", type=int, default=20)
     ap.add_argument("--part-lr-rho", type=float, default=0.3, help="Adam step (m) of the partitioned refinement")
     ap.add_argument("--part-lr-phi", type=float, default=4e-3, help="Adam step (rad) of the partitioned refinement")
-    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance", "matching"],
+    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance", "matching", "pose_solve"],
                     default=None,
                     help="run one section and print its result alone (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -581,8 +628,12 @@ def main():
     if args.only == "matching":
         print(json.dumps({"matching": matching(hg, torch, synth, args)}), flush=True)
         return
+    if args.only == "pose_solve":
+        print(json.dumps({"pose_solve": pose_solve(hg, torch, synth, args)}), flush=True)
+        return
     if args.only == "headline":
-        args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_matching = args.no_cpu = True
+        args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_matching = True
+        args.no_pose_solve = args.no_cpu = True
     h = headline(hg, torch, synth, args)
     result = {
         "metric": "rendered Mpix/s at 1080p/1M Gaussians",
@@ -622,6 +673,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_matching:
         result["matching"] = matching(hg, torch, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_pose_solve:
+        result["pose_solve"] = pose_solve(hg, torch, synth, args)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("bench: timing the CPU oracle")

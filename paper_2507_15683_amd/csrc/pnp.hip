@@ -174,13 +174,22 @@ constexpr int kPnpHypPerBlock = 64;
 constexpr int kPnpPointsPerThread = 4;
 
 __global__ __launch_bounds__(256) void pnp_score_kernel(PnpArgs a) {
-  __shared__ float s_T[kPnpHypPerBlock][12];
+  // Per hypothesis the rows of K [R | t]: with (a, b, z) = K [R | t] X the
+  // test |(a/z, b/z) - p| < tau, z > 0 is |(a - p_u z, b - p_v z)|^2 <
+  // tau^2 z^2 -- no division on the per-pair path.
+  __shared__ float s_M[kPnpHypPerBlock][12];
   __shared__ int32_t s_c[kPnpHypPerBlock];
   __shared__ int32_t s_ok[kPnpHypPerBlock];
   const int tid = threadIdx.x;
   const int h0 = blockIdx.y * kPnpHypPerBlock;
   const int nh = min(kPnpHypPerBlock, a.n_hyp - h0);
-  for (int e = tid; e < nh * 12; e += 256) s_T[e / 12][e % 12] = a.hyp[12 * h0 + e];
+  for (int e = tid; e < nh * 4; e += 256) {
+    const int h = e >> 2, q = e & 3;
+    const float* T = a.hyp + 12 * static_cast<int64_t>(h0 + h);
+    s_M[h][q] = a.fx * T[q] + a.cx * T[8 + q];
+    s_M[h][4 + q] = a.fy * T[4 + q] + a.cy * T[8 + q];
+    s_M[h][8 + q] = T[8 + q];
+  }
   for (int e = tid; e < kPnpHypPerBlock; e += 256) {
     s_c[e] = 0;
     s_ok[e] = e < nh ? (a.counts[h0 + e] >= 0) : 0;
@@ -195,22 +204,22 @@ __global__ __launch_bounds__(256) void pnp_score_kernel(PnpArgs a) {
     if (live[q]) {
       P[q][0] = a.x3d[3 * i]; P[q][1] = a.x3d[3 * i + 1]; P[q][2] = a.x3d[3 * i + 2];
       P[q][3] = a.p2d[2 * i]; P[q][4] = a.p2d[2 * i + 1];
+    } else {
+      // a point that can never count: behind the camera of every hypothesis
+      P[q][0] = P[q][1] = P[q][2] = P[q][3] = P[q][4] = 0.f;
     }
   }
   for (int h = 0; h < nh; ++h) {
     if (!s_ok[h]) continue;  // uniform
-    const float* T = s_T[h];
+    const float* M = s_M[h];
     int c = 0;
+#pragma unroll
     for (int q = 0; q < kPnpPointsPerThread; ++q) {
-      if (!live[q]) continue;
-      const float x = T[0] * P[q][0] + T[1] * P[q][1] + T[2] * P[q][2] + T[3];
-      const float y = T[4] * P[q][0] + T[5] * P[q][1] + T[6] * P[q][2] + T[7];
-      const float z = T[8] * P[q][0] + T[9] * P[q][1] + T[10] * P[q][2] + T[11];
-      if (!(z > 0.f)) continue;
-      const float iz = 1.f / z;
-      const float du = a.fx * x * iz + a.cx - P[q][3];
-      const float dv = a.fy * y * iz + a.cy - P[q][4];
-      c += (du * du + dv * dv < tau2) ? 1 : 0;
+      const float u = M[0] * P[q][0] + M[1] * P[q][1] + M[2] * P[q][2] + M[3];
+      const float v = M[4] * P[q][0] + M[5] * P[q][1] + M[6] * P[q][2] + M[7];
+      const float z = M[8] * P[q][0] + M[9] * P[q][1] + M[10] * P[q][2] + M[11];
+      const float du = u - P[q][3] * z, dv = v - P[q][4] * z;
+      c += (live[q] && z > 0.f && du * du + dv * dv < tau2 * (z * z)) ? 1 : 0;
     }
     // sum over the wave, then one LDS add per wave
 #pragma unroll
@@ -257,63 +266,85 @@ __global__ __launch_bounds__(256) void pnp_select_kernel(PnpArgs a) {
 // ------------------------------------------------------------ refinement
 constexpr int kPnpNormal = 28;  // J^T J (21), J^T r (6), inlier count
 
+// Sum of v over the 64 lanes of a wave, the same butterfly on every lane.
+template <class F>
+__device__ __forceinline__ F wave_sum64(F v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void pnp_normal_kernel(PnpArgs a, int final_pass) {
-  __shared__ float s_red[kPnpNormal][256];
-  const int tid = threadIdx.x;
+  __shared__ float s_w[4][kPnpNormal];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (!final_pass && !a.state[0]) return;  // uniform: refinement stopped
   float T[12];
   for (int k = 0; k < 12; ++k) T[k] = a.T[k];
   const float tau2 = a.tau * a.tau;
-  float A21[21] = {}, b[6] = {}, cnt = 0.f;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid; i < a.n;
-       i += static_cast<int64_t>(gridDim.x) * 256) {
-    const float X[3] = {a.x3d[3 * i], a.x3d[3 * i + 1], a.x3d[3 * i + 2]};
-    float r[2], J[2][6];
-    const bool front = reproj_rows(T, a.fx, a.fy, a.cx, a.cy, X, a.p2d[2 * i], a.p2d[2 * i + 1], r, J);
-    const bool inl = front && (r[0] * r[0] + r[1] * r[1] < tau2);
-    if (final_pass) {
-      if (a.inliers) a.inliers[i] = inl ? 1 : 0;
-      cnt += inl ? 1.f : 0.f;
-      continue;
+  float acc[kPnpNormal] = {};  // A21 (21), b (6), count
+  // chunks of 4 x 256 correspondences: the four loads are issued before the
+  // first use, one memory latency per chunk
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * 1024; base < a.n;
+       base += static_cast<int64_t>(gridDim.x) * 1024) {
+    float P[4][5];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + q * 256 + tid;
+      if (i < a.n) {
+        P[q][0] = a.x3d[3 * i]; P[q][1] = a.x3d[3 * i + 1]; P[q][2] = a.x3d[3 * i + 2];
+        P[q][3] = a.p2d[2 * i]; P[q][4] = a.p2d[2 * i + 1];
+      }
     }
-    if (!inl) continue;
-    accumulate_normal(r, J, A21, b);
-    cnt += 1.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + q * 256 + tid;
+      if (i >= a.n) continue;
+      float r[2], J[2][6];
+      const bool front = reproj_rows(T, a.fx, a.fy, a.cx, a.cy, P[q], P[q][3], P[q][4], r, J);
+      const bool inl = front && (r[0] * r[0] + r[1] * r[1] < tau2);
+      if (final_pass) {
+        if (a.inliers) a.inliers[i] = inl ? 1 : 0;
+        acc[27] += inl ? 1.f : 0.f;
+        continue;
+      }
+      if (!inl) continue;
+      accumulate_normal(r, J, acc, acc + 21);
+      acc[27] += 1.f;
+    }
   }
-  for (int k = 0; k < 21; ++k) s_red[k][tid] = A21[k];
-  for (int k = 0; k < 6; ++k) s_red[21 + k][tid] = b[k];
-  s_red[27][tid] = cnt;
+  // lanes, then the four waves in order: a fixed summation order
+#pragma unroll
+  for (int k = 0; k < kPnpNormal; ++k) {
+    const float v = wave_sum64(acc[k]);
+    if (lane == 0) s_w[wv][k] = v;
+  }
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st)
-      for (int k = 0; k < kPnpNormal; ++k) s_red[k][tid] += s_red[k][tid + st];
-    __syncthreads();
-  }
-  if (tid < kPnpNormal) a.part[static_cast<int64_t>(blockIdx.x) * kPnpNormal + tid] = s_red[tid][0];
+  if (tid < kPnpNormal)
+    a.part[static_cast<int64_t>(blockIdx.x) * kPnpNormal + tid] = ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
 }
 
-// Sum of the workgroup partials in FP64 (8 groups of 28 threads, each group a
-// fixed stride of blocks, then the groups in order), then the 6x6 solve and
+// Sum of the workgroup partials in FP64 (thread t takes blocks t, t + 256,
+// ..., then lanes and waves in a fixed order), then the 6x6 solve and
 // T <- Exp(delta) T, or (final pass) the inlier count and the pose.
 __global__ __launch_bounds__(256) void pnp_update_kernel(PnpArgs a, int n_blocks, int final_pass) {
-  constexpr int G = 8;
-  __shared__ double s_p[G][kPnpNormal];
-  const int t = threadIdx.x;
+  __shared__ double s_w[4][kPnpNormal];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   if (!final_pass && !a.state[0]) return;  // uniform
-  if (t < G * kPnpNormal) {
-    const int k = t % kPnpNormal, g = t / kPnpNormal;
-    double v = 0.0;
-    for (int bk = g; bk < n_blocks; bk += G) v += static_cast<double>(a.part[static_cast<int64_t>(bk) * kPnpNormal + k]);
-    s_p[g][k] = v;
+  double acc[kPnpNormal] = {};
+  for (int bk = t; bk < n_blocks; bk += 256) {
+    const float* q = a.part + static_cast<int64_t>(bk) * kPnpNormal;
+#pragma unroll
+    for (int k = 0; k < kPnpNormal; ++k) acc[k] += static_cast<double>(q[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kPnpNormal; ++k) {
+    const double v = wave_sum64(acc[k]);
+    if (lane == 0) s_w[wv][k] = v;
   }
   __syncthreads();
   if (t != 0) return;
   double S[kPnpNormal];
-  for (int k = 0; k < kPnpNormal; ++k) {
-    double v = 0.0;
-    for (int g = 0; g < G; ++g) v += s_p[g][k];
-    S[k] = v;
-  }
+  for (int k = 0; k < kPnpNormal; ++k) S[k] = ((s_w[0][k] + s_w[1][k]) + s_w[2][k]) + s_w[3][k];
   if (final_pass) {
     *a.n_inliers = static_cast<int32_t>(S[27]);
     for (int k = 0; k < 12; ++k) a.pose_out[k] = a.T[k];
@@ -389,7 +420,7 @@ void launch_pnp(const PnpArgs& a, hipStream_t s) {
 }
 
 int pnp_normal_blocks(int64_t n) {
-  int64_t b = (n + 255) / 256;
+  int64_t b = (n + 1023) / 1024;  // about four correspondences per thread
   if (b > 1024) b = 1024;
   return static_cast<int>(b < 1 ? 1 : b);
 }
