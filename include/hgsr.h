@@ -413,6 +413,102 @@ hgsr_status hgsr_pose_consistency(const float* poses, int32_t n, float tau_deg, 
  * around its mean (the 1/255 support of the most opaque Gaussian). */
 hgsr_status hgsr_partition_bounds(const hgsr_gaussians* g, float* part_bounds, hgsr_stream stream);
 
+/* ---------------------------------------------------------------- partition streaming
+ * Scenes larger than device memory (Sec. 3.1: the scene is trained and kept
+ * as spatial cells; Sec. 3.2: batches are processed under a memory budget
+ * and their intermediate data released).  A partition cache keeps the whole
+ * partitioned scene in library-owned pinned host memory and a fixed device
+ * budget of n_slots slots, each holding one partition; per batch of poses it
+ * makes resident the partitions that may be seen, evicting the least
+ * recently used slots the batch does not need, and hands back a scene
+ * descriptor for hgsr_render / hgsr_render_backward / hgsr_significance.
+ *
+ * The descriptor's Gaussians are the slots laid end to end
+ * (n = n_slots x slot_capacity; slot s is partition s of the descriptor,
+ * [s x capacity, (s + 1) x capacity)); a slot's unused tail has opacity 0
+ * and an empty slot an empty box, so neither is ever projected.  Renders
+ * through the descriptor equal renders of the whole resident scene up to
+ * the order of Gaussians at exactly equal depth (the index that breaks such
+ * ties is the slot index, not the scene index).  Gaussian indices in
+ * per-Gaussian outputs (gradients, visibility) are descriptor indices. */
+
+/* Host-side scene of a partition cache: every array in host memory, the
+ * layouts of hgsr_gaussians; part_offsets host int64, n_parts + 1 entries,
+ * partition k = [part_offsets[k], part_offsets[k+1]). */
+typedef struct {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  int32_t sh_degree;
+  int32_t feat_dim;
+  const uint16_t* feat;
+  int32_t n_parts;
+  const int64_t* part_offsets;
+} hgsr_host_scene;
+
+typedef struct hgsr_pcache hgsr_pcache;
+
+typedef struct {
+  int32_t needed;          /* partitions the last batch may see */
+  int32_t hits;            /* of those, already resident */
+  int32_t uploads;         /* copied from host memory for the last batch */
+  int32_t evictions;       /* resident partitions dropped for the last batch */
+  int64_t bytes_uploaded;  /* by the last batch */
+  int64_t total_uploads;   /* since creation */
+  int64_t total_bytes;     /* since creation */
+  int32_t n_slots;
+  int64_t slot_capacity;   /* Gaussians per slot (the largest partition) */
+  int64_t device_bytes;    /* the device budget in use (slots + tables) */
+} hgsr_pcache_stats;
+
+/* Create a cache on the current device: copies the host scene into pinned
+ * host memory (hipHostMalloc; the caller's arrays may be freed afterwards),
+ * computes the partition boxes (hgsr_host_partition_bounds) and allocates
+ * n_slots slots (1..64, at most n_parts).  Synchronous.  Errors:
+ * HGSR_ERR_INVALID_ARG for bad sizes or NULL arrays, HGSR_ERR_HIP when an
+ * allocation fails. */
+hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, int32_t n_slots);
+hgsr_status hgsr_pcache_destroy(hgsr_pcache* pc);
+
+/* Make the partitions that the P poses (host, P x 12) may see at
+ * intrinsics K resident, and fill *out with the device descriptor.  A
+ * partition may be seen when its box, grown by motion_margin metres (room
+ * for poses that move during refinement without a new call), passes the
+ * conservative frustum test of hgsr_partition_plan.  Uploads run on the
+ * cache's own copy stream from pinned memory; `stream` -- the stream the
+ * renders using *out run on -- waits for them, and a slot is only
+ * overwritten after the work enqueued on `stream` before the call that last
+ * needed it (no host synchronisation).  The descriptor stays valid until the
+ * next prepare on this cache.  Returns HGSR_ERR_CAPACITY (nothing enqueued)
+ * when the batch needs more partitions than the cache has slots.  stats may
+ * be NULL. */
+hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                                float near_z, float motion_margin, hgsr_gaussians* out, hgsr_pcache_stats* stats,
+                                hgsr_stream stream);
+
+/* Drop every resident partition (the slots stay allocated); the next
+ * prepare uploads what it needs.  Synchronises the copy stream. */
+hgsr_status hgsr_pcache_evict_all(hgsr_pcache* pc);
+
+/* Host-only helpers (no device work; usable without a GPU).
+ * hgsr_host_partition_bounds: per partition (host out, n_parts x 6, min xyz
+ * then max xyz) the box containing every Gaussian's ball of radius 3.33 x its
+ * largest scale around its mean (the same box as hgsr_partition_bounds,
+ * rounded outward); an empty partition gets min > max.
+ * hgsr_partition_plan: per (pose, partition) (host out, P x n_parts bytes)
+ * 1 when the box grown by motion_margin may reach the image: rejected only
+ * when all 8 corners lie behind the near plane or outside one of the four
+ * side planes through the camera centre, pushed out by 9 + 0.05 max(W, H)
+ * pixels (a pixel more than the renderer's own partition test, so that every
+ * partition the renderer would draw is planned).  Empty boxes are never
+ * seen. */
+hgsr_status hgsr_host_partition_bounds(const hgsr_host_scene* scene, float* bounds);
+hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const float* poses, int32_t P,
+                                const hgsr_intrinsics* K, float near_z, float motion_margin, uint8_t* seen);
+
 /* Check the Gaussian arrays for NaN/Inf, opacities outside [0, 1] and zero
  * quaternions.  Synchronises `stream`.  Returns HGSR_ERR_INVALID_ARG on the
  * first problem found. */

@@ -71,6 +71,10 @@ class GaussianScene:
     def feat_dim(self) -> int:
         return 0 if self.feat is None else int(self.feat.shape[1])
 
+    @property
+    def device(self) -> torch.device:
+        return self.means.device
+
     @staticmethod
     def from_numpy(s, device="cuda") -> "GaussianScene":
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
@@ -103,6 +107,98 @@ class GaussianScene:
     def validate(self):
         g = self.c()
         check(_lib.load().hgsr_validate(ctypes.byref(g), _stream_ptr()), "hgsr_validate")
+
+
+def _host_scene(s) -> tuple:
+    """A hgsr_host_scene over a synth-style host scene (numpy arrays with
+    part_offsets); returns (struct, arrays kept alive)."""
+    arrs = [np.ascontiguousarray(getattr(s, f), dtype=np.float32) for f in ("means", "log_scales", "quats",
+                                                                            "opacities", "sh")]
+    feat = None if s.feat is None else np.ascontiguousarray(s.feat).view(np.uint16)
+    offs = np.ascontiguousarray(s.part_offsets, dtype=np.int64)
+    vp = lambda a: None if a is None else a.ctypes.data
+    hs = _lib.HostScene(int(arrs[0].shape[0]), *[vp(a) for a in arrs], int(s.sh_degree),
+                        0 if feat is None else int(feat.shape[1]), vp(feat), int(len(offs) - 1), vp(offs))
+    return hs, (arrs, feat, offs)
+
+
+def host_partition_bounds(s) -> np.ndarray:
+    """Per partition (n_parts, 6) boxes of a host scene, computed on the host
+    (hgsr_host_partition_bounds)."""
+    hs, keep = _host_scene(s)
+    out = np.empty((hs.n_parts, 6), dtype=np.float32)
+    check(_lib.load().hgsr_host_partition_bounds(ctypes.byref(hs), out.ctypes.data), "hgsr_host_partition_bounds")
+    return out
+
+
+def partition_plan(bounds: np.ndarray, poses: np.ndarray, K: "Intrinsics", near: float = 0.2,
+                   motion_margin: float = 0.0) -> np.ndarray:
+    """(P, n_parts) uint8: 1 where a partition box may reach pose p's image
+    (hgsr_partition_plan, host only)."""
+    b = np.ascontiguousarray(bounds, dtype=np.float32)
+    q = np.ascontiguousarray(np.asarray(poses, dtype=np.float32).reshape(-1, 12))
+    out = np.zeros((q.shape[0], b.shape[0]), dtype=np.uint8)
+    kc = K.c()
+    check(_lib.load().hgsr_partition_plan(b.ctypes.data, b.shape[0], q.ctypes.data, q.shape[0], ctypes.byref(kc),
+                                          near, motion_margin, out.ctypes.data), "hgsr_partition_plan")
+    return out
+
+
+class StreamedScene:
+    """The device descriptor a PartitionCache hands out for one batch: usable
+    wherever a GaussianScene is (render, backward, significance); valid until
+    the cache's next prepare."""
+
+    def __init__(self, g: "_lib.Gaussians", device):
+        self._g = g
+        self.n = int(g.n)
+        self.sh_degree = int(g.sh_degree)
+        self.feat_dim = int(g.feat_dim)
+        self.device = device
+
+    def c(self, partitions: bool = True) -> "_lib.Gaussians":
+        return self._g
+
+
+class PartitionCache:
+    """Out-of-core partitioned scene: the whole scene in pinned host memory,
+    `n_slots` partitions on the device at a time (hgsr_pcache_*)."""
+
+    def __init__(self, host_scene, n_slots: int):
+        self.lib = _lib.load()
+        hs, keep = _host_scene(host_scene)
+        h = ctypes.c_void_p()
+        check(self.lib.hgsr_pcache_create(ctypes.byref(h), ctypes.byref(hs), n_slots), "hgsr_pcache_create")
+        self.pc = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stats = {}
+
+    def prepare(self, poses, K: "Intrinsics", near: float = 0.2, motion_margin: float = 0.0,
+                stream=None) -> StreamedScene:
+        q = np.ascontiguousarray(np.asarray(poses.cpu() if isinstance(poses, torch.Tensor) else poses,
+                                            dtype=np.float32).reshape(-1, 12))
+        g = _lib.Gaussians()
+        st = _lib.PcacheStats()
+        kc = K.c()
+        check(self.lib.hgsr_pcache_prepare(self.pc, q.ctypes.data, q.shape[0], ctypes.byref(kc), near, motion_margin,
+                                           ctypes.byref(g), ctypes.byref(st), _stream_ptr(stream)),
+              "hgsr_pcache_prepare")
+        self.stats = {f: getattr(st, f) for f, _ in _lib.PcacheStats._fields_}
+        return StreamedScene(g, self.device)
+
+    def evict_all(self):
+        check(self.lib.hgsr_pcache_evict_all(self.pc), "hgsr_pcache_evict_all")
+
+    def close(self):
+        if getattr(self, "pc", None):
+            self.lib.hgsr_pcache_destroy(self.pc)
+            self.pc = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _SORTS = {"bucket": SORT_BUCKET, "lsd": SORT_LSD}
@@ -142,7 +238,7 @@ class Renderer:
               "hgsr_reserve")
 
     def alloc_outputs(self, scene: GaussianScene, P: int, K: Intrinsics, feat_bf16=False):
-        dev = scene.means.device
+        dev = scene.device
         H, W = K.height, K.width
         out = dict(rgb=torch.empty((P, 3, H, W), dtype=torch.float32, device=dev),
                    depth=torch.empty((P, H, W), dtype=torch.float32, device=dev),
@@ -206,7 +302,7 @@ class Renderer:
 
     @staticmethod
     def alloc_grads(scene: GaussianScene, P: int, want=("pose", "means", "opacities")) -> dict:
-        dev = scene.means.device
+        dev = scene.device
         n, D, K = scene.n, scene.feat_dim, (scene.sh_degree + 1) ** 2
         shapes = dict(pose=(P, 6), means=(n, 3), opacities=(n,), log_scales=(n, 3), quats=(n, 4), sh=(n, K, 3),
                       feat=(n, D))
@@ -245,7 +341,7 @@ class Renderer:
         if grads is None:
             grads = self.alloc_grads(scene, P, want)
         if loss is None:
-            loss = torch.empty(P, dtype=torch.float32, device=scene.means.device)
+            loss = torch.empty(P, dtype=torch.float32, device=scene.device)
         shared = int(rgb_target.shape[0] == 1 and P > 1)
         if not shared and rgb_target.shape[0] != P:
             raise ValueError("targets must hold one image per pose or a single shared one")
@@ -297,7 +393,7 @@ class Renderer:
         the workspace and scores the batch again."""
         if poses.dim() == 1:
             poses = poses[None]
-        dev = scene.means.device
+        dev = scene.device
         n = scene.n
         if score_sum is None:
             score_sum = torch.zeros(n, dtype=torch.float32, device=dev)

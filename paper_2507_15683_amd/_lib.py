@@ -87,6 +87,17 @@ class PnpResult(ctypes.Structure):
                 ("n_inliers", P_)]
 
 
+class HostScene(ctypes.Structure):
+    _fields_ = [("n", I64), ("means", P_), ("log_scales", P_), ("quats", P_), ("opacities", P_), ("sh", P_),
+                ("sh_degree", I32), ("feat_dim", I32), ("feat", P_), ("n_parts", I32), ("part_offsets", P_)]
+
+
+class PcacheStats(ctypes.Structure):
+    _fields_ = [("needed", I32), ("hits", I32), ("uploads", I32), ("evictions", I32), ("bytes_uploaded", I64),
+                ("total_uploads", I64), ("total_bytes", I64), ("n_slots", I32), ("slot_capacity", I64),
+                ("device_bytes", I64)]
+
+
 # (name, argtypes) for every entry point declared in include/hgsr.h
 SIGNATURES = {
     "hgsr_ctx_create": [ctypes.POINTER(P_), I64, I64],
@@ -106,6 +117,13 @@ SIGNATURES = {
     "hgsr_backproject": [P_, I32, I32, P_, ctypes.POINTER(Intrinsics), P_, I64, P_, P_],
     "hgsr_pose_consistency": [P_, I32, F32, P_, P_, P_],
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
+    "hgsr_pcache_create": [ctypes.POINTER(P_), ctypes.POINTER(HostScene), I32],
+    "hgsr_pcache_destroy": [P_],
+    "hgsr_pcache_prepare": [P_, P_, I32, ctypes.POINTER(Intrinsics), F32, F32, ctypes.POINTER(Gaussians),
+                            ctypes.POINTER(PcacheStats), P_],
+    "hgsr_pcache_evict_all": [P_],
+    "hgsr_host_partition_bounds": [ctypes.POINTER(HostScene), P_],
+    "hgsr_partition_plan": [P_, I32, P_, I32, ctypes.POINTER(Intrinsics), F32, F32, P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],
     "hgsr_graph_end": [P_],

@@ -420,6 +420,11 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
 
 }  // namespace
 
+hgsr_status hgsr::report_error(hgsr_status st, const char* msg) {
+  g_err = msg;
+  return st;
+}
+
 extern "C" {
 
 const char* hgsr_last_error(void) { return g_err.c_str(); }

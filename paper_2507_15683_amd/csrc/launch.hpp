@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/hgsr.h"
 #include "hgsr_device.hpp"
 
 namespace hgsr {
+
+// Sets the thread's hgsr_last_error() text; returns st.
+hgsr_status report_error(hgsr_status st, const char* msg);
 
 struct ProjectArgs {
   GaussArgs g;

@@ -1,0 +1,483 @@
+// Partition streaming: the partitioned scene (Sec. 3.1's spatial cells) kept
+// in pinned host memory, a fixed device budget of slots, and per batch of
+// poses the uploads that make the cells it may see resident (Sec. 3.2's
+// batch processing under a memory budget with intermediate data released).
+//
+// Device layout: every per-Gaussian array of the descriptor is n_slots x
+// capacity entries, slot s holding one partition at [s x capacity, s x
+// capacity + count) and opacity 0 behind it; per-slot offsets and boxes make
+// the slots the descriptor's partitions, so the renderer's partition test
+// skips slots a pose cannot see and empty slots (empty boxes) always.
+//
+// Ordering without host waits: uploads run on the cache's copy stream.  At
+// the start of a prepare, every slot that the previous batch used gets an
+// event recorded on the render stream (it completes once that batch's work
+// has); a slot's data is overwritten only after the copy stream has waited
+// for its event, so uploads into least recently used slots overlap the
+// previous batch's renders.  The slot table (offsets are fixed; boxes
+// change) is rewritten only after everything enqueued on the render stream
+// before the call, which costs nothing since the next render follows that
+// work anyway, and the render stream waits for the batch's uploads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/hgsr.h"
+#include "launch.hpp"
+
+using namespace hgsr;
+
+namespace {
+
+constexpr int kMaxSlots = 64;  // the renderer's per-pose partition mask
+constexpr double kSupport = 3.33;
+
+hgsr_status err(hgsr_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+hgsr_status err(hgsr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return report_error(st, buf);
+}
+
+#define PC_HIP(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return err(HGSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Per-Gaussian array sizes in bytes.
+struct Widths {
+  size_t means, ls, quats, opac, sh, feat;
+  explicit Widths(int sh_degree, int feat_dim)
+      : means(12), ls(12), quats(16), opac(4), sh(12 * static_cast<size_t>((sh_degree + 1) * (sh_degree + 1))),
+        feat(2 * static_cast<size_t>(feat_dim)) {}
+  size_t total() const { return means + ls + quats + opac + sh + feat; }
+};
+
+// Slot boxes passed by value (a kernel argument is copied at launch, so the
+// host table may change right after the call).
+struct SlotBoxes {
+  float b[kMaxSlots][6];
+};
+
+__global__ void write_boxes_kernel(SlotBoxes t, int n, float* out) {
+  const int i = threadIdx.x;
+  if (i < n)
+    for (int k = 0; k < 6; ++k) out[6 * i + k] = t.b[i][k];
+}
+
+__global__ void zero_tail_kernel(float* opac, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) opac[i] = 0.f;
+}
+
+bool empty_box(const float* B) { return !(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5]); }
+
+hgsr_status check_host_scene(const hgsr_host_scene* s) {
+  if (!s) return err(HGSR_ERR_INVALID_ARG, "NULL scene");
+  if (s->n < 0) return err(HGSR_ERR_INVALID_ARG, "n < 0");
+  if (s->sh_degree < 0 || s->sh_degree > 3) return err(HGSR_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  if (!(s->feat_dim == 0 || s->feat_dim == 8 || s->feat_dim == 16 || s->feat_dim == 32 || s->feat_dim == 64))
+    return err(HGSR_ERR_INVALID_ARG, "feat_dim must be 0, 8, 16, 32 or 64");
+  if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacities || !s->sh))
+    return err(HGSR_ERR_INVALID_ARG, "scene arrays are NULL");
+  if (s->n > 0 && s->feat_dim > 0 && !s->feat) return err(HGSR_ERR_INVALID_ARG, "feat is NULL");
+  if (s->n_parts < 1 || !s->part_offsets) return err(HGSR_ERR_INVALID_ARG, "need n_parts >= 1 and part_offsets");
+  if (s->part_offsets[0] != 0 || s->part_offsets[s->n_parts] != s->n)
+    return err(HGSR_ERR_INVALID_ARG, "part_offsets must run from 0 to n");
+  for (int k = 0; k < s->n_parts; ++k)
+    if (s->part_offsets[k + 1] < s->part_offsets[k]) return err(HGSR_ERR_INVALID_ARG, "part_offsets decrease");
+  return HGSR_OK;
+}
+
+void host_bounds(const hgsr_host_scene* s, float* out) {
+  for (int k = 0; k < s->n_parts; ++k) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = s->part_offsets[k]; i < s->part_offsets[k + 1]; ++i) {
+      const float* l = s->log_scales + 3 * i;
+      const double r = kSupport * std::exp(static_cast<double>(std::max(l[0], std::max(l[1], l[2]))));
+      for (int a = 0; a < 3; ++a) {
+        const double m = s->means[3 * i + a];
+        lo[a] = std::min(lo[a], m - r);
+        hi[a] = std::max(hi[a], m + r);
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      // outward rounding to float
+      float fl = static_cast<float>(lo[a]), fh = static_cast<float>(hi[a]);
+      if (static_cast<double>(fl) > lo[a]) fl = std::nextafter(fl, -INFINITY);
+      if (static_cast<double>(fh) < hi[a]) fh = std::nextafter(fh, INFINITY);
+      out[6 * k + a] = fl;
+      out[6 * k + 3 + a] = fh;
+    }
+    if (s->part_offsets[k + 1] == s->part_offsets[k]) {
+      for (int a = 0; a < 3; ++a) {
+        out[6 * k + a] = 1.f;
+        out[6 * k + 3 + a] = -1.f;
+      }
+    }
+  }
+}
+
+// The renderer's partition test, in double, with one more pixel of margin
+// and the box grown by `grow` metres.
+bool box_may_be_seen(const float* B, const float* T, const hgsr_intrinsics& K, double near_z, double grow) {
+  if (empty_box(B)) return false;
+  const double margin = 9.0 + 0.05 * std::max(K.width, K.height);
+  const double l = (-margin - K.cx) / K.fx, r = (K.width + margin - K.cx) / K.fx;
+  const double t = (-margin - K.cy) / K.fy, b = (K.height + margin - K.cy) / K.fy;
+  bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
+  for (int q = 0; q < 8; ++q) {
+    const double w[3] = {(q & 1) ? B[3] + grow : B[0] - grow, (q & 2) ? B[4] + grow : B[1] - grow,
+                         (q & 4) ? B[5] + grow : B[2] - grow};
+    double m[3];
+    for (int r3 = 0; r3 < 3; ++r3)
+      m[r3] = T[4 * r3] * w[0] + T[4 * r3 + 1] * w[1] + T[4 * r3 + 2] * w[2] + T[4 * r3 + 3];
+    all_near &= m[2] < near_z;
+    all_l &= m[0] < l * m[2];
+    all_r &= m[0] > r * m[2];
+    all_t &= m[1] < t * m[2];
+    all_b &= m[1] > b * m[2];
+  }
+  return !(all_near || all_l || all_r || all_t || all_b);
+}
+
+hgsr_status check_plan_args(int32_t n_parts, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                            float near_z, float motion_margin) {
+  if (n_parts < 0) return err(HGSR_ERR_INVALID_ARG, "n_parts < 0");
+  if (P < 1 || !poses) return err(HGSR_ERR_INVALID_ARG, "need P >= 1 host poses");
+  if (!K || !(K->fx > 0.f) || !(K->fy > 0.f) || K->width <= 0 || K->height <= 0)
+    return err(HGSR_ERR_INVALID_ARG, "bad intrinsics");
+  if (!(near_z >= 0.f) || !(motion_margin >= 0.f) || !std::isfinite(motion_margin))
+    return err(HGSR_ERR_INVALID_ARG, "near_z and motion_margin must be finite and non-negative");
+  for (int64_t k = 0; k < 12ll * P; ++k)
+    if (!std::isfinite(poses[k])) return err(HGSR_ERR_INVALID_ARG, "non-finite pose entry");
+  return HGSR_OK;
+}
+
+}  // namespace
+
+struct hgsr_pcache {
+  int device = 0;
+  int64_t n = 0;
+  int32_t sh_degree = 0, feat_dim = 0, n_parts = 0;
+  std::vector<int64_t> offs;
+  std::vector<float> bounds;  // n_parts x 6
+  // pinned host copy
+  char* host = nullptr;
+  const char *h_means = nullptr, *h_ls = nullptr, *h_quats = nullptr, *h_opac = nullptr, *h_sh = nullptr,
+             *h_feat = nullptr;
+  // device slots
+  int32_t n_slots = 0;
+  int64_t cap = 0;
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  char *d_means = nullptr, *d_ls = nullptr, *d_quats = nullptr, *d_opac = nullptr, *d_sh = nullptr,
+       *d_feat = nullptr;
+  int64_t* d_offs = nullptr;
+  float* d_bounds = nullptr;
+  std::vector<float> slot_box;      // n_slots x 6
+  std::vector<int32_t> slot_part;   // resident partition, -1 for none
+  std::vector<int64_t> slot_last;   // last batch that needed the slot, -1 for none
+  std::vector<hipEvent_t> slot_rel;
+  std::vector<uint8_t> slot_rel_set;
+  std::vector<int32_t> part_slot;   // slot of a resident partition, -1 otherwise
+  bool table_dirty = false;         // slot boxes changed since the device table was written
+  hipStream_t copy = nullptr;
+  hipEvent_t ready = nullptr;
+  hipEvent_t prior = nullptr;       // the render stream's work before the current prepare
+  int64_t batch = 0;
+  hgsr_pcache_stats st{};
+};
+
+namespace {
+
+void release_all(hgsr_pcache* pc) {
+  if (pc->copy) (void)hipStreamSynchronize(pc->copy);
+  for (hipEvent_t e : pc->slot_rel)
+    if (e) (void)hipEventDestroy(e);
+  if (pc->ready) (void)hipEventDestroy(pc->ready);
+  if (pc->prior) (void)hipEventDestroy(pc->prior);
+  if (pc->copy) (void)hipStreamDestroy(pc->copy);
+  if (pc->dev) (void)hipFree(pc->dev);
+  if (pc->host) (void)hipHostFree(pc->host);
+}
+
+}  // namespace
+
+extern "C" {
+
+hgsr_status hgsr_host_partition_bounds(const hgsr_host_scene* scene, float* bounds) {
+  hgsr_status s = check_host_scene(scene);
+  if (s != HGSR_OK) return s;
+  if (!bounds) return err(HGSR_ERR_INVALID_ARG, "NULL output");
+  host_bounds(scene, bounds);
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const float* poses, int32_t P,
+                                const hgsr_intrinsics* K, float near_z, float motion_margin, uint8_t* seen) {
+  hgsr_status s = check_plan_args(n_parts, poses, P, K, near_z, motion_margin);
+  if (s != HGSR_OK) return s;
+  if (n_parts > 0 && (!bounds || !seen)) return err(HGSR_ERR_INVALID_ARG, "NULL bounds or output");
+  for (int p = 0; p < P; ++p)
+    for (int k = 0; k < n_parts; ++k)
+      seen[static_cast<int64_t>(p) * n_parts + k] =
+          box_may_be_seen(bounds + 6 * k, poses + 12 * p, *K, near_z, motion_margin) ? 1 : 0;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, int32_t n_slots) {
+  if (!out) return err(HGSR_ERR_INVALID_ARG, "NULL output");
+  *out = nullptr;
+  hgsr_status s = check_host_scene(scene);
+  if (s != HGSR_OK) return s;
+  if (n_slots < 1 || n_slots > kMaxSlots || n_slots > scene->n_parts)
+    return err(HGSR_ERR_INVALID_ARG, "n_slots must be 1..min(64, n_parts)");
+  hgsr_pcache* pc = new hgsr_pcache();
+  pc->n = scene->n;
+  pc->sh_degree = scene->sh_degree;
+  pc->feat_dim = scene->feat_dim;
+  pc->n_parts = scene->n_parts;
+  pc->offs.assign(scene->part_offsets, scene->part_offsets + scene->n_parts + 1);
+  pc->bounds.resize(6 * static_cast<size_t>(scene->n_parts));
+  host_bounds(scene, pc->bounds.data());
+  for (int k = 0; k < pc->n_parts; ++k) pc->cap = std::max<int64_t>(pc->cap, pc->offs[k + 1] - pc->offs[k]);
+  pc->cap = std::max<int64_t>(pc->cap, 1);
+  if (static_cast<int64_t>(n_slots) * pc->cap >= (1ll << 31)) {
+    delete pc;
+    return err(HGSR_ERR_INVALID_ARG, "n_slots x largest partition must stay below 2^31 Gaussians");
+  }
+  pc->n_slots = n_slots;
+  const Widths w(pc->sh_degree, pc->feat_dim);
+  auto fail_free = [&](hgsr_status st) {
+    release_all(pc);
+    delete pc;
+    return st;
+  };
+  if (hipGetDevice(&pc->device) != hipSuccess) return fail_free(err(HGSR_ERR_HIP, "hipGetDevice failed"));
+  // pinned host copy, one block, arrays 256-byte aligned
+  const int64_t n = pc->n;
+  const size_t hb[6] = {align256(n * w.means), align256(n * w.ls), align256(n * w.quats), align256(n * w.opac),
+                        align256(n * w.sh), align256(n * w.feat)};
+  size_t htotal = 0;
+  for (size_t b : hb) htotal += b;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&pc->host), std::max<size_t>(htotal, 256), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    pc->host = nullptr;
+    return fail_free(err(HGSR_ERR_HIP, "hipHostMalloc(%zu): %s", htotal, hipGetErrorString(e)));
+  }
+  {
+    char* p = pc->host;
+    const void* src[6] = {scene->means, scene->log_scales, scene->quats, scene->opacities, scene->sh, scene->feat};
+    const size_t bytes[6] = {n * w.means, n * w.ls, n * w.quats, n * w.opac, n * w.sh, n * w.feat};
+    const char** dst[6] = {&pc->h_means, &pc->h_ls, &pc->h_quats, &pc->h_opac, &pc->h_sh, &pc->h_feat};
+    for (int a = 0; a < 6; ++a) {
+      *dst[a] = p;
+      if (bytes[a]) std::memcpy(p, src[a], bytes[a]);
+      p += hb[a];
+    }
+  }
+  // device slots + tables
+  const int64_t m = static_cast<int64_t>(n_slots) * pc->cap;
+  const size_t db[8] = {align256(m * w.means), align256(m * w.ls), align256(m * w.quats), align256(m * w.opac),
+                        align256(m * w.sh), align256(m * w.feat),
+                        align256((n_slots + 1) * sizeof(int64_t)), align256(6 * n_slots * sizeof(float))};
+  size_t dtotal = 0;
+  for (size_t b : db) dtotal += b;
+  e = hipMalloc(reinterpret_cast<void**>(&pc->dev), dtotal);
+  if (e != hipSuccess) {
+    pc->dev = nullptr;
+    return fail_free(err(HGSR_ERR_HIP, "hipMalloc(%zu) for %d slots: %s", dtotal, n_slots, hipGetErrorString(e)));
+  }
+  pc->dev_bytes = dtotal;
+  {
+    char* p = pc->dev;
+    char** dst[6] = {&pc->d_means, &pc->d_ls, &pc->d_quats, &pc->d_opac, &pc->d_sh, &pc->d_feat};
+    for (int a = 0; a < 6; ++a) {
+      *dst[a] = p;
+      p += db[a];
+    }
+    pc->d_offs = reinterpret_cast<int64_t*>(p);
+    p += db[6];
+    pc->d_bounds = reinterpret_cast<float*>(p);
+  }
+  if (hipMemset(pc->dev, 0, dtotal) != hipSuccess) return fail_free(err(HGSR_ERR_HIP, "hipMemset failed"));
+  std::vector<int64_t> so(n_slots + 1);
+  for (int sl = 0; sl <= n_slots; ++sl) so[sl] = sl * pc->cap;
+  pc->slot_box.assign(6 * static_cast<size_t>(n_slots), 0.f);
+  for (int sl = 0; sl < n_slots; ++sl)
+    for (int a = 0; a < 3; ++a) {
+      pc->slot_box[6 * sl + a] = 1.f;
+      pc->slot_box[6 * sl + 3 + a] = -1.f;
+    }
+  if (hipMemcpy(pc->d_offs, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pc->d_bounds, pc->slot_box.data(), pc->slot_box.size() * sizeof(float), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return fail_free(err(HGSR_ERR_HIP, "hipMemcpy of the slot tables failed"));
+  pc->slot_part.assign(n_slots, -1);
+  pc->slot_last.assign(n_slots, -1);
+  pc->slot_rel.assign(n_slots, nullptr);
+  pc->slot_rel_set.assign(n_slots, 0);
+  pc->part_slot.assign(pc->n_parts, -1);
+  for (int sl = 0; sl < n_slots; ++sl)
+    if (hipEventCreateWithFlags(&pc->slot_rel[sl], hipEventDisableTiming) != hipSuccess)
+      return fail_free(err(HGSR_ERR_HIP, "hipEventCreate failed"));
+  if (hipEventCreateWithFlags(&pc->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pc->prior, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&pc->copy, hipStreamNonBlocking) != hipSuccess)
+    return fail_free(err(HGSR_ERR_HIP, "stream or event creation failed"));
+  pc->st.n_slots = n_slots;
+  pc->st.slot_capacity = pc->cap;
+  pc->st.device_bytes = static_cast<int64_t>(dtotal);
+  *out = pc;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pcache_destroy(hgsr_pcache* pc) {
+  if (!pc) return HGSR_OK;
+  release_all(pc);
+  delete pc;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pcache_evict_all(hgsr_pcache* pc) {
+  if (!pc) return err(HGSR_ERR_INVALID_ARG, "NULL cache");
+  PC_HIP(hipStreamSynchronize(pc->copy));
+  for (int sl = 0; sl < pc->n_slots; ++sl) {
+    if (pc->slot_part[sl] >= 0) pc->part_slot[pc->slot_part[sl]] = -1;
+    pc->slot_part[sl] = -1;
+    for (int a = 0; a < 3; ++a) {  // empty box: never drawn again
+      pc->slot_box[6 * sl + a] = 1.f;
+      pc->slot_box[6 * sl + 3 + a] = -1.f;
+    }
+    // the slot's last use stays recorded: its next upload still waits for it
+  }
+  pc->table_dirty = true;  // written by the next prepare, after the work already enqueued
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                                float near_z, float motion_margin, hgsr_gaussians* out, hgsr_pcache_stats* stats,
+                                hgsr_stream stream) {
+  if (!pc || !out) return err(HGSR_ERR_INVALID_ARG, "NULL cache or output");
+  hgsr_status s = check_plan_args(pc->n_parts, poses, P, K, near_z, motion_margin);
+  if (s != HGSR_OK) return s;
+  const float nz = near_z > 0.f ? near_z : 0.2f;
+  // partitions the batch may see
+  std::vector<uint8_t> need(pc->n_parts, 0);
+  int n_need = 0;
+  for (int k = 0; k < pc->n_parts; ++k) {
+    for (int p = 0; p < P && !need[k]; ++p)
+      need[k] = box_may_be_seen(pc->bounds.data() + 6 * k, poses + 12 * p, *K, nz, motion_margin) ? 1 : 0;
+    n_need += need[k];
+  }
+  if (n_need > pc->n_slots)
+    return err(HGSR_ERR_CAPACITY, "the batch may see %d partitions but the cache has %d slots", n_need,
+               pc->n_slots);
+  hipStream_t rs = reinterpret_cast<hipStream_t>(stream);
+  PC_HIP(hipEventRecord(pc->prior, rs));
+  // the previous batch's slots: released once the work enqueued so far ends
+  for (int sl = 0; sl < pc->n_slots; ++sl)
+    if (pc->slot_last[sl] == pc->batch - 1 && pc->batch > 0) {
+      PC_HIP(hipEventRecord(pc->slot_rel[sl], rs));
+      pc->slot_rel_set[sl] = 1;
+    }
+  hgsr_pcache_stats& st = pc->st;
+  st.needed = n_need;
+  st.hits = st.uploads = st.evictions = 0;
+  st.bytes_uploaded = 0;
+  std::vector<uint8_t> taken(pc->n_slots, 0);
+  for (int k = 0; k < pc->n_parts; ++k)
+    if (need[k] && pc->part_slot[k] >= 0) {
+      taken[pc->part_slot[k]] = 1;
+      pc->slot_last[pc->part_slot[k]] = pc->batch;
+      ++st.hits;
+    }
+  const Widths w(pc->sh_degree, pc->feat_dim);
+  bool uploaded = false;
+  for (int k = 0; k < pc->n_parts; ++k) {
+    if (!need[k] || pc->part_slot[k] >= 0) continue;
+    // victim: an empty slot, else the least recently used one this batch does not need
+    int v = -1;
+    for (int sl = 0; sl < pc->n_slots; ++sl)
+      if (!taken[sl] && pc->slot_part[sl] < 0 && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
+    if (v < 0)
+      for (int sl = 0; sl < pc->n_slots; ++sl)
+        if (!taken[sl] && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
+    if (v < 0) return err(HGSR_ERR_STATE, "no free slot (internal)");
+    if (pc->slot_part[v] >= 0) {
+      pc->part_slot[pc->slot_part[v]] = -1;
+      ++st.evictions;
+    }
+    if (pc->slot_rel_set[v]) PC_HIP(hipStreamWaitEvent(pc->copy, pc->slot_rel[v], 0));
+    const int64_t b = pc->offs[k], cnt = pc->offs[k + 1] - pc->offs[k];
+    const int64_t d0 = static_cast<int64_t>(v) * pc->cap;
+    const char* hsrc[6] = {pc->h_means, pc->h_ls, pc->h_quats, pc->h_opac, pc->h_sh, pc->h_feat};
+    char* ddst[6] = {pc->d_means, pc->d_ls, pc->d_quats, pc->d_opac, pc->d_sh, pc->d_feat};
+    const size_t wid[6] = {w.means, w.ls, w.quats, w.opac, w.sh, w.feat};
+    for (int a = 0; a < 6; ++a) {
+      if (!wid[a] || !cnt) continue;
+      PC_HIP(hipMemcpyAsync(ddst[a] + d0 * wid[a], hsrc[a] + b * wid[a], cnt * wid[a], hipMemcpyHostToDevice,
+                            pc->copy));
+    }
+    const int64_t tail = pc->cap - cnt;
+    if (tail > 0)
+      hipLaunchKernelGGL(zero_tail_kernel, dim3(static_cast<unsigned>((tail + 255) / 256)), dim3(256), 0, pc->copy,
+                         reinterpret_cast<float*>(pc->d_opac) + d0 + cnt, tail);
+    std::copy(pc->bounds.begin() + 6 * k, pc->bounds.begin() + 6 * k + 6, pc->slot_box.begin() + 6 * v);
+    pc->table_dirty = true;
+    pc->slot_part[v] = k;
+    pc->part_slot[k] = v;
+    pc->slot_last[v] = pc->batch;
+    taken[v] = 1;
+    ++st.uploads;
+    st.bytes_uploaded += cnt * static_cast<int64_t>(w.total());
+    uploaded = true;
+  }
+  const bool wrote_table = pc->table_dirty;
+  if (pc->table_dirty) {
+    PC_HIP(hipStreamWaitEvent(pc->copy, pc->prior, 0));
+    SlotBoxes t;
+    std::memset(&t, 0, sizeof(t));
+    for (int sl = 0; sl < pc->n_slots; ++sl)
+      for (int a = 0; a < 6; ++a) t.b[sl][a] = pc->slot_box[6 * sl + a];
+    hipLaunchKernelGGL(write_boxes_kernel, dim3(1), dim3(64), 0, pc->copy, t, pc->n_slots, pc->d_bounds);
+    PC_HIP(hipGetLastError());
+    pc->table_dirty = false;
+  }
+  if (uploaded || wrote_table) {
+    // the render stream waits for this batch's uploads and table
+    PC_HIP(hipEventRecord(pc->ready, pc->copy));
+    PC_HIP(hipStreamWaitEvent(rs, pc->ready, 0));
+  }
+  st.total_uploads += st.uploads;
+  st.total_bytes += st.bytes_uploaded;
+  ++pc->batch;
+  out->n = static_cast<int64_t>(pc->n_slots) * pc->cap;
+  out->means = reinterpret_cast<const float*>(pc->d_means);
+  out->log_scales = reinterpret_cast<const float*>(pc->d_ls);
+  out->quats = reinterpret_cast<const float*>(pc->d_quats);
+  out->opacities = reinterpret_cast<const float*>(pc->d_opac);
+  out->sh = reinterpret_cast<const float*>(pc->d_sh);
+  out->sh_degree = pc->sh_degree;
+  out->feat_dim = pc->feat_dim;
+  out->feat = pc->feat_dim ? reinterpret_cast<const uint16_t*>(pc->d_feat) : nullptr;
+  out->n_parts = pc->n_slots;
+  out->part_offsets = pc->d_offs;
+  out->part_bounds = pc->d_bounds;
+  if (stats) *stats = st;
+  return HGSR_OK;
+}
+
+}  // extern "C"

@@ -52,6 +52,7 @@ __global__ void partition_cull_kernel(const float* poses, int P, const float* bo
   uint64_t mask = 0;
   for (int k = 0; k < n_parts; ++k) {
     const float* B = bounds + 6 * k;
+    if (!(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5])) continue;  // empty box (or NaN): nothing to draw
     bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
     for (int q = 0; q < 8; ++q) {
       const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
