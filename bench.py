@@ -472,6 +472,85 @@ def pose_solve(hg, torch, synth, args):
             "centre_error_m": round(float(np.linalg.norm(C(got) - C(pose))), 5), "steps_timed": args.pnp_steps}
 
 
+def streaming(hg, torch, synth, args):
+    """Out-of-core rendering: the partitioned 8M-Gaussian scene (16 cells of
+    1 km^2) kept in pinned host memory with a device budget of 6 partitions,
+    a flight of 48 query views at 1920x1080 (f = 1500, 150 m) straight across
+    the 4 x 4 km area, each batch planned with the next 4 views so that the
+    next cell is uploaded while the current views render; against the same
+    views with the whole scene resident."""
+    import math
+    import numpy as np
+    log("bench: out-of-core streaming, 8M Gaussians, 6 of 16 partitions resident, 48 views at 1080p")
+    sc = synth.config5(0)[0]
+    cam = synth.Camera(1500.0, 1500.0, 960.0, 540.0, 1920, 1080)
+    K = hg.Intrinsics.of(cam)
+    NV, AHEAD, SLOTS = 48, 4, 6
+    poses = np.stack([synth.down_pose((-1800.0 + 3600.0 * k / (NV - 1), -1500.0 + 3000.0 * k / (NV - 1)), 150.0,
+                                      (0.05, 0.0), math.pi / 5) for k in range(NV)])
+    dev_poses = torch.from_numpy(poses).cuda()
+    s = torch.cuda.Stream()
+    pc = hg.PartitionCache(sc, SLOTS)
+    r = hg.Renderer()
+    out = None
+
+    def run(timed):
+        nonlocal out
+        ups = 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for k in range(NV):
+            desc = pc.prepare(poses[k:k + 1 + AHEAD], K, stream=s)
+            ups += pc.stats["uploads"]
+            out = r.render(desc, dev_poses[k:k + 1], K, out=out, check_overflow=not timed, stream=s)
+        e1.record(s)
+        s.synchronize()
+        return e0.elapsed_time(e1) / NV, ups
+
+    run(False)                      # sizes the renderer's workspace
+    pc.evict_all()
+    t0 = pc.stats["total_bytes"]
+    ms, ups = run(True)
+    if r.check_overflow(s) != 0:
+        raise RuntimeError("workspace overflow in the streamed flight")
+    gb = (pc.stats["total_bytes"] - t0) / 1e9
+    # one cold upload (the 4 partitions of views 10..14), timed on the host (prepare + wait)
+    pc.evict_all()
+    s.synchronize()
+    t = time.perf_counter()
+    pc.prepare(poses[10:15], K, stream=s)
+    cold = pc.stats
+    s.synchronize()
+    t_up = time.perf_counter() - t
+    dev_bytes = pc.stats["device_bytes"]
+    pc.close()
+    # the same flight with the whole scene resident
+    full = hg.GaussianScene.from_numpy(sc)
+    r2 = hg.Renderer()
+    o2 = r2.render(full, dev_poses[:1], K)
+    for k in range(NV):
+        r2.render(full, dev_poses[k:k + 1], K, out=o2, stream=s)
+    s.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k in range(NV):
+        r2.render(full, dev_poses[k:k + 1], K, out=o2, check_overflow=False, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms_res = e0.elapsed_time(e1) / NV
+    scene_bytes = sum(getattr(sc, f).nbytes for f in ("means", "log_scales", "quats", "opacities", "sh", "feat"))
+    del full
+    return {"workload": "8M Gaussians in 16 partitions over 4x4 km (SH0, 32-d features) in pinned host memory, "
+                        f"{SLOTS} partitions on the device, 48 views at 1920x1080 f=1500 from 150 m crossing the area, "
+                        f"each batch planned with the next {AHEAD} views",
+            "ms_per_view_streamed": round(ms, 3), "ms_per_view_resident": round(ms_res, 3),
+            "uploads": ups, "uploaded_gb": round(gb, 3),
+            "device_budget_gb": round(dev_bytes / 1e9, 3), "scene_gb": round(scene_bytes / 1e9, 3),
+            "cold_upload": {"partitions": cold["uploads"], "gb": round(cold["bytes_uploaded"] / 1e9, 3),
+                            "ms": round(t_up * 1e3, 2),
+                            "gb_per_s": round(cold["bytes_uploaded"] / 1e9 / t_up, 1)}}
+
+
 def partitioned(hg, torch, synth, args):
     """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
     import numpy as np
@@ -583,6 +662,7 @@ def main():
     ap.add_argument("--no-matching", action="store_true")
     ap.add_argument("--match-steps", type=int, default=10)
     ap.add_argument("--no-pose-solve", action="store_true")
+    ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--pnp-steps", type=int, default=10)
     ap.add_argument("--sig-steps", type=int, default=10)
     ap.add_argument("--fb-steps", type=int, default=20)
@@ -590,7 +670,7 @@ def main():
     ap.add_argument("--part-iters", type=int, default=20)
     ap.add_argument("--part-lr-rho", type=float, default=0.3, help="Adam step (m) of the partitioned refinement")
     ap.add_argument("--part-lr-phi", type=float, default=4e-3, help="Adam step (rad) of the partitioned refinement")
-    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance", "matching", "pose_solve"],
+    ap.add_argument("--only", choices=["headline", "fwd_bwd", "partitioned", "significance", "matching", "pose_solve", "streaming"],
                     default=None,
                     help="run one section and print its result alone (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -628,12 +708,15 @@ def main():
     if args.only == "matching":
         print(json.dumps({"matching": matching(hg, torch, synth, args)}), flush=True)
         return
+    if args.only == "streaming":
+        print(json.dumps({"streaming": streaming(hg, torch, synth, args)}), flush=True)
+        return
     if args.only == "pose_solve":
         print(json.dumps({"pose_solve": pose_solve(hg, torch, synth, args)}), flush=True)
         return
     if args.only == "headline":
         args.no_fwd_bwd = args.no_partitioned = args.no_significance = args.no_matching = True
-        args.no_pose_solve = args.no_cpu = True
+        args.no_pose_solve = args.no_streaming = args.no_cpu = True
     h = headline(hg, torch, synth, args)
     result = {
         "metric": "rendered Mpix/s at 1080p/1M Gaussians",
@@ -676,6 +759,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_pose_solve:
         result["pose_solve"] = pose_solve(hg, torch, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_streaming:
+        result["streaming"] = streaming(hg, torch, synth, args)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
