@@ -183,6 +183,7 @@ typedef struct {
   int32_t schedule;
   int32_t feat_accum;
   float ms;              /* best time per render */
+  int32_t proj_group;    /* Gaussians culled per thread by the projection of up to 4 poses: 4 or 1 */
 } hgsr_tune_result;
 
 /* Create a context on the current HIP device.  The context owns the
@@ -509,6 +510,19 @@ hgsr_status hgsr_host_partition_bounds(const hgsr_host_scene* scene, float* boun
 hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const float* poses, int32_t P,
                                 const hgsr_intrinsics* K, float near_z, float motion_margin, uint8_t* seen);
 
+/* Spatial order of a scene (host only, no device work): perm (host, n int64)
+ * lists the Gaussians sorted by the Morton code of their means (21 bits per
+ * axis over the bounding box, one scale for all axes; ties by index), within
+ * each partition when part_offsets (host, n_parts + 1) is given, so that
+ * partitions stay contiguous.  A scene stored in this order renders the same
+ * images (up to the order of Gaussians at exactly equal depth) with denser
+ * projection waves, tile counts aggregated per workgroup and tile lists
+ * whose records lie close together; Gaussian i of the reordered scene is
+ * Gaussian perm[i] of the input.  Non-finite coordinates sort as the box
+ * minimum. */
+hgsr_status hgsr_host_spatial_order(const float* means, int64_t n, const int64_t* part_offsets, int32_t n_parts,
+                                    int64_t* perm);
+
 /* Check the Gaussian arrays for NaN/Inf, opacities outside [0, 1] and zero
  * quaternions.  Synchronises `stream`.  Returns HGSR_ERR_INVALID_ARG on the
  * first problem found. */
@@ -536,7 +550,9 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges,
                                   int64_t* n, hgsr_stream stream);
 
 /* Time the renderer on this input for tile sizes 8/16/32, the blend
- * schedules and (32 channels) both feature accumulations; keep the fastest as
+ * schedules and (32 channels) both feature accumulations, then (up to 4 poses) the
+ * projection's grouping (4 Gaussians per thread, or 1 -- faster for scenes in
+ * spatial order; hgsr_host_spatial_order); keep the fastest as
  * the context's default (opts->tile == 0, opts->schedule == HGSR_SCHED_AUTO,
  * opts->feat_accum == HGSR_FEAT_AUTO) and append it to the JSON-lines cache
  * file `cache_path` (host string, may be NULL), which later calls on the same

@@ -75,13 +75,25 @@ class GaussianScene:
     def device(self) -> torch.device:
         return self.means.device
 
+    order: Optional[np.ndarray] = None  # Gaussian i is input Gaussian order[i] (spatial layout), or None
+
     @staticmethod
-    def from_numpy(s, device="cuda") -> "GaussianScene":
+    def from_numpy(s, device="cuda", spatial: bool = False) -> "GaussianScene":
+        """Upload a synth-style host scene.  spatial=True stores it in Morton
+        order (within partitions; hgsr_host_spatial_order) and keeps the
+        permutation in `order`."""
+        perm = None
+        if spatial:
+            perm = spatial_order(s.means, getattr(s, "part_offsets", None))
+            s = dataclasses.replace(s, means=s.means[perm], log_scales=s.log_scales[perm], quats=s.quats[perm],
+                                    opacities=s.opacities[perm], sh=s.sh[perm],
+                                    feat=None if s.feat is None else s.feat[perm])
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
         feat = None
         if s.feat is not None:
             feat = torch.from_numpy(np.ascontiguousarray(s.feat).view(np.int16)).to(device).view(torch.bfloat16)
         sc = GaussianScene(t(s.means), t(s.log_scales), t(s.quats), t(s.opacities), t(s.sh), int(s.sh_degree), feat)
+        sc.order = perm
         if getattr(s, "part_offsets", None) is not None:
             sc.part_offsets = t(s.part_offsets.astype(np.int64))
             sc.part_bounds = torch.empty((len(s.part_offsets) - 1, 6), dtype=torch.float32, device=device)
@@ -107,6 +119,19 @@ class GaussianScene:
     def validate(self):
         g = self.c()
         check(_lib.load().hgsr_validate(ctypes.byref(g), _stream_ptr()), "hgsr_validate")
+
+
+def spatial_order(means: np.ndarray, part_offsets: Optional[np.ndarray] = None) -> np.ndarray:
+    """Morton order of the Gaussians (within partitions), computed on the
+    host by hgsr_host_spatial_order."""
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    n = int(m.shape[0])
+    perm = np.empty(n, dtype=np.int64)
+    offs = None if part_offsets is None else np.ascontiguousarray(part_offsets, dtype=np.int64)
+    check(_lib.load().hgsr_host_spatial_order(m.ctypes.data, n, None if offs is None else offs.ctypes.data,
+                                              0 if offs is None else len(offs) - 1, perm.ctypes.data),
+          "hgsr_host_spatial_order")
+    return perm
 
 
 def _host_scene(s) -> tuple:
@@ -497,7 +522,8 @@ class Renderer:
                                      None if cache_path is None else cache_path.encode(), ctypes.byref(res),
                                      _stream_ptr(stream)), "hgsr_autotune")
         return dict(tile=res.tile, schedule={0: "grid", 1: "pose", 2: "tile"}[res.schedule],
-                    feat_accum={1: "valu", 2: "mfma"}.get(res.feat_accum, "valu"), ms=res.ms)
+                    feat_accum={1: "valu", 2: "mfma"}.get(res.feat_accum, "valu"), ms=res.ms,
+                    proj_group=res.proj_group)
 
     def profile(self, enable: bool):
         check(self.lib.hgsr_profile_enable(self.ctx, int(enable)), "hgsr_profile_enable")

@@ -54,7 +54,7 @@ class RenderStats(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("tile", I32), ("schedule", I32), ("feat_accum", I32), ("ms", F32)]
+    _fields_ = [("tile", I32), ("schedule", I32), ("feat_accum", I32), ("ms", F32), ("proj_group", I32)]
 
 
 class ResidualTargets(ctypes.Structure):
@@ -124,6 +124,7 @@ SIGNATURES = {
     "hgsr_pcache_evict_all": [P_],
     "hgsr_host_partition_bounds": [ctypes.POINTER(HostScene), P_],
     "hgsr_partition_plan": [P_, I32, P_, I32, ctypes.POINTER(Intrinsics), F32, F32, P_],
+    "hgsr_host_spatial_order": [P_, I64, P_, I32, P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],
     "hgsr_graph_end": [P_],

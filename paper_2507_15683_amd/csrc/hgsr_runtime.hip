@@ -96,6 +96,7 @@ struct hgsr_ctx {
   int tuned_tile = 0;
   int tuned_sched = -1;
   int tuned_feat = 0;
+  int tuned_proj = 0;  // Gaussians per thread of the few-pose projection (0: default 4)
 
   // stage timing
   bool profiling = false;
@@ -346,7 +347,7 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     for (int p0 = 0; p0 < P; p0 += kMaxPoses) {
       pa.P = std::min(kMaxPoses, P - p0);
       pa.pose_base = p0;
-      if (count_in_project) launch_project(pa, s);
+      if (count_in_project) launch_project(pa, c->tuned_proj ? c->tuned_proj : 4, s);
       else launch_cull(pa, s);
     }
     if (!count_in_project) launch_splat(pa, P, s);
@@ -1111,7 +1112,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     FILE* f = fopen(cache_path, "r");
     if (f) {
       char line[1024];
-      int t = 0, sc = -1, fa = HGSR_FEAT_VALU;
+      int t = 0, sc = -1, fa = HGSR_FEAT_VALU, pg = 4;
       float ms = 0.f;
       while (fgets(line, sizeof(line), f)) {
         if (!strstr(line, key)) continue;
@@ -1119,19 +1120,23 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
         const char* ps = strstr(line, "\"schedule\": ");
         const char* pf = strstr(line, "\"feat_accum\": ");
         const char* pm = strstr(line, "\"ms\": ");
+        const char* pp = strstr(line, "\"proj_group\": ");
         if (pt && ps && pm) {
           t = atoi(pt + 8);
           sc = atoi(ps + 12);
           fa = pf ? atoi(pf + 14) : HGSR_FEAT_VALU;
+          pg = pp ? atoi(pp + 14) : 4;
           ms = static_cast<float>(atof(pm + 6));
         }
       }
       fclose(f);
-      if ((t == 8 || t == 16 || t == 32) && sc >= 0 && sc <= 2 && (fa == HGSR_FEAT_VALU || fa == HGSR_FEAT_MFMA)) {
+      if ((t == 8 || t == 16 || t == 32) && sc >= 0 && sc <= 2 && (fa == HGSR_FEAT_VALU || fa == HGSR_FEAT_MFMA) &&
+          (pg == 1 || pg == 4)) {
         c->tuned_tile = t;
         c->tuned_sched = sc;
         c->tuned_feat = fa;
-        if (result) *result = {t, sc, fa, ms};
+        c->tuned_proj = pg;
+        if (result) *result = {t, sc, fa, ms, pg};
         return HGSR_OK;
       }
     }
@@ -1144,6 +1149,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
   HIP_TRY(hipEventCreate(&b));
   float best = 1e30f;
   int bt = 16, bs = HGSR_SCHED_GRID, bf = HGSR_FEAT_VALU;
+  c->tuned_proj = 4;  // the sweep runs with the default grouping
   for (int t : tiles)
     for (int sc : scheds)
       for (int fa : feats) {
@@ -1174,17 +1180,41 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
         bf = fa;
       }
     }
+  // the few-pose projection's grouping, with the chosen blend (it only
+  // matters up to kCountInProjectPoses poses); group 4 was timed in the sweep
+  int bp = 4;
+  if (P <= kCountInProjectPoses) {
+    hgsr_opts o = *opts;
+    o.tile = bt;
+    o.schedule = bs;
+    o.feat_accum = bf;
+    c->tuned_proj = 1;
+    TRY(run(&o));
+    const int reps = 5;
+    HIP_TRY(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r) TRY(run(&o));
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    ms /= reps;
+    if (ms < best) {
+      best = ms;
+      bp = 1;
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   c->tuned_tile = bt;
   c->tuned_sched = bs;
   c->tuned_feat = bf;
-  if (result) *result = {bt, bs, bf, best};
+  c->tuned_proj = bp;
+  if (result) *result = {bt, bs, bf, best, bp};
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "{%s, \"tile\": %d, \"schedule\": %d, \"feat_accum\": %d, \"ms\": %.5f}\n", key, bt, bs, bf,
-              best);
+      fprintf(f, "{%s, \"tile\": %d, \"schedule\": %d, \"feat_accum\": %d, \"proj_group\": %d, \"ms\": %.5f}\n", key,
+              bt, bs, bf, bp, best);
       fclose(f);
     }
   }

@@ -187,7 +187,8 @@ void launch_partition_cull(const float* poses, int P, const float* bounds, int n
 // few poses: the fused pass per launch of up to kMaxPoses poses; many
 // poses: the cull pass per launch of up to kMaxPoses poses, then the splat
 // pass once for all
-void launch_project(const ProjectArgs& a, hipStream_t s);
+// group: Gaussians culled per thread of the fused pass (1 or 4)
+void launch_project(const ProjectArgs& a, int group, hipStream_t s);
 void launch_cull(const ProjectArgs& a, hipStream_t s);
 void launch_splat(const ProjectArgs& a, int P_total, hipStream_t s);
 void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s);

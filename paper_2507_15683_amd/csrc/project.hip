@@ -70,76 +70,188 @@ __global__ void partition_cull_kernel(const float* poses, int P, const float* bo
 }
 
 // ------------------------------------------------------------ projection
-// Few poses: one fused pass.  One thread per Gaussian, looping over the
-// launch's poses (the Gaussian's parameters are read once for all poses).
-// Visible (pose, Gaussian) pairs are compacted per pose: phase 1 counts them
-// per block in LDS, one global atomic per (block, pose) reserves a range of
-// that pose's record segment, phase 2 recomputes the footprint and writes the
-// records.  With many poses the lanes of a wave rarely share a visible pose,
-// so the expensive footprint runs on a few lanes per wave; the two passes
-// below (cull, then one thread per candidate) keep those lanes dense.
+// Few poses, compacted: a block culls G x 256 Gaussians with the
+// cheap tests (opacity, partition, near plane, conservative footprint bound;
+// all loads of a thread issued together), appends the candidates to an LDS
+// list, and then runs the exact footprint, the record and the tile counts
+// over that list with consecutive threads -- the ~7 % of Gaussians a view
+// keeps fill whole waves instead of a few lanes of every wave.  Visible
+// (pose, Gaussian) pairs are compacted per pose: phase B counts them per
+// block in LDS, one global atomic per (block, pose) reserves a range of one
+// of the pose's kSub record sub-segments, phase C recomputes the footprint
+// (same inputs, same arithmetic) and writes the records.  G = 4 suits scenes in arbitrary order (every workgroup keeps a
+// few percent); G = 1 suits spatially ordered ones (a workgroup keeps all or
+// nothing, and small workgroups spread the kept ones over the chip).  The
+// autotuner picks.
+
+// Tile-count histogram of one block's records when they fall in a small tile
+// rectangle (a spatially ordered scene): counted in LDS, then one global
+// atomic per non-empty tile instead of one per (record, tile).
+constexpr int kProjHist = 2048;
+struct BlockHist {
+  uint32_t* bins;  // LDS, kProjHist, or null: count in global memory
+  int tx0, ty0, w;
+};
+
 template <int DEG>
-__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+__device__ __forceinline__ void write_record(const ProjectArgs& a, int64_t i, const float mu[3], float o, float k2,
+                                             const float* T, int pg, const float mc[3], const Footprint& f,
+                                             uint32_t slot, const BlockHist& hist) {
+  const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
+  const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
+  const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
+  float dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
+  const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+  dx *= inv; dy *= inv; dz *= inv;
+  float rgb[3];
+  sh_colour_raw<DEG>(a.g.sh, i, dx, dy, dz, rgb);
+  const int64_t idx = static_cast<int64_t>(pg) * a.rec_cap + slot;
+  Splat sp;
+  sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
+  sp.cc = f.cc; sp.o = o; sp.z = mc[2]; sp.gid = static_cast<uint32_t>(i);
+  sp.r = fmaxf(rgb[0], 0.f); sp.g = fmaxf(rgb[1], 0.f); sp.b = fmaxf(rgb[2], 0.f);
+  sp.pmin = -0.5f * k2;
+  float4* dst = reinterpret_cast<float4*>(a.recs + idx);
+  const float4* src = reinterpret_cast<const float4*>(&sp);
+  dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
+  const int tx0 = f.px0 >> a.c.tile_shift, tx1 = f.px1 >> a.c.tile_shift;
+  const int ty0 = f.py0 >> a.c.tile_shift, ty1 = f.py1 >> a.c.tile_shift;
+  a.rects[idx] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
+                            static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
+  if (a.tile_count || a.rec_keys) {
+    const SplatShape shp = splat_shape(sp.u, sp.v, sp.ca, sp.cb, sp.cc, -2.f * sp.pmin);
+    uint32_t ntiles = 0;
+    uint32_t* tc = a.tile_count ? a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose : nullptr;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      if (hist.bins && tc) {
+        for (int tx = ta; tx <= tb; ++tx) atomicAdd(&hist.bins[(ty - hist.ty0) * hist.w + (tx - hist.tx0)], 1u);
+        ntiles += tb >= ta ? static_cast<uint32_t>(tb - ta + 1) : 0u;
+        continue;
+      }
+      for (int tx = ta; tx <= tb; ++tx) {
+        ++ntiles;
+        if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
+      }
+    }
+    if (a.rec_keys) a.rec_keys[idx] = ntiles;
+  }
+}
+
+template <int DEG, int G>
+__global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
+  constexpr int kProjPerThread = G;
+  constexpr int kProjBlockItems = 256 * G;
   __shared__ uint32_t s_cnt[kMaxPoses];
   __shared__ uint32_t s_base[kMaxPoses];
+  __shared__ uint32_t s_nc;
+  __shared__ uint32_t s_idx[kProjBlockItems];  // candidate: offset from the block's first Gaussian
+  __shared__ uint64_t s_mask[kProjBlockItems]; // poses that may see it
+  __shared__ uint32_t s_hist[kProjHist];
+  __shared__ int s_rect[4];                     // tile rectangle of the block's records (one pose)
   const int tid = threadIdx.x;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kProjBlockItems;
   for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
+  if (tid == 0) {
+    s_nc = 0;
+    s_rect[0] = s_rect[1] = 0x7fffffff;
+    s_rect[2] = s_rect[3] = -1;
+  }
 
-  bool live = i < a.g.n;
-  float mu[3] = {0.f, 0.f, 0.f}, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, o = 0.f, k2 = 0.f;
-  float ls[3] = {0.f, 0.f, 0.f}, s2max = 0.f;
-  bool have_cov = false;  // the covariance is formed for the first pose that may see the Gaussian
-  uint64_t pose_ok = ~0ull;
-  if (live) {
-    o = a.g.opac[i];
-    live = o >= kAlphaMin;  // also false for NaN
-    if (live && a.g.n_parts > 0) {
+  // phase A: the cheap tests
+  float o[kProjPerThread];
+  uint64_t pose_ok[kProjPerThread];
+  bool live[kProjPerThread];
+#pragma unroll
+  for (int q = 0; q < kProjPerThread; ++q) {
+    const int64_t i = base + q * 256 + tid;
+    o[q] = i < a.g.n ? a.g.opac[i] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < kProjPerThread; ++q) {
+    const int64_t i = base + q * 256 + tid;
+    live[q] = o[q] >= kAlphaMin;  // also false for NaN and past the end
+    pose_ok[q] = ~0ull;
+    if (live[q] && a.g.n_parts > 0) {
       int part = 0;
       while (part + 1 < a.g.n_parts && a.g.part_offsets[part + 1] <= i) ++part;
-      pose_ok = 0;
+      uint64_t ok = 0;
       for (int p = 0; p < a.P; ++p)
-        if ((a.part_vis[a.pose_base + p] >> part) & 1ull) pose_ok |= (1ull << p);
-      live = pose_ok != 0;
+        if ((a.part_vis[a.pose_base + p] >> part) & 1ull) ok |= (1ull << p);
+      pose_ok[q] = ok;
+      live[q] = ok != 0;
     }
   }
-  if (live) {
-    mu[0] = a.g.means[3 * i];
-    mu[1] = a.g.means[3 * i + 1];
-    mu[2] = a.g.means[3 * i + 2];
-    ls[0] = a.g.log_scales[3 * i];
-    ls[1] = a.g.log_scales[3 * i + 1];
-    ls[2] = a.g.log_scales[3 * i + 2];
-    s2max = __expf(2.f * fmaxf(ls[0], fmaxf(ls[1], ls[2])));
-    k2 = 2.f * __logf(255.f * o);
+  float mu[kProjPerThread][3], lsm[kProjPerThread];
+#pragma unroll
+  for (int q = 0; q < kProjPerThread; ++q) {
+    const int64_t i = base + q * 256 + tid;
+    if (live[q]) {
+      mu[q][0] = a.g.means[3 * i];
+      mu[q][1] = a.g.means[3 * i + 1];
+      mu[q][2] = a.g.means[3 * i + 2];
+      lsm[q] = fmaxf(a.g.log_scales[3 * i], fmaxf(a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]));
+    }
   }
-  __syncthreads();
-
-  // phase 1: count visible poses per block; vis_mask keeps the result for
-  // phase 2
-  uint64_t vis_mask = 0;
-  if (live) {
+  __syncthreads();  // s_nc and s_cnt cleared
+#pragma unroll
+  for (int q = 0; q < kProjPerThread; ++q) {
+    if (!live[q]) continue;
+    const float s2max = __expf(2.f * lsm[q]);
+    const float k2 = 2.f * __logf(255.f * o[q]);
+    uint64_t cand = 0;
     for (int p = 0; p < a.P; ++p) {
-      if (!((pose_ok >> p) & 1ull)) continue;
+      if (!((pose_ok[q] >> p) & 1ull)) continue;
       const float* T = a.poses + 12 * (a.pose_base + p);
       float mc[3];
-      to_camera(T, mu, mc);
+      to_camera(T, mu[q], mc);
       if (!(mc[2] > a.c.near_z)) continue;
-      if (!maybe_visible(mc, s2max, k2, a.c)) continue;
-      if (!have_cov) {
-        cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
-        have_cov = true;
-      }
+      if (maybe_visible(mc, s2max, k2, a.c)) cand |= 1ull << p;
+    }
+    if (cand) {
+      const uint32_t e = atomicAdd(&s_nc, 1u);
+      s_idx[e] = static_cast<uint32_t>(q * 256 + tid);
+      s_mask[e] = cand;
+    }
+  }
+  __syncthreads();
+  const uint32_t nc = s_nc;
+
+  // phase B: exact footprints on the compacted candidates, counted per pose
+  uint64_t vis[kProjPerThread];
+#pragma unroll
+  for (int k = 0; k < kProjPerThread; ++k) {
+    vis[k] = 0;
+    const uint32_t e = static_cast<uint32_t>(k * 256 + tid);
+    if (e >= nc) continue;
+    const int64_t i = base + s_idx[e];
+    const uint64_t cand = s_mask[e];
+    const float m[3] = {a.g.means[3 * i], a.g.means[3 * i + 1], a.g.means[3 * i + 2]};
+    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+    const float oo = a.g.opac[i];
+    const float k2 = 2.f * __logf(255.f * oo);
+    float S[6];
+    cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
+    for (int p = 0; p < a.P; ++p) {
+      if (!((cand >> p) & 1ull)) continue;
+      const float* T = a.poses + 12 * (a.pose_base + p);
+      float mc[3];
+      to_camera(T, m, mc);
       Footprint f;
       if (footprint(T, mc, S, k2, a.c, f)) {
         atomicAdd(&s_cnt[p], 1u);
-        vis_mask |= 1ull << p;
+        vis[k] |= 1ull << p;
+        if (a.P == 1) {
+          atomicMin(&s_rect[0], f.px0 >> a.c.tile_shift);
+          atomicMin(&s_rect[1], f.py0 >> a.c.tile_shift);
+          atomicMax(&s_rect[2], f.px1 >> a.c.tile_shift);
+          atomicMax(&s_rect[3], f.py1 >> a.c.tile_shift);
+        }
       }
     }
   }
   __syncthreads();
-  // each block reserves its slots from one of kSub counters per pose, so the
-  // blocks' atomics spread over kSub addresses instead of one
   const int sub = static_cast<int>(blockIdx.x % kSub);
   const uint32_t sub_cap = a.rec_cap / kSub;
   for (int p = tid; p < a.P; p += 256) {
@@ -147,67 +259,59 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     s_base[p] = cnt ? atomicAdd(&a.pose_count[(a.pose_base + p) * kSub + sub], cnt) : 0u;
     s_cnt[p] = 0;
   }
+  // one pose whose records span a small tile rectangle: count in LDS
+  BlockHist hist;
+  hist.bins = nullptr;
+  hist.tx0 = s_rect[0];
+  hist.ty0 = s_rect[1];
+  hist.w = s_rect[2] - s_rect[0] + 1;
+  const int hist_h = s_rect[3] - s_rect[1] + 1;
+  const bool use_hist = a.P == 1 && a.tile_count && s_rect[2] >= 0 && hist.w * hist_h <= kProjHist;
+  if (use_hist) {
+    hist.bins = s_hist;
+    for (int b = tid; b < hist.w * hist_h; b += 256) s_hist[b] = 0;
+  }
   __syncthreads();
 
-  // phase 2: write records (footprints recomputed, same inputs and
-  // arithmetic as phase 1)
-  if (!vis_mask) return;
-  for (int p = 0; p < a.P; ++p) {
-    if (!((vis_mask >> p) & 1ull)) continue;
-    const int pg = a.pose_base + p;
-    const float* T = a.poses + 12 * pg;
-    float mc[3];
-    to_camera(T, mu, mc);
-    Footprint f;
-    footprint(T, mc, S, k2, a.c, f);
-    const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
-    if (local >= sub_cap) {
-      atomicOr(a.flags, 1);
-      continue;
-    }
-    const uint32_t slot = sub * sub_cap + local;
-    // view direction from the camera centre C = -R^T t
-    const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
-    const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
-    const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
-    float dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
-    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv; dy *= inv; dz *= inv;
-    float rgb[3];
-    sh_colour_raw<DEG>(a.g.sh, i, dx, dy, dz, rgb);
-    const int64_t idx = static_cast<int64_t>(pg) * a.rec_cap + slot;
-    Splat sp;
-    sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
-    sp.cc = f.cc; sp.o = o; sp.z = mc[2]; sp.gid = static_cast<uint32_t>(i);
-    sp.r = fmaxf(rgb[0], 0.f); sp.g = fmaxf(rgb[1], 0.f); sp.b = fmaxf(rgb[2], 0.f);
-    sp.pmin = -0.5f * k2;
-    float4* dst = reinterpret_cast<float4*>(a.recs + idx);
-    const float4* src = reinterpret_cast<const float4*>(&sp);
-    dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
-    const int tx0 = f.px0 >> a.c.tile_shift, tx1 = f.px1 >> a.c.tile_shift;
-    const int ty0 = f.py0 >> a.c.tile_shift, ty1 = f.py1 >> a.c.tile_shift;
-    a.rects[idx] = make_uint2(static_cast<uint32_t>(tx0) | (static_cast<uint32_t>(tx1) << 16),
-                              static_cast<uint32_t>(ty0) | (static_cast<uint32_t>(ty1) << 16));
-    // few poses: the record's tiles are counted here (row spans of the same
-    // stored values count_tiles_kernel would read); many poses: there
-    if (a.tile_count || a.rec_keys) {
-      const SplatShape shp = splat_shape(sp.u, sp.v, sp.ca, sp.cb, sp.cc, -2.f * sp.pmin);
-      uint32_t ntiles = 0;
-      uint32_t* tc = a.tile_count ? a.tile_count + static_cast<int64_t>(pg) * a.c.tiles_per_pose : nullptr;
-      for (int ty = ty0; ty <= ty1; ++ty) {
-        int ta, tb;
-        row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
-        for (int tx = ta; tx <= tb; ++tx) {
-          ++ntiles;
-          if (tc) atomicAdd(&tc[ty * a.c.ntx + tx], 1u);
-        }
+  // phase C: the records (footprints recomputed from the same inputs)
+#pragma unroll
+  for (int k = 0; k < kProjPerThread; ++k) {
+    if (!vis[k]) continue;
+    const uint32_t e = static_cast<uint32_t>(k * 256 + tid);
+    const int64_t i = base + s_idx[e];
+    const float m[3] = {a.g.means[3 * i], a.g.means[3 * i + 1], a.g.means[3 * i + 2]};
+    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+    const float oo = a.g.opac[i];
+    const float k2 = 2.f * __logf(255.f * oo);
+    float S[6];
+    cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
+    for (int p = 0; p < a.P; ++p) {
+      if (!((vis[k] >> p) & 1ull)) continue;
+      const int pg = a.pose_base + p;
+      const float* T = a.poses + 12 * pg;
+      float mc[3];
+      to_camera(T, m, mc);
+      Footprint f;
+      footprint(T, mc, S, k2, a.c, f);
+      const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
+      if (local >= sub_cap) {
+        atomicOr(a.flags, 1);
+        continue;
       }
-      if (a.rec_keys) a.rec_keys[idx] = ntiles;
+      write_record<DEG>(a, i, m, oo, k2, T, pg, mc, f, sub * sub_cap + local, hist);
+    }
+  }
+  if (use_hist) {
+    __syncthreads();
+    uint32_t* tc = a.tile_count + static_cast<int64_t>(a.pose_base) * a.c.tiles_per_pose;
+    for (int b = tid; b < hist.w * hist_h; b += 256) {
+      const uint32_t v = s_hist[b];
+      if (v) atomicAdd(&tc[(hist.ty0 + b / hist.w) * a.c.ntx + hist.tx0 + b % hist.w], v);
     }
   }
 }
 
-// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.
+// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.
 //
 // cull_kernel: one thread per Gaussian, looping over the launch's poses,
 // applies the opacity, partition, near-plane and conservative footprint
@@ -409,14 +513,20 @@ void launch_partition_cull(const float* poses, int P, const float* bounds, int n
                      margin, vis);
 }
 
-void launch_project(const ProjectArgs& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>((a.g.n + 255) / 256));
+template <int G>
+static void launch_project_g(const ProjectArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((a.g.n + 256 * G - 1) / (256 * G)));
   switch (a.g.sh_degree) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((project_dense_kernel<0, G>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_dense_kernel<1, G>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_dense_kernel<2, G>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_dense_kernel<3, G>), grid, dim3(256), 0, s, a); break;
   }
+}
+
+void launch_project(const ProjectArgs& a, int group, hipStream_t s) {
+  if (group == 1) launch_project_g<1>(a, s);
+  else launch_project_g<4>(a, s);
 }
 
 void launch_cull(const ProjectArgs& a, hipStream_t s) {

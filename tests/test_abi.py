@@ -50,7 +50,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Gaussians) == 8 + 5 * 8 + 4 + 4 + 8 + 8 + 8 + 8  # n, 5 ptrs, deg, D, feat, parts...
     assert ctypes.sizeof(_lib.Intrinsics) == 24
     assert ctypes.sizeof(_lib.Opts) == 4 * 3 + 12 + 4 + 4 + 4 + 4
-    assert ctypes.sizeof(_lib.TuneResult) == 16
+    assert ctypes.sizeof(_lib.TuneResult) == 20
     assert ctypes.sizeof(_lib.ResidualTargets) == 24
     assert ctypes.sizeof(_lib.Outputs) == 32
     assert ctypes.sizeof(_lib.Grads) == 56
