@@ -218,7 +218,7 @@ def fwd_bwd(hg, torch, synth, args):
     """64 candidate poses, 960x540, 1M Gaussians: batched + graph vs plain."""
     log("bench: fwd+bwd, 64 poses at 960x540")
     sc, P, cam, seed = synth.config3(0, with_seed=True)
-    scene = hg.GaussianScene.from_numpy(sc)
+    scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     K = hg.Intrinsics.of(cam)
     NP = P.shape[0]
     rt = hg.Renderer()
@@ -317,7 +317,7 @@ def significance(hg, torch, synth, args):
     import ctypes
     log("bench: significance scoring, 64 views at 960x540")
     sc, P, cam = synth.config3(0)
-    scene = hg.GaussianScene.from_numpy(sc)
+    scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     K = hg.Intrinsics.of(cam)
     NP, W, H, D, n = P.shape[0], cam.width, cam.height, sc.feat_dim, sc.n
     poses = torch.from_numpy(P).cuda()
@@ -492,7 +492,8 @@ def streaming(hg, torch, synth, args):
                                       (0.05, 0.0), math.pi / 5) for k in range(NV)])
     dev_poses = torch.from_numpy(poses).cuda()
     s = torch.cuda.Stream()
-    pc = hg.PartitionCache(sc, SLOTS)
+    host = hg.spatial_layout(sc)[0] if args.layout == "spatial" else sc
+    pc = hg.PartitionCache(host, SLOTS)
     r = hg.Renderer()
     out = None
 
@@ -527,7 +528,7 @@ def streaming(hg, torch, synth, args):
     dev_bytes = pc.stats["device_bytes"]
     pc.close()
     # the same flight with the whole scene resident
-    full = hg.GaussianScene.from_numpy(sc)
+    full = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     r2 = hg.Renderer()
     o2 = r2.render(full, dev_poses[:1], K)
     for k in range(NV):
@@ -558,7 +559,7 @@ def partitioned(hg, torch, synth, args):
     import numpy as np
     log("bench: partitioned scene (8M Gaussians) generation")
     sc, truth, start, cams = synth.config5(0)
-    scene = hg.GaussianScene.from_numpy(sc)
+    scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     NQ = truth.shape[0]
     s = torch.cuda.Stream()
     r = hg.Renderer()

@@ -183,7 +183,7 @@ typedef struct {
   int32_t schedule;
   int32_t feat_accum;
   float ms;              /* best time per render */
-  int32_t proj_group;    /* Gaussians culled per thread by the projection of up to 4 poses: 4 or 1 */
+  int32_t proj_group;    /* Gaussians culled per thread by the projection of up to 4 poses: 1 or 4 */
 } hgsr_tune_result;
 
 /* Create a context on the current HIP device.  The context owns the
@@ -551,8 +551,9 @@ hgsr_status hgsr_debug_tile_lists(hgsr_ctx* ctx, int32_t pose, uint32_t* ranges,
 
 /* Time the renderer on this input for tile sizes 8/16/32, the blend
  * schedules and (32 channels) both feature accumulations, then (up to 4 poses) the
- * projection's grouping (4 Gaussians per thread, or 1 -- faster for scenes in
- * spatial order; hgsr_host_spatial_order); keep the fastest as
+ * projection's grouping (1 Gaussian per thread, the default, suited to scenes
+ * in spatial order -- hgsr_host_spatial_order --, or 4, often faster for
+ * scenes in arbitrary order); keep the fastest as
  * the context's default (opts->tile == 0, opts->schedule == HGSR_SCHED_AUTO,
  * opts->feat_accum == HGSR_FEAT_AUTO) and append it to the JSON-lines cache
  * file `cache_path` (host string, may be NULL), which later calls on the same

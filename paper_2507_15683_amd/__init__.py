@@ -84,10 +84,7 @@ class GaussianScene:
         permutation in `order`."""
         perm = None
         if spatial:
-            perm = spatial_order(s.means, getattr(s, "part_offsets", None))
-            s = dataclasses.replace(s, means=s.means[perm], log_scales=s.log_scales[perm], quats=s.quats[perm],
-                                    opacities=s.opacities[perm], sh=s.sh[perm],
-                                    feat=None if s.feat is None else s.feat[perm])
+            s, perm = spatial_layout(s)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
         feat = None
         if s.feat is not None:
@@ -132,6 +129,16 @@ def spatial_order(means: np.ndarray, part_offsets: Optional[np.ndarray] = None) 
                                               0 if offs is None else len(offs) - 1, perm.ctypes.data),
           "hgsr_host_spatial_order")
     return perm
+
+
+def spatial_layout(s):
+    """A host scene (synth-style dataclass of numpy arrays) reordered into
+    Morton order within its partitions; returns (reordered scene, perm) with
+    Gaussian i of the result = Gaussian perm[i] of the input."""
+    perm = spatial_order(s.means, getattr(s, "part_offsets", None))
+    return dataclasses.replace(s, means=s.means[perm], log_scales=s.log_scales[perm], quats=s.quats[perm],
+                               opacities=s.opacities[perm], sh=s.sh[perm],
+                               feat=None if s.feat is None else s.feat[perm]), perm
 
 
 def _host_scene(s) -> tuple:

@@ -96,7 +96,7 @@ struct hgsr_ctx {
   int tuned_tile = 0;
   int tuned_sched = -1;
   int tuned_feat = 0;
-  int tuned_proj = 0;  // Gaussians per thread of the few-pose projection (0: default 4)
+  int tuned_proj = 0;  // Gaussians per thread of the few-pose projection (0: default 1, the spatial layout's)
 
   // stage timing
   bool profiling = false;
@@ -347,7 +347,7 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     for (int p0 = 0; p0 < P; p0 += kMaxPoses) {
       pa.P = std::min(kMaxPoses, P - p0);
       pa.pose_base = p0;
-      if (count_in_project) launch_project(pa, c->tuned_proj ? c->tuned_proj : 4, s);
+      if (count_in_project) launch_project(pa, c->tuned_proj ? c->tuned_proj : 1, s);
       else launch_cull(pa, s);
     }
     if (!count_in_project) launch_splat(pa, P, s);
@@ -1112,7 +1112,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     FILE* f = fopen(cache_path, "r");
     if (f) {
       char line[1024];
-      int t = 0, sc = -1, fa = HGSR_FEAT_VALU, pg = 4;
+      int t = 0, sc = -1, fa = HGSR_FEAT_VALU, pg = 1;
       float ms = 0.f;
       while (fgets(line, sizeof(line), f)) {
         if (!strstr(line, key)) continue;
@@ -1125,7 +1125,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
           t = atoi(pt + 8);
           sc = atoi(ps + 12);
           fa = pf ? atoi(pf + 14) : HGSR_FEAT_VALU;
-          pg = pp ? atoi(pp + 14) : 4;
+          pg = pp ? atoi(pp + 14) : 1;
           ms = static_cast<float>(atof(pm + 6));
         }
       }
@@ -1149,7 +1149,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
   HIP_TRY(hipEventCreate(&b));
   float best = 1e30f;
   int bt = 16, bs = HGSR_SCHED_GRID, bf = HGSR_FEAT_VALU;
-  c->tuned_proj = 4;  // the sweep runs with the default grouping
+  c->tuned_proj = 1;  // the sweep runs with the default grouping
   for (int t : tiles)
     for (int sc : scheds)
       for (int fa : feats) {
@@ -1181,14 +1181,14 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
       }
     }
   // the few-pose projection's grouping, with the chosen blend (it only
-  // matters up to kCountInProjectPoses poses); group 4 was timed in the sweep
-  int bp = 4;
+  // matters up to kCountInProjectPoses poses); group 1 was timed in the sweep
+  int bp = 1;
   if (P <= kCountInProjectPoses) {
     hgsr_opts o = *opts;
     o.tile = bt;
     o.schedule = bs;
     o.feat_accum = bf;
-    c->tuned_proj = 1;
+    c->tuned_proj = 4;
     TRY(run(&o));
     const int reps = 5;
     HIP_TRY(hipEventRecord(a, s));
@@ -1200,7 +1200,7 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
     ms /= reps;
     if (ms < best) {
       best = ms;
-      bp = 1;
+      bp = 4;
     }
   }
   (void)hipEventDestroy(a);

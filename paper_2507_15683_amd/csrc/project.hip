@@ -79,9 +79,10 @@ __global__ void partition_cull_kernel(const float* poses, int P, const float* bo
 // (pose, Gaussian) pairs are compacted per pose: phase B counts them per
 // block in LDS, one global atomic per (block, pose) reserves a range of one
 // of the pose's kSub record sub-segments, phase C recomputes the footprint
-// (same inputs, same arithmetic) and writes the records.  G = 4 suits scenes in arbitrary order (every workgroup keeps a
-// few percent); G = 1 suits spatially ordered ones (a workgroup keeps all or
-// nothing, and small workgroups spread the kept ones over the chip).  The
+// (same inputs, same arithmetic) and writes the records.  G = 1 (the
+// default) suits spatially ordered scenes (a workgroup keeps all or nothing,
+// and small workgroups spread the kept ones over the chip); G = 4 suits
+// scenes in arbitrary order (every workgroup keeps a few percent).  The
 // autotuner picks.
 
 // Tile-count histogram of one block's records when they fall in a small tile
