@@ -5,11 +5,9 @@
 // sample by Gauss-Newton steps from the prior pose (one thread per
 // hypothesis, FP64 -- a 3-point system is exactly determined, its normal
 // matrix often ill-conditioned, and the singularity test needs the range --
-// 6x6 Cholesky); pnp_score_kernel counts every
-// hypothesis' inliers (reprojection error below tau, positive depth) with the
-// hypotheses staged in LDS, per-workgroup counts in LDS and one global atomic
-// per (workgroup, hypothesis) -- integer sums, so the counts do not depend on
-// scheduling; pnp_select_kernel takes the best (ties: lowest index).  The
+// 6x6 Cholesky); pnp_score_mfma_kernel counts every hypothesis' inliers
+// (reprojection error below tau, positive depth), the per-pair transform on
+// the matrix cores; pnp_select_kernel takes the best (ties: lowest index).  The
 // refinement (the truncated quadratic min(e^2, tau^2) of Eq. 10) alternates
 // pnp_normal_kernel -- per point: inlier test, 2x6 Jacobian of the
 // reprojection under the left perturbation, accumulation of J^T J and J^T r,
@@ -170,65 +168,81 @@ __global__ void pnp_hyp_kernel(PnpArgs a) {
 }
 
 // ------------------------------------------------------------ scoring
-constexpr int kPnpHypPerBlock = 64;
-constexpr int kPnpPointsPerThread = 4;
 
-__global__ __launch_bounds__(256) void pnp_score_kernel(PnpArgs a) {
-  // Per hypothesis the rows of K [R | t]: with (a, b, z) = K [R | t] X the
-  // test |(a/z, b/z) - p| < tau, z > 0 is |(a - p_u z, b - p_v z)|^2 <
-  // tau^2 z^2 -- no division on the per-pair path.
-  __shared__ float s_M[kPnpHypPerBlock][12];
-  __shared__ int32_t s_c[kPnpHypPerBlock];
-  __shared__ int32_t s_ok[kPnpHypPerBlock];
-  const int tid = threadIdx.x;
-  const int h0 = blockIdx.y * kPnpHypPerBlock;
-  const int nh = min(kPnpHypPerBlock, a.n_hyp - h0);
-  for (int e = tid; e < nh * 4; e += 256) {
-    const int h = e >> 2, q = e & 3;
-    const float* T = a.hyp + 12 * static_cast<int64_t>(h0 + h);
-    s_M[h][q] = a.fx * T[q] + a.cx * T[8 + q];
-    s_M[h][4 + q] = a.fy * T[4 + q] + a.cy * T[8 + q];
-    s_M[h][8 + q] = T[8 + q];
+// Inlier counts with the per-pair transform on the matrix cores: for 16
+// hypotheses x 16 correspondences, (u, v, z) = (K [R | t] / tau) [X, Y, Z, 1]
+// is three 16x16x4 FP32 products (v_mfma_f32_16x16x4_f32: lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16]); the
+// VALU keeps the residual numerators, the squared error against z^2 and the
+// count (~8 operations per pair instead of ~18 with the transform on the
+// VALU); integer counts summed per workgroup in LDS, then one global atomic
+// per (workgroup, hypothesis), so they do not depend on scheduling.  A workgroup stages 1,024
+// correspondences in LDS and its four waves take 16 hypotheses each.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kMfPoints = 1024;
+constexpr int kMfHyps = 64;
+
+__global__ __launch_bounds__(256) void pnp_score_mfma_kernel(PnpArgs a) {
+  // per correspondence X, Y, Z, 1 (all 0 past the end: z = 0 never counts),
+  // interleaved so that the 64 lanes' B operands are 64 consecutive words
+  __shared__ float s_b[kMfPoints][4];
+  __shared__ float s_q[kMfPoints][2];  // p_u / tau, p_v / tau
+  __shared__ int32_t s_c[kMfHyps];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kMfPoints;
+  const float it = 1.f / a.tau;
+  for (int e = tid; e < kMfPoints; e += 256) {
+    const int64_t i = p0 + e;
+    const bool ok = i < a.n;
+    s_b[e][0] = ok ? a.x3d[3 * i] : 0.f;
+    s_b[e][1] = ok ? a.x3d[3 * i + 1] : 0.f;
+    s_b[e][2] = ok ? a.x3d[3 * i + 2] : 0.f;
+    s_b[e][3] = ok ? 1.f : 0.f;
+    s_q[e][0] = ok ? a.p2d[2 * i] * it : 0.f;
+    s_q[e][1] = ok ? a.p2d[2 * i + 1] * it : 0.f;
   }
-  for (int e = tid; e < kPnpHypPerBlock; e += 256) {
-    s_c[e] = 0;
-    s_ok[e] = e < nh ? (a.counts[h0 + e] >= 0) : 0;
-  }
-  __syncthreads();
-  const float tau2 = a.tau * a.tau;
-  float P[kPnpPointsPerThread][5];
-  bool live[kPnpPointsPerThread];
-  for (int q = 0; q < kPnpPointsPerThread; ++q) {
-    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kPnpPointsPerThread + q) * 256 + tid;
-    live[q] = i < a.n;
-    if (live[q]) {
-      P[q][0] = a.x3d[3 * i]; P[q][1] = a.x3d[3 * i + 1]; P[q][2] = a.x3d[3 * i + 2];
-      P[q][3] = a.p2d[2 * i]; P[q][4] = a.p2d[2 * i + 1];
-    } else {
-      // a point that can never count: behind the camera of every hypothesis
-      P[q][0] = P[q][1] = P[q][2] = P[q][3] = P[q][4] = 0.f;
-    }
-  }
-  for (int h = 0; h < nh; ++h) {
-    if (!s_ok[h]) continue;  // uniform
-    const float* M = s_M[h];
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < kPnpPointsPerThread; ++q) {
-      const float u = M[0] * P[q][0] + M[1] * P[q][1] + M[2] * P[q][2] + M[3];
-      const float v = M[4] * P[q][0] + M[5] * P[q][1] + M[6] * P[q][2] + M[7];
-      const float z = M[8] * P[q][0] + M[9] * P[q][1] + M[10] * P[q][2] + M[11];
-      const float du = u - P[q][3] * z, dv = v - P[q][4] * z;
-      c += (live[q] && z > 0.f && du * du + dv * dv < tau2 * (z * z)) ? 1 : 0;
-    }
-    // sum over the wave, then one LDS add per wave
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((tid & 63) == 0 && c) atomicAdd(&s_c[h], c);
+  if (tid < kMfHyps) s_c[tid] = 0;
+  // this lane's A entries: hypothesis row lane % 16 of the wave's 16, column k = lane / 16
+  const int r = lane & 15, k = lane >> 4, col = lane & 15;
+  const int h = blockIdx.y * kMfHyps + w * 16 + r;
+  float au = 0.f, av = 0.f, az = 0.f;
+  if (h < a.n_hyp) {
+    const float* T = a.hyp + 12 * static_cast<int64_t>(h);
+    au = (a.fx * T[k] + a.cx * T[8 + k]) * it;
+    av = (a.fy * T[4 + k] + a.cy * T[8 + k]) * it;
+    az = T[8 + k];
   }
   __syncthreads();
-  for (int e = tid; e < nh; e += 256)
-    if (s_ok[e] && s_c[e]) atomicAdd(&a.counts[h0 + e], s_c[e]);
+  int cnt[4] = {0, 0, 0, 0};
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int t = 0; t < kMfPoints; t += 16) {
+    const float b = s_b[t + col][k];
+    const float qu = s_q[t + col][0], qv = s_q[t + col][1];
+    const floatx4 U = __builtin_amdgcn_mfma_f32_16x16x4f32(au, b, zero, 0, 0, 0);
+    const floatx4 V = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, zero, 0, 0, 0);
+    const floatx4 Z = __builtin_amdgcn_mfma_f32_16x16x4f32(az, b, zero, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float du = fmaf(-qu, Z[q], U[q]), dv = fmaf(-qv, Z[q], V[q]);
+      cnt[q] += (Z[q] > 0.f && fmaf(dv, dv, du * du) < Z[q] * Z[q]) ? 1 : 0;
+    }
+  }
+  // rows 4 (lane / 16) + q: sum over the 16 lanes (columns) that share them
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int c = cnt[q];
+    c += __shfl_xor(c, 1, 64);
+    c += __shfl_xor(c, 2, 64);
+    c += __shfl_xor(c, 4, 64);
+    c += __shfl_xor(c, 8, 64);
+    if (col == 0 && c) atomicAdd(&s_c[w * 16 + 4 * (lane >> 4) + q], c);
+  }
+  __syncthreads();
+  if (tid < kMfHyps) {
+    const int hh = blockIdx.y * kMfHyps + tid;
+    if (hh < a.n_hyp && s_c[tid] && a.counts[hh] >= 0) atomicAdd(&a.counts[hh], s_c[tid]);
+  }
 }
 
 __global__ __launch_bounds__(256) void pnp_select_kernel(PnpArgs a) {
@@ -405,10 +419,10 @@ __global__ void pose_consistency_kernel(const float* poses, int n, float tau_deg
 // ------------------------------------------------------------ launchers
 void launch_pnp(const PnpArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(pnp_hyp_kernel, dim3((a.n_hyp + 63) / 64), dim3(64), 0, s, a);
-  const int pblocks = static_cast<int>((a.n + 256 * kPnpPointsPerThread - 1) / (256 * kPnpPointsPerThread));
+  const int pblocks = static_cast<int>((a.n + kMfPoints - 1) / kMfPoints);
   if (pblocks > 0)
-    hipLaunchKernelGGL(pnp_score_kernel, dim3(pblocks, (a.n_hyp + kPnpHypPerBlock - 1) / kPnpHypPerBlock),
-                       dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pnp_score_mfma_kernel, dim3(pblocks, (a.n_hyp + kMfHyps - 1) / kMfHyps), dim3(256), 0, s,
+                       a);
   hipLaunchKernelGGL(pnp_select_kernel, dim3(1), dim3(256), 0, s, a);
   const int nb = pnp_normal_blocks(a.n);
   for (int it = 0; it < a.refine_iters; ++it) {
