@@ -115,9 +115,10 @@ enum { HGSR_SCHED_GRID = 0, HGSR_SCHED_POSE_MAJOR = 1, HGSR_SCHED_TILE_MAJOR = 2
  * sorted in LDS (0 = default 4096; larger lists take a global-memory path).
  * feat_accum: how 32-channel features are summed at tile 8 and 16 --
  * HGSR_FEAT_AUTO (the autotuned choice, else the VALU), HGSR_FEAT_VALU
- * (per-pixel FMAs in blend order) or HGSR_FEAT_MFMA (per batch, a 32x2 by
- * 2x64 FP32 matrix-core product of features and per-pixel weights; the same
- * sum in another association order).  HGSR_FEAT_MFMA also moves the
+ * (per-pixel FMAs in blend order) or HGSR_FEAT_MFMA (per group of 8 splats,
+ * a 32x8 by 8x64 matrix-core product of the bf16 features and the per-pixel
+ * FP32 weights, each weight split exactly into three bf16 parts; the same
+ * sum in another association order, colour, depth and alpha unchanged).  HGSR_FEAT_MFMA also moves the
  * backward's per-pair feature term (the pixel's feature gradient dotted with
  * the splat's feature) onto the matrix cores, per group of 32 splats; the
  * other settings keep it on the VALU. */
