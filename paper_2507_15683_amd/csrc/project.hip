@@ -221,6 +221,10 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
 
   // phase B: exact footprints on the compacted candidates, counted per pose
   uint64_t vis[kProjPerThread];
+  // one Gaussian per thread and one pose: phase C reuses phase B's footprint
+  constexpr bool kKeep = G == 1;
+  float keep_m[3] = {0.f, 0.f, 0.f}, keep_mc[3] = {0.f, 0.f, 0.f}, keep_o = 0.f, keep_k2 = 0.f;
+  Footprint keep_f{};
 #pragma unroll
   for (int k = 0; k < kProjPerThread; ++k) {
     vis[k] = 0;
@@ -243,6 +247,15 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
       if (footprint(T, mc, S, k2, a.c, f)) {
         atomicAdd(&s_cnt[p], 1u);
         vis[k] |= 1ull << p;
+        if (kKeep && a.P == 1) {
+          for (int c = 0; c < 3; ++c) {
+            keep_m[c] = m[c];
+            keep_mc[c] = mc[c];
+          }
+          keep_o = oo;
+          keep_k2 = k2;
+          keep_f = f;
+        }
         if (a.P == 1) {
           atomicMin(&s_rect[0], f.px0 >> a.c.tile_shift);
           atomicMin(&s_rect[1], f.py0 >> a.c.tile_shift);
@@ -274,12 +287,23 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
   }
   __syncthreads();
 
-  // phase C: the records (footprints recomputed from the same inputs)
+  // phase C: the records (footprints recomputed from the same inputs, or
+  // kept from phase B)
 #pragma unroll
   for (int k = 0; k < kProjPerThread; ++k) {
     if (!vis[k]) continue;
     const uint32_t e = static_cast<uint32_t>(k * 256 + tid);
     const int64_t i = base + s_idx[e];
+    if (kKeep && a.P == 1) {
+      const uint32_t local = s_base[0] + atomicAdd(&s_cnt[0], 1u);
+      if (local >= sub_cap) {
+        atomicOr(a.flags, 1);
+        continue;
+      }
+      write_record<DEG>(a, i, keep_m, keep_o, keep_k2, a.poses + 12 * a.pose_base, a.pose_base, keep_mc, keep_f,
+                        sub * sub_cap + local, hist);
+      continue;
+    }
     const float m[3] = {a.g.means[3 * i], a.g.means[3 * i + 1], a.g.means[3 * i + 2]};
     const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
     const float oo = a.g.opac[i];
@@ -312,7 +336,7 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
   }
 }
 
-// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.
+// Many poses: two passes, so that the expensive per-pair work runs on dense lanes.
 //
 // cull_kernel: one thread per Gaussian, looping over the launch's poses,
 // applies the opacity, partition, near-plane and conservative footprint
