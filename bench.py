@@ -41,6 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, scaled by a plain copy's readings); valid only for the source it
 # was taken on, identified by a hash of the blend sources.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_fwd_1080p_1M_traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "render_1080p_1M_sq_counters.md")
+# one wave64 VALU instruction per cycle per CU: 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
 BLEND_SOURCES = ("paper_2507_15683_amd/csrc/blend.hip", "paper_2507_15683_amd/csrc/hgsr_device.hpp")
 
 
@@ -54,6 +57,35 @@ def blend_source_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _guarded_fields(path: str, tile: int, feat_accum: str):
+    """The key: value fields of a committed counter summary, or None when it
+    was taken on other blend sources or another kernel variant."""
+    try:
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("#", "|", "`")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != blend_source_hash():
+            return None
+        if int(kv.get("tile", 0)) != tile or kv.get("feat_accum") != feat_accum:
+            return None
+        return kv
+    except (OSError, ValueError):
+        return None
+
+
+def measured_valu(tile: int, feat_accum: str):
+    """VALU instructions per blend launch from the committed SQ counter
+    summary, or None."""
+    kv = _guarded_fields(SQ_FILE, tile, feat_accum)
+    try:
+        return int(kv["valu_insts_per_dispatch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
 
 
 def measured_traffic(tile: int, feat_accum: str):
@@ -171,12 +203,19 @@ def headline(hg, torch, synth, args):
     bytes_blend = W * H * bytes_px + st["visible"] * (48 + 2 * D)
     achieved = bytes_blend / (stage_ms[2] * 1e-3) / 1e9
     traffic = measured_traffic(tile, feat_accum)
+    valu = measured_valu(tile, feat_accum)
     res = dict(ms=ms, eager_ms=eager_ms, mpix=W * H / (ms * 1e-3) / 1e6, ms16=ms16, stage_ms=stage_ms, tile=tile,
                feat_accum=feat_accum, tuned=tuned, st=st, W=W, H=H, D=D, n=sc.n)
     res["roofline"] = {"kernel": f"blend_fwd (tile {tile})", "bound": "hbm", "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": traffic, "bytes_per_launch": int(bytes_blend),
                        "launch_us": round(stage_ms[2] * 1e3, 2)}
+    if valu is not None:
+        # the resource that bounds the blend: VALU instruction issue (counted
+        # by SQ_INSTS_VALU), against one wave64 instruction per CU per cycle
+        res["roofline"]["valu"] = {"instructions_per_launch": valu,
+                                   "issue_frac": round(valu / (stage_ms[2] * 1e-3) / VALU_ISSUE_PEAK, 4),
+                                   "peak": "1 wave64 VALU instruction per CU per cycle, 256 CUs at 2.4 GHz"}
     res["cpu_inputs"] = (sc, P, cam)
     del out, out16, r
     return res
