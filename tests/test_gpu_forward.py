@@ -293,3 +293,16 @@ def test_autotune_choice_and_cache(hg, tmp_path):
     resb2 = rb2.autotune(scene, _poses(Ps), K, out, with_backward=True, cache_path=cache)
     assert (resb2["tile"], resb2["schedule"]) == (resb["tile"], resb["schedule"])
     assert abs(resb2["ms"] - resb["ms"]) < 1e-4
+    # one pose: the projection's grouping is tuned too, cached, and changes
+    # no output
+    out1 = r.alloc_outputs(scene, 1, K)
+    r1 = hg.Renderer()
+    res1 = r1.autotune(scene, _poses(Ps[:1]), K, out1, cache_path=cache)
+    log("tuned one pose", res1)
+    assert res1["proj_group"] in (1, 4)
+    one = r1.render(scene, _poses(Ps[:1]), K, tile=16, feat_accum="valu")
+    for k in ("rgb", "depth", "alpha", "feat"):
+        assert np.array_equal(to_np(one[k][0]), to_np(base[k][0])), k
+    r1b = hg.Renderer()
+    res1b = r1b.autotune(scene, _poses(Ps[:1]), K, out1, cache_path=cache)
+    assert res1b["proj_group"] == res1["proj_group"] and abs(res1b["ms"] - res1["ms"]) < 1e-4
