@@ -40,3 +40,11 @@ def test_ties_and_bad_arguments(hg):
     assert list(hg.spatial_order(m)) == [0, 1, 2, 3, 4]
     with pytest.raises(hg.HgsrError):
         hg.spatial_order(m, np.array([0, 3, 2, 5], dtype=np.int64))
+
+
+def test_spatial_layout_permutes_every_array_together(hg):
+    sc = synth.tiny_scene(300, 5, feat_dim=8, sh_degree=1)[0]
+    out, perm = hg.spatial_layout(sc)
+    for f in ("means", "log_scales", "quats", "opacities", "sh", "feat"):
+        np.testing.assert_array_equal(getattr(out, f), getattr(sc, f)[perm])
+    assert out.sh_degree == sc.sh_degree
