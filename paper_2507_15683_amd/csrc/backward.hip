@@ -328,7 +328,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
         const float iom = __builtin_amdgcn_rcpf(om);  // 1/(1 - alpha), alpha <= 0.99
         const float Tj = T[k] * iom;
         const float w = alpha * Tj;
-        float h = gC[k][0] * col.x + gC[k][1] * col.y + gC[k][2] * col.z + GZ[k] * opz.z;
+        // gradient arithmetic (not a blend decision): fused multiply-adds
+        float h = fmaf(gC[k][0], col.x, fmaf(gC[k][1], col.y, fmaf(gC[k][2], col.z, GZ[k] * opz.z)));
         if constexpr (MF) {
           h += s_h[MF ? wave : 0][ii % kHGroup][lane];
         } else if constexpr (D > 0) {
@@ -342,21 +343,22 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
             h = fmaf(gF[k][4 * q + 3], f.w, h);
           }
         }
-        const float dA = Tj * h - (S[k] + gT[k] * Tf[k]) * iom;
+        const float dA = fmaf(Tj, h, -(fmaf(gT[k], Tf[k], S[k]) * iom));
         S[k] = fmaf(w, h, S[k]);
         T[k] = Tj;
-        g[7] += w * gC[k][0];
-        g[8] += w * gC[k][1];
-        g[9] += w * gC[k][2];
-        g[6] += w * GZ[k];
+        g[7] = fmaf(w, gC[k][0], g[7]);
+        g[8] = fmaf(w, gC[k][1], g[8]);
+        g[9] = fmaf(w, gC[k][2], g[9]);
+        g[6] = fmaf(w, GZ[k], g[6]);
         if (opz.y * G <= kAlphaMax) {
           const float dpow = dA * alpha;
-          g[5] += dA * G;
-          g[0] += dpow * (geo.z * dx + geo.w * dy);
-          g[1] += dpow * (geo.w * dx + opz.x * dy);
-          g[2] += -0.5f * dpow * dx * dx;
-          g[3] += -dpow * dx * dy;
-          g[4] += -0.5f * dpow * dy * dy;
+          const float hx = -0.5f * dpow * dx, hy = -0.5f * dpow * dy;
+          g[5] = fmaf(dA, G, g[5]);
+          g[0] = fmaf(dpow, fmaf(geo.z, dx, geo.w * dy), g[0]);
+          g[1] = fmaf(dpow, fmaf(geo.w, dx, opz.x * dy), g[1]);
+          g[2] = fmaf(hx, dx, g[2]);
+          g[3] = fmaf(2.f * hx, dy, g[3]);
+          g[4] = fmaf(hy, dy, g[4]);
         }
         if constexpr (FEATGRAD) {
 #pragma unroll
