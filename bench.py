@@ -116,7 +116,7 @@ def headline(hg, torch, synth, args):
     """Config: 1M Gaussians, 1920x1080, one pose (forward only)."""
     import ctypes
     log("bench: generating the 1M-Gaussian scene")
-    sc, P, cam = synth.config2(0)
+    sc, P, cam = synth.aerial_1m_1080p(0)
     # stored in spatial (Morton) order, the library's scene layout (built once
     # at load, outside the timed region): same Gaussians, same image
     scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
@@ -256,7 +256,7 @@ def reserve_headroom(r, NP, K, n, factor=1.5):
 def fwd_bwd(hg, torch, synth, args):
     """64 candidate poses, 960x540, 1M Gaussians: batched + graph vs plain."""
     log("bench: fwd+bwd, 64 poses at 960x540")
-    sc, P, cam, seed = synth.config3(0, with_seed=True)
+    sc, P, cam, seed = synth.aerial_1m_64_views(0, with_seed=True)
     scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     K = hg.Intrinsics.of(cam)
     NP = P.shape[0]
@@ -355,7 +355,7 @@ def significance(hg, torch, synth, args):
     resolution, one call per batch of 64 views."""
     import ctypes
     log("bench: significance scoring, 64 views at 960x540")
-    sc, P, cam = synth.config3(0)
+    sc, P, cam = synth.aerial_1m_64_views(0)
     scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     K = hg.Intrinsics.of(cam)
     NP, W, H, D, n = P.shape[0], cam.width, cam.height, sc.feat_dim, sc.n
@@ -523,7 +523,7 @@ def streaming(hg, torch, synth, args):
     import math
     import numpy as np
     log("bench: out-of-core streaming, 8M Gaussians, 6 of 16 partitions resident, 48 views at 1080p")
-    sc = synth.config5(0)[0]
+    sc = synth.partitioned_8m(0)[0]
     cam = synth.Camera(1500.0, 1500.0, 960.0, 540.0, 1920, 1080)
     K = hg.Intrinsics.of(cam)
     NV, AHEAD, SLOTS = 48, 4, 6
@@ -597,7 +597,7 @@ def partitioned(hg, torch, synth, args):
     """8M Gaussians in 16 partitions, 16 query poses, 3 levels x 20 steps."""
     import numpy as np
     log("bench: partitioned scene (8M Gaussians) generation")
-    sc, truth, start, cams = synth.config5(0)
+    sc, truth, start, cams = synth.partitioned_8m(0)
     scene = hg.GaussianScene.from_numpy(sc, spatial=args.layout == "spatial")
     NQ = truth.shape[0]
     s = torch.cuda.Stream()

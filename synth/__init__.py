@@ -13,12 +13,12 @@ from .scenes import (  # noqa: F401
     partitioned_scene,
     down_pose,
     perturb_poses,
-    config1,
-    config2,
-    config3,
-    config4,
-    config4_fd,
-    config5,
+    terrain_20k_view,
+    aerial_1m_1080p,
+    aerial_1m_64_views,
+    differentiable_200k,
+    fd_subset_5k,
+    partitioned_8m,
     tiny_scene,
     f32_to_bf16_bits,
     bf16_bits_to_f32,

@@ -259,9 +259,9 @@ def perturb_poses(pose, count, seed, sigma_t, sigma_rot_deg) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# the benchmark configurations
+# the workloads of the tests and the benchmark
 # --------------------------------------------------------------------------
-def config1(k=0):
+def terrain_20k_view(k=0):
     """20k Gaussians on a 200 m heightfield, SH0, no features, 256x192 view
     from 120 m with +/-10 deg tilt; 16 px tiles."""
     seed = 1000 + k
@@ -281,32 +281,32 @@ def _aerial_pose(rng, max_tilt_deg, alt_lo=100.0, alt_hi=300.0, span=200.0):
                      (ang * math.cos(d), ang * math.sin(d)), rng.uniform(0, 2 * math.pi))
 
 
-_SCENE2_CACHE = {}
+_AERIAL_CACHE = {}
 
 
-def config2_scene(k=0):
-    key = ("c2", k)
-    if key not in _SCENE2_CACHE:
-        _SCENE2_CACHE.clear()
-        _SCENE2_CACHE[key] = aerial_scene(1_000_000, 1000.0, 2000 + k, sh_degree=3, feat_dim=32)
-    return _SCENE2_CACHE[key]
+def aerial_1m_scene(k=0):
+    key = ("aerial_1m", k)
+    if key not in _AERIAL_CACHE:
+        _AERIAL_CACHE.clear()
+        _AERIAL_CACHE[key] = aerial_scene(1_000_000, 1000.0, 2000 + k, sh_degree=3, feat_dim=32)
+    return _AERIAL_CACHE[key]
 
 
-def config2(k=0):
+def aerial_1m_1080p(k=0):
     """1M Gaussians (900k terrain + 2000 buildings x 50), SH3, 32-d bf16
     features, 1920x1080 view, fx=1500, altitude U(100,300) m, tilt <= 30 deg."""
-    scene = config2_scene(k)
+    scene = aerial_1m_scene(k)
     rng = np.random.Generator(np.random.PCG64(2000 + k + 500))
     pose = _aerial_pose(rng, 30.0)
     cam = Camera(1500.0, 1500.0, 960.0, 540.0, 1920, 1080)
     return scene, pose[None], cam
 
 
-def config3(k=0, count=64, with_seed=False):
+def aerial_1m_64_views(k=0, count=64, with_seed=False):
     """The config-2 scene seen by 64 poses perturbed from a seed pose by
     N(0,5 m) and N(0,3 deg), rendered at 960x540 with fx=750.  with_seed
     also returns the seed (query) pose."""
-    scene = config2_scene(k)
+    scene = aerial_1m_scene(k)
     rng = np.random.Generator(np.random.PCG64(3000 + k))
     seed_pose = _aerial_pose(rng, 30.0)
     poses = perturb_poses(seed_pose, count, 3000 + k + 1, 5.0, 3.0)
@@ -316,7 +316,7 @@ def config3(k=0, count=64, with_seed=False):
     return scene, poses, cam
 
 
-def config4(k=0):
+def differentiable_200k(k=0):
     """200k Gaussians over 447x447 m (about 1/m^2), SH0 + 32-d features,
     640x480, fx=500, 120 m.  Returns (scene, true pose, start pose, camera):
     the start pose is the true pose offset by N(0,2 m) and N(0,2 deg)."""
@@ -330,7 +330,7 @@ def config4(k=0):
     return scene, truth[None], start[None], cam
 
 
-def config4_fd(k=0):
+def fd_subset_5k(k=0):
     """The finite-difference subset: 5k Gaussians over 80x80 m, 128x96,
     fx=220, 120 m; SH0 + 32-d features."""
     seed = 4100 + k
@@ -342,7 +342,7 @@ def config4_fd(k=0):
     return scene, pose[None], cam
 
 
-def config5(k=0, n_total=8_000_000, queries=16):
+def partitioned_8m(k=0, n_total=8_000_000, queries=16):
     """8M Gaussians over 4x4 km in 16 spatial partitions (buildings pro rata),
     16 query poses; levels 480x270 / 960x540 / 1920x1080 with fx 375/750/1500.
     Returns (scene, true poses, start poses, cameras)."""

@@ -94,9 +94,9 @@ def test_pose_means_opacity_grads_vs_fd(hg, orc):
     """The FD subset: 5k Gaussians, 128x96; residual against a hidden-offset
     target; pose (6), and means/opacities of 64 contributing Gaussians."""
     from oracle.loss import fd_gradients, residual, residual_frozen_signs
-    sc, P, cam = synth.config4_fd(0)
+    sc, P, cam = synth.fd_subset_5k(0)
     tgt, tgt_rgb, tgt_feat = _setup_residual(hg, orc, sc, P, cam, 41)
-    log("case: config4 FD subset, GPU backward")
+    log("case: differentiable_200k FD subset, GPU backward")
     g, out, loss = _gpu_grads(hg, sc, P, cam, tgt_rgb, tgt_feat, ("pose", "means", "opacities"))
     ref = orc.render(sc, P[0], cam, want_lists=True, list_cap=512)
     blended = np.unique(ref["lists"][ref["lists"] >= 0])
@@ -223,8 +223,8 @@ def test_refinement_converges(hg, orc):
     pose offset; 50 Adam steps on the pose tangent reduce the residual and
     the pose error."""
     import torch
-    sc, truth, start, cam = synth.config4(0)
-    log("case: config4 refinement, oracle target")
+    sc, truth, start, cam = synth.differentiable_200k(0)
+    log("case: differentiable_200k refinement, oracle target")
     tgt = orc.render(sc, truth[0], cam)
     tgt_rgb = _t(tgt["rgb"][None].astype(np.float32))
     tgt_feat = _t(tgt["feat"][None].astype(np.float32))

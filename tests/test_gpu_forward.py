@@ -37,12 +37,12 @@ def _render(hg, sc, P, cam, r=None, **kw):
     return out, r
 
 
-def test_config1_parity(hg, oracle_mod):
-    log("case: config1 k=0 tile16 bucket")
-    sc, P, cam = synth.config1(0)
+def test_small_terrain_parity(hg, oracle_mod):
+    log("case: terrain_20k_view k=0 tile16 bucket")
+    sc, P, cam = synth.terrain_20k_view(0)
     out, r = _render(hg, sc, P, cam, tile=16)
     ref = oracle_mod.render(sc, P[0], cam, tile=16, margin=1)
-    s = parity(out, ref, label="config1")
+    s = parity(out, ref, label="terrain_20k_view")
     st = r.stats()
     log("stats", st, "oracle", ref["stats"])
     assert st["visible"] >= ref["stats"]["visible"]
@@ -65,8 +65,8 @@ def test_tiny_ragged_parity(hg, oracle_mod, seed):
 
 
 def test_tile_lists_match_oracle(hg, oracle_mod):
-    log("case: config1 tile lists")
-    sc, P, cam = synth.config1(0)
+    log("case: terrain_20k_view tile lists")
+    sc, P, cam = synth.terrain_20k_view(0)
     tile = 16
     out, r = _render(hg, sc, P, cam, tile=tile)
     off, ids, edge = oracle_mod.tile_lists(sc, P[0], cam, tile=tile, edge_px=1e-3)
@@ -93,10 +93,10 @@ def test_tile_lists_match_oracle(hg, oracle_mod):
 
 
 def test_tile_size_invariance_bitwise(hg):
-    sc, P, cam = synth.config1(1)
+    sc, P, cam = synth.terrain_20k_view(1)
     outs = []
     for tile in (8, 16, 32):
-        log(f"case: config1 k=1 tile={tile}")
+        log(f"case: terrain_20k_view k=1 tile={tile}")
         o, _ = _render(hg, sc, P, cam, tile=tile)
         outs.append(o)
     for o in outs[1:]:
@@ -180,7 +180,7 @@ def test_empty_and_culled_scenes(hg):
 
 
 def test_overflow_regrows_to_same_result(hg):
-    sc, P, cam = synth.config1(2)
+    sc, P, cam = synth.terrain_20k_view(2)
     log("case: default capacity")
     ref, _ = _render(hg, sc, P, cam)
     small = hg.Renderer(record_hint=1024, key_hint=2048)
@@ -206,7 +206,7 @@ def test_lds_sort_fallback_bitwise(hg):
 
 
 def test_repeat_renders_bitwise(hg):
-    sc, P, cam = synth.config1(3)
+    sc, P, cam = synth.terrain_20k_view(3)
     r = hg.Renderer()
     log("case: determinism")
     a, _ = _render(hg, sc, P, cam, r=r)
@@ -216,17 +216,17 @@ def test_repeat_renders_bitwise(hg):
         assert np.array_equal(to_np(a[k]), to_np(b[k])), k
 
 
-def test_config2_full_parity(hg, oracle_mod):
+def test_1080p_1m_full_parity(hg, oracle_mod):
     """1M Gaussians (SH3, 32-d features), 1920x1080: every pixel against the
     oracle; bf16 feature output within bf16 rounding of the FP32 one."""
-    sc, P, cam = synth.config2(0)
-    log("case: config2 1080p fp32 features")
+    sc, P, cam = synth.aerial_1m_1080p(0)
+    log("case: aerial_1m_1080p 1080p fp32 features")
     out, r = _render(hg, sc, P, cam, tile=16)
     log("stats", r.stats())
     ref = oracle_mod.render(sc, P[0], cam, tile=16, margin=1)
     log("oracle stats", ref["stats"])
-    parity(out, ref, label="config2")
-    log("case: config2 bf16 features")
+    parity(out, ref, label="aerial_1m_1080p")
+    log("case: aerial_1m_1080p bf16 features")
     ob, _ = _render(hg, sc, P, cam, tile=16, feat_bf16=True)
     f32 = to_np(out["feat"][0])
     fb = to_np(ob["feat"][0])

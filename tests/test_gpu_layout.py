@@ -32,7 +32,7 @@ def _diff(a, b):
 def test_small_scene_spatial_order(hg, tile):
     import torch
     import oracle
-    sc, P, cam = synth.config1(0)
+    sc, P, cam = synth.terrain_20k_view(0)
     K = hg.Intrinsics.of(cam)
     poses = torch.from_numpy(P).cuda()
     given = hg.GaussianScene.from_numpy(sc)
@@ -54,7 +54,7 @@ def test_1080p_spatial_order(hg):
     and the same image up to exact depth ties."""
     import torch
     log("case: 1080p spatial order")
-    sc, P, cam = synth.config2(0)
+    sc, P, cam = synth.aerial_1m_1080p(0)
     K = hg.Intrinsics.of(cam)
     poses = torch.from_numpy(P).cuda()
     r = hg.Renderer()

@@ -72,7 +72,7 @@ def test_terrain_256x192_parity(hg, sg):
     """20k Gaussians (32-d features) on the small terrain, 4 views at
     256x192, maps at image resolution, tile 16."""
     log("case: terrain 20k, 4 views 256x192, planar maps 256x192")
-    base, P0, cam = synth.config1(0)
+    base, P0, cam = synth.terrain_20k_view(0)
     sc = synth.terrain_scene(20_000, 200.0, 1000, sh_degree=0, feat_dim=32)
     poses = _views(P0[0], 4, 11)
     maps = synth.feature_maps(4, 32, cam.height, cam.width, 12)
@@ -213,7 +213,7 @@ def test_full_size_64_views_sampled(hg, sg):
     GPU marked visible."""
     import torch
     log("case: 1M Gaussians, 64 views 960x540, planar maps 480x270")
-    sc, poses, cam = synth.config3(0)
+    sc, poses, cam = synth.aerial_1m_64_views(0)
     maps = synth.feature_maps(64, 32, 270, 480, 3100)
     r = hg.Renderer()
     res = r.significance(hg.GaussianScene.from_numpy(sc), _t(poses), hg.Intrinsics.of(cam),
