@@ -517,9 +517,9 @@ def streaming(hg, torch, synth, args):
     """Out-of-core rendering: the partitioned 8M-Gaussian scene (16 cells of
     1 km^2) kept in pinned host memory with a device budget of 6 partitions,
     a flight of 48 query views at 1920x1080 (f = 1500, 150 m) straight across
-    the 4 x 4 km area, each batch planned with the next 4 views so that the
-    next cell is uploaded while the current views render; against the same
-    views with the whole scene resident."""
+    the 4 x 4 km area, each view prepared with the next 4 as upcoming views,
+    so that the next cell is uploaded while the current view renders; against
+    the same views with the whole scene resident."""
     import math
     import numpy as np
     log("bench: out-of-core streaming, 8M Gaussians, 6 of 16 partitions resident, 48 views at 1080p")
@@ -538,21 +538,22 @@ def streaming(hg, torch, synth, args):
 
     def run(timed):
         nonlocal out
-        ups = 0
+        ups = pre = 0
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         for k in range(NV):
-            desc = pc.prepare(poses[k:k + 1 + AHEAD], K, stream=s)
+            desc = pc.prepare(poses[k:k + 1], K, ahead=poses[k + 1:k + 1 + AHEAD], stream=s)
             ups += pc.stats["uploads"]
+            pre += pc.stats["prefetched"]
             out = r.render(desc, dev_poses[k:k + 1], K, out=out, check_overflow=not timed, stream=s)
         e1.record(s)
         s.synchronize()
-        return e0.elapsed_time(e1) / NV, ups
+        return e0.elapsed_time(e1) / NV, ups, pre
 
     run(False)                      # sizes the renderer's workspace
     pc.evict_all()
     t0 = pc.stats["total_bytes"]
-    ms, ups = run(True)
+    ms, ups, pre = run(True)
     if r.check_overflow(s) != 0:
         raise RuntimeError("workspace overflow in the streamed flight")
     gb = (pc.stats["total_bytes"] - t0) / 1e9
@@ -584,9 +585,9 @@ def streaming(hg, torch, synth, args):
     del full
     return {"workload": "8M Gaussians in 16 partitions over 4x4 km (SH0, 32-d features) in pinned host memory, "
                         f"{SLOTS} partitions on the device, 48 views at 1920x1080 f=1500 from 150 m crossing the area, "
-                        f"each batch planned with the next {AHEAD} views",
+                        f"each view prepared with the next {AHEAD} as upcoming views",
             "ms_per_view_streamed": round(ms, 3), "ms_per_view_resident": round(ms_res, 3),
-            "uploads": ups, "uploaded_gb": round(gb, 3),
+            "uploads": ups, "uploads_ahead": pre, "uploaded_gb": round(gb, 3),
             "device_budget_gb": round(dev_bytes / 1e9, 3), "scene_gb": round(scene_bytes / 1e9, 3),
             "cold_upload": {"partitions": cold["uploads"], "gb": round(cold["bytes_uploaded"] / 1e9, 3),
                             "ms": round(t_up * 1e3, 2),

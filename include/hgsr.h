@@ -454,7 +454,7 @@ typedef struct {
 typedef struct hgsr_pcache hgsr_pcache;
 
 typedef struct {
-  int32_t needed;          /* partitions the last batch may see */
+  int32_t needed;          /* partitions the last batch's rendered views may see */
   int32_t hits;            /* of those, already resident */
   int32_t uploads;         /* copied from host memory for the last batch */
   int32_t evictions;       /* resident partitions dropped for the last batch */
@@ -464,6 +464,7 @@ typedef struct {
   int32_t n_slots;
   int64_t slot_capacity;   /* Gaussians per slot (the largest partition) */
   int64_t device_bytes;    /* the device budget in use (slots + tables) */
+  int32_t prefetched;      /* of the last batch's uploads, those for upcoming views only */
 } hgsr_pcache_stats;
 
 /* Create a cache on the current device: copies the host scene into pinned
@@ -475,21 +476,27 @@ typedef struct {
 hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, int32_t n_slots);
 hgsr_status hgsr_pcache_destroy(hgsr_pcache* pc);
 
-/* Make the partitions that the P poses (host, P x 12) may see at
- * intrinsics K resident, and fill *out with the device descriptor.  A
- * partition may be seen when its box, grown by motion_margin metres (room
- * for poses that move during refinement without a new call), passes the
- * conservative frustum test of hgsr_partition_plan.  Uploads run on the
- * cache's own copy stream from pinned memory; `stream` -- the stream the
- * renders using *out run on -- waits for them, and a slot is only
- * overwritten after the work enqueued on `stream` before the call that last
- * needed it (no host synchronisation).  The descriptor stays valid until the
- * next prepare on this cache.  Returns HGSR_ERR_CAPACITY (nothing enqueued)
- * when the batch needs more partitions than the cache has slots.  stats may
- * be NULL. */
-hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, const hgsr_intrinsics* K,
-                                float near_z, float motion_margin, hgsr_gaussians* out, hgsr_pcache_stats* stats,
-                                hgsr_stream stream);
+/* Make the partitions that the first n_render of the P poses (host, P x 12)
+ * may see at intrinsics K resident, and fill *out with the device
+ * descriptor through which those views are rendered.  Poses n_render..P-1
+ * are upcoming views: the partitions only they may see are uploaded ahead,
+ * into free or least recently used slots the rendered views cannot see (best
+ * effort, skipped when no such slot is left), behind this batch's slot table,
+ * so that the uploads overlap this batch's renders; they become visible to
+ * renders from the next prepare on.  A partition may be seen when its box,
+ * grown by motion_margin metres (room for poses that move during refinement
+ * without a new call), passes the conservative frustum test of
+ * hgsr_partition_plan.  Uploads run on the cache's own copy stream from
+ * pinned memory; `stream` -- the stream the renders using *out run on, the
+ * same on every call -- waits for the rendered views' uploads, and a slot is
+ * only overwritten after the work enqueued on `stream` before the call that
+ * last needed it (no host synchronisation).  The descriptor stays valid
+ * until the next prepare on this cache.  Returns HGSR_ERR_CAPACITY (nothing
+ * enqueued) when the rendered views may see more partitions than the cache
+ * has slots.  stats may be NULL. */
+hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, int32_t n_render,
+                                const hgsr_intrinsics* K, float near_z, float motion_margin, hgsr_gaussians* out,
+                                hgsr_pcache_stats* stats, hgsr_stream stream);
 
 /* Drop every resident partition (the slots stay allocated); the next
  * prepare uploads what it needs.  Synchronises the copy stream. */

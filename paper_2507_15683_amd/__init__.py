@@ -206,13 +206,21 @@ class PartitionCache:
         self.stats = {}
 
     def prepare(self, poses, K: "Intrinsics", near: float = 0.2, motion_margin: float = 0.0,
-                stream=None) -> StreamedScene:
+                ahead=None, stream=None) -> StreamedScene:
+        """Make what `poses` may see resident (hgsr_pcache_prepare); `ahead`
+        (upcoming poses, optional) have their partitions uploaded behind this
+        batch, overlapping its renders."""
         q = np.ascontiguousarray(np.asarray(poses.cpu() if isinstance(poses, torch.Tensor) else poses,
                                             dtype=np.float32).reshape(-1, 12))
+        n_render = q.shape[0]
+        if ahead is not None and len(ahead):
+            qa = np.asarray(ahead.cpu() if isinstance(ahead, torch.Tensor) else ahead, dtype=np.float32)
+            q = np.ascontiguousarray(np.concatenate([q, qa.reshape(-1, 12)]))
         g = _lib.Gaussians()
         st = _lib.PcacheStats()
         kc = K.c()
-        check(self.lib.hgsr_pcache_prepare(self.pc, q.ctypes.data, q.shape[0], ctypes.byref(kc), near, motion_margin,
+        check(self.lib.hgsr_pcache_prepare(self.pc, q.ctypes.data, q.shape[0], n_render, ctypes.byref(kc), near,
+                                           motion_margin,
                                            ctypes.byref(g), ctypes.byref(st), _stream_ptr(stream)),
               "hgsr_pcache_prepare")
         self.stats = {f: getattr(st, f) for f, _ in _lib.PcacheStats._fields_}

@@ -95,7 +95,7 @@ class HostScene(ctypes.Structure):
 class PcacheStats(ctypes.Structure):
     _fields_ = [("needed", I32), ("hits", I32), ("uploads", I32), ("evictions", I32), ("bytes_uploaded", I64),
                 ("total_uploads", I64), ("total_bytes", I64), ("n_slots", I32), ("slot_capacity", I64),
-                ("device_bytes", I64)]
+                ("device_bytes", I64), ("prefetched", I32)]
 
 
 # (name, argtypes) for every entry point declared in include/hgsr.h
@@ -119,7 +119,7 @@ SIGNATURES = {
     "hgsr_partition_bounds": [ctypes.POINTER(Gaussians), P_, P_],
     "hgsr_pcache_create": [ctypes.POINTER(P_), ctypes.POINTER(HostScene), I32],
     "hgsr_pcache_destroy": [P_],
-    "hgsr_pcache_prepare": [P_, P_, I32, ctypes.POINTER(Intrinsics), F32, F32, ctypes.POINTER(Gaussians),
+    "hgsr_pcache_prepare": [P_, P_, I32, I32, ctypes.POINTER(Intrinsics), F32, F32, ctypes.POINTER(Gaussians),
                             ctypes.POINTER(PcacheStats), P_],
     "hgsr_pcache_evict_all": [P_],
     "hgsr_host_partition_bounds": [ctypes.POINTER(HostScene), P_],

@@ -9,15 +9,17 @@
 // the slots the descriptor's partitions, so the renderer's partition test
 // skips slots a pose cannot see and empty slots (empty boxes) always.
 //
-// Ordering without host waits: uploads run on the cache's copy stream.  At
-// the start of a prepare, every slot that the previous batch used gets an
-// event recorded on the render stream (it completes once that batch's work
-// has); a slot's data is overwritten only after the copy stream has waited
-// for its event, so uploads into least recently used slots overlap the
-// previous batch's renders.  The slot table (offsets are fixed; boxes
-// change) is rewritten only after everything enqueued on the render stream
-// before the call, which costs nothing since the next render follows that
-// work anyway, and the render stream waits for the batch's uploads.
+// Ordering without host waits: uploads run on the cache's copy stream, each
+// slot's followed by an event of its own.  At the start of a prepare, every
+// slot that the previous batch used gets an event recorded on the render
+// stream (it completes once that batch's work has); a slot's data is
+// overwritten only after the copy stream has waited for that event, so
+// uploads into least recently used slots overlap the previous batch's
+// renders.  The slot table (offsets are fixed; boxes change) is rewritten by
+// a kernel on the render stream, after the previous renders by stream order
+// and after the uploads of exactly the slots it makes visible -- uploads for
+// upcoming views stay invisible, and unwaited, until a later table shows
+// them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -191,11 +193,11 @@ struct hgsr_pcache {
   std::vector<int64_t> slot_last;   // last batch that needed the slot, -1 for none
   std::vector<hipEvent_t> slot_rel;
   std::vector<uint8_t> slot_rel_set;
+  std::vector<hipEvent_t> slot_ready;  // recorded on the copy stream after a slot's upload
+  std::vector<uint8_t> slot_pending;   // uploaded, not yet waited for by the render stream
   std::vector<int32_t> part_slot;   // slot of a resident partition, -1 otherwise
   bool table_dirty = false;         // slot boxes changed since the device table was written
   hipStream_t copy = nullptr;
-  hipEvent_t ready = nullptr;
-  hipEvent_t prior = nullptr;       // the render stream's work before the current prepare
   int64_t batch = 0;
   hgsr_pcache_stats st{};
 };
@@ -206,8 +208,8 @@ void release_all(hgsr_pcache* pc) {
   if (pc->copy) (void)hipStreamSynchronize(pc->copy);
   for (hipEvent_t e : pc->slot_rel)
     if (e) (void)hipEventDestroy(e);
-  if (pc->ready) (void)hipEventDestroy(pc->ready);
-  if (pc->prior) (void)hipEventDestroy(pc->prior);
+  for (hipEvent_t e : pc->slot_ready)
+    if (e) (void)hipEventDestroy(e);
   if (pc->copy) (void)hipStreamDestroy(pc->copy);
   if (pc->dev) (void)hipFree(pc->dev);
   if (pc->host) (void)hipHostFree(pc->host);
@@ -329,13 +331,14 @@ hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, 
   pc->slot_last.assign(n_slots, -1);
   pc->slot_rel.assign(n_slots, nullptr);
   pc->slot_rel_set.assign(n_slots, 0);
+  pc->slot_ready.assign(n_slots, nullptr);
+  pc->slot_pending.assign(n_slots, 0);
   pc->part_slot.assign(pc->n_parts, -1);
   for (int sl = 0; sl < n_slots; ++sl)
-    if (hipEventCreateWithFlags(&pc->slot_rel[sl], hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&pc->slot_rel[sl], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pc->slot_ready[sl], hipEventDisableTiming) != hipSuccess)
       return fail_free(err(HGSR_ERR_HIP, "hipEventCreate failed"));
-  if (hipEventCreateWithFlags(&pc->ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pc->prior, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&pc->copy, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&pc->copy, hipStreamNonBlocking) != hipSuccess)
     return fail_free(err(HGSR_ERR_HIP, "stream or event creation failed"));
   pc->st.n_slots = n_slots;
   pc->st.slot_capacity = pc->cap;
@@ -362,31 +365,36 @@ hgsr_status hgsr_pcache_evict_all(hgsr_pcache* pc) {
       pc->slot_box[6 * sl + 3 + a] = -1.f;
     }
     // the slot's last use stays recorded: its next upload still waits for it
+    pc->slot_pending[sl] = 0;  // the copy stream has finished
   }
   pc->table_dirty = true;  // written by the next prepare, after the work already enqueued
   return HGSR_OK;
 }
 
-hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, const hgsr_intrinsics* K,
-                                float near_z, float motion_margin, hgsr_gaussians* out, hgsr_pcache_stats* stats,
-                                hgsr_stream stream) {
+hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, int32_t n_render,
+                                const hgsr_intrinsics* K, float near_z, float motion_margin, hgsr_gaussians* out,
+                                hgsr_pcache_stats* stats, hgsr_stream stream) {
   if (!pc || !out) return err(HGSR_ERR_INVALID_ARG, "NULL cache or output");
   hgsr_status s = check_plan_args(pc->n_parts, poses, P, K, near_z, motion_margin);
   if (s != HGSR_OK) return s;
+  if (n_render < 1 || n_render > P) return err(HGSR_ERR_INVALID_ARG, "n_render must be 1..P");
   const float nz = near_z > 0.f ? near_z : 0.2f;
-  // partitions the batch may see
+  // partitions the rendered views may see (need 1) and, not among them, the
+  // ones only the upcoming views may see (need 2)
   std::vector<uint8_t> need(pc->n_parts, 0);
   int n_need = 0;
   for (int k = 0; k < pc->n_parts; ++k) {
-    for (int p = 0; p < P && !need[k]; ++p)
-      need[k] = box_may_be_seen(pc->bounds.data() + 6 * k, poses + 12 * p, *K, nz, motion_margin) ? 1 : 0;
-    n_need += need[k];
+    const float* B = pc->bounds.data() + 6 * k;
+    for (int p = 0; p < n_render && !need[k]; ++p)
+      need[k] = box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 1 : 0;
+    for (int p = n_render; p < P && !need[k]; ++p)
+      need[k] = box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 2 : 0;
+    n_need += need[k] == 1;
   }
   if (n_need > pc->n_slots)
-    return err(HGSR_ERR_CAPACITY, "the batch may see %d partitions but the cache has %d slots", n_need,
+    return err(HGSR_ERR_CAPACITY, "the rendered views may see %d partitions but the cache has %d slots", n_need,
                pc->n_slots);
   hipStream_t rs = reinterpret_cast<hipStream_t>(stream);
-  PC_HIP(hipEventRecord(pc->prior, rs));
   // the previous batch's slots: released once the work enqueued so far ends
   for (int sl = 0; sl < pc->n_slots; ++sl)
     if (pc->slot_last[sl] == pc->batch - 1 && pc->batch > 0) {
@@ -395,31 +403,39 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     }
   hgsr_pcache_stats& st = pc->st;
   st.needed = n_need;
-  st.hits = st.uploads = st.evictions = 0;
+  st.hits = st.uploads = st.evictions = st.prefetched = 0;
   st.bytes_uploaded = 0;
   std::vector<uint8_t> taken(pc->n_slots, 0);
   for (int k = 0; k < pc->n_parts; ++k)
-    if (need[k] && pc->part_slot[k] >= 0) {
+    if (need[k] == 1 && pc->part_slot[k] >= 0) {
       taken[pc->part_slot[k]] = 1;
       pc->slot_last[pc->part_slot[k]] = pc->batch;
       ++st.hits;
     }
   const Widths w(pc->sh_degree, pc->feat_dim);
-  bool uploaded = false;
-  for (int k = 0; k < pc->n_parts; ++k) {
-    if (!need[k] || pc->part_slot[k] >= 0) continue;
-    // victim: an empty slot, else the least recently used one this batch does not need
+  // victim: an empty slot, else the least recently used one not taken
+  auto victim = [&]() {
     int v = -1;
     for (int sl = 0; sl < pc->n_slots; ++sl)
       if (!taken[sl] && pc->slot_part[sl] < 0 && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
     if (v < 0)
       for (int sl = 0; sl < pc->n_slots; ++sl)
         if (!taken[sl] && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
-    if (v < 0) return err(HGSR_ERR_STATE, "no free slot (internal)");
+    return v;
+  };
+  auto claim = [&](int k, int v) {
     if (pc->slot_part[v] >= 0) {
       pc->part_slot[pc->slot_part[v]] = -1;
       ++st.evictions;
     }
+    pc->slot_part[v] = k;
+    pc->part_slot[k] = v;
+    pc->slot_last[v] = pc->batch;
+    taken[v] = 1;
+    ++st.uploads;
+    st.bytes_uploaded += (pc->offs[k + 1] - pc->offs[k]) * static_cast<int64_t>(w.total());
+  };
+  auto upload = [&](int k, int v) -> hgsr_status {
     if (pc->slot_rel_set[v]) PC_HIP(hipStreamWaitEvent(pc->copy, pc->slot_rel[v], 0));
     const int64_t b = pc->offs[k], cnt = pc->offs[k + 1] - pc->offs[k];
     const int64_t d0 = static_cast<int64_t>(v) * pc->cap;
@@ -435,32 +451,68 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     if (tail > 0)
       hipLaunchKernelGGL(zero_tail_kernel, dim3(static_cast<unsigned>((tail + 255) / 256)), dim3(256), 0, pc->copy,
                          reinterpret_cast<float*>(pc->d_opac) + d0 + cnt, tail);
-    std::copy(pc->bounds.begin() + 6 * k, pc->bounds.begin() + 6 * k + 6, pc->slot_box.begin() + 6 * v);
+    PC_HIP(hipGetLastError());
+    PC_HIP(hipEventRecord(pc->slot_ready[v], pc->copy));
+    pc->slot_pending[v] = 1;
+    return HGSR_OK;
+  };
+  auto set_box = [&](int v, const float* B) {
+    std::copy(B, B + 6, pc->slot_box.begin() + 6 * v);
     pc->table_dirty = true;
-    pc->slot_part[v] = k;
-    pc->part_slot[k] = v;
-    pc->slot_last[v] = pc->batch;
-    taken[v] = 1;
-    ++st.uploads;
-    st.bytes_uploaded += cnt * static_cast<int64_t>(w.total());
-    uploaded = true;
+  };
+  const float kEmpty[6] = {1.f, 1.f, 1.f, -1.f, -1.f, -1.f};
+  // 1. the rendered views' misses
+  for (int k = 0; k < pc->n_parts; ++k) {
+    if (need[k] != 1 || pc->part_slot[k] >= 0) continue;
+    const int v = victim();
+    if (v < 0) return err(HGSR_ERR_STATE, "no free slot (internal)");
+    claim(k, v);
+    hgsr_status us = upload(k, v);
+    if (us != HGSR_OK) return us;
+    set_box(v, pc->bounds.data() + 6 * k);
   }
-  const bool wrote_table = pc->table_dirty;
+  // 2. upcoming views: resident ones stay warm; missing ones take free or
+  // least recently used slots the rendered views cannot see (best effort).
+  // Their slots are empty in this batch's table; a later table shows them.
+  std::vector<int> ahead_k, ahead_v;
+  for (int k = 0; k < pc->n_parts; ++k)
+    if (need[k] == 2 && pc->part_slot[k] >= 0) {
+      taken[pc->part_slot[k]] = 1;
+      pc->slot_last[pc->part_slot[k]] = pc->batch;
+    }
+  for (int k = 0; k < pc->n_parts; ++k) {
+    if (need[k] != 2 || pc->part_slot[k] >= 0) continue;
+    const int v = victim();
+    if (v < 0) continue;
+    claim(k, v);
+    ++st.prefetched;
+    set_box(v, kEmpty);
+    ahead_k.push_back(k);
+    ahead_v.push_back(v);
+  }
+  // 3. the upcoming views' uploads
+  for (size_t q = 0; q < ahead_k.size(); ++q) {
+    hgsr_status us = upload(ahead_k[q], ahead_v[q]);
+    if (us != HGSR_OK) return us;
+  }
+  // 4. the slot table on the render stream: after the previous renders (stream
+  // order) and after the uploads of the slots it shows
   if (pc->table_dirty) {
-    PC_HIP(hipStreamWaitEvent(pc->copy, pc->prior, 0));
     SlotBoxes t;
     std::memset(&t, 0, sizeof(t));
-    for (int sl = 0; sl < pc->n_slots; ++sl)
+    for (int sl = 0; sl < pc->n_slots; ++sl) {
       for (int a = 0; a < 6; ++a) t.b[sl][a] = pc->slot_box[6 * sl + a];
-    hipLaunchKernelGGL(write_boxes_kernel, dim3(1), dim3(64), 0, pc->copy, t, pc->n_slots, pc->d_bounds);
+      if (pc->slot_pending[sl] && !empty_box(&pc->slot_box[6 * sl])) {
+        PC_HIP(hipStreamWaitEvent(rs, pc->slot_ready[sl], 0));
+        pc->slot_pending[sl] = 0;
+      }
+    }
+    hipLaunchKernelGGL(write_boxes_kernel, dim3(1), dim3(64), 0, rs, t, pc->n_slots, pc->d_bounds);
     PC_HIP(hipGetLastError());
     pc->table_dirty = false;
   }
-  if (uploaded || wrote_table) {
-    // the render stream waits for this batch's uploads and table
-    PC_HIP(hipEventRecord(pc->ready, pc->copy));
-    PC_HIP(hipStreamWaitEvent(rs, pc->ready, 0));
-  }
+  // the upcoming views' slots show their boxes from the next table on
+  for (size_t q = 0; q < ahead_k.size(); ++q) set_box(ahead_v[q], pc->bounds.data() + 6 * ahead_k[q]);
   st.total_uploads += st.uploads;
   st.total_bytes += st.bytes_uploaded;
   ++pc->batch;

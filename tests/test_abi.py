@@ -60,7 +60,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.PnpProblem) == 4 * 8 + 4 * 4     # 2 ptrs, n, samples, n_hyp, tau, 2 counts
     assert ctypes.sizeof(_lib.PnpResult) == 6 * 8
     assert ctypes.sizeof(_lib.HostScene) == 8 + 5 * 8 + 4 + 4 + 8 + 4 + 4 + 8  # ..., n_parts, padding, offsets
-    assert ctypes.sizeof(_lib.PcacheStats) == 4 * 4 + 3 * 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(_lib.PcacheStats) == 4 * 4 + 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4  # ..., prefetched, padding
 
 
 def test_invalid_arguments_rejected_on_host(lib):

@@ -206,3 +206,34 @@ def test_pose_gradients_through_the_stream(hg, scene):
     log("pose grads", ga, gb)
     np.testing.assert_allclose(ga, gb, rtol=1e-5, atol=1e-5 * np.abs(gb).max())
     pc.close()
+
+
+def test_upcoming_views_upload_ahead(hg, scene):
+    """Each view prepared with the next three as upcoming views, twelve
+    batches enqueued back to back: partitions arrive ahead (prefetched
+    uploads, later hits), never more than the slots, and every render equals
+    the resident scene's."""
+    import torch
+    K = hg.Intrinsics.of(CAM)
+    full = hg.GaussianScene.from_numpy(scene)
+    pc = hg.PartitionCache(scene, 6)
+    poses = _track(15, 16)
+    s = torch.cuda.Stream()
+    r = hg.Renderer()
+    r.reserve(1, CAM.width, CAM.height, 16, 4 * 3000, 1 << 20, 16 * 3000)
+    q_all = _t(poses)
+    outs, pre, hits = [], 0, 0
+    with torch.cuda.stream(s):
+        for k in range(12):
+            sc = pc.prepare(poses[k], K, ahead=poses[k + 1:k + 4], stream=s)
+            pre += pc.stats["prefetched"]
+            hits += pc.stats["hits"]
+            outs.append(r.render(sc, q_all[k:k + 1], K, check_overflow=False, stream=s))
+    s.synchronize()
+    assert r.check_overflow(s) == 0
+    log("uploads", pc.stats["total_uploads"], "ahead", pre, "hits", hits)
+    assert pre > 0 and hits > 0
+    rf = hg.Renderer()
+    for k, a in enumerate(outs):
+        assert _same(a, rf.render(full, q_all[k:k + 1], K)) < 1e-3, k
+    pc.close()
