@@ -237,3 +237,22 @@ def test_upcoming_views_upload_ahead(hg, scene):
     for k, a in enumerate(outs):
         assert _same(a, rf.render(full, q_all[k:k + 1], K)) < 1e-3, k
     pc.close()
+
+
+def test_empty_partition_and_full_budget(hg, scene):
+    """A scene with an empty partition, cached with as many slots as
+    partitions (nothing is ever evicted): renders equal the resident
+    scene's (whose partition cull also skips the empty partition)."""
+    import dataclasses
+    offs = np.concatenate([[0], scene.part_offsets]).astype(np.int64)   # partition 0 is empty
+    sc = dataclasses.replace(scene, part_offsets=offs)
+    K = hg.Intrinsics.of(CAM)
+    full = hg.GaussianScene.from_numpy(sc)
+    pc = hg.PartitionCache(sc, len(offs) - 1)
+    r, rf = hg.Renderer(), hg.Renderer()
+    for k, pose in enumerate(_track(6, 17)):
+        desc = pc.prepare(pose, K)
+        assert pc.stats["evictions"] == 0
+        a = r.render(desc, _t(pose[None]), K)
+        assert _same(a, rf.render(full, _t(pose[None]), K)) < 1e-3, k
+    pc.close()
