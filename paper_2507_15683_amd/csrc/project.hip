@@ -41,32 +41,36 @@ __global__ __launch_bounds__(256) void partition_bounds_kernel(GaussArgs g, floa
 // Per (pose, partition): 1 when the partition's box may reach the image.
 // The box is rejected only when all 8 corners lie behind the near plane or on
 // the outer side of one of the four image-side planes (through the camera
-// centre, pushed out by a margin of `margin` pixels).
-__global__ void partition_cull_kernel(const float* poses, int P, const float* bounds, int n_parts, CamArgs c,
-                                      float margin, uint64_t* vis) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const float* T = poses + 12 * p;
-  const float l = (-margin - c.cx) / c.fx, r = (c.W + margin - c.cx) / c.fx;
-  const float t = (-margin - c.cy) / c.fy, b = (c.H + margin - c.cy) / c.fy;
-  uint64_t mask = 0;
-  for (int k = 0; k < n_parts; ++k) {
+// centre, pushed out by a margin of `margin` pixels).  One wave per pose, one
+// lane per partition (at most 64), the mask assembled by a ballot.
+__global__ __launch_bounds__(64) void partition_cull_kernel(const float* poses, int P, const float* bounds,
+                                                            int n_parts, CamArgs c, float margin, uint64_t* vis) {
+  const int p = blockIdx.x;
+  const int k = threadIdx.x;
+  if (p >= P) return;  // uniform
+  bool seen = false;
+  if (k < n_parts) {
+    const float* T = poses + 12 * p;
+    const float l = (-margin - c.cx) / c.fx, r = (c.W + margin - c.cx) / c.fx;
+    const float t = (-margin - c.cy) / c.fy, b = (c.H + margin - c.cy) / c.fy;
     const float* B = bounds + 6 * k;
-    if (!(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5])) continue;  // empty box (or NaN): nothing to draw
-    bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
-    for (int q = 0; q < 8; ++q) {
-      const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
-      float m[3];
-      to_camera(T, w, m);
-      all_near &= m[2] < c.near_z;
-      all_l &= m[0] < l * m[2];
-      all_r &= m[0] > r * m[2];
-      all_t &= m[1] < t * m[2];
-      all_b &= m[1] > b * m[2];
+    if (B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5]) {  // else empty (or NaN): nothing to draw
+      bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
+      for (int q = 0; q < 8; ++q) {
+        const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
+        float m[3];
+        to_camera(T, w, m);
+        all_near &= m[2] < c.near_z;
+        all_l &= m[0] < l * m[2];
+        all_r &= m[0] > r * m[2];
+        all_t &= m[1] < t * m[2];
+        all_b &= m[1] > b * m[2];
+      }
+      seen = !(all_near || all_l || all_r || all_t || all_b);
     }
-    if (!(all_near || all_l || all_r || all_t || all_b)) mask |= (1ull << k);
   }
-  vis[p] = mask;
+  const uint64_t mask = __ballot(seen);
+  if (k == 0) vis[p] = mask;
 }
 
 // ------------------------------------------------------------ projection
@@ -534,8 +538,7 @@ void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s) {
 void launch_partition_cull(const float* poses, int P, const float* bounds, int n_parts, const CamArgs& c,
                            uint64_t* vis, hipStream_t s) {
   const float margin = 8.f + 0.05f * static_cast<float>(c.W > c.H ? c.W : c.H);
-  hipLaunchKernelGGL(partition_cull_kernel, dim3((P + 63) / 64), dim3(64), 0, s, poses, P, bounds, n_parts, c,
-                     margin, vis);
+  hipLaunchKernelGGL(partition_cull_kernel, dim3(P), dim3(64), 0, s, poses, P, bounds, n_parts, c, margin, vis);
 }
 
 template <int G>
