@@ -622,26 +622,35 @@ __device__ void tile_sort_global(const TileSortArgs& a, uint2 r, uint32_t n, uin
 
 // Lists longer than one wave sorts: the workgroup sorts them in LDS up to the
 // LDS capacity, or with a stable LSD radix sort in global memory beyond it.
+constexpr int kLongSortCtas = 768;  // three workgroups per CU
+
+// Lists too long for one wave: each workgroup walks every gridDim.x-th tile
+// (most have short lists and are skipped; the 48 KB of LDS leaves room for
+// only three workgroups per CU, so a workgroup per tile would mostly queue).
 __global__ __launch_bounds__(256) void tile_sort_long_kernel(TileSortArgs a) {
   __shared__ uint64_t s_key[kLdsSortCap];
   __shared__ uint32_t s_val[kLdsSortCap];
   if (a.flags[0] & 3) return;
-  const uint2 r = a.ranges[blockIdx.x];
-  const uint32_t n = r.y - r.x;
-  if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) return;
-  if (n <= static_cast<uint32_t>(a.lds_cap)) {
-    tile_sort_lds(a, r, n, s_key, s_val);
-  } else {
-    // reuse the key array's LDS for the radix pass state
-    uint32_t* base = reinterpret_cast<uint32_t*>(s_key);
-    tile_sort_global(a, r, n, base, reinterpret_cast<uint32_t(*)[256]>(base + 256), base + 256 + 4 * 256);
+  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {  // uniform per workgroup
+    const uint2 r = a.ranges[t];
+    const uint32_t n = r.y - r.x;
+    if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) continue;
+    if (n <= static_cast<uint32_t>(a.lds_cap)) {
+      tile_sort_lds(a, r, n, s_key, s_val);
+    } else {
+      // reuse the key array's LDS for the radix pass state
+      uint32_t* base = reinterpret_cast<uint32_t*>(s_key);
+      tile_sort_global(a, r, n, base, reinterpret_cast<uint32_t(*)[256]>(base + 256), base + 256 + 4 * 256);
+    }
+    __syncthreads();  // the LDS is reused by the next tile
   }
 }
 
 void launch_tile_sort(const TileSortArgs& a, bool short_lists, hipStream_t s) {
   if (a.n_tiles <= 0) return;
   if (short_lists) hipLaunchKernelGGL(tile_sort_wave_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(tile_sort_long_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(tile_sort_long_kernel, dim3(a.n_tiles < kLongSortCtas ? a.n_tiles : kLongSortCtas), dim3(256), 0,
+                     s, a);
 }
 
 // ------------------------------------------------------------ LSD path
