@@ -211,3 +211,21 @@ def test_dense_stage_end_to_end(hg):
         int(g["n_inliers"].cpu().numpy()[0]), "of", n)
     assert int(g["best"].cpu().numpy()[0]) >= 0
     assert e1 < 0.5 * e0
+
+
+def test_no_correspondences(hg):
+    """With no correspondences every sample is invalid: the prior pose comes
+    back with no inliers."""
+    import torch
+    T0 = _pose(41)[:3, :].reshape(12).astype(np.float32)
+    r = hg.Renderer()
+    empty2 = torch.empty((0, 2), dtype=torch.float32, device="cuda")
+    empty3 = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    g = r.pnp(empty2, empty3, hg.Intrinsics.of(CAM), _t(T0), _t(np.array([[0, 1, 2], [3, 4, 5]], np.int32)))
+    torch.cuda.synchronize()
+    assert (g["counts"].cpu().numpy() == -1).all() and int(g["best"].cpu().numpy()[0]) == -1
+    np.testing.assert_array_equal(g["pose"].cpu().numpy(), T0)
+    assert int(g["n_inliers"].cpu().numpy()[0]) == 0
+    x = hg.backproject(torch.ones((4, 5), device="cuda"), _t(T0), hg.Intrinsics.of(CAM),
+                       torch.empty(0, dtype=torch.int32, device="cuda"))
+    assert x.shape == (0, 3)
