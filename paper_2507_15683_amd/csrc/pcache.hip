@@ -10,12 +10,12 @@
 // skips slots a pose cannot see and empty slots (empty boxes) always.
 //
 // Ordering without host waits: uploads run on the cache's copy stream, each
-// slot's followed by an event of its own.  At the start of a prepare, every
-// slot that the previous batch used gets an event recorded on the render
-// stream (it completes once that batch's work has); a slot's data is
-// overwritten only after the copy stream has waited for that event, so
-// uploads into least recently used slots overlap the previous batch's
-// renders.  The slot table (offsets are fixed; boxes change) is rewritten by
+// slot's followed by an event of its own.  At the start of a prepare one
+// event is recorded on the render stream (it completes once the previous
+// batches' work has); a slot's data is overwritten only after the copy
+// stream has waited for the event of the first batch after the slot's last
+// use, so uploads into least recently used slots overlap the previous
+// batch's renders.  The slot table (offsets are fixed; boxes change) is rewritten by
 // a kernel on the render stream, after the previous renders by stream order
 // and after the uploads of exactly the slots it makes visible -- uploads for
 // upcoming views stay invisible, and unwaited, until a later table shows
@@ -191,8 +191,11 @@ struct hgsr_pcache {
   std::vector<float> slot_box;      // n_slots x 6
   std::vector<int32_t> slot_part;   // resident partition, -1 for none
   std::vector<int64_t> slot_last;   // last batch that needed the slot, -1 for none
-  std::vector<hipEvent_t> slot_rel;
-  std::vector<uint8_t> slot_rel_set;
+  // batch_ev[b % kRing], recorded on the render stream at the start of
+  // prepare b, completes once every batch before b has; a slot last used by
+  // batch L may be overwritten after batch_ev of L + 1 (or of a later batch)
+  static constexpr int kRing = 16;
+  std::vector<hipEvent_t> batch_ev;
   std::vector<hipEvent_t> slot_ready;  // recorded on the copy stream after a slot's upload
   std::vector<uint8_t> slot_pending;   // uploaded, not yet waited for by the render stream
   std::vector<int32_t> part_slot;   // slot of a resident partition, -1 otherwise
@@ -206,7 +209,7 @@ namespace {
 
 void release_all(hgsr_pcache* pc) {
   if (pc->copy) (void)hipStreamSynchronize(pc->copy);
-  for (hipEvent_t e : pc->slot_rel)
+  for (hipEvent_t e : pc->batch_ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : pc->slot_ready)
     if (e) (void)hipEventDestroy(e);
@@ -329,14 +332,15 @@ hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, 
     return fail_free(err(HGSR_ERR_HIP, "hipMemcpy of the slot tables failed"));
   pc->slot_part.assign(n_slots, -1);
   pc->slot_last.assign(n_slots, -1);
-  pc->slot_rel.assign(n_slots, nullptr);
-  pc->slot_rel_set.assign(n_slots, 0);
+  pc->batch_ev.assign(hgsr_pcache::kRing, nullptr);
   pc->slot_ready.assign(n_slots, nullptr);
   pc->slot_pending.assign(n_slots, 0);
   pc->part_slot.assign(pc->n_parts, -1);
   for (int sl = 0; sl < n_slots; ++sl)
-    if (hipEventCreateWithFlags(&pc->slot_rel[sl], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pc->slot_ready[sl], hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&pc->slot_ready[sl], hipEventDisableTiming) != hipSuccess)
+      return fail_free(err(HGSR_ERR_HIP, "hipEventCreate failed"));
+  for (int r = 0; r < hgsr_pcache::kRing; ++r)
+    if (hipEventCreateWithFlags(&pc->batch_ev[r], hipEventDisableTiming) != hipSuccess)
       return fail_free(err(HGSR_ERR_HIP, "hipEventCreate failed"));
   if (hipStreamCreateWithFlags(&pc->copy, hipStreamNonBlocking) != hipSuccess)
     return fail_free(err(HGSR_ERR_HIP, "stream or event creation failed"));
@@ -395,12 +399,9 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     return err(HGSR_ERR_CAPACITY, "the rendered views may see %d partitions but the cache has %d slots", n_need,
                pc->n_slots);
   hipStream_t rs = reinterpret_cast<hipStream_t>(stream);
-  // the previous batch's slots: released once the work enqueued so far ends
-  for (int sl = 0; sl < pc->n_slots; ++sl)
-    if (pc->slot_last[sl] == pc->batch - 1 && pc->batch > 0) {
-      PC_HIP(hipEventRecord(pc->slot_rel[sl], rs));
-      pc->slot_rel_set[sl] = 1;
-    }
+  // everything enqueued before this batch (the release point of the slots the
+  // previous batch used)
+  PC_HIP(hipEventRecord(pc->batch_ev[pc->batch % hgsr_pcache::kRing], rs));
   hgsr_pcache_stats& st = pc->st;
   st.needed = n_need;
   st.hits = st.uploads = st.evictions = st.prefetched = 0;
@@ -436,7 +437,12 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     st.bytes_uploaded += (pc->offs[k + 1] - pc->offs[k]) * static_cast<int64_t>(w.total());
   };
   auto upload = [&](int k, int v) -> hgsr_status {
-    if (pc->slot_rel_set[v]) PC_HIP(hipStreamWaitEvent(pc->copy, pc->slot_rel[v], 0));
+    if (pc->slot_last[v] >= 0) {
+      // released at the first prepare after its last use, or (conservatively)
+      // at the oldest batch the ring still holds
+      const int64_t rel = std::max<int64_t>(pc->slot_last[v] + 1, pc->batch - (hgsr_pcache::kRing - 1));
+      PC_HIP(hipStreamWaitEvent(pc->copy, pc->batch_ev[rel % hgsr_pcache::kRing], 0));
+    }
     const int64_t b = pc->offs[k], cnt = pc->offs[k + 1] - pc->offs[k];
     const int64_t d0 = static_cast<int64_t>(v) * pc->cap;
     const char* hsrc[6] = {pc->h_means, pc->h_ls, pc->h_quats, pc->h_opac, pc->h_sh, pc->h_feat};
