@@ -73,6 +73,22 @@ __global__ __launch_bounds__(64) void partition_cull_kernel(const float* poses, 
   if (k == 0) vis[p] = mask;
 }
 
+// True when no pose of the launch may see a partition overlapping the
+// Gaussian range [i0, i1]: the workgroup covering it exits before reading
+// anything (the same for all its threads).
+__device__ __forceinline__ bool range_culled(const ProjectArgs& a, int64_t i0, int64_t i1) {
+  if (a.g.n_parts <= 0) return false;
+  int p0 = 0;
+  while (p0 + 1 < a.g.n_parts && a.g.part_offsets[p0 + 1] <= i0) ++p0;
+  int p1 = p0;
+  while (p1 + 1 < a.g.n_parts && a.g.part_offsets[p1 + 1] <= i1) ++p1;
+  uint64_t seen = 0;
+  for (int p = 0; p < a.P; ++p) seen |= a.part_vis[a.pose_base + p];
+  const int w = p1 - p0 + 1;
+  const uint64_t span = (w >= 64 ? ~0ull : ((1ull << w) - 1ull)) << p0;
+  return (seen & span) == 0;
+}
+
 // ------------------------------------------------------------ projection
 // Few poses, compacted: a block culls G x 256 Gaussians with the
 // cheap tests (opacity, partition, near plane, conservative footprint bound;
@@ -157,6 +173,7 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
   __shared__ int s_rect[4];                     // tile rectangle of the block's records (one pose)
   const int tid = threadIdx.x;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kProjBlockItems;
+  if (range_culled(a, base, min(base + kProjBlockItems, a.g.n) - 1)) return;
   for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
   if (tid == 0) {
     s_nc = 0;
@@ -358,6 +375,8 @@ __global__ __launch_bounds__(256) void cull_kernel(ProjectArgs a) {
   __shared__ uint32_t s_base[kMaxPoses];
   const int tid = threadIdx.x;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  if (range_culled(a, static_cast<int64_t>(blockIdx.x) * 256, min(static_cast<int64_t>(blockIdx.x) * 256 + 256, a.g.n) - 1))
+    return;
   for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
 
   bool live = i < a.g.n;
