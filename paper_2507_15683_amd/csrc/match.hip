@@ -90,33 +90,57 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
     if (row0 + cl < a.nq)
       aop[ks] = *reinterpret_cast<const uint2*>(a.qvec + static_cast<int64_t>(row0 + cl) * D + 8 * ks + 4 * half);
   }
-  float nq[16], rs[16], ra[16];
+  // Per row 1/|q| and a bias that removes rows past the end: stats adds
+  // exp2(-inf) = 0 for them, argmax compares 2 S - inf = -inf, which never
+  // wins.  With the column's scale w_j (1/|r| times 2/tau or log2(e)/tau)
+  // an entry costs one product iq_i w_j instead of a reciprocal of
+  // |q||r| + eps: the two differ by a relative eps / (|q||r|), and for a
+  // zero vector both give a cosine of 0.
+  float iq[16], rs[16], ra[16];
   int32_t ri[16];
   bool rv[16];
+  const float k1 = kLog2e * a.inv_tau;
+  const float two_tau = 2.f * a.inv_tau;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = row0 + 8 * (r / 4) + 4 * half + (r % 4);
     rv[r] = i < a.nq;
-    nq[r] = rv[r] ? a.qnorm[i] : 1.f;
+    const float n = rv[r] ? a.qnorm[i] : 0.f;
+    iq[r] = n > 0.f ? 1.f / n : 0.f;
     rs[r] = ARGMAX ? -INFINITY : 0.f;  // stats: sum; argmax: best value of 2 S - b
-    ra[r] = ARGMAX && rv[r] ? a.row_lse[i] : 0.f;
+    // stats: exponent bias -log2(e)/tau; argmax: a_i
+    ra[r] = ARGMAX ? (rv[r] ? a.row_lse[i] : INFINITY) : (rv[r] ? -k1 : -INFINITY);
     ri[r] = -1;
   }
-  const float k1 = kLog2e * a.inv_tau;
-  const float two_tau = 2.f * a.inv_tau;
-  for (int c0 = c_begin; c0 < c_end; c0 += RC) {
-    // this round's B operands, all loads in flight before the first product
-    uint2 bop[kTilesPerRound][D / 8];
+  // Stats: a round's B operands and column norms are loaded one round ahead,
+  // so their latency hides behind the previous round's products.  Argmax
+  // (more registers live, two waves per SIMD) loads them at the round's
+  // start: ahead it was measured slower.
+  constexpr bool kAhead = !ARGMAX;
+  uint2 bop[kTilesPerRound][D / 8];
+  float nrm[kTilesPerRound], lse[kTilesPerRound];
+  auto load_round = [&](int c0, uint2 (&b)[kTilesPerRound][D / 8], float (&n)[kTilesPerRound],
+                        float (&l)[kTilesPerRound]) {
 #pragma unroll
     for (int t = 0; t < kTilesPerRound; ++t) {
       const int col = c0 + 32 * t + cl;
+      const bool cv = col < c_end;
 #pragma unroll
       for (int ks = 0; ks < D / 8; ++ks) {
-        bop[t][ks] = make_uint2(0u, 0u);
-        if (col < c_end)
-          bop[t][ks] = *reinterpret_cast<const uint2*>(a.rvec + static_cast<int64_t>(col) * D + 8 * ks + 4 * half);
+        b[t][ks] = make_uint2(0u, 0u);
+        if (cv) b[t][ks] = *reinterpret_cast<const uint2*>(a.rvec + static_cast<int64_t>(col) * D + 8 * ks + 4 * half);
       }
+      n[t] = cv ? a.rnorm[col] : 0.f;
+      // argmax: b_j, +inf past the end (row objectives -inf there)
+      l[t] = ARGMAX ? (cv ? a.col_lse[col] : INFINITY) : 0.f;
     }
+  };
+  if constexpr (kAhead) load_round(c_begin, bop, nrm, lse);
+  for (int c0 = c_begin; c0 < c_end; c0 += RC) {
+    uint2 bnext[kTilesPerRound][D / 8];
+    float nnext[kTilesPerRound], lnext[kTilesPerRound];
+    if constexpr (kAhead) load_round(c0 + RC, bnext, nnext, lnext);  // all zero past c_end
+    else load_round(c0, bop, nrm, lse);
 #pragma unroll
     for (int t = 0; t < kTilesPerRound; ++t) {
       const int col = c0 + 32 * t + cl;
@@ -129,27 +153,27 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
         __builtin_memcpy(&B, &bop[t][ks], 8);
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, acc, 0, 0, 0);
       }
-      const float nr = cv ? a.rnorm[col] : 1.f;
-      const float cb = ARGMAX && cv ? a.col_lse[col] : 0.f;
+      const float nr = nrm[t];
+      const float wc = (nr > 0.f ? __builtin_amdgcn_rcpf(nr) : 0.f) * (ARGMAX ? two_tau : k1);
+      const float cb = lse[t];
       float cacc = ARGMAX ? -INFINITY : 0.f;
       int32_t cidx = -1;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float m = acc[r] * __builtin_amdgcn_rcpf(fmaf(nq[r], nr, kCosEps));  // cosine
-        const bool ok = rv[r] && cv;
+        const float x = acc[r] * (iq[r] * wc);  // cosine times 2/tau or log2(e)/tau
         if constexpr (!ARGMAX) {
           // exp(S - 1/tau) = 2^((m - 1) log2(e) / tau)
-          const float e = ok ? __builtin_amdgcn_exp2f(fmaf(m, k1, -k1)) : 0.f;
+          const float e = cv ? __builtin_amdgcn_exp2f(x + ra[r]) : 0.f;
           rs[r] += e;
           cacc += e;
         } else {
-          const float vr = fmaf(m, two_tau, -cb);     // row i's objective 2 S - b at column j
-          const float vc = fmaf(m, two_tau, -ra[r]);  // column j's objective 2 S - a at row i
-          if (ok && vr > rs[r]) {       // a lane's columns arrive in increasing order
+          const float vr = x - cb;     // row i's objective 2 S - b at column j
+          const float vc = x - ra[r];  // column j's objective 2 S - a at row i
+          if (vr > rs[r]) {            // a lane's columns arrive in increasing order
             rs[r] = vr;
             ri[r] = col;
           }
-          if (ok && vc > cacc) {        // a lane's rows increase with r
+          if (vc > cacc) {             // a lane's rows increase with r
             cacc = vc;
             cidx = row0 + 8 * (r / 4) + 4 * half + (r % 4);
           }
@@ -191,6 +215,15 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
       }
     }
     __syncthreads();
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int t = 0; t < kTilesPerRound; ++t) {
+#pragma unroll
+        for (int ks = 0; ks < D / 8; ++ks) bop[t][ks] = bnext[t][ks];
+        nrm[t] = nnext[t];
+        lse[t] = lnext[t];
+      }
+    }
   }
   // rows: combine the 32 lanes of each half (the lanes hold different columns)
 #pragma unroll
