@@ -20,10 +20,10 @@
 // column), then reduced.  MNN keeps (i, j) when column j's best row is i; the
 // correspondences are compacted in query order by a scan.
 //
-// Fine level: one workgroup of 64 threads per coarse correspondence; thread
-// t owns query window position t and computes its 64 cosines against the
-// render window (staged in LDS), the window's 64 x 64 matrix goes to LDS for
-// the column statistics, and each thread reports its position's mutual match.
+// Fine level: one workgroup of 64 threads per coarse correspondence; the
+// two windows' vectors are staged in LDS, the window's 64 x 64 cosine matrix
+// comes from the matrix cores and goes to LDS, thread t takes row t's and
+// column t's statistics and reports query position t's mutual match.
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -352,13 +352,18 @@ struct FineArgs {
   float* fp;
 };
 
-// w = 8: 64 window positions, one thread each.
+// w = 8: 64 window positions, one thread each.  The window's 64 x 64
+// products run on the matrix cores (v_mfma_f32_32x32x8_bf16: four 32 x 32
+// tiles, K = D in steps of 8; the bf16 vectors enter exactly, the sums are
+// FP32), staged through LDS as position-major bf16 vectors.
 template <int D>
 __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
   constexpr int WW = 64, w = 8;
-  constexpr int RS = D + 4;            // row stride: 16-byte aligned rows
-  __shared__ float s_r[WW * RS];       // render window vectors (FP32)
+  constexpr int VS = D + 4;            // bf16 vector stride: rows 8-byte aligned, banks spread
+  __shared__ __align__(16) uint16_t s_qv[WW * VS];  // query window vectors
+  __shared__ __align__(16) uint16_t s_rv[WW * VS];  // render window vectors
   __shared__ float s_m[WW][WW + 1];  // the window's cosines [query][render]
+  __shared__ float s_qn[WW];
   __shared__ float s_rn[WW];
   __shared__ float s_cl[WW];         // column log-sum-exps
   __shared__ int32_t s_ca[WW];       // column winners
@@ -371,36 +376,61 @@ __global__ __launch_bounds__(64) void match_fine_kernel(FineArgs a) {
   const int ty = t / w, tx = t % w;
   const int64_t qpix = static_cast<int64_t>(qy0 + ty) * a.Wf + qx0 + tx;
   const int64_t rpix = static_cast<int64_t>(ry0 + ty) * a.Wf + rx0 + tx;
-  float q[D];
   float qq = 0.f, rr = 0.f;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    q[d] = __uint_as_float(static_cast<uint32_t>(a.qf[d * a.plane + qpix]) << 16);
-    qq = fmaf(q[d], q[d], qq);
-    const float rv = __uint_as_float(static_cast<uint32_t>(a.rf[d * a.plane + rpix]) << 16);
-    s_r[t * RS + d] = rv;
+    const uint16_t qb = a.qf[d * a.plane + qpix];
+    const uint16_t rb = a.rf[d * a.plane + rpix];
+    s_qv[t * VS + d] = qb;
+    s_rv[t * VS + d] = rb;
+    const float qv = __uint_as_float(static_cast<uint32_t>(qb) << 16);
+    const float rv = __uint_as_float(static_cast<uint32_t>(rb) << 16);
+    qq = fmaf(qv, qv, qq);
     rr = fmaf(rv, rv, rr);
   }
-  const float nq = sqrtf(qq);
+  s_qn[t] = sqrtf(qq);
   s_rn[t] = sqrtf(rr);
   __syncthreads();
-  // row t: cosines, and the row log-sum-exp with its exact maximum
-  float mx = -INFINITY;
-  for (int j = 0; j < WW; ++j) {
-    float dot = 0.f;
-    const float4* rj = reinterpret_cast<const float4*>(&s_r[j * RS]);  // the same address in every lane
+  {
+    // lane l: operand row / column l % 32 of its tile, channels 8 ks + 4 (l / 32) .. + 3
+    const int cl = t & 31, half = t >> 5;
+    floatx16 acc[2][2];
 #pragma unroll
-    for (int d4 = 0; d4 < D / 4; ++d4) {
-      const float4 v = rj[d4];
-      dot = fmaf(q[4 * d4 + 0], v.x, dot);
-      dot = fmaf(q[4 * d4 + 1], v.y, dot);
-      dot = fmaf(q[4 * d4 + 2], v.z, dot);
-      dot = fmaf(q[4 * d4 + 3], v.w, dot);
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = floatx16{};
+#pragma unroll
+    for (int ks = 0; ks < D / 8; ++ks) {
+      shortx4 A[2], B[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        __builtin_memcpy(&A[u], &s_qv[(32 * u + cl) * VS + 8 * ks + 4 * half], 8);
+        __builtin_memcpy(&B[u], &s_rv[(32 * u + cl) * VS + 8 * ks + 4 * half], 8);
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[ti], B[tj], acc[ti][tj], 0, 0, 0);
     }
-    const float m = dot * __builtin_amdgcn_rcpf(fmaf(nq, s_rn[j], kCosEps));
-    s_m[t][j] = m;
-    mx = fmaxf(mx, m);
+    // result r of a tile: row 8 (r / 4) + 4 half + r % 4, column cl
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      const int j = 32 * tj + cl;
+      const float nr = s_rn[j];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 32 * ti + 8 * (r / 4) + 4 * half + (r % 4);
+          s_m[i][j] = acc[ti][tj][r] * __builtin_amdgcn_rcpf(fmaf(s_qn[i], nr, kCosEps));
+        }
+    }
   }
+  __syncthreads();
+  // row t: the row log-sum-exp with its exact maximum
+  float mx = -INFINITY;
+  for (int j = 0; j < WW; ++j) mx = fmaxf(mx, s_m[t][j]);
   float se = 0.f;
   for (int j = 0; j < WW; ++j) se += __expf((s_m[t][j] - mx) * a.inv_tau);
   const float row_lse = mx * a.inv_tau + __logf(se);
