@@ -160,13 +160,16 @@ __global__ __launch_bounds__(256) void match_pass_kernel(MatchArgs a) {
       int32_t cidx = -1;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float x = acc[r] * (iq[r] * wc);  // cosine times 2/tau or log2(e)/tau
+        const float sc = iq[r] * wc;  // the cosine is acc / (|q||r|); times 2/tau or log2(e)/tau
         if constexpr (!ARGMAX) {
           // exp(S - 1/tau) = 2^((m - 1) log2(e) / tau)
-          const float e = cv ? __builtin_amdgcn_exp2f(x + ra[r]) : 0.f;
+          const float e = cv ? __builtin_amdgcn_exp2f(fmaf(acc[r], sc, ra[r])) : 0.f;
           rs[r] += e;
           cacc += e;
         } else {
+          // a product and two differences: the same with two fused multiply-adds
+          // measured slower
+          const float x = acc[r] * sc;
           const float vr = x - cb;     // row i's objective 2 S - b at column j
           const float vc = x - ra[r];  // column j's objective 2 S - a at row i
           if (vr > rs[r]) {            // a lane's columns arrive in increasing order
