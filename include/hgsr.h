@@ -453,6 +453,23 @@ typedef struct {
 
 typedef struct hgsr_pcache hgsr_pcache;
 
+#define HGSR_MAX_SLOTS 64
+
+/* One partition upload of a batch: partition `part` into device slot `slot`.
+ * `release` is the batch whose start the copy waits for before it overwrites
+ * the slot: the first batch after the slot's previous use (work enqueued on
+ * the render stream before that batch's prepare may still read the slot's
+ * old partition), or the oldest of the last 16 batches when that use is
+ * older still (a conservative, later release); -1 when the slot was never
+ * used (no wait).  `ahead` is 1 for an upload made for upcoming views only. */
+typedef struct {
+  int32_t part;
+  int32_t slot;
+  int64_t release;
+  int32_t ahead;
+  int32_t reserved;
+} hgsr_slot_upload;
+
 typedef struct {
   int32_t needed;          /* partitions the last batch's rendered views may see */
   int32_t hits;            /* of those, already resident */
@@ -465,6 +482,7 @@ typedef struct {
   int64_t slot_capacity;   /* Gaussians per slot (the largest partition) */
   int64_t device_bytes;    /* the device budget in use (slots + tables) */
   int32_t prefetched;      /* of the last batch's uploads, those for upcoming views only */
+  hgsr_slot_upload upload[HGSR_MAX_SLOTS]; /* the last batch's uploads, in enqueue order (`uploads` entries) */
 } hgsr_pcache_stats;
 
 /* Create a cache on the current device: copies the host scene into pinned
@@ -515,6 +533,23 @@ hgsr_status hgsr_pcache_evict_all(hgsr_pcache* pc);
  * partition the renderer would draw is planned).  Empty boxes are never
  * seen. */
 hgsr_status hgsr_host_partition_bounds(const hgsr_host_scene* scene, float* bounds);
+
+/* The partition cache's slot policy on its own (host only; the policy
+ * hgsr_pcache_prepare applies, exposed so that it can be checked without a
+ * GPU).  A step takes, per partition (host, n_parts bytes), 1 when the
+ * batch's rendered views may see it, 2 when only its upcoming views may, 0
+ * otherwise.  Missing partitions of the rendered views take an empty slot
+ * (least recently used first), else the least recently used slot the batch
+ * does not need (ties to the lower slot); then the upcoming views' missing
+ * partitions take the slots left over, while any remain.  It fills needed,
+ * hits, uploads, evictions, prefetched and upload[] of *st (the byte
+ * counters are left alone).  HGSR_ERR_CAPACITY, with the state unchanged,
+ * when the rendered views need more partitions than there are slots. */
+typedef struct hgsr_slot_policy hgsr_slot_policy;
+hgsr_status hgsr_slot_policy_create(hgsr_slot_policy** out, int32_t n_parts, int32_t n_slots);
+hgsr_status hgsr_slot_policy_destroy(hgsr_slot_policy* policy);
+hgsr_status hgsr_slot_policy_step(hgsr_slot_policy* policy, const uint8_t* need, hgsr_pcache_stats* st);
+hgsr_status hgsr_slot_policy_evict_all(hgsr_slot_policy* policy);
 hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const float* poses, int32_t P,
                                 const hgsr_intrinsics* K, float near_z, float motion_margin, uint8_t* seen);
 

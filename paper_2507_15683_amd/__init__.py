@@ -223,7 +223,7 @@ class PartitionCache:
                                            motion_margin,
                                            ctypes.byref(g), ctypes.byref(st), _stream_ptr(stream)),
               "hgsr_pcache_prepare")
-        self.stats = {f: getattr(st, f) for f, _ in _lib.PcacheStats._fields_}
+        self.stats = st.as_dict()
         return StreamedScene(g, self.device)
 
     def evict_all(self):
@@ -233,6 +233,40 @@ class PartitionCache:
         if getattr(self, "pc", None):
             self.lib.hgsr_pcache_destroy(self.pc)
             self.pc = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SlotPolicy:
+    """The partition cache's slot policy on its own (host only, no GPU):
+    step(need) with need[k] = 1 (rendered views may see partition k), 2 (only
+    upcoming views may) or 0 returns the batch's counts and its upload list
+    [(partition, slot, release batch or -1, ahead)]."""
+
+    def __init__(self, n_parts: int, n_slots: int):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(self.lib.hgsr_slot_policy_create(ctypes.byref(h), n_parts, n_slots), "hgsr_slot_policy_create")
+        self.h = h
+        self.n_parts = n_parts
+
+    def step(self, need) -> dict:
+        nd = np.ascontiguousarray(np.asarray(need, dtype=np.uint8).reshape(self.n_parts))
+        st = _lib.PcacheStats()
+        check(self.lib.hgsr_slot_policy_step(self.h, nd.ctypes.data, ctypes.byref(st)), "hgsr_slot_policy_step")
+        return st.as_dict()
+
+    def evict_all(self):
+        check(self.lib.hgsr_slot_policy_evict_all(self.h), "hgsr_slot_policy_evict_all")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hgsr_slot_policy_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

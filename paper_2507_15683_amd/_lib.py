@@ -92,10 +92,22 @@ class HostScene(ctypes.Structure):
                 ("sh_degree", I32), ("feat_dim", I32), ("feat", P_), ("n_parts", I32), ("part_offsets", P_)]
 
 
+MAX_SLOTS = 64
+
+
+class SlotUpload(ctypes.Structure):
+    _fields_ = [("part", I32), ("slot", I32), ("release", I64), ("ahead", I32), ("reserved", I32)]
+
+
 class PcacheStats(ctypes.Structure):
     _fields_ = [("needed", I32), ("hits", I32), ("uploads", I32), ("evictions", I32), ("bytes_uploaded", I64),
                 ("total_uploads", I64), ("total_bytes", I64), ("n_slots", I32), ("slot_capacity", I64),
-                ("device_bytes", I64), ("prefetched", I32)]
+                ("device_bytes", I64), ("prefetched", I32), ("upload", SlotUpload * MAX_SLOTS)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "upload"}
+        d["upload_list"] = [(u.part, u.slot, u.release, u.ahead) for u in self.upload[: self.uploads]]
+        return d
 
 
 # (name, argtypes) for every entry point declared in include/hgsr.h
@@ -125,6 +137,10 @@ SIGNATURES = {
     "hgsr_host_partition_bounds": [ctypes.POINTER(HostScene), P_],
     "hgsr_partition_plan": [P_, I32, P_, I32, ctypes.POINTER(Intrinsics), F32, F32, P_],
     "hgsr_host_spatial_order": [P_, I64, P_, I32, P_],
+    "hgsr_slot_policy_create": [ctypes.POINTER(P_), I32, I32],
+    "hgsr_slot_policy_destroy": [P_],
+    "hgsr_slot_policy_step": [P_, P_, ctypes.POINTER(PcacheStats)],
+    "hgsr_slot_policy_evict_all": [P_],
     "hgsr_validate": [ctypes.POINTER(Gaussians), P_],
     "hgsr_graph_begin": [P_, P_],
     "hgsr_graph_end": [P_],

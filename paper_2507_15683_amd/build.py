@@ -11,13 +11,17 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgsr.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["project.hip", "binning.hip", "blend.hip", "backward.hip", "refine.hip", "score.hip", "match.hip", "pnp.hip",
-           "pcache.hip", "layout.hip", "hgsr_runtime.hip"]
+           "pcache.hip", "hgsr_runtime.hip", "host.cpp"]
 
 # No packed-FP32 instructions; no FMA contraction (forward and reverse replay
 # take bit-identical decisions; FMAs are written explicitly).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
+
+
+# Host-only sources (no device code).
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(HERE, "..", "include")]
 
 
 # Matrix-core results written to ordinary VGPRs, where the epilogue reads them
@@ -30,8 +34,11 @@ def build(verbose: bool = False) -> str:
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
     def compile_one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        if src.endswith(".cpp"):  # host-only C++
+            cmd = ["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        else:
+            cmd = ["hipcc", *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

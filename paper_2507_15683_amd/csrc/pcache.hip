@@ -30,14 +30,15 @@
 #include <vector>
 
 #include "../../include/hgsr.h"
+#include "host.hpp"
 #include "launch.hpp"
 
 using namespace hgsr;
+using host::SlotPolicy;
 
 namespace {
 
-constexpr int kMaxSlots = 64;  // the renderer's per-pose partition mask
-constexpr double kSupport = 3.33;
+constexpr int kMaxSlots = host::kMaxSlots;
 
 hgsr_status err(hgsr_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 hgsr_status err(hgsr_status st, const char* fmt, ...) {
@@ -83,90 +84,6 @@ __global__ void zero_tail_kernel(float* opac, int64_t count) {
   if (i < count) opac[i] = 0.f;
 }
 
-bool empty_box(const float* B) { return !(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5]); }
-
-hgsr_status check_host_scene(const hgsr_host_scene* s) {
-  if (!s) return err(HGSR_ERR_INVALID_ARG, "NULL scene");
-  if (s->n < 0) return err(HGSR_ERR_INVALID_ARG, "n < 0");
-  if (s->sh_degree < 0 || s->sh_degree > 3) return err(HGSR_ERR_INVALID_ARG, "sh_degree must be 0..3");
-  if (!(s->feat_dim == 0 || s->feat_dim == 8 || s->feat_dim == 16 || s->feat_dim == 32 || s->feat_dim == 64))
-    return err(HGSR_ERR_INVALID_ARG, "feat_dim must be 0, 8, 16, 32 or 64");
-  if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacities || !s->sh))
-    return err(HGSR_ERR_INVALID_ARG, "scene arrays are NULL");
-  if (s->n > 0 && s->feat_dim > 0 && !s->feat) return err(HGSR_ERR_INVALID_ARG, "feat is NULL");
-  if (s->n_parts < 1 || !s->part_offsets) return err(HGSR_ERR_INVALID_ARG, "need n_parts >= 1 and part_offsets");
-  if (s->part_offsets[0] != 0 || s->part_offsets[s->n_parts] != s->n)
-    return err(HGSR_ERR_INVALID_ARG, "part_offsets must run from 0 to n");
-  for (int k = 0; k < s->n_parts; ++k)
-    if (s->part_offsets[k + 1] < s->part_offsets[k]) return err(HGSR_ERR_INVALID_ARG, "part_offsets decrease");
-  return HGSR_OK;
-}
-
-void host_bounds(const hgsr_host_scene* s, float* out) {
-  for (int k = 0; k < s->n_parts; ++k) {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = s->part_offsets[k]; i < s->part_offsets[k + 1]; ++i) {
-      const float* l = s->log_scales + 3 * i;
-      const double r = kSupport * std::exp(static_cast<double>(std::max(l[0], std::max(l[1], l[2]))));
-      for (int a = 0; a < 3; ++a) {
-        const double m = s->means[3 * i + a];
-        lo[a] = std::min(lo[a], m - r);
-        hi[a] = std::max(hi[a], m + r);
-      }
-    }
-    for (int a = 0; a < 3; ++a) {
-      // outward rounding to float
-      float fl = static_cast<float>(lo[a]), fh = static_cast<float>(hi[a]);
-      if (static_cast<double>(fl) > lo[a]) fl = std::nextafter(fl, -INFINITY);
-      if (static_cast<double>(fh) < hi[a]) fh = std::nextafter(fh, INFINITY);
-      out[6 * k + a] = fl;
-      out[6 * k + 3 + a] = fh;
-    }
-    if (s->part_offsets[k + 1] == s->part_offsets[k]) {
-      for (int a = 0; a < 3; ++a) {
-        out[6 * k + a] = 1.f;
-        out[6 * k + 3 + a] = -1.f;
-      }
-    }
-  }
-}
-
-// The renderer's partition test, in double, with one more pixel of margin
-// and the box grown by `grow` metres.
-bool box_may_be_seen(const float* B, const float* T, const hgsr_intrinsics& K, double near_z, double grow) {
-  if (empty_box(B)) return false;
-  const double margin = 9.0 + 0.05 * std::max(K.width, K.height);
-  const double l = (-margin - K.cx) / K.fx, r = (K.width + margin - K.cx) / K.fx;
-  const double t = (-margin - K.cy) / K.fy, b = (K.height + margin - K.cy) / K.fy;
-  bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
-  for (int q = 0; q < 8; ++q) {
-    const double w[3] = {(q & 1) ? B[3] + grow : B[0] - grow, (q & 2) ? B[4] + grow : B[1] - grow,
-                         (q & 4) ? B[5] + grow : B[2] - grow};
-    double m[3];
-    for (int r3 = 0; r3 < 3; ++r3)
-      m[r3] = T[4 * r3] * w[0] + T[4 * r3 + 1] * w[1] + T[4 * r3 + 2] * w[2] + T[4 * r3 + 3];
-    all_near &= m[2] < near_z;
-    all_l &= m[0] < l * m[2];
-    all_r &= m[0] > r * m[2];
-    all_t &= m[1] < t * m[2];
-    all_b &= m[1] > b * m[2];
-  }
-  return !(all_near || all_l || all_r || all_t || all_b);
-}
-
-hgsr_status check_plan_args(int32_t n_parts, const float* poses, int32_t P, const hgsr_intrinsics* K,
-                            float near_z, float motion_margin) {
-  if (n_parts < 0) return err(HGSR_ERR_INVALID_ARG, "n_parts < 0");
-  if (P < 1 || !poses) return err(HGSR_ERR_INVALID_ARG, "need P >= 1 host poses");
-  if (!K || !(K->fx > 0.f) || !(K->fy > 0.f) || K->width <= 0 || K->height <= 0)
-    return err(HGSR_ERR_INVALID_ARG, "bad intrinsics");
-  if (!(near_z >= 0.f) || !(motion_margin >= 0.f) || !std::isfinite(motion_margin))
-    return err(HGSR_ERR_INVALID_ARG, "near_z and motion_margin must be finite and non-negative");
-  for (int64_t k = 0; k < 12ll * P; ++k)
-    if (!std::isfinite(poses[k])) return err(HGSR_ERR_INVALID_ARG, "non-finite pose entry");
-  return HGSR_OK;
-}
-
 }  // namespace
 
 struct hgsr_pcache {
@@ -189,19 +106,17 @@ struct hgsr_pcache {
   int64_t* d_offs = nullptr;
   float* d_bounds = nullptr;
   std::vector<float> slot_box;      // n_slots x 6
-  std::vector<int32_t> slot_part;   // resident partition, -1 for none
-  std::vector<int64_t> slot_last;   // last batch that needed the slot, -1 for none
+  // which partition each slot holds; each upload's release batch
+  SlotPolicy pol{1, 1};
   // batch_ev[b % kRing], recorded on the render stream at the start of
   // prepare b, completes once every batch before b has; a slot last used by
   // batch L may be overwritten after batch_ev of L + 1 (or of a later batch)
-  static constexpr int kRing = 16;
+  static constexpr int kRing = SlotPolicy::kRing;
   std::vector<hipEvent_t> batch_ev;
   std::vector<hipEvent_t> slot_ready;  // recorded on the copy stream after a slot's upload
   std::vector<uint8_t> slot_pending;   // uploaded, not yet waited for by the render stream
-  std::vector<int32_t> part_slot;   // slot of a resident partition, -1 otherwise
   bool table_dirty = false;         // slot boxes changed since the device table was written
   hipStream_t copy = nullptr;
-  int64_t batch = 0;
   hgsr_pcache_stats st{};
 };
 
@@ -222,30 +137,10 @@ void release_all(hgsr_pcache* pc) {
 
 extern "C" {
 
-hgsr_status hgsr_host_partition_bounds(const hgsr_host_scene* scene, float* bounds) {
-  hgsr_status s = check_host_scene(scene);
-  if (s != HGSR_OK) return s;
-  if (!bounds) return err(HGSR_ERR_INVALID_ARG, "NULL output");
-  host_bounds(scene, bounds);
-  return HGSR_OK;
-}
-
-hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const float* poses, int32_t P,
-                                const hgsr_intrinsics* K, float near_z, float motion_margin, uint8_t* seen) {
-  hgsr_status s = check_plan_args(n_parts, poses, P, K, near_z, motion_margin);
-  if (s != HGSR_OK) return s;
-  if (n_parts > 0 && (!bounds || !seen)) return err(HGSR_ERR_INVALID_ARG, "NULL bounds or output");
-  for (int p = 0; p < P; ++p)
-    for (int k = 0; k < n_parts; ++k)
-      seen[static_cast<int64_t>(p) * n_parts + k] =
-          box_may_be_seen(bounds + 6 * k, poses + 12 * p, *K, near_z, motion_margin) ? 1 : 0;
-  return HGSR_OK;
-}
-
 hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, int32_t n_slots) {
   if (!out) return err(HGSR_ERR_INVALID_ARG, "NULL output");
   *out = nullptr;
-  hgsr_status s = check_host_scene(scene);
+  hgsr_status s = host::check_host_scene(scene);
   if (s != HGSR_OK) return s;
   if (n_slots < 1 || n_slots > kMaxSlots || n_slots > scene->n_parts)
     return err(HGSR_ERR_INVALID_ARG, "n_slots must be 1..min(64, n_parts)");
@@ -256,7 +151,7 @@ hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, 
   pc->n_parts = scene->n_parts;
   pc->offs.assign(scene->part_offsets, scene->part_offsets + scene->n_parts + 1);
   pc->bounds.resize(6 * static_cast<size_t>(scene->n_parts));
-  host_bounds(scene, pc->bounds.data());
+  host::partition_bounds(scene, pc->bounds.data());
   for (int k = 0; k < pc->n_parts; ++k) pc->cap = std::max<int64_t>(pc->cap, pc->offs[k + 1] - pc->offs[k]);
   pc->cap = std::max<int64_t>(pc->cap, 1);
   if (static_cast<int64_t>(n_slots) * pc->cap >= (1ll << 31)) {
@@ -330,12 +225,10 @@ hgsr_status hgsr_pcache_create(hgsr_pcache** out, const hgsr_host_scene* scene, 
       hipMemcpy(pc->d_bounds, pc->slot_box.data(), pc->slot_box.size() * sizeof(float), hipMemcpyHostToDevice) !=
           hipSuccess)
     return fail_free(err(HGSR_ERR_HIP, "hipMemcpy of the slot tables failed"));
-  pc->slot_part.assign(n_slots, -1);
-  pc->slot_last.assign(n_slots, -1);
+  pc->pol = SlotPolicy(pc->n_parts, n_slots);
   pc->batch_ev.assign(hgsr_pcache::kRing, nullptr);
   pc->slot_ready.assign(n_slots, nullptr);
   pc->slot_pending.assign(n_slots, 0);
-  pc->part_slot.assign(pc->n_parts, -1);
   for (int sl = 0; sl < n_slots; ++sl)
     if (hipEventCreateWithFlags(&pc->slot_ready[sl], hipEventDisableTiming) != hipSuccess)
       return fail_free(err(HGSR_ERR_HIP, "hipEventCreate failed"));
@@ -361,14 +254,13 @@ hgsr_status hgsr_pcache_destroy(hgsr_pcache* pc) {
 hgsr_status hgsr_pcache_evict_all(hgsr_pcache* pc) {
   if (!pc) return err(HGSR_ERR_INVALID_ARG, "NULL cache");
   PC_HIP(hipStreamSynchronize(pc->copy));
+  // the slots' last uses stay recorded: their next uploads still wait for them
+  pc->pol.evict_all();
   for (int sl = 0; sl < pc->n_slots; ++sl) {
-    if (pc->slot_part[sl] >= 0) pc->part_slot[pc->slot_part[sl]] = -1;
-    pc->slot_part[sl] = -1;
     for (int a = 0; a < 3; ++a) {  // empty box: never drawn again
       pc->slot_box[6 * sl + a] = 1.f;
       pc->slot_box[6 * sl + 3 + a] = -1.f;
     }
-    // the slot's last use stays recorded: its next upload still waits for it
     pc->slot_pending[sl] = 0;  // the copy stream has finished
   }
   pc->table_dirty = true;  // written by the next prepare, after the work already enqueued
@@ -379,70 +271,37 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
                                 const hgsr_intrinsics* K, float near_z, float motion_margin, hgsr_gaussians* out,
                                 hgsr_pcache_stats* stats, hgsr_stream stream) {
   if (!pc || !out) return err(HGSR_ERR_INVALID_ARG, "NULL cache or output");
-  hgsr_status s = check_plan_args(pc->n_parts, poses, P, K, near_z, motion_margin);
+  hgsr_status s = host::check_plan_args(pc->n_parts, poses, P, K, near_z, motion_margin);
   if (s != HGSR_OK) return s;
   if (n_render < 1 || n_render > P) return err(HGSR_ERR_INVALID_ARG, "n_render must be 1..P");
   const float nz = near_z > 0.f ? near_z : 0.2f;
   // partitions the rendered views may see (need 1) and, not among them, the
   // ones only the upcoming views may see (need 2)
   std::vector<uint8_t> need(pc->n_parts, 0);
-  int n_need = 0;
   for (int k = 0; k < pc->n_parts; ++k) {
     const float* B = pc->bounds.data() + 6 * k;
     for (int p = 0; p < n_render && !need[k]; ++p)
-      need[k] = box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 1 : 0;
+      need[k] = host::box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 1 : 0;
     for (int p = n_render; p < P && !need[k]; ++p)
-      need[k] = box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 2 : 0;
-    n_need += need[k] == 1;
+      need[k] = host::box_may_be_seen(B, poses + 12 * p, *K, nz, motion_margin) ? 2 : 0;
   }
-  if (n_need > pc->n_slots)
-    return err(HGSR_ERR_CAPACITY, "the rendered views may see %d partitions but the cache has %d slots", n_need,
-               pc->n_slots);
+  hgsr_pcache_stats& st = pc->st;
+  const int64_t batch = pc->pol.batch;
+  s = pc->pol.step(need.data(), &st);  // nothing changes on HGSR_ERR_CAPACITY
+  if (s != HGSR_OK) return s;
   hipStream_t rs = reinterpret_cast<hipStream_t>(stream);
   // everything enqueued before this batch (the release point of the slots the
   // previous batch used)
-  PC_HIP(hipEventRecord(pc->batch_ev[pc->batch % hgsr_pcache::kRing], rs));
-  hgsr_pcache_stats& st = pc->st;
-  st.needed = n_need;
-  st.hits = st.uploads = st.evictions = st.prefetched = 0;
+  PC_HIP(hipEventRecord(pc->batch_ev[batch % hgsr_pcache::kRing], rs));
   st.bytes_uploaded = 0;
-  std::vector<uint8_t> taken(pc->n_slots, 0);
-  for (int k = 0; k < pc->n_parts; ++k)
-    if (need[k] == 1 && pc->part_slot[k] >= 0) {
-      taken[pc->part_slot[k]] = 1;
-      pc->slot_last[pc->part_slot[k]] = pc->batch;
-      ++st.hits;
-    }
   const Widths w(pc->sh_degree, pc->feat_dim);
-  // victim: an empty slot, else the least recently used one not taken
-  auto victim = [&]() {
-    int v = -1;
-    for (int sl = 0; sl < pc->n_slots; ++sl)
-      if (!taken[sl] && pc->slot_part[sl] < 0 && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
-    if (v < 0)
-      for (int sl = 0; sl < pc->n_slots; ++sl)
-        if (!taken[sl] && (v < 0 || pc->slot_last[sl] < pc->slot_last[v])) v = sl;
-    return v;
-  };
-  auto claim = [&](int k, int v) {
-    if (pc->slot_part[v] >= 0) {
-      pc->part_slot[pc->slot_part[v]] = -1;
-      ++st.evictions;
-    }
-    pc->slot_part[v] = k;
-    pc->part_slot[k] = v;
-    pc->slot_last[v] = pc->batch;
-    taken[v] = 1;
-    ++st.uploads;
-    st.bytes_uploaded += (pc->offs[k + 1] - pc->offs[k]) * static_cast<int64_t>(w.total());
-  };
-  auto upload = [&](int k, int v) -> hgsr_status {
-    if (pc->slot_last[v] >= 0) {
-      // released at the first prepare after its last use, or (conservatively)
-      // at the oldest batch the ring still holds
-      const int64_t rel = std::max<int64_t>(pc->slot_last[v] + 1, pc->batch - (hgsr_pcache::kRing - 1));
-      PC_HIP(hipStreamWaitEvent(pc->copy, pc->batch_ev[rel % hgsr_pcache::kRing], 0));
-    }
+  const float kEmpty[6] = {1.f, 1.f, 1.f, -1.f, -1.f, -1.f};
+  // uploads in the policy's order (the rendered views' misses, then the
+  // upcoming views'), each after the release point of its slot's previous use
+  for (int u = 0; u < st.uploads; ++u) {
+    const hgsr_slot_upload& up = st.upload[u];
+    const int k = up.part, v = up.slot;
+    if (up.release >= 0) PC_HIP(hipStreamWaitEvent(pc->copy, pc->batch_ev[up.release % hgsr_pcache::kRing], 0));
     const int64_t b = pc->offs[k], cnt = pc->offs[k + 1] - pc->offs[k];
     const int64_t d0 = static_cast<int64_t>(v) * pc->cap;
     const char* hsrc[6] = {pc->h_means, pc->h_ls, pc->h_quats, pc->h_opac, pc->h_sh, pc->h_feat};
@@ -460,55 +319,20 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     PC_HIP(hipGetLastError());
     PC_HIP(hipEventRecord(pc->slot_ready[v], pc->copy));
     pc->slot_pending[v] = 1;
-    return HGSR_OK;
-  };
-  auto set_box = [&](int v, const float* B) {
-    std::copy(B, B + 6, pc->slot_box.begin() + 6 * v);
+    st.bytes_uploaded += cnt * static_cast<int64_t>(w.total());
+    // an upcoming view's slot stays empty in this batch's table
+    const float* box = up.ahead ? kEmpty : pc->bounds.data() + 6 * k;
+    std::copy(box, box + 6, pc->slot_box.begin() + 6 * v);
     pc->table_dirty = true;
-  };
-  const float kEmpty[6] = {1.f, 1.f, 1.f, -1.f, -1.f, -1.f};
-  // 1. the rendered views' misses
-  for (int k = 0; k < pc->n_parts; ++k) {
-    if (need[k] != 1 || pc->part_slot[k] >= 0) continue;
-    const int v = victim();
-    if (v < 0) return err(HGSR_ERR_STATE, "no free slot (internal)");
-    claim(k, v);
-    hgsr_status us = upload(k, v);
-    if (us != HGSR_OK) return us;
-    set_box(v, pc->bounds.data() + 6 * k);
   }
-  // 2. upcoming views: resident ones stay warm; missing ones take free or
-  // least recently used slots the rendered views cannot see (best effort).
-  // Their slots are empty in this batch's table; a later table shows them.
-  std::vector<int> ahead_k, ahead_v;
-  for (int k = 0; k < pc->n_parts; ++k)
-    if (need[k] == 2 && pc->part_slot[k] >= 0) {
-      taken[pc->part_slot[k]] = 1;
-      pc->slot_last[pc->part_slot[k]] = pc->batch;
-    }
-  for (int k = 0; k < pc->n_parts; ++k) {
-    if (need[k] != 2 || pc->part_slot[k] >= 0) continue;
-    const int v = victim();
-    if (v < 0) continue;
-    claim(k, v);
-    ++st.prefetched;
-    set_box(v, kEmpty);
-    ahead_k.push_back(k);
-    ahead_v.push_back(v);
-  }
-  // 3. the upcoming views' uploads
-  for (size_t q = 0; q < ahead_k.size(); ++q) {
-    hgsr_status us = upload(ahead_k[q], ahead_v[q]);
-    if (us != HGSR_OK) return us;
-  }
-  // 4. the slot table on the render stream: after the previous renders (stream
+  // the slot table on the render stream: after the previous renders (stream
   // order) and after the uploads of the slots it shows
   if (pc->table_dirty) {
     SlotBoxes t;
     std::memset(&t, 0, sizeof(t));
     for (int sl = 0; sl < pc->n_slots; ++sl) {
       for (int a = 0; a < 6; ++a) t.b[sl][a] = pc->slot_box[6 * sl + a];
-      if (pc->slot_pending[sl] && !empty_box(&pc->slot_box[6 * sl])) {
+      if (pc->slot_pending[sl] && !host::empty_box(&pc->slot_box[6 * sl])) {
         PC_HIP(hipStreamWaitEvent(rs, pc->slot_ready[sl], 0));
         pc->slot_pending[sl] = 0;
       }
@@ -518,10 +342,14 @@ hgsr_status hgsr_pcache_prepare(hgsr_pcache* pc, const float* poses, int32_t P, 
     pc->table_dirty = false;
   }
   // the upcoming views' slots show their boxes from the next table on
-  for (size_t q = 0; q < ahead_k.size(); ++q) set_box(ahead_v[q], pc->bounds.data() + 6 * ahead_k[q]);
+  for (int u = 0; u < st.uploads; ++u)
+    if (st.upload[u].ahead) {
+      const float* box = pc->bounds.data() + 6 * st.upload[u].part;
+      std::copy(box, box + 6, pc->slot_box.begin() + 6 * st.upload[u].slot);
+      pc->table_dirty = true;
+    }
   st.total_uploads += st.uploads;
   st.total_bytes += st.bytes_uploaded;
-  ++pc->batch;
   out->n = static_cast<int64_t>(pc->n_slots) * pc->cap;
   out->means = reinterpret_cast<const float*>(pc->d_means);
   out->log_scales = reinterpret_cast<const float*>(pc->d_ls);

@@ -60,7 +60,45 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.PnpProblem) == 4 * 8 + 4 * 4     # 2 ptrs, n, samples, n_hyp, tau, 2 counts
     assert ctypes.sizeof(_lib.PnpResult) == 6 * 8
     assert ctypes.sizeof(_lib.HostScene) == 8 + 5 * 8 + 4 + 4 + 8 + 4 + 4 + 8  # ..., n_parts, padding, offsets
-    assert ctypes.sizeof(_lib.PcacheStats) == 4 * 4 + 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4  # ..., prefetched, padding
+    assert ctypes.sizeof(_lib.SlotUpload) == 24
+    assert ctypes.sizeof(_lib.PcacheStats) == 4 * 4 + 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 64 * 24  # ..., upload[64]
+
+
+# (ctypes mirror, C struct name) of every struct the binding passes by pointer
+_MIRRORS = [("Gaussians", "hgsr_gaussians"), ("Intrinsics", "hgsr_intrinsics"), ("Opts", "hgsr_opts"),
+            ("Outputs", "hgsr_outputs"), ("GradOutputs", "hgsr_grad_outputs"), ("Grads", "hgsr_grads"),
+            ("RenderStats", "hgsr_render_stats"), ("TuneResult", "hgsr_tune_result"),
+            ("ResidualTargets", "hgsr_residual_targets"), ("FeatureMaps", "hgsr_feature_maps"),
+            ("MatchMaps", "hgsr_match_maps"), ("MatchOut", "hgsr_match_out"), ("PnpProblem", "hgsr_pnp_problem"),
+            ("PnpResult", "hgsr_pnp_result"), ("HostScene", "hgsr_host_scene"), ("SlotUpload", "hgsr_slot_upload"),
+            ("PcacheStats", "hgsr_pcache_stats")]
+
+
+def test_struct_offsets_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what
+    the C compiler lays out from include/hgsr.h."""
+    import subprocess
+    from paper_2507_15683_amd import _lib
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hgsr.h"', 'int main(void) {']
+    for py, c in _MIRRORS:
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(_lib, py)._fields_:
+            lines.append(f'  printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        py, f, v = line.split()
+        got[(py, f)] = int(v)
+    for py, _ in _MIRRORS:
+        cls = getattr(_lib, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for f, _ in cls._fields_:
+            assert got[(py, f)] == getattr(cls, f).offset, (py, f)
 
 
 def test_invalid_arguments_rejected_on_host(lib):

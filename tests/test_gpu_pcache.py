@@ -91,41 +91,28 @@ def test_streamed_render_matches_oracle_and_resident(hg, scene):
 
 
 def test_eviction_bookkeeping_follows_the_policy(hg, scene):
-    """Hits, uploads and evictions per batch equal a model of the policy
-    (the plan of hgsr_partition_plan; empty slots first, then the least
-    recently used slot the batch does not need)."""
+    """Hits, uploads, evictions and every upload's (partition, slot, release
+    batch) per batch equal a model of the policy (the plan of
+    hgsr_partition_plan; empty slots first, then the least recently used slot
+    the batch does not need; a copy waits for the first batch after the
+    slot's previous use)."""
+    from policy_model import PolicyModel
     K = hg.Intrinsics.of(CAM)
     b = hg.host_partition_bounds(scene)
     poses = _track(24, 12, alt=(50.0, 120.0), tilt=20.0)
     S = 5
     pc = hg.PartitionCache(scene, S)
-    slot_part, slot_last = [-1] * S, [-1] * S
-    where = {}
+    model = PolicyModel(len(b), S)
     for batch in range(0, len(poses), 2):
         q = poses[batch:batch + 2]
-        need = np.nonzero(hg.partition_plan(b, q, K).any(axis=0))[0].tolist()
-        if len(need) > S:
+        need = hg.partition_plan(b, q, K).any(axis=0).astype(np.uint8)
+        if need.sum() > S:
             continue
-        hits = [k for k in need if k in where]
-        taken = {where[k] for k in hits}
-        for k in hits:
-            slot_last[where[k]] = batch
-        ups = ev = 0
-        for k in need:
-            if k in where:
-                continue
-            free = [s for s in range(S) if s not in taken and slot_part[s] < 0]
-            cand = free or [s for s in range(S) if s not in taken]
-            v = min(cand, key=lambda s: (slot_last[s], s))
-            if slot_part[v] >= 0:
-                del where[slot_part[v]]
-                ev += 1
-            slot_part[v], slot_last[v], where[k] = k, batch, v
-            taken.add(v)
-            ups += 1
+        want = model.step(need)
         pc.prepare(q, K)
         st = pc.stats
-        assert (st["needed"], st["hits"], st["uploads"], st["evictions"]) == (len(need), len(hits), ups, ev), batch
+        for f in ("needed", "hits", "uploads", "evictions", "upload_list"):
+            assert st[f] == want[f], (batch, f)
     pc.close()
 
 
