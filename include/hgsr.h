@@ -42,9 +42,11 @@
  *   - Every call returns an hgsr_status and never throws; arguments are
  *     validated on the host before anything is enqueued.  HIP failures return
  *     HGSR_ERR_HIP; hgsr_last_error() gives a thread-local message.
- *   - All calls except hgsr_check_overflow, hgsr_stats, hgsr_debug_* and
- *     hgsr_autotune are asynchronous on the given stream and can be captured
- *     into a HIP graph.
+ *   - All calls except hgsr_check_overflow, hgsr_stats, hgsr_debug_*,
+ *     hgsr_autotune, hgsr_validate, the partition cache (hgsr_pcache_*, which
+ *     plans on the host) and the host-only helpers are asynchronous on the
+ *     given stream and can be captured into a HIP graph (after hgsr_reserve:
+ *     a call that would grow the workspace while capturing fails).
  */
 #ifndef HGSR_H_
 #define HGSR_H_
@@ -167,6 +169,12 @@ typedef struct {
   float* quats;
   float* sh;
   float* feat;
+  /* Which render these gradients are for: 0 = the context's last render;
+   * otherwise an id hgsr_render_id returned, and the call fails with
+   * HGSR_ERR_STATE (nothing enqueued) unless that render is still the
+   * context's last one (a later render or scoring pass replaced the saved
+   * lists, transmittances and pose pointers the backward replays). */
+  int64_t render_id;
 } hgsr_grads;
 
 /* Per-render counters (host struct, from hgsr_stats). */
@@ -211,12 +219,43 @@ hgsr_status hgsr_render(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* pos
                         const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
                         hgsr_stream stream);
 
-/* Backward of the last hgsr_render on this context: replays each pixel's
- * blend in reverse from the saved final transmittance and writes the
- * requested gradients.  The forward's inputs and its depth/alpha outputs
- * must still hold the values of that render. */
+/* Backward of the last hgsr_render on this context: the gradient of a loss
+ * on the rendered maps with respect to the poses and the Gaussian parameters
+ * (Algorithm 1 back-propagates the summed rendered RGB and keeps the
+ * Gaussians whose mean gradient is non-zero; the dense stage's refinement,
+ * Sec. 3.4, descends the residual of the rendered package against the
+ * query).  grad_out holds dL/d{rgb, depth, alpha, feat} (device, FP32, the
+ * layouts of hgsr_outputs; NULL = zero).  Replays each pixel's blend in
+ * reverse from the saved final transmittance and list length (no per-pixel
+ * lists are stored) and writes the requested gradients (see hgsr_grads,
+ * including its render_id check).  The forward's inputs and its depth/alpha
+ * outputs must still hold the values of that render.  HGSR_ERR_STATE before
+ * any render or after a scoring pass. */
 hgsr_status hgsr_render_backward(hgsr_ctx* ctx, const hgsr_grad_outputs* grad_out, const hgsr_grads* grads,
                                  hgsr_stream stream);
+
+/* Id of the context's last render (host, no synchronisation): 1, 2, ... in
+ * the order of the context's renders, 0 when the last call that built tile
+ * lists was not a render (or there was none).  Pass it in hgsr_grads.render_id
+ * to have a backward refuse gradients for a render that is no longer the
+ * last one. */
+hgsr_status hgsr_render_id(hgsr_ctx* ctx, int64_t* id);
+
+/* Left retraction of P poses: out = Exp(xi) T per pose, xi (device, P x 6,
+ * (rho, phi), translation first) in the tangent every pose gradient of this
+ * library uses; poses and out P x 12 (may alias).  Evaluated in FP64, stored
+ * in FP32.  Asynchronous on `stream`. */
+hgsr_status hgsr_pose_retract(const float* poses, const float* xi, int32_t P, float* out, hgsr_stream stream);
+
+/* Chain rule through the retraction: given g = dL/d(delta) at delta = 0 for
+ * Exp(delta) Exp(xi) T (what hgsr_render_backward returns for a render at
+ * the retracted pose), writes dL/dxi = J_l(xi)^T g with J_l the left Jacobian
+ * of SE(3), Exp(xi + dxi) = Exp(J_l(xi) dxi) Exp(xi) to first order.  J_l is
+ * the series sum_n ad(xi)^n / (n + 1)!, summed to 40 terms in FP64 (its
+ * truncation is below double rounding for |phi| <= 2 pi; rho enters
+ * linearly).  xi, g, g_xi: device, P x 6 (g_xi may alias g).  J_l(0) is the
+ * identity, so at xi = 0 g_xi equals g bit for bit. */
+hgsr_status hgsr_pose_tangent_grad(const float* xi, const float* g, int32_t P, float* g_xi, hgsr_stream stream);
 
 /* Refinement residual of P rendered poses against targets (Sec. 3.4 compares
  * the rendered package with the query): per pose
@@ -566,9 +605,11 @@ hgsr_status hgsr_partition_plan(const float* bounds, int32_t n_parts, const floa
 hgsr_status hgsr_host_spatial_order(const float* means, int64_t n, const int64_t* part_offsets, int32_t n_parts,
                                     int64_t* perm);
 
-/* Check the Gaussian arrays for NaN/Inf, opacities outside [0, 1] and zero
- * quaternions.  Synchronises `stream`.  Returns HGSR_ERR_INVALID_ARG on the
- * first problem found. */
+/* Check the Gaussian arrays for NaN/Inf (means, log-scales, quaternions, SH
+ * coefficients and bfloat16 features), opacities outside [0, 1] and zero
+ * quaternions.  Allocates a 4-byte device flag and synchronises `stream`, so
+ * it cannot be captured: HGSR_ERR_STATE when `stream` is capturing.  Returns
+ * HGSR_ERR_INVALID_ARG when any entry fails. */
 hgsr_status hgsr_validate(const hgsr_gaussians* g, hgsr_stream stream);
 
 /* Graph capture of everything enqueued on `stream` between begin and end;

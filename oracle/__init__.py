@@ -21,7 +21,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hgsr_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HGSR_ORACLE_LIB names another build of the same source (the sanitizer test
+# loads an AddressSanitizer/UBSan build through it).
+_LIB = os.environ.get("HGSR_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 
 def build(force: bool = True) -> str:

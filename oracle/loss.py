@@ -117,3 +117,21 @@ def fd_gradients(scene, pose, cam, loss_fn, h=1e-4, gauss_ids=(), params=("means
                 g[(j,) + comp] = (L(pose, {p: plus}) - L(pose, {p: minus})) / (2 * h)
         out[p] = g
     return g_pose, out, ref
+
+
+def fd_tangent_gradient(scene, pose, xi, cam, loss_fn, h=1e-4, tile=16, list_cap=512, bg=(0.0, 0.0, 0.0)):
+    """Central differences of loss_fn(frozen render at Exp(xi) T) with
+    respect to the six components of xi itself (not of a perturbation at
+    the retracted pose).  Returns (g_xi (6,), reference render at Exp(xi) T)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    base = left_perturb(pose, xi)
+    ref = render(scene, base, cam, mode="tiled", tile=tile, bg=bg, want_lists=True, list_cap=list_cap)
+    lists, counts = ref["lists"], ref["nblend"]
+    g = np.zeros(6)
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        lp = loss_fn(render_frozen(scene, left_perturb(pose, xi + e), cam, lists, counts, bg=bg))
+        lm = loss_fn(render_frozen(scene, left_perturb(pose, xi - e), cam, lists, counts, bg=bg))
+        g[k] = (lp - lm) / (2 * h)
+    return g, ref

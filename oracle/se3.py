@@ -1,9 +1,14 @@
-"""SE(3) pose tangent used by the pose gradient -- oracle side, FP64.
+"""SE(3) pose tangent used by the pose gradient -- oracle side, FP64, TEST
+INFRASTRUCTURE ONLY.
 
 The pose gradient is taken with respect to a left perturbation of the
 world->camera pose, T <- Exp(xi) T, xi = (rho, phi) with translation first.
 Exp is the closed form of the matrix exponential of the 4x4 twist
 [[phi^, rho], [0, 0]] (Rodrigues for the rotation, V rho for the translation).
+A loss of the poses Exp(xi) T has d/dxi = J_l(xi)^T dL/d(delta), J_l the left
+Jacobian, Exp(xi + dxi) = Exp(J_l(xi) dxi) Exp(xi) to first order; by
+definition J_l(xi) = sum_{n >= 0} ad(xi)^n / (n + 1)! with the adjoint
+ad(rho, phi) = [[phi^, rho^], [0, phi^]].
 """
 from __future__ import annotations
 
@@ -40,3 +45,24 @@ def left_perturb(pose12, xi) -> np.ndarray:
     T = np.eye(4)
     T[:3, :] = np.asarray(pose12, dtype=np.float64).reshape(3, 4)
     return (exp_se3(xi) @ T)[:3, :].reshape(12)
+
+
+def ad_se3(xi) -> np.ndarray:
+    """6x6 adjoint of the twist (rho, phi): [[phi^, rho^], [0, phi^]]."""
+    xi = np.asarray(xi, dtype=np.float64)
+    A = np.zeros((6, 6))
+    A[:3, :3] = hat(xi[3:])
+    A[:3, 3:] = hat(xi[:3])
+    A[3:, 3:] = hat(xi[3:])
+    return A
+
+
+def left_jacobian(xi, terms: int = 60) -> np.ndarray:
+    """J_l(xi) as its defining series sum_n ad^n / (n + 1)!."""
+    A = ad_se3(xi)
+    M = np.eye(6)
+    J = np.eye(6)
+    for n in range(1, terms):
+        M = M @ A / (n + 1)
+        J = J + M
+    return J

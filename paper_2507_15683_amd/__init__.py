@@ -382,20 +382,29 @@ class Renderer:
                       feat=(n, D))
         return {k: torch.empty(shapes[k], dtype=torch.float32, device=dev) for k in want}
 
+    def render_id(self) -> int:
+        """Id of this context's last render (0: none, or a scoring pass
+        came after it); hgsr_render_id."""
+        v = ctypes.c_int64(0)
+        check(self.lib.hgsr_render_id(self.ctx, ctypes.byref(v)), "hgsr_render_id")
+        return int(v.value)
+
     def backward(self, grad_out: dict, want=("pose", "means", "opacities"), P: Optional[int] = None,
-                 scene: Optional[GaussianScene] = None, grads: Optional[dict] = None, stream=None) -> dict:
+                 scene: Optional[GaussianScene] = None, grads: Optional[dict] = None, stream=None,
+                 render_id: int = 0) -> dict:
         """Gradients of the last render given dL/d{rgb, depth, alpha, feat}
         (device FP32 tensors; missing keys mean zero).  `want` names the
         gradients to compute among pose, means, opacities, log_scales, quats,
         sh, feat; `grads` may supply preallocated outputs (required under
-        graph capture).  Returns the dict of device tensors."""
+        graph capture).  A non-zero render_id makes the call fail unless that
+        render is still the last one.  Returns the dict of device tensors."""
         scene = scene if scene is not None else self._keep[0]
         P = P if P is not None else self._keep[1].shape[0]
         if grads is None:
             grads = self.alloc_grads(scene, P, want)
         go = _lib.GradOutputs(*[_ptr(_f32(grad_out.get(k))) for k in ("rgb", "depth", "alpha", "feat")])
         gr = _lib.Grads(*[_ptr(grads.get(k)) for k in ("pose", "means", "opacities", "log_scales", "quats", "sh",
-                                                      "feat")])
+                                                      "feat")], render_id)
         self._keep_grad = (grad_out, grads)
         check(self.lib.hgsr_render_backward(self.ctx, ctypes.byref(go), ctypes.byref(gr), _stream_ptr(stream)),
               "hgsr_render_backward")
@@ -404,7 +413,7 @@ class Renderer:
     def residual_backward(self, rgb_target: torch.Tensor, feat_target: Optional[torch.Tensor] = None,
                           lam_f: float = 1.0, want=("pose",), loss: Optional[torch.Tensor] = None,
                           grads: Optional[dict] = None, P: Optional[int] = None,
-                          scene: Optional[GaussianScene] = None, stream=None):
+                          scene: Optional[GaussianScene] = None, stream=None, render_id: int = 0):
         """Loss and gradients of the refinement residual of the last render
         against targets ((P,3,H,W)/(P,D,H,W), or a single (1,...) target
         shared by all poses), formed inside the blend backward.  The last
@@ -421,7 +430,7 @@ class Renderer:
             raise ValueError("targets must hold one image per pose or a single shared one")
         rt = _lib.ResidualTargets(_ptr(_f32(rgb_target)), _ptr(_f32(feat_target)), lam_f, shared)
         gr = _lib.Grads(*[_ptr(grads.get(k)) for k in ("pose", "means", "opacities", "log_scales", "quats", "sh",
-                                                      "feat")])
+                                                      "feat")], render_id)
         self._keep_grad = (rgb_target, feat_target, loss, grads)
         check(self.lib.hgsr_residual_backward(self.ctx, ctypes.byref(rt), _ptr(loss), ctypes.byref(gr),
                                               _stream_ptr(stream)), "hgsr_residual_backward")
@@ -614,33 +623,67 @@ def render_grad(renderer: Renderer, scene: GaussianScene, poses: torch.Tensor, o
     return renderer.backward(grad_out, want=want, P=poses.shape[0], scene=scene)
 
 
+def pose_retract(poses: torch.Tensor, xi: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+    """Exp(xi) T per pose (hgsr_pose_retract): poses (P, 12), xi (P, 6)."""
+    poses, xi = _f32(poses), _f32(xi)
+    if out is None:
+        out = torch.empty_like(poses)
+    check(_lib.load().hgsr_pose_retract(_ptr(poses), _ptr(xi), poses.shape[0], _ptr(out), _stream_ptr(stream)),
+          "hgsr_pose_retract")
+    return out
+
+
+def pose_tangent_grad(xi: torch.Tensor, g: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+    """dL/dxi = J_l(xi)^T g (hgsr_pose_tangent_grad): the pose gradient at
+    Exp(xi) T carried back to xi."""
+    xi, g = _f32(xi), _f32(g)
+    if out is None:
+        out = torch.empty_like(g)
+    check(_lib.load().hgsr_pose_tangent_grad(_ptr(xi), _ptr(g), xi.shape[0], _ptr(out), _stream_ptr(stream)),
+          "hgsr_pose_tangent_grad")
+    return out
+
+
 class _RenderFn(torch.autograd.Function):
-    """Differentiable render: gradients flow to the pose tangent xi (left
-    perturbation at 0) and to the Gaussian means and opacities."""
+    """Differentiable render at the poses Exp(xi) T: gradients flow to the
+    pose tangent xi and to the Gaussian means and opacities.  The backward
+    is refused (HgsrError, STATE) when the renderer has rendered again since
+    this forward."""
 
     @staticmethod
     def forward(ctx, xi, means, opacities, renderer, scene, poses, K, kw):
-        out = renderer.render(scene, poses, K, **kw)
+        ctx.set_materialize_grads(False)  # unused outputs pass None: no zero images
+        eff = pose_retract(poses, xi.detach())
+        out = renderer.render(scene, eff, K, **kw)
         ctx.renderer = renderer
         ctx.scene = scene
+        ctx.render_id = renderer.render_id()
         ctx.P = poses.shape[0]
         ctx.has_feat = out["feat"] is not None
         ctx.needs = (xi.requires_grad, means.requires_grad, opacities.requires_grad)
+        ctx.save_for_backward(xi)
         feat = out["feat"] if out["feat"] is not None else torch.empty(0, device=poses.device)
         return out["rgb"], out["depth"], out["alpha"], feat
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_alpha, g_feat):
+        (xi,) = ctx.saved_tensors
         want = [k for k, need in zip(("pose", "means", "opacities"), ctx.needs) if need]
         go = dict(rgb=g_rgb, depth=g_depth, alpha=g_alpha, feat=g_feat if ctx.has_feat else None)
-        grads = ctx.renderer.backward(go, want=want or ("pose",), P=ctx.P, scene=ctx.scene)
-        return (grads.get("pose"), grads.get("means"), grads.get("opacities"), None, None, None, None, None)
+        grads = ctx.renderer.backward(go, want=want or ("pose",), P=ctx.P, scene=ctx.scene,
+                                      render_id=ctx.render_id)
+        g_xi = pose_tangent_grad(xi.detach(), grads["pose"]) if ctx.needs[0] else None
+        return (g_xi, grads.get("means"), grads.get("opacities"), None, None, None, None, None)
 
 
 def render_differentiable(renderer: Renderer, scene: GaussianScene, poses: torch.Tensor, K: Intrinsics,
                           xi: Optional[torch.Tensor] = None, **kw):
-    """Autograd form: returns (rgb, depth, alpha, feat); d/d xi is the pose
-    gradient in the left-perturbation tangent (rho, phi)."""
+    """Autograd form: renders the poses Exp(xi) T and returns (rgb, depth,
+    alpha, feat); d/d xi is carried through the left Jacobian of the
+    retraction (at xi = 0 it is the pose gradient in the left-perturbation
+    tangent (rho, phi)).  Gradients reach scene.means / scene.opacities when
+    they require grad.  The returned maps are the renderer's; another render
+    on the same renderer before .backward() makes the backward fail."""
     P = poses.shape[0]
     if xi is None:
         xi = torch.zeros((P, 6), dtype=torch.float32, device=poses.device, requires_grad=True)

@@ -46,7 +46,7 @@ class GradOutputs(ctypes.Structure):
 
 class Grads(ctypes.Structure):
     _fields_ = [("pose", P_), ("means", P_), ("opacities", P_), ("log_scales", P_), ("quats", P_), ("sh", P_),
-                ("feat", P_)]
+                ("feat", P_), ("render_id", I64)]
 
 
 class RenderStats(ctypes.Structure):
@@ -121,6 +121,9 @@ SIGNATURES = {
     "hgsr_residual_backward": [P_, ctypes.POINTER(ResidualTargets), P_, ctypes.POINTER(Grads), P_],
     "hgsr_residual": [P_, P_, I32, P_, P_, I32, I32, I32, I32, F32, P_, P_, P_, P_],
     "hgsr_pose_adam": [P_, P_, P_, P_, P_, I32, F32, F32, F32, F32, F32, P_],
+    "hgsr_render_id": [P_, ctypes.POINTER(I64)],
+    "hgsr_pose_retract": [P_, P_, I32, P_, P_],
+    "hgsr_pose_tangent_grad": [P_, P_, I32, P_, P_],
     "hgsr_significance": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
                           ctypes.POINTER(FeatureMaps), P_, P_, P_, P_],
     "hgsr_significance_final": [P_, P_, I64, P_, P_],

@@ -83,6 +83,7 @@ struct hgsr_ctx {
   // the last render
   bool have_lists = false;   // records and tile lists of the last call (render or scoring)
   bool have_render = false;  // ... and that call was a render (the backward's input)
+  int64_t render_seq = 0;    // renders so far; the last render's id while have_render
   hgsr_gaussians g{};
   const float* poses = nullptr;
   int32_t P = 0;
@@ -540,6 +541,7 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
 
   c->have_lists = true;
   c->have_render = true;
+  ++c->render_seq;
   c->g = *g;
   c->poses = poses;
   c->P = P;
@@ -880,6 +882,10 @@ hgsr_status hgsr_validate(const hgsr_gaussians* g, hgsr_stream stream) {
   TRY(check_gaussians(g));
   if (g->n == 0) return HGSR_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(HGSR_ERR_STATE, "hgsr_validate allocates and synchronises: not allowed while the stream is captured");
   int32_t* bad = nullptr;
   HIP_TRY(hipMalloc(&bad, sizeof(int32_t)));
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
@@ -888,7 +894,9 @@ hgsr_status hgsr_validate(const hgsr_gaussians* g, hgsr_stream stream) {
   HIP_TRY(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(bad));
-  if (h) return fail(HGSR_ERR_INVALID_ARG, "Gaussian arrays hold NaN/Inf, an opacity outside [0,1] or a zero quaternion");
+  if (h)
+    return fail(HGSR_ERR_INVALID_ARG,
+                "Gaussian arrays hold NaN/Inf, an opacity outside [0,1], a zero quaternion or a non-finite feature");
   return HGSR_OK;
 }
 
@@ -963,6 +971,9 @@ static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const
                                  float* loss, const hgsr_grads* gr, hgsr_stream stream) {
   if (!c || !(go || rt) || !gr) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   if (!c->have_render) return fail(HGSR_ERR_STATE, "backward before any render");
+  if (gr->render_id != 0 && gr->render_id != c->render_seq)
+    return fail(HGSR_ERR_STATE, "backward for render %lld, but the context's last render is %lld",
+                static_cast<long long>(gr->render_id), static_cast<long long>(c->render_seq));
   const int D = c->g.feat_dim;
   static const hgsr_grad_outputs none = {nullptr, nullptr, nullptr, nullptr};
   if (!go) go = &none;
@@ -1059,6 +1070,26 @@ hgsr_status hgsr_residual_backward(hgsr_ctx* c, const hgsr_residual_targets* t, 
                                    hgsr_stream stream) {
   if (!t) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
   return backward_impl(c, nullptr, t, loss, gr, stream);
+}
+
+hgsr_status hgsr_render_id(hgsr_ctx* c, int64_t* id) {
+  if (!c || !id) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  *id = c->have_render ? c->render_seq : 0;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pose_retract(const float* poses, const float* xi, int32_t P, float* out, hgsr_stream stream) {
+  if (P <= 0 || !poses || !xi || !out) return fail(HGSR_ERR_INVALID_ARG, "need P >= 1 and three arrays");
+  launch_pose_retract(poses, xi, P, out, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_pose_tangent_grad(const float* xi, const float* g, int32_t P, float* g_xi, hgsr_stream stream) {
+  if (P <= 0 || !xi || !g || !g_xi) return fail(HGSR_ERR_INVALID_ARG, "need P >= 1 and three arrays");
+  launch_pose_tangent_grad(xi, g, P, g_xi, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return HGSR_OK;
 }
 
 hgsr_status hgsr_residual(const float* rgb, const void* feat, int32_t feat_bf16, const float* rgb_target,

@@ -297,6 +297,8 @@ void launch_score_final(const float* sum, const uint32_t* count, int64_t n, floa
 void launch_residual(const float* rgb, const void* feat, int feat_bf16, const float* rgb_t, const float* feat_t,
                      int P, int H, int W, int D, float lam_f, float* loss, float* g_rgb, float* g_feat,
                      hipStream_t s);
+void launch_pose_retract(const float* poses, const float* xi, int P, float* out, hipStream_t s);
+void launch_pose_tangent_grad(const float* xi, const float* g, int P, float* g_xi, hipStream_t s);
 void launch_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step, int P, float lr_rho,
                       float lr_phi, float b1, float b2, float eps, hipStream_t s);
 

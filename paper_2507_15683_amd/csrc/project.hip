@@ -546,6 +546,8 @@ __global__ void validate_kernel(GaussArgs g, int32_t* bad) {
   ok &= (o >= 0.f && o <= 1.f);
   const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
   for (int k = 0; k < 3 * K; ++k) ok &= isfinite(g.sh[static_cast<int64_t>(3 * K) * i + k]);
+  // bfloat16 features: an all-ones exponent is Inf or NaN
+  for (int k = 0; k < g.feat_dim; ++k) ok &= (g.feat[static_cast<int64_t>(g.feat_dim) * i + k] & 0x7f80u) != 0x7f80u;
   if (!ok) atomicOr(bad, 1);
 }
 

@@ -1,6 +1,7 @@
 // Pose-refinement kernels around the renderer: the per-pose residual with
-// its output gradients, and an Adam step on the left-perturbation tangent
-// followed by the update T <- Exp(-step) T.
+// its output gradients, an Adam step on the left-perturbation tangent
+// followed by the update T <- Exp(-step) T, and the retraction T <- Exp(xi) T
+// with the chain rule of its tangent (the left Jacobian of SE(3)).
 #include "hgsr_device.hpp"
 #include "launch.hpp"
 
@@ -139,6 +140,101 @@ __global__ __launch_bounds__(256) void pose_adam_kernel(float* poses, const floa
                      V[r][2] * d[2];
     }
   }
+}
+
+// FP64 Exp of the twist (rho, phi): Rodrigues rotation and V rho.
+__device__ void exp_se3_f64(const double* xi, double Rd[3][3], double td[3]) {
+  const double wx = xi[3], wy = xi[4], wz = xi[5];
+  const double th2 = wx * wx + wy * wy + wz * wz;
+  const double th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-4) {  // series, truncation below double rounding
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[3][3] = {{0.0, -wz, wy}, {wz, 0.0, -wx}, {-wy, wx, 0.0}};
+  for (int r = 0; r < 3; ++r) {
+    double v[3];
+    for (int c = 0; c < 3; ++c) {
+      const double k2 = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
+      const double I = r == c ? 1.0 : 0.0;
+      Rd[r][c] = I + A * K[r][c] + B * k2;
+      v[c] = I + B * K[r][c] + C * k2;
+    }
+    td[r] = v[0] * xi[0] + v[1] * xi[1] + v[2] * xi[2];
+  }
+}
+
+// out = Exp(xi) T per pose, one thread per pose.
+__global__ __launch_bounds__(64) void pose_retract_kernel(const float* poses, const float* xi, int P, float* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double x[6], Rd[3][3], td[3], T[12];
+  for (int k = 0; k < 6; ++k) x[k] = xi[6 * p + k];
+  for (int k = 0; k < 12; ++k) T[k] = poses[12 * p + k];
+  exp_se3_f64(x, Rd, td);
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c)
+      out[12 * p + 4 * r + c] = static_cast<float>(Rd[r][0] * T[c] + Rd[r][1] * T[4 + c] + Rd[r][2] * T[8 + c]);
+    out[12 * p + 4 * r + 3] =
+        static_cast<float>(Rd[r][0] * T[3] + Rd[r][1] * T[7] + Rd[r][2] * T[11] + td[r]);
+  }
+}
+
+// g_xi = J_l(xi)^T g with J_l = sum_n ad(xi)^n / (n + 1)!, ad(rho, phi) =
+// [[phi^, rho^], [0, phi^]]; one thread per pose, FP64.
+__global__ __launch_bounds__(64) void pose_tangent_grad_kernel(const float* xi, const float* g, int P, float* g_xi) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const double r0 = xi[6 * p], r1 = xi[6 * p + 1], r2 = xi[6 * p + 2];
+  const double w0 = xi[6 * p + 3], w1 = xi[6 * p + 4], w2 = xi[6 * p + 5];
+  double ad[6][6] = {};
+  const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+  const double Rh[3][3] = {{0.0, -r2, r1}, {r2, 0.0, -r0}, {-r1, r0, 0.0}};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      ad[r][c] = W[r][c];
+      ad[r][3 + c] = Rh[r][c];
+      ad[3 + r][3 + c] = W[r][c];
+    }
+  double M[6][6], J[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) M[r][c] = J[r][c] = r == c ? 1.0 : 0.0;
+  for (int n = 1; n <= 40; ++n) {
+    double Mn[6][6];
+    const double inv = 1.0 / static_cast<double>(n + 1);
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < 6; ++k) acc += M[r][k] * ad[k][c];
+        Mn[r][c] = acc * inv;
+      }
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) {
+        M[r][c] = Mn[r][c];
+        J[r][c] += Mn[r][c];
+      }
+  }
+  double gi[6];
+  for (int k = 0; k < 6; ++k) gi[k] = g[6 * p + k];
+  for (int c = 0; c < 6; ++c) {
+    double acc = 0.0;
+    for (int r = 0; r < 6; ++r) acc += J[r][c] * gi[r];
+    g_xi[6 * p + c] = static_cast<float>(acc);
+  }
+}
+
+void launch_pose_retract(const float* poses, const float* xi, int P, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(pose_retract_kernel, dim3((P + 63) / 64), dim3(64), 0, s, poses, xi, P, out);
+}
+
+void launch_pose_tangent_grad(const float* xi, const float* g, int P, float* g_xi, hipStream_t s) {
+  hipLaunchKernelGGL(pose_tangent_grad_kernel, dim3((P + 63) / 64), dim3(64), 0, s, xi, g, P, g_xi);
 }
 
 void launch_pose_adam(float* poses, const float* grad, float* m, float* v, int32_t* step, int P, float lr_rho,

@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.TuneResult) == 20
     assert ctypes.sizeof(_lib.ResidualTargets) == 24
     assert ctypes.sizeof(_lib.Outputs) == 32
-    assert ctypes.sizeof(_lib.Grads) == 56
+    assert ctypes.sizeof(_lib.Grads) == 7 * 8 + 8  # 7 pointers, render_id
     assert ctypes.sizeof(_lib.FeatureMaps) == 8 + 3 * 4 + 4   # pointer, width, height, layout, tail padding
     assert ctypes.sizeof(_lib.MatchMaps) == 4 * 8 + 3 * 4 + 4  # 4 pointers, D, width, height, tail padding
     assert ctypes.sizeof(_lib.MatchOut) == 7 * 8

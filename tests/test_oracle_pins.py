@@ -507,3 +507,45 @@ def test_translation_identity_of_finite_differences(oracle_lib):
     want = R @ g_means.sum(0)
     assert np.linalg.norm(want) > 1e-4
     np.testing.assert_allclose(g_pose[:3], want, rtol=1e-5, atol=1e-9)
+
+
+def test_left_jacobian_against_the_matrix_exponential():
+    """The oracle's left Jacobian of SE(3) (its defining series) against
+    scipy's matrix exponential and logarithm: the columns of J_l(xi) are
+    central differences of log(Exp(xi + h e_k) Exp(xi)^-1); J_l(0) = I; the
+    rotation block is the V of Exp's translation; and the first-order rule
+    holds for rotations up to 170 degrees with translations of tens of metres."""
+    from scipy.linalg import expm, logm
+    from oracle.se3 import exp_se3, left_jacobian
+
+    def twist(x):
+        M = np.zeros((4, 4))
+        M[:3, :3] = np.array([[0, -x[5], x[4]], [x[5], 0, -x[3]], [-x[4], x[3], 0]])
+        M[:3, 3] = x[:3]
+        return M
+
+    def vee(M):
+        return np.r_[M[:3, 3], M[2, 1], M[0, 2], M[1, 0]]
+
+    assert np.array_equal(left_jacobian(np.zeros(6)), np.eye(6))
+    rng = np.random.default_rng(4)
+    for scale_r, scale_w in ((0.1, 0.01), (3.0, 0.5), (20.0, 2.0), (5.0, np.radians(170))):
+        xi = np.r_[rng.normal(0, scale_r, 3), rng.normal(size=3)]
+        xi[3:] *= scale_w / np.linalg.norm(xi[3:])
+        np.testing.assert_allclose(exp_se3(xi), expm(twist(xi)), atol=1e-12 * max(1.0, scale_r))
+        J = left_jacobian(xi)
+        h = 1e-6
+        base_inv = np.linalg.inv(expm(twist(xi)))
+        fd = np.zeros((6, 6))
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = h
+            lp = vee(np.real(logm(expm(twist(xi + e)) @ base_inv)))
+            lm = vee(np.real(logm(expm(twist(xi - e)) @ base_inv)))
+            fd[:, k] = (lp - lm) / (2 * h)
+        np.testing.assert_allclose(J, fd, atol=1e-6 * max(1.0, scale_r))
+        # the rotation block is V (Exp's translation is V rho)
+        V = exp_se3(np.r_[1.0, 0, 0, xi[3:]])[:3, 3], exp_se3(np.r_[0, 1.0, 0, xi[3:]])[:3, 3], \
+            exp_se3(np.r_[0, 0, 1.0, xi[3:]])[:3, 3]
+        np.testing.assert_allclose(J[3:, 3:], np.stack(V, 1), atol=1e-12)
+        np.testing.assert_allclose(J[:3, :3], np.stack(V, 1), atol=1e-12)
