@@ -219,6 +219,33 @@ hgsr_status hgsr_render(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* pos
                         const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
                         hgsr_stream stream);
 
+/* hgsr_render for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as hgsr_render (bit for bit: the
+ * tile lists' order does not depend on the capacities), but no context: the workspace (projected splats, keys,
+ * per-tile lists, per-pixel transmittance and list length) is laid out in a
+ * static device array of 128 MiB that each GPU the library runs on holds
+ * from the library's load until the process ends.  The call allocates
+ * nothing, host or device, and does not synchronise.
+ *   records_per_pose, keys: capacities (visible Gaussians per pose, tile
+ *     entries in total), both > 0, or both 0 to split the space the
+ *     per-pixel (8 B) and per-tile (20 B) buffers leave evenly between
+ *     records (60 B each) and keys (28 B each).
+ *   flags_out: device int32 (may be NULL) that receives the overflow bits
+ *     after the render (bit 0 records, bit 1 keys; 0 = complete).  When
+ *     non-zero the outputs are undefined: render again with larger
+ *     capacities, or with hgsr_render.
+ * HGSR_ERR_CAPACITY (nothing enqueued) when the layout would exceed 128 MiB
+ * (for example 16 poses at 1920x1080: 8 B per pixel alone is 265 MB).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each render clears what must start at zero): calls that overlap on
+ * one GPU -- on different streams, or a graph replayed while another call
+ * runs -- race, and the array holds nothing a backward can use.  The HIP
+ * device current at the call must be the one `stream` belongs to. */
+hgsr_status hgsr_render_noalloc(const hgsr_gaussians* g, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                                const hgsr_opts* opts, const hgsr_outputs* out, int64_t records_per_pose,
+                                int64_t keys, int32_t* flags_out, hgsr_stream stream);
+
 /* Backward of the last hgsr_render on this context: the gradient of a loss
  * on the rendered maps with respect to the poses and the Gaussian parameters
  * (Algorithm 1 back-propagates the summed rendered RGB and keeps the

@@ -117,6 +117,8 @@ SIGNATURES = {
     "hgsr_reserve": [P_, I32, I32, I32, I32, I64, I64, I64],
     "hgsr_render": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
                     ctypes.POINTER(Outputs), P_],
+    "hgsr_render_noalloc": [ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
+                            ctypes.POINTER(Outputs), I64, I64, P_, P_],
     "hgsr_render_backward": [P_, ctypes.POINTER(GradOutputs), ctypes.POINTER(Grads), P_],
     "hgsr_residual_backward": [P_, ctypes.POINTER(ResidualTargets), P_, ctypes.POINTER(Grads), P_],
     "hgsr_residual": [P_, P_, I32, P_, P_, I32, I32, I32, I32, F32, P_, P_, P_, P_],

@@ -24,6 +24,12 @@ __global__ void fill_f32_kernel(float* p, float v, int64_t n) {
     p[i] = v;
 }
 
+__global__ void copy_u32_kernel(uint32_t* dst, const uint32_t* src, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Zero up to four u32 ranges in one launch.
 __global__ void clear4_kernel(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2,
                               uint32_t* p3, int64_t n3) {
@@ -48,6 +54,10 @@ void launch_clear4(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t*
                    int64_t n3, hipStream_t s) {
   const int64_t mx = std::max(std::max(n0, n1), std::max(n2, n3));
   hipLaunchKernelGGL(clear4_kernel, dim3(fill_grid(mx)), dim3(256), 0, s, p0, n0, p1, n1, p2, n2, p3, n3);
+}
+
+void launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(copy_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s, dst, src, n);
 }
 
 void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {

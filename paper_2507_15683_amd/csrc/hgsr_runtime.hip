@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,6 +65,7 @@ int bits_for(uint64_t n) {
 struct hgsr_ctx {
   int device = 0;
   int n_cu = 256;
+  bool no_alloc = false;  // workspace borrowed from the static scratch array: never grows
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -120,6 +122,7 @@ constexpr int kMiscWords = 64;
 
 hgsr_status ensure(hgsr_ctx* c, Buf& b, size_t bytes) {
   if (bytes <= b.bytes) return HGSR_OK;
+  if (c->no_alloc) return fail(HGSR_ERR_CAPACITY, "a buffer outside the static scratch layout was requested");
   if (c->capturing) return fail(HGSR_ERR_CAPACITY, "workspace must grow while a graph is being captured; call hgsr_reserve first");
   if (b.p) HIP_TRY(hipFree(b.p));
   b.p = nullptr;
@@ -221,6 +224,43 @@ uint32_t round_rec_cap(int64_t r) {
   return static_cast<uint32_t>(std::min<int64_t>(sub * kSub, 0x7fffffffll / kSub * kSub));
 }
 
+// Every buffer of a render's list build and blend with its size in bytes,
+// for P poses at the context's record and key capacities: f(buf, bytes).
+template <class F>
+hgsr_status for_each_render_buf(hgsr_ctx* c, int P, const CamArgs& cam, bool lsd, F&& f) {
+  const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
+  const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
+  const int64_t npix = static_cast<int64_t>(P) * cam.W * cam.H;
+  TRY(f(c->recs, nrec * sizeof(Splat)));
+  TRY(f(c->rects, nrec * sizeof(uint2)));
+  // record sub-segment counters, then the cull pass's candidate counters
+  TRY(f(c->pose_count, 2 * static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
+  TRY(f(c->cand, nrec * sizeof(uint32_t)));
+  TRY(f(c->tile_count, ntile * sizeof(uint32_t)));
+  TRY(f(c->tile_cursor, ntile * sizeof(uint32_t)));
+  TRY(f(c->ranges, ntile * sizeof(uint2)));
+  TRY(f(c->keys0, c->key_cap * sizeof(uint64_t)));
+  TRY(f(c->keys1, c->key_cap * sizeof(uint64_t)));
+  TRY(f(c->vals0, c->key_cap * sizeof(uint32_t)));
+  TRY(f(c->vals1, c->key_cap * sizeof(uint32_t)));
+  TRY(f(c->list, c->key_cap * sizeof(uint32_t)));
+  const int64_t scan_n = std::max<int64_t>(ntile, lsd ? nrec : 0);
+  TRY(f(c->scan_tmp, (scan_block_count(scan_n) + 16) * sizeof(uint32_t)));
+  TRY(f(c->finalT, npix * sizeof(float)));
+  TRY(f(c->nused, npix * sizeof(uint32_t)));
+  TRY(f(c->part_vis, std::max(P, 1) * sizeof(uint64_t)));
+  TRY(f(c->loss_part, ntile * sizeof(float)));
+  if (lsd) {
+    TRY(f(c->rec_keys, nrec * sizeof(uint32_t)));
+    TRY(f(c->rec_offsets, nrec * sizeof(uint32_t)));
+    TRY(f(c->gids0, c->key_cap * sizeof(uint32_t)));
+    TRY(f(c->gids1, c->key_cap * sizeof(uint32_t)));
+    const int64_t nb = static_cast<int64_t>((c->key_cap + 2047) / 2048);
+    TRY(f(c->hist, (256 * nb + scan_block_count(256 * nb) + 16) * sizeof(uint32_t)));
+  }
+  return HGSR_OK;
+}
+
 // Size the workspace for P poses, given tile config, gaussians n.
 hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bool lsd) {
   if (c->rec_cap == 0) {
@@ -232,39 +272,9 @@ hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bo
     c->key_cap = c->key_hint > 0 ? static_cast<uint64_t>(c->key_hint)
                                  : std::max<uint64_t>(1ull << 21, 8ull * c->rec_cap * static_cast<uint64_t>(P));
   }
-  const int64_t nrec = static_cast<int64_t>(P) * c->rec_cap;
-  const int64_t ntile = static_cast<int64_t>(P) * cam.tiles_per_pose;
-  const int64_t npix = static_cast<int64_t>(P) * cam.W * cam.H;
-  if (nrec > static_cast<int64_t>(kRecMask))
+  if (static_cast<int64_t>(P) * c->rec_cap > static_cast<int64_t>(kRecMask))
     return fail(HGSR_ERR_INVALID_ARG, "too many (pose, Gaussian) records for one render: split the poses");
-  TRY(ensure(c, c->recs, nrec * sizeof(Splat)));
-  TRY(ensure(c, c->rects, nrec * sizeof(uint2)));
-  // record sub-segment counters, then the cull pass's candidate counters
-  TRY(ensure(c, c->pose_count, 2 * static_cast<size_t>(P) * kSub * sizeof(uint32_t)));
-  TRY(ensure(c, c->cand, nrec * sizeof(uint32_t)));
-  TRY(ensure(c, c->tile_count, ntile * sizeof(uint32_t)));
-  TRY(ensure(c, c->tile_cursor, ntile * sizeof(uint32_t)));
-  TRY(ensure(c, c->ranges, ntile * sizeof(uint2)));
-  TRY(ensure(c, c->keys0, c->key_cap * sizeof(uint64_t)));
-  TRY(ensure(c, c->keys1, c->key_cap * sizeof(uint64_t)));
-  TRY(ensure(c, c->vals0, c->key_cap * sizeof(uint32_t)));
-  TRY(ensure(c, c->vals1, c->key_cap * sizeof(uint32_t)));
-  TRY(ensure(c, c->list, c->key_cap * sizeof(uint32_t)));
-  const int64_t scan_n = std::max<int64_t>(ntile, lsd ? nrec : 0);
-  TRY(ensure(c, c->scan_tmp, (scan_block_count(scan_n) + 16) * sizeof(uint32_t)));
-  TRY(ensure(c, c->finalT, npix * sizeof(float)));
-  TRY(ensure(c, c->nused, npix * sizeof(uint32_t)));
-  TRY(ensure(c, c->part_vis, std::max(P, 1) * sizeof(uint64_t)));
-  TRY(ensure(c, c->loss_part, ntile * sizeof(float)));
-  if (lsd) {
-    TRY(ensure(c, c->rec_keys, nrec * sizeof(uint32_t)));
-    TRY(ensure(c, c->rec_offsets, nrec * sizeof(uint32_t)));
-    TRY(ensure(c, c->gids0, c->key_cap * sizeof(uint32_t)));
-    TRY(ensure(c, c->gids1, c->key_cap * sizeof(uint32_t)));
-    const int64_t nb = static_cast<int64_t>((c->key_cap + 2047) / 2048);
-    TRY(ensure(c, c->hist, (256 * nb + scan_block_count(256 * nb) + 16) * sizeof(uint32_t)));
-  }
-  return HGSR_OK;
+  return for_each_render_buf(c, P, cam, lsd, [c](Buf& b, size_t bytes) { return ensure(c, b, bytes); });
 }
 
 // Options of a render-like call resolved against the context's defaults.
@@ -493,9 +503,11 @@ hgsr_status hgsr_reserve(hgsr_ctx* c, int32_t P, int32_t width, int32_t height, 
   return HGSR_OK;
 }
 
-hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
-                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
-                        hgsr_stream stream) {
+// The render of hgsr_render on context c (its own workspace or, for
+// hgsr_render_noalloc, one laid out in the static scratch array).
+static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                               const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                               hgsr_stream stream) {
   Resolved rs;
   TRY(resolve(c, g, poses, P, K, opts, &rs));
   if (!out) return fail(HGSR_ERR_INVALID_ARG, "out is NULL");
@@ -551,6 +563,147 @@ hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
   c->out = *out;
   c->cam = cam;
   c->sorted = sorted;
+  return HGSR_OK;
+}
+
+hgsr_status hgsr_render(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses, int32_t P,
+                        const hgsr_intrinsics* K, const hgsr_opts* opts, const hgsr_outputs* out,
+                        hgsr_stream stream) {
+  return render_impl(c, g, poses, P, K, opts, out, stream);
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------ allocation-free render
+// hgsr_render_noalloc lays the render's workspace out in one static device
+// array instead of allocating it.  The HIP runtime gives every device its
+// own copy of the array when the library's code object is loaded there, and
+// keeps it until the process ends.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchAlign = 256;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Per device: the array's device address (hipGetSymbolAddress, taken once
+// with that device current; the array's name in host code is not a device
+// address) and a host context whose buffers point into it.
+struct NoAllocDevice {
+  std::mutex mu;
+  bool ready = false;
+  unsigned char* base = nullptr;
+  hgsr_ctx ctx;
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+
+size_t align_up(size_t b) { return (b + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+
+// Bytes the layout takes at the context's current record and key capacities.
+size_t scratch_bytes(hgsr_ctx* c, int P, const CamArgs& cam, bool lsd) {
+  size_t total = align_up(kMiscWords * sizeof(int32_t));
+  (void)for_each_render_buf(c, P, cam, lsd, [&total](Buf&, size_t bytes) {
+    total += align_up(bytes);
+    return HGSR_OK;
+  });
+  return total;
+}
+
+// Capacities for a render of P poses in the scratch array: the caller's, or
+// with records_per_pose = keys = 0 the space left by the per-pixel and
+// per-tile buffers split evenly between records and keys.
+hgsr_status scratch_capacities(hgsr_ctx* c, int P, const CamArgs& cam, bool lsd, int64_t records_per_pose,
+                               int64_t keys) {
+  if (records_per_pose > 0 || keys > 0) {
+    if (records_per_pose <= 0 || keys <= 0)
+      return fail(HGSR_ERR_INVALID_ARG, "give both records_per_pose and keys, or neither");
+    c->rec_cap = round_rec_cap(records_per_pose);
+    c->key_cap = static_cast<uint64_t>(keys);
+  } else {
+    c->rec_cap = 0;
+    c->key_cap = 0;
+    const size_t base = scratch_bytes(c, P, cam, lsd);
+    if (base + (size_t(1) << 20) > kScratchBytes)
+      return fail(HGSR_ERR_CAPACITY,
+                  "%d pose(s) of %dx%d need %zu bytes of per-pixel and per-tile buffers; the static scratch holds %zu",
+                  P, cam.W, cam.H, base, kScratchBytes);
+    const uint32_t r1 = kSub * 1024;
+    c->rec_cap = r1;
+    const size_t per_rec = (scratch_bytes(c, P, cam, lsd) - base + r1 - 1) / r1;
+    c->rec_cap = 0;
+    c->key_cap = 1u << 20;
+    const size_t per_key = (scratch_bytes(c, P, cam, lsd) - base + (1u << 20) - 1) / (1u << 20);
+    const size_t avail = kScratchBytes - base - 64 * kScratchAlign;
+    int64_t rc = static_cast<int64_t>(avail / 2 / per_rec) / kSub * kSub;
+    rc = std::min<int64_t>(rc, static_cast<int64_t>(kRecMask) / P / kSub * kSub);
+    c->rec_cap = static_cast<uint32_t>(std::max<int64_t>(rc, kSub));
+    c->key_cap = std::max<uint64_t>(avail / 2 / per_key, 1024);
+    while (scratch_bytes(c, P, cam, lsd) > kScratchBytes && c->key_cap > 1024) c->key_cap -= c->key_cap / 64 + 1;
+  }
+  if (static_cast<int64_t>(P) * c->rec_cap > static_cast<int64_t>(kRecMask))
+    return fail(HGSR_ERR_INVALID_ARG, "too many (pose, Gaussian) records for one render: split the poses");
+  const size_t need = scratch_bytes(c, P, cam, lsd);
+  if (need > kScratchBytes)
+    return fail(HGSR_ERR_CAPACITY,
+                "the render needs %zu bytes of workspace (%d pose(s) of %dx%d, %u records per pose, %llu keys); "
+                "the static scratch holds %zu",
+                need, P, cam.W, cam.H, c->rec_cap, static_cast<unsigned long long>(c->key_cap), kScratchBytes);
+  return HGSR_OK;
+}
+
+// Point the context's buffers at consecutive aligned ranges of the array.
+void carve_scratch(hgsr_ctx* c, unsigned char* base, int P, const CamArgs& cam, bool lsd) {
+  size_t off = 0;
+  c->misc.p = base;
+  c->misc.bytes = kMiscWords * sizeof(int32_t);
+  off += align_up(c->misc.bytes);
+  (void)for_each_render_buf(c, P, cam, lsd, [&](Buf& b, size_t bytes) {
+    b.p = base + off;
+    b.bytes = bytes;
+    off += align_up(bytes);
+    return HGSR_OK;
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+hgsr_status hgsr_render_noalloc(const hgsr_gaussians* g, const float* poses, int32_t P, const hgsr_intrinsics* K,
+                                const hgsr_opts* opts, const hgsr_outputs* out, int64_t records_per_pose,
+                                int64_t keys, int32_t* flags_out, hgsr_stream stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HGSR_ERR_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  if (records_per_pose < 0 || keys < 0) return fail(HGSR_ERR_INVALID_ARG, "negative capacity");
+  NoAllocDevice& d = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(d.mu);
+  if (!d.ready) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HGSR_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    d.base = static_cast<unsigned char*>(p);
+    d.ctx.device = dev;
+    d.ctx.no_alloc = true;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      d.ctx.n_cu = cu;
+    d.ready = true;
+  }
+  hgsr_ctx* c = &d.ctx;
+  Resolved rs;
+  TRY(resolve(c, g, poses, P, K, opts, &rs));
+  TRY(scratch_capacities(c, P, rs.cam, rs.lsd, records_per_pose, keys));
+  carve_scratch(c, d.base, P, rs.cam, rs.lsd);
+  TRY(render_impl(c, g, poses, P, K, opts, out, stream));
+  if (flags_out)
+    launch_copy_u32(reinterpret_cast<uint32_t*>(flags_out), reinterpret_cast<const uint32_t*>(c->misc.p) + kFlags, 1,
+                    reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
   return HGSR_OK;
 }
 

@@ -196,6 +196,7 @@ void launch_validate(const GaussArgs& g, int32_t* bad, hipStream_t s);
 // binning.hip
 void launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
+void launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t n, hipStream_t s);
 void launch_clear4(uint32_t* p0, int64_t n0, uint32_t* p1, int64_t n1, uint32_t* p2, int64_t n2, uint32_t* p3,
                    int64_t n3, hipStream_t s);
 int64_t scan_block_count(int64_t n);
