@@ -35,7 +35,7 @@ constexpr int kHGroup = 32;
 // differs from the FP32 dot product.  H goes to LDS, where the walk reads its
 // pixel's value of each splat.
 template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH>
-__global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
+__device__ __forceinline__ void blend_bwd_item(const BackArgs& a, const int item) {
   using Sh = BlendShape<TILE>;
   constexpr int NT = Sh::kThreads, NB = Sh::kBatch, NW = Sh::kWaves, BW = Sh::kBlockW, BH = Sh::kBlockH;
   constexpr int PPT = Sh::kPPT;
@@ -57,14 +57,18 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   __shared__ float s_g[NB][10];  // per staged splat: the workgroup's gradient sums
   __shared__ uint32_t s_max;
   __shared__ float s_lw[NW];
-  if (a.flags[0] & 3) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int W = a.c.W, H = a.c.H;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  const int pose = item / a.c.tiles_per_pose;
-  const int tile = item - pose * a.c.tiles_per_pose;
+  int pose, tile;
+  if (a.schedule == kSchedTileMajor) {
+    tile = item / a.P;
+    pose = item - tile * a.P;
+  } else {
+    pose = item / a.c.tiles_per_pose;
+    tile = item - pose * a.c.tiles_per_pose;
+  }
   const int ty = tile / a.c.ntx, tx = tile - ty * a.c.ntx;
   const uint2 range = a.ranges[static_cast<int64_t>(pose) * a.c.tiles_per_pose + tile];
   const int bx0 = tx * TILE + (wave % Sh::kBlocksX) * BW, by0 = ty * TILE + (wave / Sh::kBlocksX) * BH;
@@ -191,6 +195,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
       const int e = tid % NB, part = tid / NB;
       if (e < nb) {
         const uint32_t lv = a.list[range.x + b0 + e];
+        const uint32_t gid = a.list_gid[range.x + b0 + e];
         const uint32_t r = lv & kRecMask;
         const float4* sp = reinterpret_cast<const float4*>(a.recs + r);
         const float4 g1 = sp[1];
@@ -204,8 +209,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
         if constexpr (DV > 0) {
           if (part < PARTS) {
             constexpr int QV = DV / PARTS;
-            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) +
-                              static_cast<int64_t>(__float_as_uint(g1.w)) * DV + part * QV;
+            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(gid) * DV + part * QV;
 #pragma unroll
             for (int q = 0; q < QV; ++q) {
               const uint4 f = fv[q];
@@ -233,6 +237,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
       n_mine += __popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
+    // the next entry's index is read one step ahead
+    int jn = n_mine > 0 ? static_cast<int>(s_list[wave][n_mine - 1]) : 0;
     for (int ii = n_mine - 1; ii >= 0; --ii) {
       if constexpr (MF) {
         if (ii == n_mine - 1 || (ii + 1) % kHGroup == 0) {
@@ -300,7 +306,8 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
           __builtin_amdgcn_wave_barrier();
         }
       }
-      const int jj = s_list[wave][ii];
+      const int jj = __builtin_amdgcn_readfirstlane(jn);
+      jn = ii > 0 ? static_cast<int>(s_list[wave][ii - 1]) : 0;
       const uint32_t pos = b0 + jj;
       const float4 geo = s_geo[jj];
       const float4 opz = s_opz[jj];
@@ -390,6 +397,31 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
   }
 }
 
+// One workgroup per (pose, tile) item, or (PERSIST) a grid of workgroups
+// claiming runs of kQueueChunk items from a device counter until it passes
+// the item count.
+template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH, bool PERSIST>
+__global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
+  if (a.flags[0] & 3) return;
+  if constexpr (PERSIST) {
+    __shared__ int s_item;
+    for (;;) {
+      if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(a.queue, static_cast<uint32_t>(kQueueChunk)));
+      __syncthreads();
+      const int first = s_item;
+      __syncthreads();
+      if (first >= a.n_items) break;
+      const int last = min(first + kQueueChunk, a.n_items);
+      for (int item = first; item < last; ++item) {
+        blend_bwd_item<TILE, D, FEATGRAD, RES, MFH>(a, item);
+        __syncthreads();  // the item's LDS is reused by the next one
+      }
+    }
+  } else {
+    blend_bwd_item<TILE, D, FEATGRAD, RES, MFH>(a, xcd_item(blockIdx.x, gridDim.x));
+  }
+}
+
 // Per-pose loss from the per-tile shares, in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void loss_reduce_kernel(const float* part, int32_t tiles_per_pose, float* loss) {
   __shared__ float s_r[256];
@@ -410,22 +442,34 @@ void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, fl
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(P), dim3(256), 0, s, part, tiles_per_pose, loss);
 }
 
-template <int TILE, int D>
-static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
+template <int TILE, int D, bool PERSIST>
+static void launch_bwd_tdp(const BackArgs& a, int items, hipStream_t s) {
   constexpr int NT = BlendShape<TILE>::kThreads;
   // the feature term on the matrix cores: 32 channels, one pixel per lane,
   // no per-Gaussian feature gradient
   constexpr bool MFOK = D == 32 && BlendShape<TILE>::kPPT == 1;
   const bool mf = MFOK && a.feat_mfma && !a.g_featvec;
   if (a.res_rgb_t) {
-    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true, false>), dim3(items), dim3(NT), 0, s, a);
-    else if (mf) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, MFOK>), dim3(items), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, false>), dim3(items), dim3(NT), 0, s, a);
+    if (a.g_featvec)
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
+    else if (mf)
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, MFOK, PERSIST>), dim3(items), dim3(NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
   } else {
-    if (a.g_featvec) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, false, false>), dim3(items), dim3(NT), 0, s, a);
-    else if (mf) hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, MFOK>), dim3(items), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, false>), dim3(items), dim3(NT), 0, s, a);
+    if (a.g_featvec)
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, false, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
+    else if (mf)
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, MFOK, PERSIST>), dim3(items), dim3(NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, false, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
   }
+}
+
+template <int TILE, int D>
+static void launch_bwd_td(const BackArgs& a, int items, hipStream_t s) {
+  if (a.schedule != kSchedGrid) launch_bwd_tdp<TILE, D, true>(a, a.n_ctas, s);
+  else launch_bwd_tdp<TILE, D, false>(a, items, s);
 }
 
 template <int TILE>

@@ -486,7 +486,10 @@ __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
   r.y = __builtin_amdgcn_readfirstlane(r.y);
   const uint32_t n = r.y - r.x;
   if (n <= 1 || n > static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) {
-    if (n == 1 && lane == 0) a.list[r.x] = a.vals[r.x];
+    if (n == 1 && lane == 0) {
+      a.list[r.x] = a.vals[r.x];
+      a.list_gid[r.x] = static_cast<uint32_t>(a.keys[r.x]);
+    }
     return;
   }
   const int R = static_cast<int>((n + kWave - 1) / kWave);  // keys per lane, 1..4
@@ -516,7 +519,10 @@ __global__ __launch_bounds__(256) void tile_sort_wave_kernel(TileSortArgs a) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t e = q * kWave + lane;
-    if (q < R && e < n) a.list[r.x + rank[q]] = val[q];
+    if (q < R && e < n) {
+      a.list[r.x + rank[q]] = val[q];
+      a.list_gid[r.x + rank[q]] = static_cast<uint32_t>(key[q]);
+    }
   }
 }
 
@@ -556,7 +562,10 @@ __device__ void tile_sort_lds(const TileSortArgs& a, uint2 r, uint32_t n, uint64
       __syncthreads();
     }
   }
-  for (uint32_t k = threadIdx.x; k < n; k += 256) a.list[r.x + k] = s_val[k];
+  for (uint32_t k = threadIdx.x; k < n; k += 256) {
+    a.list[r.x + k] = s_val[k];
+    a.list_gid[r.x + k] = static_cast<uint32_t>(s_key[k]);
+  }
 }
 
 // Stable rank of one element per thread within a 256-element chunk, by 8-bit
@@ -627,7 +636,10 @@ __device__ void tile_sort_global(const TileSortArgs& a, uint2 r, uint32_t n, uin
     uint32_t* tv = sv; sv = dv; dv = tv;
     __syncthreads();
   }
-  for (uint32_t k = threadIdx.x; k < n; k += 256) a.list[r.x + k] = sv[k];
+  for (uint32_t k = threadIdx.x; k < n; k += 256) {
+    a.list[r.x + k] = sv[k];
+    a.list_gid[r.x + k] = static_cast<uint32_t>(sk[k]);
+  }
 }
 
 // Lists longer than one wave sorts: the workgroup sorts them in LDS up to the

@@ -7,7 +7,9 @@
 // colour, FP32 feature vector) into LDS and marks which waves' blocks its
 // support rectangle touches; each wave then compacts the batch to the entries
 // that touch its block and runs its pixels through them, reading each splat
-// as an LDS broadcast.  Pairs whose exponent is clearly below the 1/255 gate
+// as an LDS broadcast.  Each splat's tile-list entry carries its Gaussian
+// index beside its record index, so the staging loads of record and feature
+// vector go out together.  Pairs whose exponent is clearly below the 1/255 gate
 // are rejected before the exponential; the exact gate, clamp and stop tests
 // follow.  A pixel stops at the first splat that would take its transmittance
 // below 1e-4; the batch loop ends when every pixel of the tile has stopped.
@@ -55,14 +57,20 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
   const int W = a.c.W, H = a.c.H;
   const int64_t HW = static_cast<int64_t>(W) * H;
   const bool persistent = a.schedule != kSchedGrid;
+  int chunk_next = 0, chunk_left = 0;  // persistent: the claimed run of items
 
   for (int iter = 0;; ++iter) {
     int item;
     if (persistent) {
-      if (tid == 0) s_item = static_cast<int>(atomicAdd(a.queue, 1u));
-      __syncthreads();
-      item = s_item;
-      __syncthreads();
+      if (chunk_left == 0) {
+        if (tid == 0) s_item = static_cast<int>(atomicAdd(a.queue, static_cast<uint32_t>(kQueueChunk)));
+        __syncthreads();
+        chunk_next = s_item;
+        chunk_left = kQueueChunk;
+        __syncthreads();
+      }
+      item = chunk_next++;
+      --chunk_left;
       if (item >= a.n_items) break;
     } else {
       if (iter > 0) break;
@@ -112,6 +120,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
       const uint32_t j = b0 + e;
       if (j < range.y) {
         const uint32_t lv = a.list[j];
+        const uint32_t gid = a.list_gid[j];
         const float4* sp = reinterpret_cast<const float4*>(a.recs + (lv & kRecMask));
         const float4 g1 = sp[1];
         if (part == 0) {
@@ -123,8 +132,7 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
         if constexpr (D > 0) {
           if (part < PARTS) {
             constexpr int QV = DV / PARTS;
-            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) +
-                              static_cast<int64_t>(__float_as_uint(g1.w)) * DV + part * QV;
+            const uint4* fv = reinterpret_cast<const uint4*>(a.feat) + static_cast<int64_t>(gid) * DV + part * QV;
             if constexpr (LDS_F32) {
 #pragma unroll
               for (int q = 0; q < QV; ++q) {
@@ -253,15 +261,21 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
           }
         }
       } else {
+        // the next entry's index is read one step ahead, and a splat's
+        // geometry, colour and feature vector each in one round of LDS reads,
+        // so that a step waits on LDS latency twice instead of seven times
+        int jn = n_mine > 0 ? static_cast<int>(s_list[wave][0]) : 0;
         for (int ii = 0; ii < n_mine; ++ii) {
           bool mine = true;
 #pragma unroll
           for (int k = 0; k < PPT; ++k) mine &= done[k];
           if (mine) break;
-          const int jj = s_list[wave][ii];
+          const int jj = __builtin_amdgcn_readfirstlane(jn);
+          jn = ii + 1 < n_mine ? static_cast<int>(s_list[wave][ii + 1]) : 0;
           const float4 geo = s_geo[jj];
           const float4 opz = s_opz[jj];
-          const float pmin = s_col[jj].w;
+          const float4 col = s_col[jj];
+          const float pmin = col.w;
 #pragma unroll
           for (int k = 0; k < PPT; ++k) {
             if (done[k]) continue;
@@ -276,14 +290,17 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
               continue;
             }
             const float w = alpha * T[k];
-            const float4 col = s_col[jj];
             C[k][0] = fmaf(w, col.x, C[k][0]);
             C[k][1] = fmaf(w, col.y, C[k][1]);
             C[k][2] = fmaf(w, col.z, C[k][2]);
             Z[k] = fmaf(w, opz.z, Z[k]);
             if constexpr (D > 0) {
               if constexpr (LDS_F32) {
-                const float4* fq = reinterpret_cast<const float4*>(&s_fw[jj * FS]);
+                const float4* fsrc = reinterpret_cast<const float4*>(&s_fw[jj * FS]);
+                float4 fq[D / 4];
+#pragma unroll
+                for (int q = 0; q < D / 4; ++q) fq[q] = fsrc[q];
+                __builtin_amdgcn_sched_barrier(0);  // all reads issued before the first FMA
 #pragma unroll
                 for (int q = 0; q < D / 4; ++q) {
                   const float4 f = fq[q];

@@ -24,6 +24,10 @@ constexpr int kWave = 64;
 // blend launch shapes: one workgroup per (pose, tile), or a persistent grid
 // pulling (pose, tile) items pose-major or tile-major from a device counter
 enum { kSchedGrid = 0, kSchedPoseMajor = 1, kSchedTileMajor = 2 };
+// Items a persistent workgroup claims per queue atomic: the counter is one
+// device-scope address, whose atomics are performed one after another at the
+// memory side, so one atomic per (pose, tile) item would serialise the launch.
+constexpr int kQueueChunk = 16;
 
 // One visible (pose, Gaussian): what the blend reads per list entry.
 struct alignas(16) Splat {

@@ -78,7 +78,7 @@ struct hgsr_ctx {
 
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
-      gids0, gids1, list, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
+      gids0, gids1, list, list_gid, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
       match, tune, pnp;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
@@ -94,6 +94,7 @@ struct hgsr_ctx {
   hgsr_outputs out{};
   CamArgs cam{};
   const uint32_t* sorted = nullptr;
+  const uint32_t* sorted_gid = nullptr;  // Gaussian index per sorted entry
 
   // autotuned defaults
   int tuned_tile = 0;
@@ -118,6 +119,7 @@ constexpr int kFlags = 0;       // overflow bits
 constexpr int kTotalKeys = 1;   // keys emitted (u32)
 constexpr int kQueue = 2;       // persistent blend work counter
 constexpr int kBad = 3;         // validation result
+constexpr int kQueueBwd = 4;    // persistent blend-backward work counter
 constexpr int kMiscWords = 64;
 
 hgsr_status ensure(hgsr_ctx* c, Buf& b, size_t bytes) {
@@ -244,6 +246,7 @@ hgsr_status for_each_render_buf(hgsr_ctx* c, int P, const CamArgs& cam, bool lsd
   TRY(f(c->vals0, c->key_cap * sizeof(uint32_t)));
   TRY(f(c->vals1, c->key_cap * sizeof(uint32_t)));
   TRY(f(c->list, c->key_cap * sizeof(uint32_t)));
+  TRY(f(c->list_gid, c->key_cap * sizeof(uint32_t)));
   const int64_t scan_n = std::max<int64_t>(ntile, lsd ? nrec : 0);
   TRY(f(c->scan_tmp, (scan_block_count(scan_n) + 16) * sizeof(uint32_t)));
   TRY(f(c->finalT, npix * sizeof(float)));
@@ -263,18 +266,32 @@ hgsr_status for_each_render_buf(hgsr_ctx* c, int P, const CamArgs& cam, bool lsd
 
 // Size the workspace for P poses, given tile config, gaussians n.
 hgsr_status size_workspace(hgsr_ctx* c, int P, const CamArgs& cam, int64_t n, bool lsd) {
+  // First sizes, before any render has measured its needs: records per pose
+  // from the image (one visible splat per 8 pixels, at least 64k; never more
+  // than the scene), keys four per record slot.  A render that needs more
+  // raises the overflow flag and hgsr_check_overflow grows to the counts the
+  // device measured, so the workspace follows the visible work rather than
+  // the scene size times the pose count.
   if (c->rec_cap == 0) {
-    int64_t r = c->rec_hint > 0 ? c->rec_hint : std::max<int64_t>(1 << 16, n / 4);
+    int64_t r = c->rec_hint > 0 ? c->rec_hint
+                                : std::max<int64_t>(1 << 16, static_cast<int64_t>(cam.W) * cam.H / 8);
     r = std::min<int64_t>(std::max<int64_t>(r, 1024), std::max<int64_t>(n, 1024));
     c->rec_cap = round_rec_cap(r);
   }
   if (c->key_cap == 0) {
     c->key_cap = c->key_hint > 0 ? static_cast<uint64_t>(c->key_hint)
-                                 : std::max<uint64_t>(1ull << 21, 8ull * c->rec_cap * static_cast<uint64_t>(P));
+                                 : std::max<uint64_t>(1ull << 21, 4ull * c->rec_cap * static_cast<uint64_t>(P));
   }
   if (static_cast<int64_t>(P) * c->rec_cap > static_cast<int64_t>(kRecMask))
     return fail(HGSR_ERR_INVALID_ARG, "too many (pose, Gaussian) records for one render: split the poses");
   return for_each_render_buf(c, P, cam, lsd, [c](Buf& b, size_t bytes) { return ensure(c, b, bytes); });
+}
+
+// Workgroups of a persistent blend or blend-backward launch: 32 waves per
+// CU (tile 8 workgroups are one wave, the others four).
+int64_t persistent_ctas(const hgsr_ctx* c, int tile) {
+  const int waves_per_wg = tile == 8 ? 1 : 4;
+  return 32ll * c->n_cu / waves_per_wg;
 }
 
 // Options of a render-like call resolved against the context's defaults.
@@ -395,11 +412,13 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     ta.keys_alt = c->keys1.as<uint64_t>();
     ta.vals_alt = c->vals1.as<uint32_t>();
     ta.list = c->list.as<uint32_t>();
+    ta.list_gid = c->list_gid.as<uint32_t>();
     ta.lds_cap = opts->lds_sort_cap > 0 ? std::min(opts->lds_sort_cap, 4096) : 4096;
     ta.gid_bits = bits_for(static_cast<uint64_t>(std::max<int64_t>(g->n, 2)));
     ta.flags = misc + kFlags;
     launch_tile_sort(ta, true, s);
     sorted = c->list.as<uint32_t>();
+    c->sorted_gid = c->list_gid.as<uint32_t>();
   } else {
     launch_scan(c->rec_keys.as<uint32_t>(), nrec, c->rec_offsets.as<uint32_t>(), nullptr, c->scan_tmp.as<uint32_t>(),
                 total, c->key_cap, misc + kFlags, 2, s);
@@ -421,6 +440,7 @@ hgsr_status build_lists(hgsr_ctx* c, const hgsr_gaussians* g, const float* poses
     launch_ranges_from_sorted(la.keys[outb], total, c->key_cap, c->ranges.as<uint2>(), static_cast<int32_t>(ntile),
                               misc + kFlags, s);
     sorted = la.vals[outb];
+    c->sorted_gid = la.gids[outb];
   }
 
   hipEvent_t e2 = stamp(c, s);
@@ -471,7 +491,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   Buf* all[] = {&c->recs, &c->rects, &c->rec_keys, &c->rec_offsets, &c->pose_count, &c->tile_count,
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
-                &c->gids1, &c->list, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
+                &c->gids1, &c->list, &c->list_gid, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
                 &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match, &c->tune,
                 &c->pnp};
   for (Buf* b : all)
@@ -526,6 +546,7 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   bl.P = P;
   bl.ranges = c->ranges.as<uint2>();
   bl.list = sorted;
+  bl.list_gid = c->sorted_gid;
   {
     int fa = opts->feat_accum;
     if (fa == HGSR_FEAT_AUTO) fa = c->tuned_feat ? c->tuned_feat : HGSR_FEAT_VALU;
@@ -545,7 +566,7 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   bl.queue = reinterpret_cast<uint32_t*>(misc + kQueue);
   bl.flags = misc + kFlags;
   int n_ctas = static_cast<int>(ntile);
-  if (sched != HGSR_SCHED_GRID) n_ctas = static_cast<int>(std::min<int64_t>(ntile, 8ll * c->n_cu));
+  if (sched != HGSR_SCHED_GRID) n_ctas = static_cast<int>(std::min<int64_t>(ntile, persistent_ctas(c, tile)));
   launch_blend_fwd(bl, g->feat_dim, opts->feat_out_bf16 != 0, n_ctas, s);
   HIP_TRY(hipGetLastError());
   hipEvent_t e3 = stamp(c, s);
@@ -560,6 +581,7 @@ static hgsr_status render_impl(hgsr_ctx* c, const hgsr_gaussians* g, const float
   c->K = *K;
   c->opts = *opts;
   c->opts.tile = tile;
+  c->opts.schedule = sched;  // the backward replays with the same launch shape
   c->out = *out;
   c->cam = cam;
   c->sorted = sorted;
@@ -1163,6 +1185,7 @@ static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   b.feat_mfma = c->opts.feat_accum == HGSR_FEAT_MFMA ? 1 : 0;
   b.ranges = c->ranges.as<uint2>();
   b.list = c->sorted;
+  b.list_gid = c->sorted_gid;
   b.recs = c->recs.as<Splat>();
   b.feat = c->g.feat;
   b.D = D;
@@ -1186,6 +1209,11 @@ static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   b.res_lam = rt ? rt->lam_f : 0.f;
   b.res_inv_hw = 1.f / static_cast<float>(static_cast<int64_t>(c->cam.W) * c->cam.H);
   b.res_part = c->loss_part.as<float>();
+  b.schedule = c->opts.schedule;
+  b.n_items = static_cast<int32_t>(static_cast<int64_t>(P) * c->cam.tiles_per_pose);
+  b.n_ctas = static_cast<int32_t>(std::min<int64_t>(b.n_items, persistent_ctas(c, c->cam.tile)));
+  b.queue = reinterpret_cast<uint32_t*>(misc + kQueueBwd);
+  if (b.schedule != HGSR_SCHED_GRID) launch_fill_u32(b.queue, 0u, 1, s);
   launch_blend_bwd(b, s);
   if (rt) launch_loss_reduce(c->loss_part.as<float>(), c->cam.tiles_per_pose, P, loss, s);
   hipEvent_t e1 = stamp(c, s);
@@ -1276,16 +1304,27 @@ hgsr_status hgsr_autotune(hgsr_ctx* c, const hgsr_gaussians* g, const float* pos
   if (c->capturing) return fail(HGSR_ERR_STATE, "cannot autotune while capturing");
   if (P <= 0) return fail(HGSR_ERR_INVALID_ARG, "need at least one pose");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (with_backward) TRY(ensure(c, c->tune, static_cast<size_t>(P) * 6 * sizeof(float)));
+  if (with_backward) TRY(ensure(c, c->tune, static_cast<size_t>(P) * 7 * sizeof(float)));
   auto run = [&](const hgsr_opts* o) -> hgsr_status {
     TRY(hgsr_render(c, g, poses, P, K, o, out, stream));
     if (!with_backward) return HGSR_OK;
-    // the refinement step's backward: pose gradient of a loss whose output
-    // gradients are the rendered maps themselves (nonzero, right shapes)
     const bool f32feat = g->feat_dim > 0 && out->feat && !o->feat_out_bf16;
-    const hgsr_grad_outputs go = {out->rgb, nullptr, nullptr, f32feat ? static_cast<const float*>(out->feat) : nullptr};
     hgsr_grads gr{};
     gr.pose = c->tune.as<float>();
+    if (g->feat_dim == 0 || f32feat) {
+      // the refinement step's backward: the residual formed inside the blend
+      // backward, against the rendered maps themselves as targets (the same
+      // per-pixel work as any target)
+      hgsr_residual_targets rt{};
+      rt.rgb_target = out->rgb;
+      rt.feat_target = f32feat ? static_cast<const float*>(out->feat) : nullptr;
+      rt.lam_f = 1.f;
+      rt.shared_target = 0;
+      return hgsr_residual_backward(c, &rt, c->tune.as<float>() + 6 * static_cast<int64_t>(P), &gr, stream);
+    }
+    // bf16 feature maps (no FP32 target): the plain backward of a loss whose
+    // output gradients are the rendered colour maps
+    const hgsr_grad_outputs go = {out->rgb, nullptr, nullptr, nullptr};
     return hgsr_render_backward(c, &go, &gr, stream);
   };
   char key[256];

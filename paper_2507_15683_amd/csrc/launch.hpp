@@ -57,6 +57,7 @@ struct TileSortArgs {
   uint64_t* keys_alt;
   uint32_t* vals_alt;
   uint32_t* list;            // sorted record indices
+  uint32_t* list_gid;        // Gaussian index of each sorted entry
   int32_t lds_cap;
   int32_t gid_bits;
   const int32_t* flags;
@@ -78,6 +79,7 @@ struct BlendArgs {
   int32_t P;
   const uint2* ranges;
   const uint32_t* list;      // per-tile record indices in (depth, index) order
+  const uint32_t* list_gid;  // Gaussian index of each list entry
   int32_t feat_mfma;         // accumulate 32 feature channels on the matrix cores
   const Splat* recs;
   const uint16_t* feat;      // n x D bf16
@@ -100,10 +102,15 @@ struct BackArgs {
   int32_t feat_mfma;         // feature term of h on the matrix cores (D 32, one pixel per lane)
   const uint2* ranges;
   const uint32_t* list;
+  const uint32_t* list_gid;  // Gaussian index of each list entry
   const Splat* recs;
   const uint16_t* feat;
   int32_t D;
   float bg[3];
+  int32_t schedule;          // kSchedGrid, or a persistent queue of (pose, tile) items
+  int32_t n_items;
+  int32_t n_ctas;            // workgroups of the persistent launch
+  uint32_t* queue;           // item counter (zero before the launch)
   const float* fwd_depth;
   const float* final_T;
   const uint32_t* n_used;

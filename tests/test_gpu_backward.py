@@ -394,3 +394,39 @@ def test_matrix_core_feature_term_matches_valu(hg, orc, tile):
             log(which, k, rel)
             assert rel < 1e-5, (which, k, rel)
     np.testing.assert_allclose(res["mfma"][2], res["valu"][2], rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_backward_schedules_agree(hg, tile):
+    """The blend backward under its persistent work queues (pose-major and
+    tile-major) gives the grid launch's gradients -- pose, means, opacities
+    and features -- up to float-atomic rounding, for the plain backward and
+    for the residual formed inside it."""
+    import torch
+    sc, P, cam = synth.tiny_scene(600, 70 + tile, width=97, height=71, feat_dim=16, sh_degree=1)
+    Ps = synth.perturb_poses(P[0], 5, 71, 1.0, 2.0)
+    tg = synth.perturb_poses(P[0], 5, 72, 1.0, 2.0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    tgt = hg.Renderer().render(scene, _t(tg), K)
+    tgt = {k: (None if v is None else v.clone()) for k, v in tgt.items()}
+    want = ("pose", "means", "opacities", "feat")
+    res = {}
+    for sched in ("grid", "pose", "tile"):
+        log(f"case: backward schedule {sched}, tile {tile}, 5 poses")
+        r = hg.Renderer()
+        out = r.render(scene, _t(Ps), K, tile=tile, schedule=sched)
+        g = r.backward(dict(rgb=torch.ones_like(out["rgb"]), feat=torch.ones_like(out["feat"])), want=want)
+        g = {k: to_np(v).copy() for k, v in g.items()}
+        r.render(scene, _t(Ps), K, tile=tile, schedule=sched)
+        loss, gr = r.residual_backward(tgt["rgb"], tgt["feat"], want=("pose", "means"))
+        res[sched] = (g, {k: to_np(v).copy() for k, v in gr.items()}, to_np(loss).copy())
+        r.close()
+    g0, r0, l0 = res["grid"]
+    for sched in ("pose", "tile"):
+        g1, r1, l1 = res[sched]
+        for k in want:
+            assert _rel(g1[k], g0[k]) < 1e-5, (sched, k)
+        for k in ("pose", "means"):
+            assert _rel(r1[k], r0[k]) < 1e-5, (sched, "residual", k)
+        assert np.array_equal(l1, l0), (sched, "loss")
