@@ -677,6 +677,14 @@ hgsr_status hgsr_autotune(hgsr_ctx* ctx, const hgsr_gaussians* g, const float* p
                           int32_t with_backward, const char* cache_path, hgsr_tune_result* result,
                           hgsr_stream stream);
 
+/* Measured VALU issue rate, for rooflines of instruction-bound kernels: the
+ * device's rate of wave64 FP32 fused multiply-add instructions (independent
+ * chains, no packed forms) over all its compute units, from one timed
+ * launch on `stream`.  Allocates a small buffer and synchronises the stream
+ * (HGSR_ERR_STATE while it is being captured). */
+hgsr_status hgsr_probe_valu_rate(double* wave_fma_per_s, hgsr_stream stream);
+
+
 /* Stage timing.  While enabled, hgsr_render records HIP events on its
  * stream around its stages (0: projection, 1: tile binning and sort,
  * 2: blend), hgsr_render_backward around its stages (3: blend backward,

@@ -155,6 +155,7 @@ SIGNATURES = {
     "hgsr_debug_tile_lists": [P_, I32, P_, P_, I64, ctypes.POINTER(I64), P_],
     "hgsr_autotune": [P_, ctypes.POINTER(Gaussians), P_, I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(Opts),
                       ctypes.POINTER(Outputs), I32, ctypes.c_char_p, ctypes.POINTER(TuneResult), P_],
+    "hgsr_probe_valu_rate": [ctypes.POINTER(ctypes.c_double), P_],
     "hgsr_profile_enable": [P_, I32],
     "hgsr_profile_read": [P_, P_, P_],
     "hgsr_last_error": [],

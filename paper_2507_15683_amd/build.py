@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgsr.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["project.hip", "binning.hip", "blend.hip", "backward.hip", "refine.hip", "score.hip", "match.hip", "pnp.hip",
-           "pcache.hip", "hgsr_runtime.hip", "host.cpp"]
+           "pcache.hip", "probe.hip", "hgsr_runtime.hip", "host.cpp"]
 
 # No packed-FP32 instructions; no FMA contraction (forward and reverse replay
 # take bit-identical decisions; FMAs are written explicitly).

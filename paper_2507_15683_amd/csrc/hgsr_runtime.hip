@@ -1110,6 +1110,19 @@ hgsr_status hgsr_graph_launch(hgsr_ctx* c, int32_t replays, hgsr_stream stream) 
   return HGSR_OK;
 }
 
+hgsr_status hgsr_probe_valu_rate(double* wave_fma_per_s, hgsr_stream stream) {
+  if (!wave_fma_per_s) return fail(HGSR_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(HGSR_ERR_STATE, "the probe synchronises: not while capturing");
+  int dev = 0, cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(probe_valu_rate(cu > 0 ? cu : 256, s, wave_fma_per_s));
+  return HGSR_OK;
+}
+
 hgsr_status hgsr_profile_enable(hgsr_ctx* c, int32_t enable) {
   if (!c) return fail(HGSR_ERR_INVALID_ARG, "ctx is NULL");
   c->profiling = enable != 0;

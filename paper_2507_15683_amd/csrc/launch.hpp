@@ -223,6 +223,8 @@ void launch_ranges_from_sorted(const uint64_t* keys, const uint32_t* total, uint
 
 // blend.hip
 void launch_loss_reduce(const float* part, int32_t tiles_per_pose, int32_t P, float* loss, hipStream_t s);
+// probe.hip: wave64 FP32 FMA instructions per second the device issues
+hipError_t probe_valu_rate(int n_cu, hipStream_t s, double* wave_fma_per_s);
 void launch_blend_fwd(const BlendArgs& a, int D, bool bf16_out, int n_ctas, hipStream_t s);
 
 // backward.hip
