@@ -28,6 +28,10 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 #define HGSR_MF_GROUP 8
 #endif
 constexpr int kMfGroup = HGSR_MF_GROUP;
+#ifndef HGSR_FEAT_ROUND
+#define HGSR_FEAT_ROUND 4
+#endif
+constexpr int kFeatRound = HGSR_FEAT_ROUND;
 
 template <int TILE, int D, bool BF16, bool MFK>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(BlendArgs a) {
@@ -297,17 +301,21 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_fwd_kernel(B
             if constexpr (D > 0) {
               if constexpr (LDS_F32) {
                 const float4* fsrc = reinterpret_cast<const float4*>(&s_fw[jj * FS]);
-                float4 fq[D / 4];
+                constexpr int FR = (D / 4 > kFeatRound) ? kFeatRound : D / 4;  // float4 reads per round
 #pragma unroll
-                for (int q = 0; q < D / 4; ++q) fq[q] = fsrc[q];
-                __builtin_amdgcn_sched_barrier(0);  // all reads issued before the first FMA
+                for (int q0 = 0; q0 < D / 4; q0 += FR) {
+                  float4 fq[FR];
 #pragma unroll
-                for (int q = 0; q < D / 4; ++q) {
-                  const float4 f = fq[q];
-                  F[k][4 * q + 0] = fmaf(w, f.x, F[k][4 * q + 0]);
-                  F[k][4 * q + 1] = fmaf(w, f.y, F[k][4 * q + 1]);
-                  F[k][4 * q + 2] = fmaf(w, f.z, F[k][4 * q + 2]);
-                  F[k][4 * q + 3] = fmaf(w, f.w, F[k][4 * q + 3]);
+                  for (int q = 0; q < FR; ++q) fq[q] = fsrc[q0 + q];
+                  __builtin_amdgcn_sched_barrier(0);  // the round's reads issued before its FMAs
+#pragma unroll
+                  for (int q = 0; q < FR; ++q) {
+                    const float4 f = fq[q];
+                    F[k][4 * (q0 + q) + 0] = fmaf(w, f.x, F[k][4 * (q0 + q) + 0]);
+                    F[k][4 * (q0 + q) + 1] = fmaf(w, f.y, F[k][4 * (q0 + q) + 1]);
+                    F[k][4 * (q0 + q) + 2] = fmaf(w, f.z, F[k][4 * (q0 + q) + 2]);
+                    F[k][4 * (q0 + q) + 3] = fmaf(w, f.w, F[k][4 * (q0 + q) + 3]);
+                  }
                 }
               } else {
                 const uint4* fq = reinterpret_cast<const uint4*>(&s_fw[jj * FS]);
