@@ -355,34 +355,67 @@ void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_ke
 // tile's bucket (enough waves in flight to hide the atomics' latency).
 constexpr int kEmitLanes = 4;
 
+// The pose's used record slots, compacted: records of sub-segment s occupy
+// the first min(count_s, sub_cap) of its slots; the prefix over the kSub
+// counters maps a compacted index to its slot, so the workgroups walk only
+// records (a grid-stride loop) instead of a grid over the whole capacity, most
+// of whose waves would find empty slots.
+constexpr int kEmitRecsPerBlock = 256 / kEmitLanes;
+constexpr int kEmitBlocksPerPose = 2048;
+
 __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
+  __shared__ uint32_t s_pre[kSub + 1];
   if (a.flags[0] & 1) return;
   const int pose = blockIdx.y;
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t slot = t / kEmitLanes, sub = t % kEmitLanes;
-  if (slot >= a.rec_cap || !rec_in_use(a.pose_count, a.rec_cap, pose, slot)) return;
-  const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
-  const uint2 r = a.rects[idx];
-  const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
-  const float4 geo = rp[0], hdr = rp[1];  // u, v, ca, cb | cc, o, z, gid
-  const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
-  const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
-  const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+  const uint32_t sub_cap = a.rec_cap / kSub;
+  if (threadIdx.x < kWave) {
+    // inclusive scan of the clamped counters over the first kSub lanes
+    const int l = threadIdx.x;
+    uint32_t v = l < kSub ? min(a.pose_count[pose * kSub + l], sub_cap) : 0u;
+#pragma unroll
+    for (int off = 1; off < kSub; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, kWave);
+      if (l >= off) v += u;
+    }
+    if (l < kSub) s_pre[l + 1] = v;
+    if (l == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = s_pre[kSub];
+  const uint32_t sub = threadIdx.x % kEmitLanes;
   const int64_t tbase = static_cast<int64_t>(pose) * a.c.tiles_per_pose;
-  // the record's tiles row by row (the projection counted the same spans);
-  // the kEmitLanes lanes of a record take every kEmitLanes-th tile in order
-  int q = 0;
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    int ta, tb;
-    row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
-    const int first = ta + ((static_cast<int>(sub) - q) % kEmitLanes + kEmitLanes) % kEmitLanes;
-    if (tb >= ta) q += tb - ta + 1;
-    for (int tx = first; tx <= tb; tx += kEmitLanes) {
-      const int64_t tg = tbase + ty * a.c.ntx + tx;
-      const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
-      if (pos < a.key_cap) {
-        a.keys[pos] = key;
-        a.vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+  for (uint32_t c = blockIdx.x * kEmitRecsPerBlock + threadIdx.x / kEmitLanes; c < total;
+       c += gridDim.x * kEmitRecsPerBlock) {
+    // the sub-segment holding compacted record c (binary search of the prefix)
+    int lo = 0, hi = kSub;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t slot = static_cast<uint32_t>(lo) * sub_cap + (c - s_pre[lo]);
+    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
+    const uint2 r = a.rects[idx];
+    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
+    const float4 geo = rp[0], hdr = rp[1];  // u, v, ca, cb | cc, o, z, gid
+    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+    const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    // the record's tiles row by row (the projection counted the same spans);
+    // the kEmitLanes lanes of a record take every kEmitLanes-th tile in order
+    int q = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+      int ta, tb;
+      row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
+      const int first = ta + ((static_cast<int>(sub) - q) % kEmitLanes + kEmitLanes) % kEmitLanes;
+      if (tb >= ta) q += tb - ta + 1;
+      for (int tx = first; tx <= tb; tx += kEmitLanes) {
+        const int64_t tg = tbase + ty * a.c.ntx + tx;
+        const uint64_t pos = static_cast<uint64_t>(a.ranges[tg].x) + atomicAdd(&a.tile_cursor[tg], 1u);
+        if (pos < a.key_cap) {
+          a.keys[pos] = key;
+          a.vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+        }
       }
     }
   }
@@ -449,8 +482,9 @@ void launch_emit_bucket(const BinArgs& a, bool lds, hipStream_t s) {
     hipLaunchKernelGGL(emit_bucket_lds_kernel, grid, dim3(256), a.c.tiles_per_pose * sizeof(uint32_t), s, a);
     return;
   }
-  const dim3 grid((a.rec_cap * kEmitLanes + 255) / 256, a.P);
-  hipLaunchKernelGGL(emit_bucket_kernel, grid, dim3(256), 0, s, a);
+  const uint32_t blocks = std::min<uint32_t>((a.rec_cap + kEmitRecsPerBlock - 1) / kEmitRecsPerBlock,
+                                             static_cast<uint32_t>(kEmitBlocksPerPose));
+  hipLaunchKernelGGL(emit_bucket_kernel, dim3(blocks, a.P), dim3(256), 0, s, a);
 }
 
 // Short lists (<= 256 entries): one wave per tile (4 tiles per workgroup).
