@@ -79,7 +79,7 @@ struct hgsr_ctx {
   // workspace
   Buf recs, rects, rec_keys, rec_offsets, pose_count, tile_count, tile_cursor, ranges, keys0, keys1, vals0, vals1,
       gids0, gids1, list, list_gid, scan_tmp, hist, misc, finalT, nused, part_vis, grad_rec, dbg, loss_part, vis, cand,
-      match, tune, pnp;
+      match, tune, pnp, sig_reg, sig_rng, sig_tmp, sig_pairs, sig_cos;
   int32_t* h_misc = nullptr;  // pinned mirror of the misc block
 
   // the last render
@@ -493,7 +493,7 @@ hgsr_status hgsr_ctx_destroy(hgsr_ctx* c) {
                 &c->tile_cursor, &c->ranges, &c->keys0, &c->keys1, &c->vals0, &c->vals1, &c->gids0,
                 &c->gids1, &c->list, &c->list_gid, &c->scan_tmp, &c->hist, &c->misc, &c->finalT, &c->nused,
                 &c->part_vis, &c->grad_rec, &c->dbg, &c->loss_part, &c->vis, &c->cand, &c->match, &c->tune,
-                &c->pnp};
+                &c->pnp, &c->sig_reg, &c->sig_rng, &c->sig_tmp, &c->sig_pairs, &c->sig_cos};
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->h_misc) (void)hipHostFree(c->h_misc);
@@ -784,7 +784,35 @@ hgsr_status hgsr_significance(hgsr_ctx* c, const hgsr_gaussians* g, const float*
   sa.vis_count = vis_count;
   sa.visible = visible;
   sa.flags = misc + kFlags;
-  launch_score(sa, s);
+  if (maps->layout == HGSR_MAP_PLANAR) {
+    // pairs binned by (view, map region), each region's planes staged once
+    sa.n_rx = (maps->width + kScoreRegionW - 1) / kScoreRegionW;
+    sa.n_ry = (maps->height + kScoreRegionH - 1) / kScoreRegionH;
+    const int64_t nreg = static_cast<int64_t>(P) * sa.n_rx * sa.n_ry;
+    if (nreg >= (1ll << 31)) return fail(HGSR_ERR_INVALID_ARG, "too many (view, map region) pairs: split the views");
+    // every pair is a blended (view, Gaussian): at most one per record slot
+    const int64_t pair_cap = static_cast<int64_t>(P) * c->rec_cap;
+    TRY(ensure(c, c->sig_reg, 2 * nreg * sizeof(uint32_t)));
+    TRY(ensure(c, c->sig_rng, nreg * sizeof(uint2)));
+    TRY(ensure(c, c->sig_tmp, (scan_block_count(nreg) + 32) * sizeof(uint32_t)));
+    TRY(ensure(c, c->sig_pairs, pair_cap * sizeof(uint2)));
+    TRY(ensure(c, c->sig_cos, static_cast<size_t>(nvis) * sizeof(float) + 16));
+    sa.rcount = c->sig_reg.as<uint32_t>();
+    sa.rcursor = c->sig_reg.as<uint32_t>() + nreg;
+    sa.rranges = c->sig_rng.as<uint2>();
+    sa.pairs = c->sig_pairs.as<uint2>();
+    sa.cosb = c->sig_cos.as<float>();
+    launch_fill_u32(c->sig_reg.as<uint32_t>(), 0u, 2 * nreg, s);
+    launch_score_bin(sa, 0, s);
+    uint32_t* tmp = c->sig_tmp.as<uint32_t>();
+    launch_scan(sa.rcount, nreg, nullptr, c->sig_rng.as<uint2>(), tmp + 16, tmp, static_cast<uint64_t>(pair_cap),
+                nullptr, 0, s);
+    launch_score_bin(sa, 1, s);
+    launch_score_regions(sa, s);
+    launch_score_reduce(sa, s);
+  } else {
+    launch_score(sa, s);
+  }
   HIP_TRY(hipGetLastError());
   hipEvent_t e4 = stamp(c, s);
   mark(c, 2, e2, e3);

@@ -185,7 +185,20 @@ struct ScoreArgs {
   uint32_t* vis_count;
   uint8_t* visible;
   const int32_t* flags;
+  // planar maps, scored by map region (kScoreRegionW x kScoreRegionH cells
+  // of one view): pairs binned per region, the region's planes staged in LDS
+  int32_t n_rx, n_ry;        // regions per view along x and y
+  uint32_t* rcount;          // pairs per region
+  uint32_t* rcursor;         // placement cursor per region (zero before the scatter)
+  const uint2* rranges;      // [begin, end) of each region's pairs
+  uint2* pairs;              // (Gaussian, cell within its region) per pair
+  float* cosb;               // per (Gaussian, view), Gaussian-major: the pair's cosine
 };
+
+constexpr int kScoreRegionW = 32;  // cells: a region row is one 128-byte line of a plane
+constexpr int kScoreRegionH = 8;
+constexpr int kScoreSegCells = 8;  // cells: a row segment is one 32-byte sector of a plane
+static_assert(kScoreRegionW * kScoreRegionH / kScoreSegCells == 32, "one bit per row segment of a region");
 
 // project.hip
 void launch_partition_bounds(const GaussArgs& g, float* bounds, hipStream_t s);
@@ -301,6 +314,10 @@ void launch_pose_consistency(const float* poses, int n, float tau_deg, int32_t* 
 // score.hip
 void launch_contrib(const ContribArgs& a, int n_items, hipStream_t s);
 void launch_score(const ScoreArgs& a, hipStream_t s);
+// planar maps by region: count pairs per region (pass 0) or place them (pass 1)
+void launch_score_bin(const ScoreArgs& a, int pass, hipStream_t s);
+void launch_score_regions(const ScoreArgs& a, hipStream_t s);
+void launch_score_reduce(const ScoreArgs& a, hipStream_t s);
 void launch_score_final(const float* sum, const uint32_t* count, int64_t n, float* score, hipStream_t s);
 
 // refine.hip

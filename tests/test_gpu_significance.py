@@ -244,3 +244,42 @@ def test_full_size_64_views_sampled(hg, sg):
     assert (d <= SUM_TOL * np.maximum(cnt[~shaky], 1)).all()
     assert vis.sum() > 1_000_000
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("D,Wf,Hf", [(8, 83, 61), (16, 64, 48), (32, 97, 33), (64, 40, 9)])
+def test_planar_regions_equal_interleaved(hg, D, Wf, Hf):
+    """Planar maps are scored by map region (pairs binned by view and 32x8
+    cells, the region's planes staged in LDS); channels-last maps by one
+    gather per pair.  Same cosines, same order: the sums, counts and
+    visibility flags are equal bit for bit, on map sizes that leave ragged
+    regions at the right and bottom edges."""
+    sc, P, cam = synth.tiny_scene(700, 60 + D, width=96, height=72, feat_dim=D, sh_degree=1)
+    poses = _views(P[0], 19, 61 + D, 1.5, 3.0)
+    maps = synth.feature_maps(19, D, Hf, Wf, 62 + D)
+    g = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    log(f"case: D {D}, 19 views, maps {Wf}x{Hf}: planar (regions) against interleaved")
+    a = hg.Renderer().significance(g, _t(poses), K, _t(maps), want_visible=True, layout="planar", tile=16)
+    b = hg.Renderer().significance(g, _t(poses), K, _t(np.ascontiguousarray(maps.transpose(0, 2, 3, 1))),
+                                   want_visible=True, layout="interleaved", tile=16)
+    for k in ("score_sum", "vis_count", "visible", "score"):
+        x, y = a[k].cpu().numpy(), b[k].cpu().numpy()
+        assert np.array_equal(x, y), (k, np.argwhere(x != y)[:5])
+    log("visible pairs", int(a["visible"].sum().item()), "gaussians seen", int((a["vis_count"] > 0).sum().item()))
+
+
+def test_planar_regions_equal_interleaved_full_size(hg):
+    """The 1M-Gaussian, 64-view batch of the benchmark: planar and
+    channels-last maps give the same sums, counts and flags bit for bit."""
+    import torch
+    sc, poses, cam = synth.aerial_1m_64_views(0)
+    maps = synth.feature_maps(64, 32, 270, 480, 3100)
+    g = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    log("case: 1M Gaussians, 64 views, maps 480x270: planar (regions) against interleaved")
+    a = hg.Renderer().significance(g, _t(poses), K, _t(maps), want_visible=True, tile=16)
+    il = _t(np.ascontiguousarray(maps.transpose(0, 2, 3, 1)))
+    b = hg.Renderer().significance(g, _t(poses), K, il, want_visible=True, layout="interleaved", tile=16)
+    for k in ("score_sum", "vis_count", "visible"):
+        assert torch.equal(a[k], b[k]), k
+    torch.cuda.synchronize()
