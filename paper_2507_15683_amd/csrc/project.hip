@@ -114,18 +114,30 @@ struct BlockHist {
   int tx0, ty0, w;
 };
 
+// SH colour (Sec. 3.1) of Gaussian i seen from the camera of pose T: the
+// basis evaluated at the unit direction from the camera centre to the mean.
 template <int DEG>
-__device__ __forceinline__ void write_record(const ProjectArgs& a, int64_t i, const float mu[3], float o, float k2,
-                                             const float* T, int pg, const float mc[3], const Footprint& f,
-                                             uint32_t slot, const BlockHist& hist) {
+__device__ __forceinline__ void view_colour(const ProjectArgs& a, int64_t i, const float mu[3], const float* T,
+                                            float rgb[3]) {
   const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
   const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
   const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
   float dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
   const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
   dx *= inv; dy *= inv; dz *= inv;
-  float rgb[3];
   sh_colour_raw<DEG>(a.g.sh, i, dx, dy, dz, rgb);
+}
+
+template <int DEG>
+__device__ __forceinline__ void write_record(const ProjectArgs& a, int64_t i, const float mu[3], float o, float k2,
+                                             const float* T, int pg, const float mc[3], const Footprint& f,
+                                             uint32_t slot, const BlockHist& hist, const float* rgb_in = nullptr) {
+  float rgb[3];
+  if (rgb_in) {
+    rgb[0] = rgb_in[0]; rgb[1] = rgb_in[1]; rgb[2] = rgb_in[2];
+  } else {
+    view_colour<DEG>(a, i, mu, T, rgb);
+  }
   const int64_t idx = static_cast<int64_t>(pg) * a.rec_cap + slot;
   Splat sp;
   sp.u = f.u; sp.v = f.v; sp.ca = f.ca; sp.cb = f.cb;
@@ -172,6 +184,8 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
   __shared__ uint32_t s_hist[kProjHist];
   __shared__ int s_rect[4];                     // tile rectangle of the block's records (one pose)
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const uint64_t lanes_below = (uint64_t{1} << lane) - 1u;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kProjBlockItems;
   if (range_culled(a, base, min(base + kProjBlockItems, a.g.n) - 1)) return;
   for (int p = tid; p < a.P; p += 256) s_cnt[p] = 0;
@@ -180,16 +194,27 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
     s_rect[0] = s_rect[1] = 0x7fffffff;
     s_rect[2] = s_rect[3] = -1;
   }
-
-  // phase A: the cheap tests
-  float o[kProjPerThread];
-  uint64_t pose_ok[kProjPerThread];
-  bool live[kProjPerThread];
+  // opacity, mean and largest log-scale in one round of loads (not gated on
+  // the opacity test: a dependent round costs more than the few bytes of
+  // the Gaussians that test drops)
+  float o[kProjPerThread], mu[kProjPerThread][3], lsm[kProjPerThread];
 #pragma unroll
   for (int q = 0; q < kProjPerThread; ++q) {
     const int64_t i = base + q * 256 + tid;
-    o[q] = i < a.g.n ? a.g.opac[i] : 0.f;
+    o[q] = 0.f;
+    mu[q][0] = mu[q][1] = mu[q][2] = lsm[q] = 0.f;
+    if (i < a.g.n) {
+      o[q] = a.g.opac[i];
+      mu[q][0] = a.g.means[3 * i];
+      mu[q][1] = a.g.means[3 * i + 1];
+      mu[q][2] = a.g.means[3 * i + 2];
+      lsm[q] = fmaxf(a.g.log_scales[3 * i], fmaxf(a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]));
+    }
   }
+
+  // phase A: the cheap tests
+  uint64_t pose_ok[kProjPerThread];
+  bool live[kProjPerThread];
 #pragma unroll
   for (int q = 0; q < kProjPerThread; ++q) {
     const int64_t i = base + q * 256 + tid;
@@ -205,42 +230,44 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
       live[q] = ok != 0;
     }
   }
-  float mu[kProjPerThread][3], lsm[kProjPerThread];
-#pragma unroll
-  for (int q = 0; q < kProjPerThread; ++q) {
-    const int64_t i = base + q * 256 + tid;
-    if (live[q]) {
-      mu[q][0] = a.g.means[3 * i];
-      mu[q][1] = a.g.means[3 * i + 1];
-      mu[q][2] = a.g.means[3 * i + 2];
-      lsm[q] = fmaxf(a.g.log_scales[3 * i], fmaxf(a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]));
-    }
-  }
   __syncthreads();  // s_nc and s_cnt cleared
 #pragma unroll
   for (int q = 0; q < kProjPerThread; ++q) {
-    if (!live[q]) continue;
-    const float s2max = __expf(2.f * lsm[q]);
-    const float k2 = 2.f * __logf(255.f * o[q]);
     uint64_t cand = 0;
-    for (int p = 0; p < a.P; ++p) {
-      if (!((pose_ok[q] >> p) & 1ull)) continue;
-      const float* T = a.poses + 12 * (a.pose_base + p);
-      float mc[3];
-      to_camera(T, mu[q], mc);
-      if (!(mc[2] > a.c.near_z)) continue;
-      if (maybe_visible(mc, s2max, k2, a.c)) cand |= 1ull << p;
+    if (live[q]) {
+      const float s2max = __expf(2.f * lsm[q]);
+      const float k2 = 2.f * __logf(255.f * o[q]);
+      for (int p = 0; p < a.P; ++p) {
+        if (!((pose_ok[q] >> p) & 1ull)) continue;
+        const float* T = a.poses + 12 * (a.pose_base + p);
+        float mc[3];
+        to_camera(T, mu[q], mc);
+        if (!(mc[2] > a.c.near_z)) continue;
+        if (maybe_visible(mc, s2max, k2, a.c)) cand |= 1ull << p;
+      }
     }
-    if (cand) {
-      const uint32_t e = atomicAdd(&s_nc, 1u);
-      s_idx[e] = static_cast<uint32_t>(q * 256 + tid);
-      s_mask[e] = cand;
+    // appended per wave: one LDS atomic, each lane at its rank
+    const uint64_t bal = __ballot(cand != 0);
+    if (bal) {
+      const int leader = __builtin_ctzll(bal);
+      uint32_t wbase = 0;
+      if (lane == leader) wbase = atomicAdd(&s_nc, static_cast<uint32_t>(__popcll(bal)));
+      wbase = __shfl(wbase, leader, kWave);
+      if (cand) {
+        const uint32_t e = wbase + static_cast<uint32_t>(__popcll(bal & lanes_below));
+        s_idx[e] = static_cast<uint32_t>(q * 256 + tid);
+        s_mask[e] = cand;
+      }
     }
   }
   __syncthreads();
   const uint32_t nc = s_nc;
+  if (nc == 0) return;  // uniform: no candidate, nothing counted or written
 
   // phase B: exact footprints on the compacted candidates, counted per pose
+  // (per wave first: an LDS atomic from every lane on one address would be
+  // performed one lane after another)
+  int rect[4] = {0x7fffffff, 0x7fffffff, -1, -1};  // one pose: tile rectangle of this lane's records
   uint64_t vis[kProjPerThread];
   // one Gaussian per thread and one pose: phase C reuses phase B's footprint
   constexpr bool kKeep = G == 1;
@@ -266,7 +293,6 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
       to_camera(T, m, mc);
       Footprint f;
       if (footprint(T, mc, S, k2, a.c, f)) {
-        atomicAdd(&s_cnt[p], 1u);
         vis[k] |= 1ull << p;
         if (kKeep && a.P == 1) {
           for (int c = 0; c < 3; ++c) {
@@ -278,12 +304,32 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
           keep_f = f;
         }
         if (a.P == 1) {
-          atomicMin(&s_rect[0], f.px0 >> a.c.tile_shift);
-          atomicMin(&s_rect[1], f.py0 >> a.c.tile_shift);
-          atomicMax(&s_rect[2], f.px1 >> a.c.tile_shift);
-          atomicMax(&s_rect[3], f.py1 >> a.c.tile_shift);
+          rect[0] = min(rect[0], f.px0 >> a.c.tile_shift);
+          rect[1] = min(rect[1], f.py0 >> a.c.tile_shift);
+          rect[2] = max(rect[2], f.px1 >> a.c.tile_shift);
+          rect[3] = max(rect[3], f.py1 >> a.c.tile_shift);
         }
       }
+    }
+  }
+  for (int p = 0; p < a.P; ++p) {  // uniform: every lane of the wave
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kProjPerThread; ++k) cnt += static_cast<uint32_t>(__popcll(__ballot((vis[k] >> p) & 1ull)));
+    if (lane == 0 && cnt) atomicAdd(&s_cnt[p], cnt);
+  }
+  if (a.P == 1) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      rect[0] = min(rect[0], __shfl_xor(rect[0], off, kWave));
+      rect[1] = min(rect[1], __shfl_xor(rect[1], off, kWave));
+      rect[2] = max(rect[2], __shfl_xor(rect[2], off, kWave));
+      rect[3] = max(rect[3], __shfl_xor(rect[3], off, kWave));
+    }
+    if (lane == 0 && rect[2] >= 0) {
+      atomicMin(&s_rect[0], rect[0]);
+      atomicMin(&s_rect[1], rect[1]);
+      atomicMax(&s_rect[2], rect[2]);
+      atomicMax(&s_rect[3], rect[3]);
     }
   }
   __syncthreads();
@@ -309,41 +355,49 @@ __global__ __launch_bounds__(256) void project_dense_kernel(ProjectArgs a) {
   __syncthreads();
 
   // phase C: the records (footprints recomputed from the same inputs, or
-  // kept from phase B)
+  // kept from phase B), in slots the wave takes together: one LDS atomic per
+  // wave and pose, each lane's slot at its rank among the wave's records
 #pragma unroll
   for (int k = 0; k < kProjPerThread; ++k) {
-    if (!vis[k]) continue;
     const uint32_t e = static_cast<uint32_t>(k * 256 + tid);
-    const int64_t i = base + s_idx[e];
-    if (kKeep && a.P == 1) {
-      const uint32_t local = s_base[0] + atomicAdd(&s_cnt[0], 1u);
+    int64_t i = 0;
+    float m[3] = {0.f, 0.f, 0.f}, oo = 0.f, k2 = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const bool keep = kKeep && a.P == 1;
+    if (vis[k]) {
+      i = base + s_idx[e];
+      if (!keep) {
+        m[0] = a.g.means[3 * i]; m[1] = a.g.means[3 * i + 1]; m[2] = a.g.means[3 * i + 2];
+        const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
+        oo = a.g.opac[i];
+        k2 = 2.f * __logf(255.f * oo);
+        cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
+      }
+    }
+    for (int p = 0; p < a.P; ++p) {  // uniform: every lane of the wave
+      const bool has = (vis[k] >> p) & 1ull;
+      const uint64_t bal = __ballot(has);
+      if (bal == 0) continue;
+      const int leader = __builtin_ctzll(bal);
+      uint32_t wbase = 0;
+      if (lane == leader) wbase = atomicAdd(&s_cnt[p], static_cast<uint32_t>(__popcll(bal)));
+      wbase = __shfl(wbase, leader, kWave);
+      if (!has) continue;
+      const uint32_t local = s_base[p] + wbase + static_cast<uint32_t>(__popcll(bal & lanes_below));
       if (local >= sub_cap) {
         atomicOr(a.flags, 1);
         continue;
       }
-      write_record<DEG>(a, i, keep_m, keep_o, keep_k2, a.poses + 12 * a.pose_base, a.pose_base, keep_mc, keep_f,
-                        sub * sub_cap + local, hist);
-      continue;
-    }
-    const float m[3] = {a.g.means[3 * i], a.g.means[3 * i + 1], a.g.means[3 * i + 2]};
-    const float ls[3] = {a.g.log_scales[3 * i], a.g.log_scales[3 * i + 1], a.g.log_scales[3 * i + 2]};
-    const float oo = a.g.opac[i];
-    const float k2 = 2.f * __logf(255.f * oo);
-    float S[6];
-    cov3_from(reinterpret_cast<const float4*>(a.g.quats)[i], ls, S);
-    for (int p = 0; p < a.P; ++p) {
-      if (!((vis[k] >> p) & 1ull)) continue;
+      if (keep) {
+        write_record<DEG>(a, i, keep_m, keep_o, keep_k2, a.poses + 12 * a.pose_base, a.pose_base, keep_mc, keep_f,
+                          sub * sub_cap + local, hist);
+        continue;
+      }
       const int pg = a.pose_base + p;
       const float* T = a.poses + 12 * pg;
       float mc[3];
       to_camera(T, m, mc);
       Footprint f;
       footprint(T, mc, S, k2, a.c, f);
-      const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
-      if (local >= sub_cap) {
-        atomicOr(a.flags, 1);
-        continue;
-      }
       write_record<DEG>(a, i, m, oo, k2, T, pg, mc, f, sub * sub_cap + local, hist);
     }
   }
