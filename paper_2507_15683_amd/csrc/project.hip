@@ -457,18 +457,22 @@ __global__ __launch_bounds__(256) void cull_kernel(ProjectArgs a) {
     k2 = 2.f * __logf(255.f * o);
   }
   __syncthreads();
+  // counted per wave and pose (an LDS atomic from every lane on one address
+  // would be performed one lane after another)
+  const int lane = tid & (kWave - 1);
+  const uint64_t lanes_below = (uint64_t{1} << lane) - 1u;
   uint64_t cand = 0;
-  if (live) {
-    for (int p = 0; p < a.P; ++p) {
-      if (!((pose_ok >> p) & 1ull)) continue;
+  for (int p = 0; p < a.P; ++p) {  // uniform: every lane of the wave
+    bool ok = false;
+    if (live && ((pose_ok >> p) & 1ull)) {
       const float* T = a.poses + 12 * (a.pose_base + p);
       float mc[3];
       to_camera(T, mu, mc);
-      if (!(mc[2] > a.c.near_z)) continue;
-      if (!maybe_visible(mc, s2max, k2, a.c)) continue;
-      atomicAdd(&s_cnt[p], 1u);
-      cand |= 1ull << p;
+      ok = mc[2] > a.c.near_z && maybe_visible(mc, s2max, k2, a.c);
     }
+    const uint64_t bal = __ballot(ok);
+    if (lane == 0 && bal) atomicAdd(&s_cnt[p], static_cast<uint32_t>(__popcll(bal)));
+    if (ok) cand |= 1ull << p;
   }
   __syncthreads();
   const int sub = static_cast<int>(blockIdx.x % kSub);
@@ -479,10 +483,26 @@ __global__ __launch_bounds__(256) void cull_kernel(ProjectArgs a) {
     s_cnt[p] = 0;
   }
   __syncthreads();
-  while (cand) {
-    const int p = __builtin_ctzll(cand);
-    cand &= cand - 1ull;
-    const uint32_t local = s_base[p] + atomicAdd(&s_cnt[p], 1u);
+  // each pose's candidates take their slots per wave: one LDS atomic, each
+  // lane at its rank
+  uint64_t wave_cand = cand;  // OR over the wave (butterfly)
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const uint64_t other =
+        (static_cast<uint64_t>(__shfl_xor(static_cast<uint32_t>(wave_cand >> 32), off, kWave)) << 32) |
+        __shfl_xor(static_cast<uint32_t>(wave_cand), off, kWave);
+    wave_cand |= other;
+  }
+  while (wave_cand) {  // uniform: the poses any lane of the wave keeps
+    const int p = __builtin_ctzll(wave_cand);
+    wave_cand &= wave_cand - 1ull;
+    const bool has = (cand >> p) & 1ull;
+    const uint64_t bal = __ballot(has);
+    const int leader = __builtin_ctzll(bal);
+    uint32_t wbase = 0;
+    if (lane == leader) wbase = atomicAdd(&s_cnt[p], static_cast<uint32_t>(__popcll(bal)));
+    wbase = __shfl(wbase, leader, kWave);
+    if (!has) continue;
+    const uint32_t local = s_base[p] + wbase + static_cast<uint32_t>(__popcll(bal & lanes_below));
     if (local >= sub_cap) {
       atomicOr(a.flags, 1);
       continue;
@@ -527,9 +547,16 @@ __global__ __launch_bounds__(kSplatBlock) void splat_kernel(ProjectArgs a) {
     to_camera(T, mu, mc);
     vis = footprint(T, mc, S, k2, a.c, f);
   }
-  __syncthreads();
+  // slots taken per wave (one LDS atomic, each lane at its rank)
+  const int lane = tid & (kWave - 1);
+  __syncthreads();  // s_cnt cleared
+  const uint64_t bal = __ballot(vis);
   uint32_t local = 0;
-  if (vis) local = atomicAdd(&s_cnt, 1u);
+  if (bal) {
+    const int leader = __builtin_ctzll(bal);
+    if (lane == leader) local = atomicAdd(&s_cnt, static_cast<uint32_t>(__popcll(bal)));
+    local = __shfl(local, leader, kWave) + static_cast<uint32_t>(__popcll(bal & ((uint64_t{1} << lane) - 1u)));
+  }
   __syncthreads();
   // records go to one of the pose's kSub record sub-segments, picked by
   // block index, so that the reservation atomics spread over kSub addresses
