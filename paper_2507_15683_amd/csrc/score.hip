@@ -338,7 +338,10 @@ __global__ __launch_bounds__(256) void score_region_kernel(ScoreArgs a) {
   {
     uint32_t used = first ? 1u << (pr0.y / kScoreSegCells) : 0u;
     for (uint32_t q = q0 + 256; q < range.y; q += 256) used |= 1u << (a.pairs[q].y / kScoreSegCells);
-    if (used) atomicOr(s_seg, used);
+    // OR over the wave first: one LDS atomic per wave, not one per lane on
+    // the same word (those are performed one lane after another)
+    for (int off = kWave / 2; off > 0; off >>= 1) used |= __shfl_xor(used, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && used) atomicOr(s_seg, used);
   }
   __syncthreads();
   const uint32_t seg = *s_seg;
