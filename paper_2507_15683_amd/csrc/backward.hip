@@ -34,7 +34,10 @@ constexpr int kHGroup = 32;
 // significant bits), so the products are exact and only the summation order
 // differs from the FP32 dot product.  H goes to LDS, where the walk reads its
 // pixel's value of each splat.
-template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH>
+// PO (pose only, residual loss): the opacity and depth sums are not formed
+// (the residual has no depth term and no opacity gradient was asked for),
+// eight sums per splat instead of ten.
+template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH, bool PO>
 __device__ __forceinline__ void blend_bwd_item(const BackArgs& a, const int item) {
   using Sh = BlendShape<TILE>;
   constexpr int NT = Sh::kThreads, NB = Sh::kBatch, NW = Sh::kWaves, BW = Sh::kBlockW, BH = Sh::kBlockH;
@@ -356,11 +359,11 @@ __device__ __forceinline__ void blend_bwd_item(const BackArgs& a, const int item
         g[7] = fmaf(w, gC[k][0], g[7]);
         g[8] = fmaf(w, gC[k][1], g[8]);
         g[9] = fmaf(w, gC[k][2], g[9]);
-        g[6] = fmaf(w, GZ[k], g[6]);
+        if constexpr (!PO) g[6] = fmaf(w, GZ[k], g[6]);
         if (opz.y * G <= kAlphaMax) {
           const float dpow = dA * alpha;
           const float hx = -0.5f * dpow * dx, hy = -0.5f * dpow * dy;
-          g[5] = fmaf(dA, G, g[5]);
+          if constexpr (!PO) g[5] = fmaf(dA, G, g[5]);
           g[0] = fmaf(dpow, fmaf(geo.z, dx, geo.w * dy), g[0]);
           g[1] = fmaf(dpow, fmaf(geo.w, dx, opz.x * dy), g[1]);
           g[2] = fmaf(hx, dx, g[2]);
@@ -373,7 +376,8 @@ __device__ __forceinline__ void blend_bwd_item(const BackArgs& a, const int item
         }
       }
       if (!__any(any)) continue;
-      wave_add10(g, s_g[jj]);
+      if constexpr (PO) wave_add8(g, s_g[jj]);
+      else wave_add10(g, s_g[jj]);
       if constexpr (FEATGRAD) {
 #pragma unroll
         for (int d = 0; d < DD; ++d) gfe[d] = wave_sum(gfe[d]);
@@ -400,7 +404,7 @@ __device__ __forceinline__ void blend_bwd_item(const BackArgs& a, const int item
 // One workgroup per (pose, tile) item, or (PERSIST) a grid of workgroups
 // claiming runs of kQueueChunk items from a device counter until it passes
 // the item count.
-template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH, bool PERSIST>
+template <int TILE, int D, bool FEATGRAD, bool RES, bool MFH, bool PERSIST, bool PO = false>
 __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(BackArgs a) {
   if (a.flags[0] & 3) return;
   if constexpr (PERSIST) {
@@ -413,12 +417,12 @@ __global__ __launch_bounds__(BlendShape<TILE>::kThreads) void blend_bwd_kernel(B
       if (first >= a.n_items) break;
       const int last = min(first + kQueueChunk, a.n_items);
       for (int item = first; item < last; ++item) {
-        blend_bwd_item<TILE, D, FEATGRAD, RES, MFH>(a, item);
+        blend_bwd_item<TILE, D, FEATGRAD, RES, MFH, PO>(a, item);
         __syncthreads();  // the item's LDS is reused by the next one
       }
     }
   } else {
-    blend_bwd_item<TILE, D, FEATGRAD, RES, MFH>(a, xcd_item(blockIdx.x, gridDim.x));
+    blend_bwd_item<TILE, D, FEATGRAD, RES, MFH, PO>(a, xcd_item(blockIdx.x, gridDim.x));
   }
 }
 
@@ -454,6 +458,9 @@ static void launch_bwd_tdp(const BackArgs& a, int items, hipStream_t s) {
       hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, true, true, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
     else if (mf)
       hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, MFOK, PERSIST>), dim3(items), dim3(NT), 0, s, a);
+    else if (a.pose_only)
+      hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, false, PERSIST, true>), dim3(items), dim3(NT), 0, s,
+                         a);
     else
       hipLaunchKernelGGL((blend_bwd_kernel<TILE, D, false, true, false, PERSIST>), dim3(items), dim3(NT), 0, s, a);
   } else {

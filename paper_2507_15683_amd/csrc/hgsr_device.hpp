@@ -124,6 +124,30 @@ __device__ __forceinline__ void wave_add10(const float g[10], float* dst) {
   }
 }
 
+// The same for eight of the ten sums (0-4 and 7-9; 5 and 6 are left alone):
+// each value meets the same reduction tree as in wave_add10 (lane pairs 32
+// apart, then 16 apart, then a row sum), so the eight results have the same
+// bits.
+__device__ __forceinline__ void wave_add8(const float g[10], float* dst) {
+  const float lo[4] = {g[0], g[1], g[2], g[3]}, hi[4] = {g[4], g[7], g[8], g[9]};
+  float b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo[i]), __float_as_uint(hi[i]), false, false);
+    b[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  }
+  const auto s0 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[0]), __float_as_uint(b[1]), false, false);
+  const auto s1 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[2]), __float_as_uint(b[3]), false, false);
+  const float c0 = row_sum16(__uint_as_float(s0[0]) + __uint_as_float(s0[1]));
+  const float c1 = row_sum16(__uint_as_float(s1[0]) + __uint_as_float(s1[1]));
+  const int lane = threadIdx.x & (kWave - 1);
+  if ((lane & 15) == 0) {
+    const int half = lane >> 5, odd = (lane >> 4) & 1;
+    atomicAdd(dst + (half ? (odd ? 7 : 4) : odd), c0);       // g0, g1 | g4, g7
+    atomicAdd(dst + (half ? (odd ? 9 : 8) : 2 + odd), c1);   // g2, g3 | g8, g9
+  }
+}
+
 // World covariance Sigma_w = R_q diag(exp(2 ls)) R_q^T, (w,x,y,z) quaternion
 // normalised here.  Returns xx, xy, xz, yy, yz, zz.
 __device__ __forceinline__ void cov3_from(const float4 q4, const float ls[3], float S[6]) {

@@ -1250,6 +1250,7 @@ static hgsr_status backward_impl(hgsr_ctx* c, const hgsr_grad_outputs* go, const
   b.res_lam = rt ? rt->lam_f : 0.f;
   b.res_inv_hw = 1.f / static_cast<float>(static_cast<int64_t>(c->cam.W) * c->cam.H);
   b.res_part = c->loss_part.as<float>();
+  b.pose_only = rt && !gr->opacities ? 1 : 0;
   b.schedule = c->opts.schedule;
   b.n_items = static_cast<int32_t>(static_cast<int64_t>(P) * c->cam.tiles_per_pose);
   b.n_ctas = static_cast<int32_t>(std::min<int64_t>(b.n_items, persistent_ctas(c, c->cam.tile)));

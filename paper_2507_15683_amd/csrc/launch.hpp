@@ -107,6 +107,9 @@ struct BackArgs {
   const uint16_t* feat;
   int32_t D;
   float bg[3];
+  // residual loss and no per-Gaussian opacity gradient asked for: the
+  // blend backward forms eight of the ten per-splat sums (no opacity or depth)
+  int32_t pose_only;
   int32_t schedule;          // kSchedGrid, or a persistent queue of (pose, tile) items
   int32_t n_items;
   int32_t n_ctas;            // workgroups of the persistent launch

@@ -339,6 +339,33 @@ def test_residual_backward_matches_separate(hg, orc, D, tile, bf16):
     assert _rel(to_np(gb["means"]), ga["means"]) < 1e-5
 
 
+@pytest.mark.parametrize("tile", [8, 16])
+def test_pose_only_residual_backward_matches_full(hg, tile):
+    """Without an opacity gradient the residual backward forms eight
+    per-splat sums instead of ten (no opacity or depth sum): the loss is
+    bitwise that of the full form, pose and mean gradients agree to
+    float-atomic rounding."""
+    import torch
+    sc, P, cam = synth.tiny_scene(700, 91, width=97, height=66, feat_dim=32, sh_degree=3)
+    Ps = synth.perturb_poses(P[0], 3, 92, 1.0, 2.0)
+    tg = synth.perturb_poses(P[0], 3, 93, 1.0, 2.0)
+    scene = hg.GaussianScene.from_numpy(sc)
+    K = hg.Intrinsics.of(cam)
+    tgt = hg.Renderer().render(scene, _t(tg), K)
+    tgt = {k: (None if v is None else v.clone()) for k, v in tgt.items()}
+    log(f"case: pose-only residual backward tile={tile}")
+    r = hg.Renderer()
+    r.render(scene, _t(Ps), K, tile=tile, feat_accum="valu")
+    lf, gf = r.residual_backward(tgt["rgb"], tgt["feat"], want=("pose", "means", "opacities"))
+    lf = lf.clone()
+    gf = {k: to_np(v).copy() for k, v in gf.items()}
+    lp, gp = r.residual_backward(tgt["rgb"], tgt["feat"], want=("pose", "means"))
+    assert torch.equal(lf, lp)
+    assert np.abs(gf["opacities"]).max() > 0
+    assert _rel(to_np(gp["pose"]), gf["pose"]) < 1e-5
+    assert _rel(to_np(gp["means"]), gf["means"]) < 1e-5
+
+
 def test_residual_backward_shared_target(hg):
     """One target shared by all poses gives what the same target replicated
     per pose gives (loss bitwise, gradients to float-atomic rounding)."""
