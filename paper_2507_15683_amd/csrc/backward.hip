@@ -551,16 +551,33 @@ __device__ __forceinline__ void sh_grad_dir(const float* c, float x, float y, fl
   }
 }
 
+// The Gaussian's SH coefficients (3 (DEG+1)^2 floats), read once for the
+// colour and its direction gradient (16-byte loads when the array allows).
 template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
+__device__ __forceinline__ void load_sh(const float* sh, int64_t i, float* v) {
+  constexpr int N = 3 * (DEG + 1) * (DEG + 1);
+  const float* c = sh + static_cast<int64_t>(N) * i;
+  if constexpr (N % 4 == 0) {
+    if ((reinterpret_cast<uintptr_t>(sh) & 15) == 0) {
+#pragma unroll
+      for (int q = 0; q < N / 4; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(c)[q];
+        v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = c[k];
+}
+
+// One record's gradients: the pose tangent's six components are added to gp;
+// GAUSS: the Gaussian's own gradients (means, opacity, scales, rotation, SH)
+// where their arrays are given.
+template <int DEG, bool GAUSS>
+__device__ __forceinline__ void record_grad(const ProjBackArgs& a, const int pose, const uint32_t slot, float gp[6]) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  __shared__ float s_red[6][256];
-  const int pose = blockIdx.y;
-  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const bool ok = !(a.flags[0] & 3);
-  const bool use = ok && slot < a.rec_cap && rec_in_use(a.pose_count, a.rec_cap, pose, slot);
-  if (use) {
+  {
     const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
     const float* gr = a.g_rec + idx * kGradRecStride;
     const float g_u = gr[0], g_v = gr[1], g_ca = gr[2], g_cb = gr[3], g_cc = gr[4], g_o = gr[5], g_z = gr[6];
@@ -651,17 +668,27 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
     float dir[3] = {mu[0] - Cx, mu[1] - Cy, mu[2] - Cz};
     const float inv = rsqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
     const float n0 = dir[0] * inv, n1 = dir[1] * inv, n2 = dir[2] * inv;
-    float raw[3];
-    sh_colour_raw<DEG>(a.g.sh, i, n0, n1, n2, raw);
+    // the forward's unclamped colour (the sums of sh_colour_raw, in its
+    // order), from coefficients read once
+    float shv[3 * K];
+    load_sh<DEG>(a.g.sh, i, shv);
+    float Y[K];
+    sh_basis<DEG>(n0, n1, n2, Y);
+    float raw[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      raw[0] = fmaf(shv[3 * k + 0], Y[k], raw[0]);
+      raw[1] = fmaf(shv[3 * k + 1], Y[k], raw[1]);
+      raw[2] = fmaf(shv[3 * k + 2], Y[k], raw[2]);
+    }
     float graw[3];
     for (int c2 = 0; c2 < 3; ++c2) graw[c2] = raw[c2] > 0.f ? gcol[c2] : 0.f;
     float gdir[3] = {0.f, 0.f, 0.f};
     if constexpr (DEG >= 1) {
-      const float* shc = a.g.sh + static_cast<int64_t>(K) * 3 * i;
       for (int c2 = 0; c2 < 3; ++c2) {
         if (graw[c2] == 0.f) continue;
         float cch[K];
-        for (int k = 0; k < K; ++k) cch[k] = shc[3 * k + c2];
+        for (int k = 0; k < K; ++k) cch[k] = shv[3 * k + c2];
         float gg[3];
         sh_grad_dir<DEG>(cch, n0, n1, n2, gg);
         const float nd = gg[0] * n0 + gg[1] * n1 + gg[2] * n2;
@@ -670,23 +697,21 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
         gdir[2] += graw[c2] * (gg[2] - n2 * nd) * inv;
       }
     }
-    if (a.g_sh) {
-      float Y[K];
-      sh_basis<DEG>(n0, n1, n2, Y);
+    if (GAUSS && a.g_sh) {
       float* gs = a.g_sh + static_cast<int64_t>(K) * 3 * i;
       for (int k = 0; k < K; ++k)
         for (int c2 = 0; c2 < 3; ++c2)
           if (graw[c2] != 0.f) atomicAdd(gs + 3 * k + c2, graw[c2] * Y[k]);
     }
     // Gaussian gradients
-    if (a.g_means) {
+    if (GAUSS && a.g_means) {
       for (int c2 = 0; c2 < 3; ++c2) {
         const float gm = Pm[c2] * gmc[0] + Pm[4 + c2] * gmc[1] + Pm[8 + c2] * gmc[2] + gdir[c2];
         atomicAdd(a.g_means + 3 * i + c2, gm);
       }
     }
-    if (a.g_opac) atomicAdd(a.g_opac + i, g_o);
-    if (a.g_log_scales || a.g_quats) {
+    if (GAUSS && a.g_opac) atomicAdd(a.g_opac + i, g_o);
+    if (GAUSS && (a.g_log_scales || a.g_quats)) {
       // dL/dSigma_w = M^T Gs M
       float Gw[3][3];
       for (int r = 0; r < 3; ++r)
@@ -727,22 +752,63 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
       }
     }
     // pose tangent (rho, phi)
-    gp[0] = gmc[0] + Pm[0] * gdir[0] + Pm[1] * gdir[1] + Pm[2] * gdir[2];
-    gp[1] = gmc[1] + Pm[4] * gdir[0] + Pm[5] * gdir[1] + Pm[6] * gdir[2];
-    gp[2] = gmc[2] + Pm[8] * gdir[0] + Pm[9] * gdir[1] + Pm[10] * gdir[2];
-    gp[3] = (y * gmc[2] - z * gmc[1]) + (B[1][2] - B[2][1]);
-    gp[4] = (z * gmc[0] - x * gmc[2]) + (B[2][0] - B[0][2]);
-    gp[5] = (x * gmc[1] - y * gmc[0]) + (B[0][1] - B[1][0]);
+    gp[0] += gmc[0] + Pm[0] * gdir[0] + Pm[1] * gdir[1] + Pm[2] * gdir[2];
+    gp[1] += gmc[1] + Pm[4] * gdir[0] + Pm[5] * gdir[1] + Pm[6] * gdir[2];
+    gp[2] += gmc[2] + Pm[8] * gdir[0] + Pm[9] * gdir[1] + Pm[10] * gdir[2];
+    gp[3] += (y * gmc[2] - z * gmc[1]) + (B[1][2] - B[2][1]);
+    gp[4] += (z * gmc[0] - x * gmc[2]) + (B[2][0] - B[0][2]);
+    gp[5] += (x * gmc[1] - y * gmc[0]) + (B[0][1] - B[1][0]);
+  }
+}
+
+// Records of one pose per blockIdx.y, walked compacted (the in-use slots of
+// the kSub sub-segments, through the prefix of their counters) by a grid of
+// workgroups; each thread sums its records' pose tangents, the workgroup
+// reduces them (wave sums, then four waves) and adds them once per pose.
+template <int DEG, bool GAUSS>
+__global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
+  __shared__ uint32_t s_pre[kSub + 1];
+  __shared__ float s_red[4][6];
+  if (a.flags[0] & 3) return;
+  const int pose = blockIdx.y;
+  const uint32_t sub_cap = a.rec_cap / kSub;
+  if (threadIdx.x < kWave) {
+    const int l = threadIdx.x;
+    uint32_t v = l < kSub ? min(a.pose_count[pose * kSub + l], sub_cap) : 0u;
+#pragma unroll
+    for (int off = 1; off < kSub; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, kWave);
+      if (l >= off) v += u;
+    }
+    if (l < kSub) s_pre[l + 1] = v;
+    if (l == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = s_pre[kSub];
+  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < total; c += gridDim.x * 256) {
+    int lo = 0, hi = kSub;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    record_grad<DEG, GAUSS>(a, pose, static_cast<uint32_t>(lo) * sub_cap + (c - s_pre[lo]), gp);
   }
   if (!a.g_pose) return;
-  for (int k = 0; k < 6; ++k) s_red[k][threadIdx.x] = gp[k];
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int k = 0; k < 6; ++k) s_red[k][threadIdx.x] += s_red[k][threadIdx.x + st];
-    __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float v = gp[k];
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane == 0) s_red[wave][k] = v;
   }
-  if (threadIdx.x < 6 && s_red[threadIdx.x][0] != 0.f) atomicAdd(a.g_pose + 6 * pose + threadIdx.x, s_red[threadIdx.x][0]);
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    const float v = (s_red[0][k] + s_red[1][k]) + (s_red[2][k] + s_red[3][k]);
+    if (v != 0.f) atomicAdd(a.g_pose + 6 * pose + k, v);
+  }
 }
 
 __global__ __launch_bounds__(256) void zero_grad_rec_kernel(float* g, const uint32_t* pose_count, uint32_t rec_cap) {
@@ -758,14 +824,24 @@ void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap
   hipLaunchKernelGGL(zero_grad_rec_kernel, dim3((rec_cap + 255) / 256, P), dim3(256), 0, s, g, pose_count, rec_cap);
 }
 
-void launch_project_bwd(const ProjBackArgs& a, hipStream_t s) {
-  const dim3 grid((a.rec_cap + 255) / 256, a.P);
+template <bool GAUSS>
+static void launch_project_bwd_g(const ProjBackArgs& a, hipStream_t s) {
+  // enough workgroups per pose for its slots at one record per thread, at
+  // most kProjBwdBlocks (the walk strides over the rest)
+  constexpr uint32_t kProjBwdBlocks = 512;
+  const dim3 grid(std::min<uint32_t>((a.rec_cap + 255) / 256, kProjBwdBlocks), a.P);
   switch (a.g.sh_degree) {
-    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((project_bwd_kernel<0, GAUSS>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((project_bwd_kernel<1, GAUSS>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((project_bwd_kernel<2, GAUSS>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((project_bwd_kernel<3, GAUSS>), grid, dim3(256), 0, s, a); break;
   }
+}
+
+void launch_project_bwd(const ProjBackArgs& a, hipStream_t s) {
+  // without per-Gaussian gradients the kernel carries none of their code
+  if (a.g_means || a.g_opac || a.g_log_scales || a.g_quats || a.g_sh) launch_project_bwd_g<true>(a, s);
+  else launch_project_bwd_g<false>(a, s);
 }
 
 }  // namespace hgsr
