@@ -811,17 +811,42 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjBackArgs a) {
   }
 }
 
+// The gradient sums of the in-use records, cleared before the blend backward
+// adds into them: a grid per pose walking the compacted slots.
 __global__ __launch_bounds__(256) void zero_grad_rec_kernel(float* g, const uint32_t* pose_count, uint32_t rec_cap) {
+  __shared__ uint32_t s_pre[kSub + 1];
   const int pose = blockIdx.y;
-  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-  if (slot >= rec_cap || !rec_in_use(pose_count, rec_cap, pose, slot)) return;
-  float4* d = reinterpret_cast<float4*>(g + (static_cast<int64_t>(pose) * rec_cap + slot) * kGradRecStride);
+  const uint32_t sub_cap = rec_cap / kSub;
+  if (threadIdx.x < kWave) {
+    const int l = threadIdx.x;
+    uint32_t v = l < kSub ? min(pose_count[pose * kSub + l], sub_cap) : 0u;
+#pragma unroll
+    for (int off = 1; off < kSub; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, kWave);
+      if (l >= off) v += u;
+    }
+    if (l < kSub) s_pre[l + 1] = v;
+    if (l == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = s_pre[kSub];
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  d[0] = z; d[1] = z; d[2] = z;
+  for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < total; c += gridDim.x * 256) {
+    int lo = 0, hi = kSub;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t slot = static_cast<uint32_t>(lo) * sub_cap + (c - s_pre[lo]);
+    float4* d = reinterpret_cast<float4*>(g + (static_cast<int64_t>(pose) * rec_cap + slot) * kGradRecStride);
+    d[0] = z; d[1] = z; d[2] = z;
+  }
 }
 
 void launch_zero_grad_rec(float* g, const uint32_t* pose_count, uint32_t rec_cap, int P, hipStream_t s) {
-  hipLaunchKernelGGL(zero_grad_rec_kernel, dim3((rec_cap + 255) / 256, P), dim3(256), 0, s, g, pose_count, rec_cap);
+  const dim3 grid(std::min<uint32_t>((rec_cap + 255) / 256, 512), P);
+  hipLaunchKernelGGL(zero_grad_rec_kernel, grid, dim3(256), 0, s, g, pose_count, rec_cap);
 }
 
 template <bool GAUSS>
