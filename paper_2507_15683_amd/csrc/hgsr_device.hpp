@@ -233,13 +233,15 @@ __device__ __forceinline__ bool footprint(const float* P, const float mc[3], con
 // widened by 0.1% and one pixel for rounding, misses the image; such a
 // Gaussian fails footprint() too.
 __device__ __forceinline__ bool maybe_visible(const float mc[3], float s2max, float k2, const CamArgs& c) {
-  const float iz = 1.0f / mc[2];
+  // hardware reciprocal and square root (about 1 ulp): the widening below
+  // covers their error many times over
+  const float iz = __builtin_amdgcn_rcpf(mc[2]);
   const float xz = mc[0] * iz, yz = mc[1] * iz;
   const float xh = fminf(fmaxf(xz, -c.limx), c.limx);
   const float yh = fminf(fmaxf(yz, -c.limy), c.limy);
   const float gx = c.fx * iz, gy = c.fy * iz;
-  const float rx = 1.001f * sqrtf(k2 * fmaf(gx * gx * fmaf(xh, xh, 1.f), s2max, kDilation)) + 1.f;
-  const float ry = 1.001f * sqrtf(k2 * fmaf(gy * gy * fmaf(yh, yh, 1.f), s2max, kDilation)) + 1.f;
+  const float rx = 1.001f * __builtin_amdgcn_sqrtf(k2 * fmaf(gx * gx * fmaf(xh, xh, 1.f), s2max, kDilation)) + 1.f;
+  const float ry = 1.001f * __builtin_amdgcn_sqrtf(k2 * fmaf(gy * gy * fmaf(yh, yh, 1.f), s2max, kDilation)) + 1.f;
   const float u = fmaf(c.fx, xz, c.cx), v = fmaf(c.fy, yz, c.cy);
   return u + rx >= 0.f && v + ry >= 0.f && u - rx <= static_cast<float>(c.W) && v - ry <= static_cast<float>(c.H);
 }
