@@ -686,19 +686,40 @@ constexpr int kLongSortCtas = 768;  // three workgroups per CU
 __global__ __launch_bounds__(256) void tile_sort_long_kernel(TileSortArgs a) {
   __shared__ uint64_t s_key[kLdsSortCap];
   __shared__ uint32_t s_val[kLdsSortCap];
+  __shared__ uint64_t s_long[256 / kWave];  // per wave: which of its lanes' tiles are long
   if (a.flags[0] & 3) return;
-  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {  // uniform per workgroup
-    const uint2 r = a.ranges[t];
-    const uint32_t n = r.y - r.x;
-    if (n <= static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap))) continue;
-    if (n <= static_cast<uint32_t>(a.lds_cap)) {
-      tile_sort_lds(a, r, n, s_key, s_val);
-    } else {
-      // reuse the key array's LDS for the radix pass state
-      uint32_t* base = reinterpret_cast<uint32_t*>(s_key);
-      tile_sort_global(a, r, n, base, reinterpret_cast<uint32_t(*)[256]>(base + 256), base + 256 + 4 * 256);
+  const uint32_t short_max = static_cast<uint32_t>(min(a.lds_cap, kWaveSortCap));
+  // the workgroup's tiles (every gridDim.x-th) looked at 256 at a time, one
+  // range load per thread, and only the long ones sorted
+  for (int64_t t0 = blockIdx.x; t0 < a.n_tiles; t0 += static_cast<int64_t>(gridDim.x) * 256) {
+    const int64_t t = t0 + static_cast<int64_t>(threadIdx.x) * gridDim.x;
+    bool is_long = false;
+    if (t < a.n_tiles) {
+      const uint2 r = a.ranges[t];
+      is_long = r.y - r.x > short_max;
     }
-    __syncthreads();  // the LDS is reused by the next tile
+    const uint64_t bal = __ballot(is_long);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_long[threadIdx.x / kWave] = bal;
+    __syncthreads();
+    for (int w = 0; w < 256 / kWave; ++w) {
+      uint64_t m = s_long[w];  // uniform
+      while (m) {
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        const int64_t tl = t0 + static_cast<int64_t>(w * kWave + l) * gridDim.x;
+        const uint2 r = a.ranges[tl];
+        const uint32_t n = r.y - r.x;
+        if (n <= static_cast<uint32_t>(a.lds_cap)) {
+          tile_sort_lds(a, r, n, s_key, s_val);
+        } else {
+          // reuse the key array's LDS for the radix pass state
+          uint32_t* base = reinterpret_cast<uint32_t*>(s_key);
+          tile_sort_global(a, r, n, base, reinterpret_cast<uint32_t(*)[256]>(base + 256), base + 256 + 4 * 256);
+        }
+        __syncthreads();  // the LDS is reused by the next tile
+      }
+    }
+    __syncthreads();  // s_long is rewritten by the next round
   }
 }
 
