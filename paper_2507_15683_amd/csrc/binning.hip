@@ -303,28 +303,91 @@ __global__ __launch_bounds__(256) void count_tiles_kernel(BinArgs a, uint32_t* t
   if (rec_keys) rec_keys[idx] = ntiles;
 }
 
-// Many poses (bucket path): a workgroup takes a run of kRecPerBlock record
-// slots of one pose and counts their tile entries in an LDS copy of that
+// Many poses (bucket path): a workgroup takes a chunk of kRecChunk in-use
+// records of one pose (compacted through the prefix of the pose's
+// sub-segment counters, so no thread waits on empty slots; consecutive
+// records share tiles) and counts their tile entries in an LDS copy of that
 // pose's tile counters, then adds each nonzero counter to global memory once
-// (one global atomic per (workgroup, tile) instead of one per entry).
-constexpr uint32_t kRecPerBlock = 4096;
+// (one global atomic per (workgroup, tile) instead of one per entry).  Each
+// thread reads its kRecChunk / 256 records with all their loads in flight.
+constexpr uint32_t kRecChunk = 1024;
+constexpr int kRecPerThread = static_cast<int>(kRecChunk / 256);
+
+// The prefix of one pose's clamped sub-segment counters (s_pre[0] = 0,
+// s_pre[kSub] = in-use records), by the first wave; the caller synchronises.
+__device__ __forceinline__ void sub_prefix(const uint32_t* pose_count, int pose, uint32_t sub_cap, uint32_t* s_pre) {
+  if (threadIdx.x < kWave) {
+    const int l = threadIdx.x;
+    uint32_t v = l < kSub ? min(pose_count[pose * kSub + l], sub_cap) : 0u;
+#pragma unroll
+    for (int off = 1; off < kSub; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, kWave);
+      if (l >= off) v += u;
+    }
+    if (l < kSub) s_pre[l + 1] = v;
+    if (l == 0) s_pre[0] = 0;
+  }
+}
+
+// The slot of compacted record c (binary search of the prefix).
+__device__ __forceinline__ uint32_t compact_slot(const uint32_t* s_pre, uint32_t c, uint32_t sub_cap) {
+  int lo = 0, hi = kSub;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_pre[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return static_cast<uint32_t>(lo) * sub_cap + (c - s_pre[lo]);
+}
+
+// One thread's records of a chunk: rectangle, geometry and header.
+struct ChunkRecs {
+  bool ok[kRecPerThread];
+  int64_t idx[kRecPerThread];
+  uint2 rect[kRecPerThread];
+  float4 geo[kRecPerThread], hdr[kRecPerThread];
+  float pmin[kRecPerThread];
+};
+
+__device__ __forceinline__ void load_chunk_recs(const BinArgs& a, int pose, const uint32_t* s_pre, uint32_t c0,
+                                                uint32_t total, ChunkRecs& r) {
+  const uint32_t sub_cap = a.rec_cap / kSub;
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    const uint32_t c = c0 + threadIdx.x + 256u * q;
+    r.ok[q] = c < total;
+    r.idx[q] = 0;
+    if (r.ok[q]) {
+      r.idx[q] = static_cast<int64_t>(pose) * a.rec_cap + compact_slot(s_pre, c, sub_cap);
+      const float4* rp = reinterpret_cast<const float4*>(a.recs + r.idx[q]);
+      r.rect[q] = a.rects[r.idx[q]];
+      r.geo[q] = rp[0];
+      r.hdr[q] = rp[1];
+      r.pmin[q] = rp[2].w;
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void count_tiles_lds_kernel(BinArgs a, uint32_t* tile_count) {
   extern __shared__ uint32_t s_hist[];  // tiles_per_pose counters
+  __shared__ uint32_t s_pre[kSub + 1];
   if (a.flags[0] & 1) return;
   const int pose = blockIdx.y;
   const int T = a.c.tiles_per_pose;
+  sub_prefix(a.pose_count, pose, a.rec_cap / kSub, s_pre);
+  __syncthreads();
+  const uint32_t total = s_pre[kSub];
+  const uint32_t c0 = blockIdx.x * kRecChunk;
+  if (c0 >= total) return;  // uniform
+  ChunkRecs r;
+  load_chunk_recs(a, pose, s_pre, c0, total, r);
   for (int t = threadIdx.x; t < T; t += 256) s_hist[t] = 0;
   __syncthreads();
-  const uint32_t s0 = blockIdx.x * kRecPerBlock, s1 = min(s0 + kRecPerBlock, a.rec_cap);
-  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
-    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
-    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
-    const uint2 r = a.rects[idx];
-    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
-    const float4 geo = rp[0], hdr = rp[1];
-    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
-    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    if (!r.ok[q]) continue;
+    const SplatShape shp = splat_shape(r.geo[q].x, r.geo[q].y, r.geo[q].z, r.geo[q].w, r.hdr[q].x, -2.f * r.pmin[q]);
+    const int tx0 = r.rect[q].x & 0xffff, tx1 = r.rect[q].x >> 16, ty0 = r.rect[q].y & 0xffff, ty1 = r.rect[q].y >> 16;
     for (int ty = ty0; ty <= ty1; ++ty) {
       int ta, tb;
       row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
@@ -341,7 +404,7 @@ __global__ __launch_bounds__(256) void count_tiles_lds_kernel(BinArgs a, uint32_
 
 void launch_count_tiles(const BinArgs& a, uint32_t* tile_count, uint32_t* rec_keys, hipStream_t s) {
   if (tile_count && !rec_keys && a.c.tiles_per_pose <= kLdsTileMax) {
-    const dim3 grid((a.rec_cap + kRecPerBlock - 1) / kRecPerBlock, a.P);
+    const dim3 grid((a.rec_cap + kRecChunk - 1) / kRecChunk, a.P);
     hipLaunchKernelGGL(count_tiles_lds_kernel, grid, dim3(256), a.c.tiles_per_pose * sizeof(uint32_t), s, a,
                        tile_count);
     return;
@@ -426,21 +489,25 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
 // atomic, and places its entries from LDS cursors.
 __global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
   extern __shared__ uint32_t s_pos[];  // per tile: count, then next position
+  __shared__ uint32_t s_pre[kSub + 1];
   if (a.flags[0] & 1) return;
   const int pose = blockIdx.y;
   const int T = a.c.tiles_per_pose;
+  sub_prefix(a.pose_count, pose, a.rec_cap / kSub, s_pre);
+  __syncthreads();
+  const uint32_t total = s_pre[kSub];
+  const uint32_t c0 = blockIdx.x * kRecChunk;
+  if (c0 >= total) return;  // uniform
+  ChunkRecs r;
+  load_chunk_recs(a, pose, s_pre, c0, total, r);
   for (int t = threadIdx.x; t < T; t += 256) s_pos[t] = 0;
   __syncthreads();
-  const uint32_t s0 = blockIdx.x * kRecPerBlock, s1 = min(s0 + kRecPerBlock, a.rec_cap);
   const int64_t tbase = static_cast<int64_t>(pose) * T;
-  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
-    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
-    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
-    const uint2 r = a.rects[idx];
-    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
-    const float4 geo = rp[0], hdr = rp[1];
-    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
-    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    if (!r.ok[q]) continue;
+    const SplatShape shp = splat_shape(r.geo[q].x, r.geo[q].y, r.geo[q].z, r.geo[q].w, r.hdr[q].x, -2.f * r.pmin[q]);
+    const int tx0 = r.rect[q].x & 0xffff, tx1 = r.rect[q].x >> 16, ty0 = r.rect[q].y & 0xffff, ty1 = r.rect[q].y >> 16;
     for (int ty = ty0; ty <= ty1; ++ty) {
       int ta, tb;
       row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
@@ -453,15 +520,13 @@ __global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
     if (c) s_pos[t] = a.ranges[tbase + t].x + atomicAdd(&a.tile_cursor[tbase + t], c);
   }
   __syncthreads();
-  for (uint32_t slot = s0 + threadIdx.x; slot < s1; slot += 256) {
-    if (!rec_in_use(a.pose_count, a.rec_cap, pose, slot)) continue;
-    const int64_t idx = static_cast<int64_t>(pose) * a.rec_cap + slot;
-    const uint2 r = a.rects[idx];
-    const float4* rp = reinterpret_cast<const float4*>(a.recs + idx);
-    const float4 geo = rp[0], hdr = rp[1];  // u, v, ca, cb | cc, o, z, gid
-    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * rp[2].w);
+#pragma unroll
+  for (int q = 0; q < kRecPerThread; ++q) {
+    if (!r.ok[q]) continue;
+    const float4 geo = r.geo[q], hdr = r.hdr[q];  // u, v, ca, cb | cc, o, z, gid
+    const SplatShape shp = splat_shape(geo.x, geo.y, geo.z, geo.w, hdr.x, -2.f * r.pmin[q]);
     const uint64_t key = (static_cast<uint64_t>(zbits(hdr.z)) << 32) | static_cast<uint64_t>(__float_as_uint(hdr.w));
-    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    const int tx0 = r.rect[q].x & 0xffff, tx1 = r.rect[q].x >> 16, ty0 = r.rect[q].y & 0xffff, ty1 = r.rect[q].y >> 16;
     for (int ty = ty0; ty <= ty1; ++ty) {
       int ta, tb;
       row_span(shp, ty, a.c.tile, a.c.W, a.c.H, tx0, tx1, &ta, &tb);
@@ -469,7 +534,7 @@ __global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
         const uint64_t pos = atomicAdd(&s_pos[ty * a.c.ntx + tx], 1u);
         if (pos < a.key_cap) {
           a.keys[pos] = key;
-          a.vals[pos] = static_cast<uint32_t>(idx) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
+          a.vals[pos] = static_cast<uint32_t>(r.idx[q]) | (block_mask(shp, tx, ty, a.c.tile) << kRecBits);
         }
       }
     }
@@ -478,7 +543,7 @@ __global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
 
 void launch_emit_bucket(const BinArgs& a, bool lds, hipStream_t s) {
   if (lds && a.c.tiles_per_pose <= kLdsTileMax) {
-    const dim3 grid((a.rec_cap + kRecPerBlock - 1) / kRecPerBlock, a.P);
+    const dim3 grid((a.rec_cap + kRecChunk - 1) / kRecChunk, a.P);
     hipLaunchKernelGGL(emit_bucket_lds_kernel, grid, dim3(256), a.c.tiles_per_pose * sizeof(uint32_t), s, a);
     return;
   }
