@@ -43,32 +43,35 @@ __global__ __launch_bounds__(256) void partition_bounds_kernel(GaussArgs g, floa
 // the outer side of one of the four image-side planes (through the camera
 // centre, pushed out by a margin of `margin` pixels).  One wave per pose, one
 // lane per partition (at most 64), the mask assembled by a ballot.
+__device__ __forceinline__ bool box_may_be_seen(const float* T, const float* B, const CamArgs& c, float margin) {
+  if (!(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5])) return false;  // empty (or NaN): nothing to draw
+  const float l = (-margin - c.cx) / c.fx, r = (c.W + margin - c.cx) / c.fx;
+  const float t = (-margin - c.cy) / c.fy, b = (c.H + margin - c.cy) / c.fy;
+  bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
+  for (int q = 0; q < 8; ++q) {
+    const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
+    float m[3];
+    to_camera(T, w, m);
+    all_near &= m[2] < c.near_z;
+    all_l &= m[0] < l * m[2];
+    all_r &= m[0] > r * m[2];
+    all_t &= m[1] < t * m[2];
+    all_b &= m[1] > b * m[2];
+  }
+  return !(all_near || all_l || all_r || all_t || all_b);
+}
+
+// The margin in pixels by which the image-side planes are pushed out.
+__device__ __forceinline__ float box_margin(const CamArgs& c) {
+  return 8.f + 0.05f * static_cast<float>(c.W > c.H ? c.W : c.H);
+}
+
 __global__ __launch_bounds__(64) void partition_cull_kernel(const float* poses, int P, const float* bounds,
                                                             int n_parts, CamArgs c, float margin, uint64_t* vis) {
   const int p = blockIdx.x;
   const int k = threadIdx.x;
   if (p >= P) return;  // uniform
-  bool seen = false;
-  if (k < n_parts) {
-    const float* T = poses + 12 * p;
-    const float l = (-margin - c.cx) / c.fx, r = (c.W + margin - c.cx) / c.fx;
-    const float t = (-margin - c.cy) / c.fy, b = (c.H + margin - c.cy) / c.fy;
-    const float* B = bounds + 6 * k;
-    if (B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5]) {  // else empty (or NaN): nothing to draw
-      bool all_near = true, all_l = true, all_r = true, all_t = true, all_b = true;
-      for (int q = 0; q < 8; ++q) {
-        const float w[3] = {(q & 1) ? B[3] : B[0], (q & 2) ? B[4] : B[1], (q & 4) ? B[5] : B[2]};
-        float m[3];
-        to_camera(T, w, m);
-        all_near &= m[2] < c.near_z;
-        all_l &= m[0] < l * m[2];
-        all_r &= m[0] > r * m[2];
-        all_t &= m[1] < t * m[2];
-        all_b &= m[1] > b * m[2];
-      }
-      seen = !(all_near || all_l || all_r || all_t || all_b);
-    }
-  }
+  const bool seen = k < n_parts && box_may_be_seen(poses + 12 * p, bounds + 6 * k, c, margin);
   const uint64_t mask = __ballot(seen);
   if (k == 0) vis[p] = mask;
 }
@@ -456,13 +459,50 @@ __global__ __launch_bounds__(256) void cull_kernel(ProjectArgs a) {
     s2max = __expf(2.f * fmaxf(l0, fmaxf(l1, l2)));
     k2 = 2.f * __logf(255.f * o);
   }
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
+  const uint64_t lanes_below = (uint64_t{1} << lane) - 1u;
+  // The poses that may see any Gaussian of this block: the block's box (each
+  // live Gaussian's ball of twice the 1/255 support radius of its largest
+  // scale, 2 x 3.33 s: the linearised footprint the per-Gaussian test bounds
+  // stays inside it) against each pose's frustum, the image-side planes
+  // pushed out as for partitions.  The per-Gaussian tests then run only for
+  // those poses (a view sees a few percent of the scene).
+  __shared__ float s_box[256 / kWave][6];
+  __shared__ uint64_t s_pmask;
+  {
+    float bx[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    if (live) {
+      const float rr = 2.f * 3.33f * sqrtf(s2max);
+      for (int d = 0; d < 3; ++d) {
+        bx[d] = mu[d] - rr;
+        bx[3 + d] = mu[d] + rr;
+      }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1)
+      for (int d = 0; d < 3; ++d) {
+        bx[d] = fminf(bx[d], __shfl_xor(bx[d], off, kWave));
+        bx[3 + d] = fmaxf(bx[3 + d], __shfl_xor(bx[3 + d], off, kWave));
+      }
+    if (lane == 0)
+      for (int d = 0; d < 6; ++d) s_box[wave][d] = bx[d];
+  }
+  __syncthreads();  // s_box written, s_cnt cleared
+  if (tid < kWave) {  // the first wave, one lane per pose (P <= 64)
+    float B[6];
+    for (int d = 0; d < 3; ++d) {
+      B[d] = fminf(fminf(s_box[0][d], s_box[1][d]), fminf(s_box[2][d], s_box[3][d]));
+      B[3 + d] = fmaxf(fmaxf(s_box[0][3 + d], s_box[1][3 + d]), fmaxf(s_box[2][3 + d], s_box[3][3 + d]));
+    }
+    const bool seen = tid < a.P && box_may_be_seen(a.poses + 12 * (a.pose_base + tid), B, a.c, box_margin(a.c));
+    const uint64_t m = __ballot(seen);
+    if (tid == 0) s_pmask = m;
+  }
   __syncthreads();
   // counted per wave and pose (an LDS atomic from every lane on one address
   // would be performed one lane after another)
-  const int lane = tid & (kWave - 1);
-  const uint64_t lanes_below = (uint64_t{1} << lane) - 1u;
   uint64_t cand = 0;
-  for (int p = 0; p < a.P; ++p) {  // uniform: every lane of the wave
+  for (uint64_t pm = s_pmask; pm; pm &= pm - 1) {  // uniform: every lane of the wave
+    const int p = __builtin_ctzll(pm);
     bool ok = false;
     if (live && ((pose_ok >> p) & 1ull)) {
       const float* T = a.poses + 12 * (a.pose_base + p);
