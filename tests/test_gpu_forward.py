@@ -183,6 +183,42 @@ def test_batched_equals_single(hg):
             assert np.array_equal(to_np(batch[k][p]), to_np(one[k][0])), (p, k)
 
 
+def test_batched_equals_single_64_views_1m(hg):
+    """The many-pose path (per-workgroup chunk box against each frustum,
+    then per-Gaussian tests; chunked tile counting and emission) renders
+    the 1M-Gaussian scene at 64 poses bit for bit as one-pose renders (the
+    single-pass projection, which has no chunk test) do, at sampled poses."""
+    sc, P, cam = synth.aerial_1m_64_views(0)
+    sc, _ = hg.spatial_layout(sc)
+    log("case: 64 poses at 960x540, 1M Gaussians, batched vs single at 6 poses")
+    r = hg.Renderer()
+    batch, _ = _render(hg, sc, P, cam, r=r, tile=16, feat_accum="valu")
+    batch = {k: to_np(v) for k, v in batch.items() if v is not None}
+    for p in (0, 7, 21, 38, 50, 63):
+        one, _ = _render(hg, sc, P[p:p + 1], cam, tile=16, feat_accum="valu")
+        for k in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(batch[k][p], to_np(one[k][0])), (p, k)
+
+
+def test_batched_equals_single_large_gaussians_at_borders(hg):
+    """Large Gaussians close to the camera, with poses turned so that their
+    supports straddle the image borders, where the chunk box test's margin
+    is tightest: batched renders (chunk test) equal one-pose renders."""
+    sc, P, cam = synth.tiny_scene(600, 77, width=96, height=72, feat_dim=8, sh_degree=1, altitude=12.0)
+    sc = sc.copy()
+    sc.log_scales[:] += np.log(6.0)
+    Ps = synth.perturb_poses(P[0], 9, 78, 4.0, 25.0)
+    log("case: large Gaussians at the borders, 9 poses batched vs single")
+    batch, _ = _render(hg, sc, Ps, cam)
+    seen = 0
+    for p in range(len(Ps)):
+        one, _ = _render(hg, sc, Ps[p:p + 1], cam)
+        for k in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(to_np(batch[k][p]), to_np(one[k][0])), (p, k)
+        seen += int(to_np(one["alpha"][0]).max() > 0)
+    assert seen > len(Ps) // 2
+
+
 def test_more_than_64_poses(hg, oracle_mod):
     """Poses beyond one projection launch (64) go through further launches."""
     sc, P, cam = synth.tiny_scene(150, 9, width=40, height=32)
