@@ -484,9 +484,9 @@ __global__ __launch_bounds__(256) void emit_bucket_kernel(BinArgs a) {
   }
 }
 
-// Many poses: the same run of record slots as count_tiles_lds_kernel counts
-// its entries per tile in LDS, reserves each tile's range with one global
-// atomic, and places its entries from LDS cursors.
+// Many poses: the same chunk of in-use records as count_tiles_lds_kernel
+// counts its entries per tile in LDS, reserves each tile's range with one
+// global atomic, and places its entries from LDS cursors.
 __global__ __launch_bounds__(256) void emit_bucket_lds_kernel(BinArgs a) {
   extern __shared__ uint32_t s_pos[];  // per tile: count, then next position
   __shared__ uint32_t s_pre[kSub + 1];

@@ -100,9 +100,13 @@ __device__ __forceinline__ bool range_culled(const ProjectArgs& a, int64_t i0, i
 // over that list with consecutive threads -- the ~7 % of Gaussians a view
 // keeps fill whole waves instead of a few lanes of every wave.  Visible
 // (pose, Gaussian) pairs are compacted per pose: phase B counts them per
-// block in LDS, one global atomic per (block, pose) reserves a range of one
-// of the pose's kSub record sub-segments, phase C recomputes the footprint
-// (same inputs, same arithmetic) and writes the records.  G = 1 (the
+// wave and then per block in LDS, one global atomic per (block, pose)
+// reserves a range of one of the pose's kSub record sub-segments, and phase
+// C writes the records at each lane's rank in its wave's share (with the
+// footprint kept from phase B for one pose and one Gaussian per thread,
+// else recomputed from the same inputs with the same arithmetic).  Every
+// LDS counter is taken once per wave: LDS atomics from all lanes on one
+// address are performed one lane after another.  G = 1 (the
 // default) suits spatially ordered scenes (a workgroup keeps all or nothing,
 // and small workgroups spread the kept ones over the chip); G = 4 suits
 // scenes in arbitrary order (every workgroup keeps a few percent).  The
