@@ -222,6 +222,49 @@ def test_termination_stack(oracle_lib):
     np.testing.assert_allclose(r["rgb"][:, 24, 32], want, atol=1e-12)
 
 
+def test_stop_threshold_is_1e4(oracle_lib):
+    """The walk stops before blending a Gaussian that would take T below 1e-4
+    (Sec. 3.1's tile rasterizer): three o = 0.9 layers leave T = 1e-3; a
+    fourth layer of 0.93 would leave 7e-5 (not blended), one of 0.88 leaves
+    1.2e-4 (blended)."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    cols = np.random.default_rng(7).uniform(0, 1, (4, 3))
+    for o4, nb in ((0.93, 3), (0.88, 4)):
+        sc = _one([[0, 0, 10 + k] for k in range(4)], [[0.0] * 3] * 4, [[1, 0, 0, 0]] * 4, [0.9] * 3 + [o4], cols)
+        o = sc.opacities.astype(np.float64)
+        T3 = (1 - o[0]) ** 3
+        assert (T3 * (1 - o[3]) < 1e-4) == (nb == 3) and 5e-5 < T3 * (1 - o[3]) < 1.5e-4
+        r = oracle_lib.render(sc, IDENT, cam)
+        assert r["nblend"][24, 32] == nb
+        np.testing.assert_allclose(r["T"][24, 32], T3 * ((1 - o[3]) if nb == 4 else 1.0), rtol=1e-12)
+
+
+def test_equal_depths_blend_in_index_order(oracle_lib):
+    """Two Gaussians at the same depth are taken in index order (the (z, i)
+    key): rgb = c0 a + c1 a (1 - a) at their common centre."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    c = np.array([[1.0, 0.0, 0.2], [0.0, 1.0, 0.6]])
+    for order in ([0, 1], [1, 0]):
+        sc = _one([[0, 0, 10]] * 2, [[0.0] * 3] * 2, [[1, 0, 0, 0]] * 2, [0.5, 0.5], c[order])
+        col = sc.sh[:, 0, :].astype(np.float64) * Y00 + 0.5
+        a = float(sc.opacities[0])
+        r = oracle_lib.render(sc, IDENT, cam)
+        np.testing.assert_allclose(r["rgb"][:, 24, 32], col[0] * a + col[1] * a * (1 - a), atol=1e-12)
+
+
+def test_gate_admits_alpha_of_exactly_1_255(oracle_lib):
+    """The gate drops alpha < 1/255 only: an FP64 opacity of exactly 1/255
+    centred on a pixel centre is blended there (support radius 0), and one
+    just below it is not drawn at all."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    sc = _one([[0, 0, 10]], [[0.0] * 3], [[1, 0, 0, 0]], [0.5], [[1, 1, 1]])
+    r = oracle_lib.render(sc, IDENT, cam, overrides={"opacities": np.array([1 / 255])})
+    assert r["nblend"][24, 32] == 1 and r["nblend"].sum() == 1
+    assert abs(r["alpha"][24, 32] - 1 / 255) < 1e-15
+    r = oracle_lib.render(sc, IDENT, cam, overrides={"opacities": np.array([np.nextafter(1 / 255, 0)])})
+    assert r["alpha"].max() == 0
+
+
 def test_associativity_front_back(oracle_lib):
     """Compositing the front half and then the back half with 'over' equals
     compositing the whole depth-sorted list (no termination: low opacity)."""
@@ -378,6 +421,58 @@ def test_view_dependent_colour_uses_camera_centre(oracle_lib):
     C1 = math.sqrt(3 / (4 * math.pi))
     np.testing.assert_allclose([p["r"][0], p["g"][0], p["b"][0]],
                                np.maximum(0, 0.5 + np.array([1.0, -0.5, 0.25]) * C1 * d[2]), atol=1e-12)
+
+
+def test_sh_coefficients_indexed_l2_l_m(oracle_lib):
+    """Degree-3 colour: coefficient k = l^2 + l + m multiplies the real
+    harmonic Y_lm (scipy's, Condon-Shortley phase) at the unit direction from
+    the camera centre to the mean; colour = max(0, 0.5 + sum)."""
+    from scipy.special import sph_harm_y
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    pose = _rand_pose(9)
+    R, t = pose.reshape(3, 4)[:, :3], pose.reshape(3, 4)[:, 3]
+    mw = (np.array([0.7, -0.4, 8.0]) - t) @ R
+    sc = _one([mw], [[0.0] * 3], [[1, 0, 0, 0]], [0.9], [[0.5] * 3], sh_degree=3)
+    rng = np.random.default_rng(11)
+    sc.sh[0] = rng.uniform(-0.3, 0.3, (16, 3)).astype(np.float32)
+    sc.sh[0, 0, :] = 2.0  # keeps every channel above the clamp
+    p = oracle_lib.project(sc, pose, cam)
+    d = sc.means[0].astype(np.float64) + R.T @ t
+    d /= np.linalg.norm(d)
+    theta, phi = np.arccos(d[2]), np.arctan2(d[1], d[0])
+    want = np.full(3, 0.5)
+    for l in range(4):
+        for m in range(-l, l + 1):
+            cpx = sph_harm_y(l, abs(m), theta, phi)
+            y = cpx.real if m == 0 else np.sqrt(2) * (cpx.real if m > 0 else cpx.imag)
+            want += sc.sh[0, l * l + l + m].astype(np.float64) * y
+    assert want.min() > 0
+    np.testing.assert_allclose([p["r"][0], p["g"][0], p["b"][0]], want, atol=1e-12)
+
+
+def test_negative_colour_is_clamped_to_zero(oracle_lib):
+    """colour = max(0, SH sum + 0.5): a DC term below -0.5 gives 0, and the
+    render shows no trace of that channel."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    sc = _one([[0, 0, 10]], [[0.0] * 3], [[1, 0, 0, 0]], [0.8], [[-0.4, 0.3, 1.2]])
+    p = oracle_lib.project(sc, IDENT, cam)
+    assert p["r"][0] == 0.0 and p["g"][0] > 0 and p["b"][0] > 1
+    r = oracle_lib.render(sc, IDENT, cam)
+    assert r["rgb"][0].max() == 0.0 and r["rgb"][1].max() > 0
+
+
+def test_fp64_inputs_read_like_fp32(oracle_lib):
+    """The FP64 input path (finite differences, exact pins) reads every array
+    in the layout of the FP32 one: the same values through either path render
+    the same images bit for bit."""
+    sc, P, cam = synth.tiny_scene(60, 13, feat_dim=8, sh_degree=3)
+    base = oracle_lib.render(sc, P[0], cam)
+    feat = synth.bf16_bits_to_f32(sc.feat).astype(np.float64)
+    for key, arr in (("means", sc.means), ("opacities", sc.opacities), ("log_scales", sc.log_scales),
+                     ("quats", sc.quats), ("sh", sc.sh), ("feat", feat)):
+        r = oracle_lib.render(sc, P[0], cam, overrides={key: np.asarray(arr, np.float64)})
+        for out in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(r[out], base[out]), (key, out)
 
 
 # ------------------------------------------------------------------ tile lists
