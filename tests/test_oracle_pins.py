@@ -476,13 +476,16 @@ def test_fp64_inputs_read_like_fp32(oracle_lib):
 
 
 # ------------------------------------------------------------------ tile lists
-def test_tile_lists_follow_the_listing_rule(oracle_lib):
+@pytest.mark.parametrize("size", [(64, 48, 13), (60, 44, 17)])
+def test_tile_lists_follow_the_listing_rule(oracle_lib, size):
     """A visible Gaussian is listed in a tile of its pixel rectangle exactly
-    when the tile's rectangle of pixel centres meets its support ellipse
+    when the tile's rectangle of pixel centres (clipped to the image: the
+    ragged size has partial tiles) meets its support ellipse
     q <= 2 ln(255 o); checked here by brute force on a 1/40 px grid of each
     such rectangle (grid minimum vs the listing decision), in (z, index)
     order.  Listing must also be a subset of the rectangle rule."""
-    sc, P, cam = synth.tiny_scene(180, 13)
+    W, H, seed = size
+    sc, P, cam = synth.tiny_scene(180, seed, width=W, height=H)
     tile = 16
     p = oracle_lib.project(sc, P[0], cam)
     off, ids, edge = oracle_lib.tile_lists(sc, P[0], cam, tile)
@@ -517,6 +520,39 @@ def test_tile_lists_follow_the_listing_rule(oracle_lib):
             want.sort(key=lambda i: (p["z"][i], i))
             assert got == want, (tx, ty)
     assert dropped > 0  # the rule is tighter than the rectangle on this scene
+
+
+def test_edge_flag_marks_an_ellipse_grazing_a_tile_corner(oracle_lib):
+    """A Gaussian whose support ellipse passes within the edge tolerance of a
+    tile's corner of pixel centres is flagged as a tile-edge Gaussian even
+    though its pixel rectangle is far from every tile boundary; moved 0.3 px
+    further into that tile it is not flagged."""
+    cam = Camera(100.0, 100.0, 32.0, 24.0, 64, 48)
+    z, tile, corner = 10.0, 16, 15.5  # tile (0, 0)'s last pixel centre
+
+    def scene_at(t):
+        u = v = corner + t  # centre on the corner's diagonal, outside tile 0
+        m = [(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z]
+        return _one([m], [[math.log(0.15)] * 3], [[1, 0, 0, 0]], [0.8], [[1, 1, 1]])
+
+    def gap(t):  # q at the corner minus the support threshold
+        p = oracle_lib.project(scene_at(t), IDENT, cam)
+        dx, dy = corner - p["u"][0], corner - p["v"][0]
+        q = p["conic_a"][0] * dx * dx + 2 * p["conic_b"][0] * dx * dy + p["conic_c"][0] * dy * dy
+        return q - 2 * np.log(255 * p["o"][0]), p
+
+    lo, hi = 0.0, 8.0
+    assert gap(lo)[0] < 0 < gap(hi)[0]
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if gap(mid)[0] < 0 else (lo, mid)
+    for t, flagged in ((lo - 1e-5, 1), (lo - 0.3, 0)):
+        _, p = gap(t)
+        for b in (p["bx0"][0], p["bx1"][0], p["by0"][0], p["by1"][0]):  # rectangle far from tile bounds
+            assert abs(b - round(b)) > 0.05 or int(round(b)) % tile not in (0, tile - 1)
+        off, ids, edge = oracle_lib.tile_lists(scene_at(t), IDENT, cam, tile)
+        assert 0 in ids[off[0]:off[1]]  # tile 0 lists it (the corner lies inside the ellipse)
+        assert edge[0] == flagged, t
 
 
 def test_min_q_box_closed_forms_and_grid(oracle_lib):
@@ -580,12 +616,23 @@ def test_residual_gradient_closed_form():
     assert abs(residual(rgbt, ft, rgbt, ft)) < 1e-8
 
 
-def test_frozen_render_reproduces_reference(oracle_lib):
+@pytest.mark.parametrize("opaque", [False, True])
+def test_frozen_render_reproduces_reference(oracle_lib, opaque):
+    """Replaying the blended lists with the decisions frozen reproduces the
+    render bit for bit, also where alpha is clamped at 0.99 (opaque case)."""
     sc, P, cam = synth.tiny_scene(150, 21, feat_dim=4)
+    if opaque:
+        sc.opacities[:] = 1.0
     r = oracle_lib.render(sc, P[0], cam, want_lists=True)
     fz = oracle_lib.render_frozen(sc, P[0], cam, r["lists"], r["nblend"])
     for k in ("rgb", "depth", "alpha", "T", "feat"):
         assert np.array_equal(r[k], fz[k]), k
+    if opaque:  # some Gaussian's pair at its nearest pixel centre is clamped
+        p = oracle_lib.project(sc, P[0], cam)
+        dx = np.floor(p["u"]) + 0.5 - p["u"]
+        dy = np.floor(p["v"]) + 0.5 - p["v"]
+        q = p["conic_a"] * dx * dx + 2 * p["conic_b"] * dx * dy + p["conic_c"] * dy * dy
+        assert ((q < -2 * np.log(0.99)) & (p["visible"] == 1)).any()
 
 
 def test_translation_identity_of_finite_differences(oracle_lib):

@@ -184,3 +184,25 @@ def test_significance_invariances(oracle_lib):
     rv = sg.significance(sc, poses[::-1], cam, maps[::-1])
     assert np.array_equal(rv["count"], r["count"])
     np.testing.assert_allclose(rv["score_sum"], r["score_sum"], rtol=0, atol=1e-12)
+
+
+def test_contrib_flags_follow_the_blended_lists(oracle_lib):
+    """contrib marks the Gaussians blended at some pixel, robust those blended
+    at some pixel that is not fragile: recomputed here from the render's own
+    per-pixel blended lists and fragile map."""
+    for seed in (3, 8):
+        sc, P, cam = synth.tiny_scene(150, seed)
+        r = oracle_lib.render(sc, P[0], cam, want_lists=True)
+        c, robust, _ = oracle_lib.contrib(sc, P[0], cam)
+        want_c = np.zeros(sc.n, bool)
+        want_r = np.zeros(sc.n, bool)
+        nb = r["nblend"].reshape(-1)
+        frag = r["fragile"].reshape(-1)
+        for pix in np.nonzero(nb)[0]:
+            ids = r["lists"][pix, :nb[pix]]
+            want_c[ids] = True
+            if not frag[pix]:
+                want_r[ids] = True
+        assert want_r.any() and (want_c & ~want_r).sum() < want_c.sum()
+        assert np.array_equal(c.astype(bool), want_c)
+        assert np.array_equal(robust.astype(bool), want_r)
