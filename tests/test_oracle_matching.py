@@ -30,6 +30,9 @@ def test_two_by_two_by_hand():
     b = 1.0 - a
     np.testing.assert_allclose(c["P"], [[a * a, b * b], [b * b, a * a]], rtol=1e-7)
     assert list(c["i"]) == [0, 1] and list(c["j"]) == [0, 1]
+    # margins: log of best over second-best, log(a^2 / b^2) = 4 per row and column
+    np.testing.assert_allclose(c["row_margin"], [4.0, 4.0], rtol=1e-6)
+    np.testing.assert_allclose(c["col_margin"], [4.0, 4.0], rtol=1e-6)
 
 
 def test_many_to_one_keeps_one_mutual_pair():

@@ -155,3 +155,26 @@ def test_refinement_retakes_the_inlier_set_until_it_is_a_fixed_point():
         Th[:3, :] = r["hyps"][r["best"]]
         cost = lambda M: np.minimum(pnp.errors(M, K, X, p) ** 2, tau * tau).sum()
         assert cost(Tr) <= cost(Th), seed
+
+
+def test_score_counts_errors_below_tau_in_front_of_the_camera():
+    """The RANSAC score of the exact pose: correspondences with reprojection
+    error below tau and positive depth.  Three exact, three 1.5 px off
+    (counted at tau = 2), three 3 px off (not counted), one world point
+    behind the camera on the ray of its pixel (error 0, not counted), two
+    more exact: 8.  Two identical samples tie and the lower index wins."""
+    T = _pose(7)
+    p, X, _ = _scene(T, 12, 8)
+    p[3:6] += [1.5, 0.0]
+    p[6:9] += [0.0, 3.0]
+    Xc9 = X[9] @ T[:3, :3].T + T[:3, 3]
+    X[9] = (-Xc9 - T[:3, 3]) @ T[:3, :3]  # same pixel, negative depth
+    r = pnp.pnp_ransac(p, X, K, T[:3, :].reshape(12), [[0, 1, 2], [0, 1, 2]], tau=2.0, gn_iters=3,
+                       refine_iters=0)
+    assert list(r["counts"]) == [8, 8] and r["best"] == 0
+    want = np.array([1] * 6 + [0] * 4 + [1] * 2, dtype=bool)
+    assert np.array_equal(r["inliers"], want)
+    e = r["hyp_err"][0]
+    np.testing.assert_allclose(e[3:6], 1.5, atol=1e-6)
+    np.testing.assert_allclose(e[6:9], 3.0, atol=1e-6)
+    assert np.isinf(e[9])
