@@ -249,6 +249,45 @@ def test_empty_and_culled_scenes(hg):
     assert to_np(out["alpha"]).max() == 0
 
 
+def _hand_scene(means, opac, rgb, sigma=1.0):
+    """Camera-facing isotropic Gaussians of scale sigma with DC colours rgb."""
+    n = len(means)
+    sh = np.zeros((n, 1, 3), np.float32)
+    sh[:, 0, :] = (np.asarray(rgb, np.float64) - 0.5) * (2.0 * np.sqrt(np.pi))
+    return synth.Scene(np.asarray(means, np.float32), np.full((n, 3), np.log(sigma), np.float32),
+                       np.tile(np.float32([1, 0, 0, 0]), (n, 1)), np.asarray(opac, np.float32), sh, 0, None)
+
+
+def test_stop_clamps_and_ties_match_oracle(hg, oracle_mod):
+    """Hand-built edge cases against the oracle: layers whose transmittance
+    crosses the 1e-4 stop just after (7e-5: not blended) or just before
+    (1.2e-4: blended) the fourth layer, an opaque Gaussian (alpha clamped at
+    0.99), a negative SH colour (clamped at 0), and two Gaussians at one depth
+    (taken in index order)."""
+    cam = synth.Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    ident = np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]], np.float32)
+    cols = np.random.default_rng(7).uniform(0, 1, (4, 3))
+    cases = {f"stack o4={o4}": _hand_scene([[0, 0, 10 + k] for k in range(4)], [0.9] * 3 + [o4], cols)
+             for o4 in (0.93, 0.88)}
+    cases["opaque"] = _hand_scene([[0, 0, 10]], [1.0], [[0.2, 0.7, 0.4]])
+    cases["negative colour"] = _hand_scene([[0, 0, 10]], [0.8], [[-0.4, 0.3, 1.2]])
+    for name, sc in cases.items():
+        log("case:", name)
+        out, r = _render(hg, sc, ident, cam, tile=16)
+        ref = oracle_mod.render(sc, ident[0], cam, tile=16, margin=1)
+        parity(out, ref, label=name)
+        assert to_np(out["alpha"][0])[24, 32] == pytest.approx(ref["alpha"][24, 32], abs=1e-6)
+    # equal depths: index order, rgb = c0 a + c1 a (1 - a) at the common centre
+    c = np.array([[1.0, 0.0, 0.2], [0.0, 1.0, 0.6]])
+    for order in ([0, 1], [1, 0]):
+        log("case: equal depths, order", order)
+        sc = _hand_scene([[0, 0, 10]] * 2, [0.5, 0.5], c[order])
+        out, _ = _render(hg, sc, ident, cam, tile=16)
+        col = sc.sh[:, 0, :].astype(np.float64) / (2.0 * np.sqrt(np.pi)) + 0.5
+        want = col[0] * 0.5 + col[1] * 0.25
+        np.testing.assert_allclose(to_np(out["rgb"][0])[:, 24, 32], want, atol=1e-6)
+
+
 def test_overflow_regrows_to_same_result(hg):
     sc, P, cam = synth.terrain_20k_view(2)
     log("case: default capacity")
