@@ -265,6 +265,37 @@ def test_gate_admits_alpha_of_exactly_1_255(oracle_lib):
     assert r["alpha"].max() == 0
 
 
+def test_fragile_pixels_mark_decisions_within_fp32_error(oracle_lib):
+    """A pixel is fragile where a decision lies within the FP32 error bound of
+    going the other way: alpha within it of 1/255 (above or below), T within
+    it of 1e-4 at a step, or two blended Gaussians whose depths differ by
+    less than their FP32 depth error.  The same decisions far from their
+    thresholds leave the pixel robust."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    one = _one([[0, 0, 10]], [[0.0] * 3], [[1, 0, 0, 0]], [0.5], [[1, 1, 1]])
+    # the gate: the pixel one to the right of the centre (d = 1 px) sees
+    # alpha = o exp(-1 / (2 s2)), s2 = (f sigma / z)^2 + 0.3
+    s2 = (cam.fx * 1.0 / 10.0) ** 2 + 0.3
+    for rel, frag in ((1 + 1e-9, True), (1 - 1e-9, True), (2.0, False)):
+        o = rel / 255 * math.exp(0.5 / s2)
+        r = oracle_lib.render(one, IDENT, cam, overrides={"opacities": np.array([o])})
+        assert bool(r["fragile"][24, 33]) == frag, rel
+    # the stop: three layers of 0.9, then a fourth leaving T = 1e-4 (1 +- 1e-9)
+    four = _one([[0, 0, 10 + k] for k in range(4)], [[0.0] * 3] * 4, [[1, 0, 0, 0]] * 4, [0.5] * 4, [[1, 1, 1]] * 4)
+    T3 = 0.1 ** 3
+    for rel, frag in ((1 + 1e-9, True), (1 - 1e-9, True), (0.5, False)):
+        o4 = 1 - 1e-4 * rel / T3
+        r = oracle_lib.render(four, IDENT, cam, overrides={"opacities": np.array([0.9, 0.9, 0.9, o4])})
+        assert bool(r["fragile"][24, 32]) == frag, rel
+    # depth order: two blended Gaussians 5e-7 apart at z = 10 (FP32 error of
+    # z there ~1e-6), then 1e-3 apart
+    two = _one([[0, 0, 10]] * 2, [[0.0] * 3] * 2, [[1, 0, 0, 0]] * 2, [0.5, 0.5], [[1, 0, 0], [0, 1, 0]])
+    for dz, frag in ((5e-7, True), (0.0, True), (1e-3, False)):
+        m = np.array([[0, 0, 10.0], [0, 0, 10.0 + dz]])
+        r = oracle_lib.render(two, IDENT, cam, overrides={"means": m})
+        assert bool(r["fragile"][24, 32]) == frag, dz
+
+
 def test_associativity_front_back(oracle_lib):
     """Compositing the front half and then the back half with 'over' equals
     compositing the whole depth-sorted list (no termination: low opacity)."""
