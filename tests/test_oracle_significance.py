@@ -167,6 +167,13 @@ def test_cell_rule_on_a_non_integer_grid():
     assert list(got) == want
     assert near[0] and near[5] and near[7]                     # on the border
     assert not near[1] and not near[3]
+    # near a cell border from either side: 5e-4 px below the border at
+    # U = 19.2 is near, 5e-3 px below it is not (the default tolerance,
+    # 1e-3 px); the same on the upper side of the border at V = 19.2
+    U2 = np.array([19.1995, 19.195, 30.0, 30.0])
+    V2 = np.array([14.4, 14.4, 19.2005, 19.205])
+    _, _, near2 = sg.sample_cosines(feat[:4], U2, V2, fmap, W, H)
+    assert list(near2) == [True, False, True, False]
 
 
 def test_significance_invariances(oracle_lib):
@@ -206,3 +213,19 @@ def test_contrib_flags_follow_the_blended_lists(oracle_lib):
         assert want_r.any() and (want_c & ~want_r).sum() < want_c.sum()
         assert np.array_equal(c.astype(bool), want_c)
         assert np.array_equal(robust.astype(bool), want_r)
+
+
+def test_fragile_only_visibility_is_exempt(oracle_lib):
+    """A pair whose visibility rests only on fragile pixels is exempt: a
+    Gaussian of opacity float32(1/255) centred on a pixel centre is blended
+    at that pixel alone, where its alpha is within the FP32 error of the
+    gate.  Its mean is inside the image, away from cell borders."""
+    cam = Camera(100.0, 100.0, 32.5, 24.5, 64, 48)
+    rng = np.random.default_rng(3)
+    sc = _scene([[0.0, 0.0, 10.0], [0.5, 0.3, 12.0]], [1.0, 0.3], [1 / 255, 0.8], rng.normal(0, 1, (2, 8)))
+    maps = rng.normal(0, 1, (1, 8, 12, 16)).astype(np.float32)
+    c, robust, touched = oracle_lib.contrib(sc, _pose((0, 0, 0)), cam)
+    assert c[0] and not robust[0] and touched[0]
+    r = sg.significance(sc, _pose((0, 0, 0))[None], cam, maps)
+    assert r["visible"][0, 0] and r["exempt"][0, 0]
+    assert r["visible"][0, 1] and not r["exempt"][0, 1]
